@@ -1,0 +1,190 @@
+"""Throughput benchmark of the BFCS Lippmann-Schwinger solver on one MI355X.
+
+A step is one complete BFCS solve of the default workload (3D 128^3 voxels =
+8x8x8 unit cells of 16^3, one sphere per cell at volume fraction 0.25,
+inclusion/matrix Young's contrast 10, nu = 0.3, vector bump force of radius 12
+voxels with seeded centre and direction, reference medium = mean of the
+extreme Lame constants, basic scheme, FP32 transforms and updates with the
+FP64 residual and stopping test, tol 1e-8): force transform and free term,
+the fixed-point iterations until the stopping or stagnation rule fires, and
+materialization of u, eps and sigma.  Inputs are resident in HBM before the
+timed region starts.
+
+Printed: one JSON line with voxel-iterations/s (sum of |N| x iterations over
+the timed solves divided by wall time), solves/s, the roofline of the
+dominant kernel (algorithmic bytes per launch over its mean HIP-event
+duration inside the timed region), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iters/s + BFCS solves/s at 1e-8 residual; surrogate vs solver speedup"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "bfcs128": dict(shape=(128, 128, 128), cell=16, vf=0.25, contrast=10.0, radius=12.0,
+                    desc="3D 128^3 (8^3 cells of 16^3), one sphere per cell vf 0.25, contrast 10, "
+                         "vector bump R=12, basic scheme to 1e-8"),
+    "bfcs256": dict(shape=(256, 256, 256), cell=16, vf=0.30, contrast=100.0, radius=12.0, rsa=True,
+                    desc="3D 256^3 (16^3 cells of 16^3), RSA spheres vf 0.3 r 3-6, contrast 100, "
+                         "vector bump R=12, basic scheme to 1e-8"),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("kernels_impl.hpp", "fft_core.hpp"):
+        with open(os.path.join(ROOT, "paper_2601_00822_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, prec: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_hash:\s*(\w+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def make_inputs(wl: dict, seed: int = 0):
+    import numpy as np
+    import gen
+    shape = wl["shape"]
+    if wl.get("rsa"):
+        cell, _ = gen.rsa_cell(wl["cell"], 3, wl["vf"], 3.0, 6.0, seed=seed)
+        phase = gen.tile_cell(cell, shape)
+    else:
+        phase, _ = gen.inclusion_per_cell(shape, wl["cell"], wl["vf"])
+    f = gen.bump_force(shape, gen.random_center(shape, seed), wl["radius"], gen.random_direction(3, seed + 1))
+    table = gen.Material.two_phase(1.0, wl["contrast"]).table()
+    return phase, f, table, np.asarray(table)
+
+
+def cpu_baseline(wl: dict, phase, f, table, budget_s: float = 20.0):
+    """The FP64 oracle as it stands, timed on the host on a bounded sample:
+    Algorithm 1 on the full grid for a fixed number of iterations."""
+    from oracle import lsfft_oracle as O
+    lame = O.lame_from_young(table)
+    nvox = int(phase.size)
+    t0 = time.perf_counter()
+    O.solve_basic(phase, lame, f, tol=1e-30, max_iter=1)            # free term + 1 iteration
+    t1 = time.perf_counter()
+    per_iter = max(t1 - t0, 1e-3) / 2.0
+    iters = max(1, min(20, int(budget_s / per_iter) - 1))
+    t0 = time.perf_counter()
+    res = O.solve_basic(phase, lame, f, tol=1e-30, max_iter=iters)
+    dt = time.perf_counter() - t0
+    return {"value": nvox * res.iters / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"full {phase.shape} grid, {res.iters} iterations of Algorithm 1 in FP64 NumPy "
+                      f"(pocketfft, single thread), {dt:.1f} s including the free term"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="bfcs128", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--scheme", default="basic", choices=["basic", "cg"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the solver path is single-GPU (requested --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    from paper_2601_00822_amd import Plan, K_GREEN, K_XPASS, K_YPASS, K_REDUCE
+
+    wl = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    phase, f, table, _ = make_inputs(wl)
+    from paper_2601_00822_amd import lame_from_young
+    lame = lame_from_young(table)
+    dt = torch.float32 if args.prec == "f32" else torch.float64
+    phase_d = torch.from_numpy(phase).to(dev)
+    f_d = torch.from_numpy(f).to(dev).to(dt)
+    plan = Plan([wl["shape"]], prec=args.prec, scheme=args.scheme, timing=True)
+    nvox = int(np.prod(wl["shape"]))
+
+    for _ in range(args.warmup):
+        plan.solve(phase_d, lame, f_d, tol=1e-8)
+    torch.cuda.synchronize()
+    plan.kernel_times_reset()
+    iters = 0
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, rep = plan.solve(phase_d, lame, f_d, tol=1e-8)
+        iters += rep.iters
+        reps.append(rep)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    classes = {"green": K_GREEN, "xpass": K_XPASS, "ypass": K_YPASS, "reduce": K_REDUCE}
+    ktimes = {k: plan.kernel_times(c) for k, c in classes.items()}
+    dom = max(("green", "xpass", "ypass"), key=lambda k: ktimes[k][0])
+    ms, launches = ktimes[dom]
+    per_launch_s = ms / 1e3 / max(launches, 1)
+    bytes_per_iter = plan.iteration_bytes(classes[dom])
+    if dom == "ypass":
+        bytes_per_iter /= 2.0                      # two y launches per iteration
+    achieved = bytes_per_iter / per_launch_s / 1e9
+    traffic = measured_traffic(dom, args.workload, args.prec)
+
+    out = {
+        "metric": METRIC,
+        "value": nvox * iters / elapsed,
+        "unit": "voxel-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(wl["shape"]), "scheme": args.scheme,
+                   "precision": f"{args.prec} transforms/updates, f64 residual", "tol": 1e-8,
+                   "description": wl["desc"]},
+        "solves_per_s": args.steps / elapsed,
+        "iterations_per_solve": iters / args.steps,
+        "final_residual": reps[-1].residual,
+        "status": reps[-1].status,
+        "kernel_ms_per_iteration": {k: v[0] / max(iters, 1) for k, v in ktimes.items()},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_iter,
+                     "mean_launch_us": per_launch_s * 1e6, "launches": launches},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, phase, f, table, args.cpu_budget)
+    plan.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,208 @@
+/*
+ * liblsfft -- FFT-based modified Lippmann-Schwinger solver for periodic
+ * linear-elastic composites under a body force with compact support (BFCS),
+ * with translated averaging of the solved fields, for AMD MI355X (gfx950).
+ *
+ * Method: V. A. Buryachenko, "New RVE concept and FFT methods in
+ * micromechanics of composites subjected to body force with compact support",
+ * arXiv 2601.00822.  Equation numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid (Sec. 4, Eq. 4.1): nodes x = k h, k_alpha = 0..n_alpha-1, every
+ *    n_alpha even.  Supported axis lengths: 4, 6, 8, 12, 16, 24, 32, 48, 64,
+ *    96, 128, 256.  2D grids are plane strain.
+ *  - Layout: fields are component-major and C-ordered [comp][z][y][x] with x
+ *    fastest (2D: [comp][y][x]); vector components (x, y[, z]); symmetric
+ *    tensors in Voigt order (11,22,33,23,13,12) in 3D and (11,22,12) in 2D,
+ *    tensor (not engineering) shear.  Phase maps are uint8 [z][y][x].
+ *  - Precision: a plan computes in FP32 or FP64 (transforms, pointwise
+ *    updates, all real and complex fields); the equilibrium residual norm, the
+ *    stopping test and the translated-average accumulation are FP64 always.
+ *  - Ownership: the caller owns every input and output buffer (device memory
+ *    unless stated "host").  The plan owns its workspace (allocated lazily,
+ *    grown as needed, freed by lsfft_plan_destroy).  The library never frees
+ *    caller memory.
+ *  - Synchrony: work is enqueued on the plan's HIP stream; every solve call
+ *    returns after its outputs and reports are complete.  A plan is not
+ *    re-entrant: use one plan per thread.
+ *  - Errors: every argument check runs on the host before any kernel is
+ *    launched (phase ids are checked by a small device reduction before the
+ *    solve starts).  No exception crosses the ABI.
+ *  - Determinism: for a fixed plan, device and input, results are bitwise
+ *    reproducible (fixed-order reductions, no floating-point atomics).
+ */
+#ifndef LSFFT_H
+#define LSFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LSFFT_OK = 0,
+  LSFFT_W_STAGNATED = 1,   /* residual stopped improving above tol; result holds the last iterate */
+  LSFFT_E_ARG = -1,        /* invalid argument (nothing was launched) */
+  LSFFT_E_ALLOC = -2,      /* device allocation failed */
+  LSFFT_E_DEVICE = -3,     /* HIP runtime error */
+  LSFFT_E_NOCONV = -4,     /* max_iter reached; outputs hold the last iterate */
+  LSFFT_E_NONEQUIL = -5,   /* LSFFT_STRICT_EQUIL set and the force is not self-equilibrated */
+  LSFFT_E_DIVERGED = -6    /* residual became non-finite or grew for more than 20 iterations */
+} lsfft_status;
+
+typedef enum { LSFFT_F32 = 0, LSFFT_F64 = 1 } lsfft_prec;
+
+/* LSFFT_BASIC: Algorithm 1 (modified basic scheme, Sec. 5, Eqs. 5.7-5.11).
+ * LSFFT_CG: conjugate gradients on the displacement form of the same
+ * discrete equilibrium system (Algorithm 2's operator in the displacement
+ * unknown of Eqs. 5.14-5.22), preconditioned by the reference-medium Green
+ * operator; same limit, fewer iterations at high contrast. */
+typedef enum { LSFFT_BASIC = 0, LSFFT_CG = 1 } lsfft_scheme;
+
+/* plan flags */
+#define LSFFT_STRICT_EQUIL 0x1u  /* reject forces whose voxel sum is not ~0 (Eq. 2.5) instead of projecting */
+#define LSFFT_TIMING       0x2u  /* record HIP events around every kernel launch (see lsfft_kernel_times) */
+
+typedef struct {
+  int dim;          /* 2 or 3 */
+  int64_t n[3];     /* (nx, ny, nz); nz ignored (treated as 1) when dim == 2 */
+  double h[3];      /* grid spacing per axis (> 0); the unit of length of u */
+} lsfft_grid;
+
+typedef struct {
+  int nphase;            /* 1..256 */
+  const double* lame;    /* host, [nphase][2] = (lambda, mu); mu > 0, lambda + 2 mu / d > 0 */
+} lsfft_phases;
+
+/* Reference medium L0 of Algorithm 1.  NaN in both fields selects the default
+ * (mean of the smallest and largest Lame constants over the phases). */
+typedef struct {
+  double lambda0, mu0;
+} lsfft_ref;
+
+typedef struct {
+  int iters;               /* Green updates applied (basic) or CG updates */
+  double residual;         /* ||i xi . sigma^ + P f^|| / ||P f^|| of the returned iterate (FP64) */
+  double removed_mean[3];  /* voxel mean of the force removed by the projection onto Eq. 2.5 */
+  int status;              /* lsfft_status of this solve */
+  double seconds;          /* wall time of the batch this solve ran in */
+} lsfft_report;
+
+typedef struct lsfft_plan_s* lsfft_plan_t;
+
+/*
+ * lsfft_plan -- create a plan for solves on the given grids.
+ *  out        host, receives the plan handle (NULL on failure)
+ *  grids      host [ngrid]; every axis length must be supported
+ *  max_batch  largest number of solves (or shifts) run concurrently; larger
+ *             requests are processed in successive batches (>= 1)
+ *  hip_stream hipStream_t to enqueue on (NULL = the null stream)
+ * Errors: LSFFT_E_ARG for an unsupported grid, ngrid < 1, max_batch < 1;
+ * LSFFT_E_DEVICE if no HIP device is usable.
+ */
+lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, int max_batch,
+                        lsfft_prec prec, lsfft_scheme scheme, unsigned flags, void* hip_stream);
+
+/*
+ * lsfft_solve_bfcs -- solve the modified Lippmann-Schwinger equation
+ * (Eq. 2.14; Algorithm 1 or its CG variant) for nsolve independent problems,
+ * run as one batch: material L(x) = table[phase(x)], reference medium c0,
+ * body force f (projected onto the self-equilibrated subspace, Eq. 2.5),
+ * free term u^b = G0 * f (Eqs. 2.8-2.9), stopping rule ||div sigma + Pf|| /
+ * ||Pf|| <= tol (Eq. 5.11 adapted to body-force loading).  The returned
+ * iterate is the first one meeting the rule.
+ *  grid_idx  host [nsolve], index into the plan's grids
+ *  phase     host array [nsolve] of device pointers, uint8 [nz][ny][nx]
+ *  tab       host [nsolve] phase tables
+ *  c0        host [nsolve] reference media, or NULL for the default of each
+ *  f         host array [nsolve] of device pointers, force [d][N] in the plan precision
+ *  tol       > 0
+ *  max_iter  >= 0
+ *  eps, sig  host arrays [nsolve] of device pointers [s][N] (plan precision),
+ *            or NULL; an individual entry may be NULL to skip that output
+ *  u         host array [nsolve] of device pointers [d][N], or NULL
+ *  u_init    must be NULL (the free term u^b starts every solve)
+ *  rep       host [nsolve], filled on every return except LSFFT_E_ARG
+ * Returns the worst per-solve status (errors before warnings before OK).
+ */
+lsfft_status lsfft_solve_bfcs(lsfft_plan_t p, int nsolve, const int* grid_idx,
+                              const uint8_t* const* phase, const lsfft_phases* tab,
+                              const lsfft_ref* c0, const void* const* f, double tol, int max_iter,
+                              void* const* eps, void* const* sig, void* const* u,
+                              const void* const* u_init, lsfft_report* rep);
+
+/*
+ * lsfft_translate_average -- translated (ensemble) averages of Sec. 3
+ * (Eqs. 3.3-3.7): the microstructure is rigidly shifted by each chi
+ * (phase_chi(x) = phase(x - chi)), the force stays fixed, every shifted
+ * problem is solved, and
+ *   avg = (1/nshift) sum_chi [u, u V, eps, eps V, sigma, sigma V, V]
+ * with V the indicator of phase incl_phase in the shifted microstructure.
+ *  shifts  host [nshift][dim] in (x, y[, z]) order, 0 <= shift_a < n_a
+ *  avg     device FP64 [2d + 4s + 1][N] (overwritten); component order
+ *          u[d], u1[d], eps[s], eps1[s], sig[s], sig1[s], occupancy[1]
+ *  rep     host [nshift], per shift
+ */
+lsfft_status lsfft_translate_average(lsfft_plan_t p, int grid_idx, const uint8_t* phase,
+                                     const lsfft_phases* tab, const lsfft_ref* c0, const void* f,
+                                     const int32_t* shifts, int nshift, int incl_phase, double tol,
+                                     int max_iter, double* avg, lsfft_report* rep);
+
+/* One averaging group of lsfft_translate_average_batch. */
+typedef struct {
+  int grid_idx;
+  const uint8_t* phase;       /* device */
+  const lsfft_phases* tab;    /* host */
+  const lsfft_ref* c0;        /* host or NULL */
+  const void* f;              /* device force */
+  const int32_t* shifts;      /* host [nshift][dim] */
+  int nshift;
+  int incl_phase;
+  double* avg;                /* device FP64 [2d + 4s + 1][N] */
+} lsfft_avg_group;
+
+/*
+ * lsfft_translate_average_batch -- several averaging groups (different
+ * microstructures, forces and grid sizes) solved together as batches of up
+ * to max_batch solves; rep is host [sum of nshift], groups in order.
+ */
+lsfft_status lsfft_translate_average_batch(lsfft_plan_t p, int ngroup, const lsfft_avg_group* groups,
+                                           double tol, int max_iter, lsfft_report* rep);
+
+/* Release the plan and its workspace.  NULL is accepted. */
+lsfft_status lsfft_plan_destroy(lsfft_plan_t p);
+
+/* Static, human-readable text for a status code. */
+const char* lsfft_status_string(lsfft_status s);
+
+/* Isotropic (E, nu) pairs to Lame pairs (lambda, mu); host [nphase][2] each.
+ * Returns LSFFT_E_ARG for nu outside (-1, 0.5) or E <= 0. */
+lsfft_status lsfft_lame_from_young(int nphase, const double* e_nu, double* lame_out);
+
+/* Kernel classes timed under LSFFT_TIMING. */
+typedef enum {
+  LSFFT_K_XPASS = 0,  /* x sweep: C2R, Hooke's law, R2C */
+  LSFFT_K_YPASS = 1,  /* y sweeps (3D) */
+  LSFFT_K_GREEN = 2,  /* outer-axis sweep fused with the Green/body-force update */
+  LSFFT_K_REDUCE = 3, /* FP64 residual reduction and stopping rule */
+  LSFFT_K_CGUPD = 4,  /* CG vector update */
+  LSFFT_K_OTHER = 5,  /* setup, materialize, averaging */
+  LSFFT_K_COUNT = 6
+} lsfft_kernel_class;
+
+/* Accumulated device time (ms) and launch count of one kernel class, restricted
+ * to the iteration loop, since the last reset.  Requires LSFFT_TIMING. */
+lsfft_status lsfft_kernel_times(lsfft_plan_t p, int kernel_class, double* total_ms, int64_t* launches);
+lsfft_status lsfft_kernel_times_reset(lsfft_plan_t p);
+
+/* Algorithmic HBM bytes that one iteration of one solve on grid grid_idx
+ * moves in each kernel class (complex half-spectrum streams and phase map). */
+lsfft_status lsfft_iteration_bytes(lsfft_plan_t p, int grid_idx, int kernel_class, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSFFT_H */

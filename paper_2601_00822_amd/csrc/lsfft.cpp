@@ -1,0 +1,907 @@
+// Host side of liblsfft: plans, argument validation, workspace, batch
+// scheduling of the pass kernels, convergence polling and reports.
+#include "../../include/lsfft.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "launch.hpp"
+#include "lsfft_internal.hpp"
+
+using namespace lsfft;
+
+namespace {
+
+constexpr int kMaxGrid = 4096;  // blocks of a persistent launch
+
+bool supported_len(int64_t n) {
+  for (int i = 0; i < kNumLens; ++i)
+    if (len_at(i) == n) return true;
+  return false;
+}
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  bool ensure(size_t bytes) {
+    if (bytes <= cap) return true;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    cap = bytes;
+    return true;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+// One solve of a batch, as resolved on the host.
+struct Spec {
+  int grid = 0;
+  const uint8_t* phase = nullptr;
+  const lsfft_phases* tab = nullptr;
+  double lam0 = 0, mu0 = 0;
+  const void* f = nullptr;
+  void* eps = nullptr;
+  void* sig = nullptr;
+  void* u = nullptr;
+  int shift[3] = {0, 0, 0};
+  int group = -1;     // index into the batch's groups
+  int leader = -1;    // solve that owns the force spectrum (itself if own)
+  int out_index = 0;  // report slot
+};
+
+struct BatchGroup {
+  double* avg = nullptr;
+  int incl_phase = 1;
+  int first = 0, count = 0;
+};
+
+enum ListId { L_XLEAD, L_YLEAD, L_GLEAD, L_X, L_Y, L_G, L_CG, L_XALL, L_YALL, L_GALL, L_NUM };
+
+}  // namespace
+
+struct lsfft_plan_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool f64 = false;
+  lsfft_scheme scheme = LSFFT_BASIC;
+  unsigned flags = 0;
+  std::vector<lsfft_grid> grids;
+  int max_batch = 1;
+  int poll = 8;
+  DevBuf tw, arena, meta, lists;
+  // timing
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_pending;  // (class, index of start event)
+  size_t ev_next = 0;
+  double kt_ms[LSFFT_K_COUNT] = {0};
+  int64_t kt_n[LSFFT_K_COUNT] = {0};
+  bool timing_active = false;
+};
+
+namespace {
+
+lsfft_status dev_err(hipError_t e) { return e == hipSuccess ? LSFFT_OK : LSFFT_E_DEVICE; }
+
+#define LSFFT_TRY(expr)                          \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) return LSFFT_E_DEVICE; \
+  } while (0)
+
+int grid_dim(const lsfft_grid& g) { return g.dim; }
+int64_t gnx(const lsfft_grid& g) { return g.n[0]; }
+int64_t gny(const lsfft_grid& g) { return g.n[1]; }
+int64_t gnz(const lsfft_grid& g) { return g.dim == 3 ? g.n[2] : 1; }
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+lsfft_status check_table(const lsfft_phases* t, int dim) {
+  if (!t || !t->lame || t->nphase < 1 || t->nphase > kMaxPhases) return LSFFT_E_ARG;
+  for (int p = 0; p < t->nphase; ++p) {
+    const double lam = t->lame[2 * p], mu = t->lame[2 * p + 1];
+    if (!is_fin(lam) || !is_fin(mu) || mu <= 0.0 || lam + 2.0 * mu / dim <= 0.0) return LSFFT_E_ARG;
+  }
+  return LSFFT_OK;
+}
+
+// default reference medium: mean of the extreme Lame constants (Algorithm 1 datum)
+lsfft_status resolve_ref(const lsfft_phases* t, const lsfft_ref* c0, double* lam0, double* mu0) {
+  double lmin = t->lame[0], lmax = t->lame[0], mmin = t->lame[1], mmax = t->lame[1];
+  for (int p = 1; p < t->nphase; ++p) {
+    lmin = std::min(lmin, t->lame[2 * p]);
+    lmax = std::max(lmax, t->lame[2 * p]);
+    mmin = std::min(mmin, t->lame[2 * p + 1]);
+    mmax = std::max(mmax, t->lame[2 * p + 1]);
+  }
+  if (c0 && !(std::isnan(c0->lambda0) && std::isnan(c0->mu0))) {
+    if (!is_fin(c0->lambda0) || !is_fin(c0->mu0) || c0->mu0 <= 0.0 || c0->lambda0 + 2.0 * c0->mu0 <= 0.0)
+      return LSFFT_E_ARG;
+    *lam0 = c0->lambda0;
+    *mu0 = c0->mu0;
+  } else {
+    *lam0 = 0.5 * (lmin + lmax);
+    *mu0 = 0.5 * (mmin + mmax);
+  }
+  return LSFFT_OK;
+}
+
+struct Geometry {
+  int nx, ny, nz, nxh, dim, s;
+  long long P, nvox;
+  int items_x, items_y, items_g, items_cg, ntile_y, ntile_g;
+  size_t lds_x, lds_y, lds_g;
+};
+
+bool geometry(bool f64, const lsfft_grid& g, Geometry* o) {
+  o->dim = g.dim;
+  o->nx = (int)gnx(g);
+  o->ny = (int)gny(g);
+  o->nz = (int)gnz(g);
+  o->nxh = o->nx / 2 + 1;
+  o->s = g.dim == 3 ? 6 : 3;
+  o->P = (long long)o->nz * o->ny * o->nxh;
+  o->nvox = (long long)o->nz * o->ny * o->nx;
+  int mr = 0, mpy = 0, mpg = 0;
+  o->lds_x = query_geometry(f64, 0, o->nx, &mr);
+  o->lds_y = (g.dim == 3) ? query_geometry(f64, 1, o->ny, &mpy) : 0;
+  const int outer = (g.dim == 3) ? o->nz : o->ny;
+  o->lds_g = query_geometry(f64, 1, outer, &mpg);
+  if (!o->lds_x || !o->lds_g || (g.dim == 3 && !o->lds_y)) return false;
+  const int rows = o->ny * o->nz;
+  o->items_x = (rows + mr - 1) / mr;
+  o->ntile_y = (g.dim == 3) ? (o->nxh + mpy - 1) / mpy : 0;
+  o->items_y = (g.dim == 3) ? o->nz * o->ntile_y : 0;
+  o->ntile_g = (o->nxh + mpg - 1) / mpg;
+  o->items_g = ((g.dim == 3) ? o->ny : 1) * o->ntile_g;
+  o->items_cg = (int)((o->P + kThreads * 4 - 1) / (kThreads * 4));
+  return true;
+}
+
+// -------------------------------------------------------------------------
+// timing helpers
+// -------------------------------------------------------------------------
+int timed_begin(lsfft_plan_s* p, int cls) {
+  if (!p->timing_active) return -1;
+  if (p->ev_next + 2 > p->ev_pool.size()) {
+    for (int k = 0; k < 256; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      p->ev_pool.push_back(e);
+    }
+  }
+  const int idx = (int)p->ev_next;
+  p->ev_next += 2;
+  (void)hipEventRecord(p->ev_pool[idx], p->stream);
+  p->ev_pending.push_back({cls, idx});
+  return idx;
+}
+void timed_end(lsfft_plan_s* p, int idx) {
+  if (idx < 0) return;
+  (void)hipEventRecord(p->ev_pool[idx + 1], p->stream);
+}
+void timed_collect(lsfft_plan_s* p) {
+  for (auto& pr : p->ev_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev_pool[pr.second], p->ev_pool[pr.second + 1]) == hipSuccess) {
+      p->kt_ms[pr.first] += ms;
+      p->kt_n[pr.first] += 1;
+    }
+  }
+  p->ev_pending.clear();
+  p->ev_next = 0;
+}
+
+// -------------------------------------------------------------------------
+// the batch engine
+// -------------------------------------------------------------------------
+struct Batch {
+  lsfft_plan_s* p;
+  std::vector<Spec> specs;
+  std::vector<BatchGroup> groups;
+  std::vector<Geometry> geo;
+  std::vector<InstDesc> desc;
+  std::vector<InstState> state;
+  std::vector<double> lame;
+  // device views into plan buffers
+  InstDesc* d_desc = nullptr;
+  InstState* d_state = nullptr;
+  double* d_lame = nullptr;
+  GroupDesc* d_groups = nullptr;
+  int* d_counts = nullptr;
+  int* d_inst = nullptr;
+  int* d_phasemax = nullptr;
+  WorkItem* d_lists[L_NUM] = {nullptr};
+  int list_cap[L_NUM] = {0};
+  int list_len[L_NUM] = {0};
+  size_t list_lds[L_NUM] = {0};
+  int n_running = 0;
+  double tol = 1e-8;
+  int max_iter = 0;
+  bool averaging = false;
+};
+
+LaunchArgs largs(Batch& b, int list) {
+  LaunchArgs a;
+  const int n = std::max(1, b.list_len[list]);
+  a.grid = dim3((unsigned)std::min(n, kMaxGrid));
+  a.lds = b.list_lds[list];
+  a.stream = b.p->stream;
+  a.desc = b.d_desc;
+  a.state = b.d_state;
+  a.items = b.d_lists[list];
+  a.count = b.d_counts + list;
+  a.lame = b.d_lame;
+  a.tw = b.p->tw.p;
+  return a;
+}
+
+// Build work lists for the given instance subset; host copies into device.
+lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_too) {
+  std::vector<WorkItem> lists[L_NUM];
+  std::vector<size_t> lds(L_NUM, 0);
+  auto add = [&](int id, int inst, int n, size_t l) {
+    for (int k = 0; k < n; ++k) lists[id].push_back({inst, k});
+    if (n > 0) lds[id] = std::max(lds[id], l);
+  };
+  for (int i : running) {
+    const Geometry& g = b.geo[i];
+    add(L_X, i, g.items_x, g.lds_x);
+    add(L_Y, i, g.items_y, g.lds_y);
+    add(L_G, i, g.items_g, g.lds_g);
+    add(L_CG, i, g.items_cg, 0);
+  }
+  if (all_too) {
+    for (int i = 0; i < (int)b.specs.size(); ++i) {
+      const Geometry& g = b.geo[i];
+      add(L_XALL, i, g.items_x, g.lds_x);
+      add(L_YALL, i, g.items_y, g.lds_y);
+      add(L_GALL, i, g.items_g, g.lds_g);
+      if (b.specs[i].leader == i) {
+        add(L_XLEAD, i, g.items_x, g.lds_x);
+        add(L_YLEAD, i, g.items_y, g.lds_y);
+        add(L_GLEAD, i, g.items_g, g.lds_g);
+      }
+    }
+  }
+  std::vector<int> counts(L_NUM);
+  for (int l = 0; l < L_NUM; ++l) {
+    const bool dynamic = (l == L_X || l == L_Y || l == L_G || l == L_CG);
+    if (!dynamic && !all_too) {
+      counts[l] = b.list_len[l];
+      continue;
+    }
+    if ((int)lists[l].size() > b.list_cap[l]) return LSFFT_E_ALLOC;  // capacities sized up front
+    b.list_len[l] = (int)lists[l].size();
+    if (dynamic && !all_too) {
+      // keep the LDS size of the full list: launches need the max anyway
+    } else {
+      b.list_lds[l] = lds[l];
+    }
+    counts[l] = b.list_len[l];
+    if (!lists[l].empty())
+      LSFFT_TRY(hipMemcpyAsync(b.d_lists[l], lists[l].data(), lists[l].size() * sizeof(WorkItem),
+                               hipMemcpyHostToDevice, b.p->stream));
+  }
+  LSFFT_TRY(hipMemcpyAsync(b.d_counts, counts.data(), sizeof(int) * L_NUM, hipMemcpyHostToDevice, b.p->stream));
+  std::vector<int> inst(running.begin(), running.end());
+  if (!inst.empty())
+    LSFFT_TRY(hipMemcpyAsync(b.d_inst, inst.data(), sizeof(int) * inst.size(), hipMemcpyHostToDevice, b.p->stream));
+  b.n_running = (int)inst.size();
+  // the host vectors above die at return: wait for the copies
+  LSFFT_TRY(hipStreamSynchronize(b.p->stream));
+  return LSFFT_OK;
+}
+
+lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
+  lsfft_plan_s* p = b.p;
+  const bool f64 = p->f64;
+  const size_t rs = f64 ? 8 : 4;   // real scalar
+  const size_t cs = 2 * rs;        // complex scalar
+  const int n = (int)b.specs.size();
+  const bool cg = p->scheme == LSFFT_CG;
+
+  // geometry, Lame tables
+  b.geo.resize(n);
+  b.desc.assign(n, InstDesc{});
+  b.state.assign(n, InstState{});
+  b.lame.clear();
+  for (int i = 0; i < n; ++i) {
+    if (!geometry(f64, p->grids[b.specs[i].grid], &b.geo[i])) return LSFFT_E_ARG;
+  }
+
+  // workspace layout
+  size_t off = 0;
+  std::vector<size_t> o_S(n), o_U0(n), o_U1(n), o_F(n), o_R(n), o_P(n), o_Q(n), o_oe(n), o_ou(n), o_part(n), o_hist(n);
+  for (int i = 0; i < n; ++i) {
+    const Geometry& g = b.geo[i];
+    const size_t comp = (size_t)g.P * cs;
+    o_S[i] = off; off = align_up(off + comp * (g.s + g.dim));
+    o_U0[i] = off; off = align_up(off + comp * g.dim);
+    if (!cg) { o_U1[i] = off; off = align_up(off + comp * g.dim); }
+    if (b.specs[i].leader == i) { o_F[i] = off; off = align_up(off + comp * g.dim); }
+    if (cg) {
+      o_R[i] = off; off = align_up(off + comp * g.dim);
+      o_P[i] = off; off = align_up(off + comp * g.dim);
+      o_Q[i] = off; off = align_up(off + comp * g.dim);
+    }
+    if (b.averaging) {
+      o_oe[i] = off; off = align_up(off + (size_t)g.nvox * rs * g.s);
+      o_ou[i] = off; off = align_up(off + (size_t)g.nvox * rs * g.dim);
+    }
+    o_part[i] = off; off = align_up(off + sizeof(double) * 2 * (size_t)std::max(g.items_g, g.items_cg));
+    o_hist[i] = off; off = align_up(off + sizeof(double) * ((size_t)b.max_iter + 2));
+  }
+  if (!p->arena.ensure(off)) return LSFFT_E_ALLOC;
+  char* A = static_cast<char*>(p->arena.p);
+
+  // metadata buffer: desc, state, lame, groups, counts, inst list, phase max, lists
+  int list_need[L_NUM] = {0};
+  for (int i = 0; i < n; ++i) {
+    const Geometry& g = b.geo[i];
+    list_need[L_X] += g.items_x; list_need[L_Y] += g.items_y; list_need[L_G] += g.items_g;
+    list_need[L_CG] += g.items_cg;
+  }
+  list_need[L_XALL] = list_need[L_XLEAD] = list_need[L_X];
+  list_need[L_YALL] = list_need[L_YLEAD] = list_need[L_Y];
+  list_need[L_GALL] = list_need[L_GLEAD] = list_need[L_G];
+  size_t total_lame = 0;
+  for (int i = 0; i < n; ++i) total_lame += 2 * (size_t)b.specs[i].tab->nphase;
+  size_t moff = 0;
+  const size_t m_desc = moff; moff = align_up(moff + sizeof(InstDesc) * n);
+  const size_t m_state = moff; moff = align_up(moff + sizeof(InstState) * n);
+  const size_t m_lame = moff; moff = align_up(moff + sizeof(double) * total_lame);
+  const size_t m_groups = moff; moff = align_up(moff + sizeof(GroupDesc) * std::max<size_t>(1, b.groups.size()));
+  const size_t m_counts = moff; moff = align_up(moff + sizeof(int) * L_NUM);
+  const size_t m_inst = moff; moff = align_up(moff + sizeof(int) * n);
+  const size_t m_pmax = moff; moff = align_up(moff + sizeof(int) * n);
+  size_t m_list[L_NUM];
+  for (int l = 0; l < L_NUM; ++l) {
+    m_list[l] = moff;
+    moff = align_up(moff + sizeof(WorkItem) * std::max(1, list_need[l]));
+  }
+  if (!p->meta.ensure(moff)) return LSFFT_E_ALLOC;
+  char* M = static_cast<char*>(p->meta.p);
+  b.d_desc = reinterpret_cast<InstDesc*>(M + m_desc);
+  b.d_state = reinterpret_cast<InstState*>(M + m_state);
+  b.d_lame = reinterpret_cast<double*>(M + m_lame);
+  b.d_groups = reinterpret_cast<GroupDesc*>(M + m_groups);
+  b.d_counts = reinterpret_cast<int*>(M + m_counts);
+  b.d_inst = reinterpret_cast<int*>(M + m_inst);
+  b.d_phasemax = reinterpret_cast<int*>(M + m_pmax);
+  for (int l = 0; l < L_NUM; ++l) {
+    b.d_lists[l] = reinterpret_cast<WorkItem*>(M + m_list[l]);
+    b.list_cap[l] = std::max(1, list_need[l]);
+  }
+
+  // descriptors
+  for (int i = 0; i < n; ++i) {
+    const Spec& sp = b.specs[i];
+    const Geometry& g = b.geo[i];
+    const lsfft_grid& gr = p->grids[sp.grid];
+    InstDesc& D = b.desc[i];
+    D.dim = g.dim; D.nx = g.nx; D.ny = g.ny; D.nz = g.nz; D.nxh = g.nxh; D.ncomp_s = g.s;
+    D.items_x = g.items_x; D.items_y = g.items_y; D.items_g = g.items_g;
+    D.ntile_y = g.ntile_y; D.ntile_g = g.ntile_g;
+    D.nphase = sp.tab->nphase;
+    D.lame_off = (int)(b.lame.size() / 2);
+    for (int q = 0; q < 2 * sp.tab->nphase; ++q) b.lame.push_back(sp.tab->lame[q]);
+    D.sx = sp.shift[0]; D.sy = sp.shift[1]; D.sz = sp.shift[2];
+    D.max_iter = b.max_iter;
+    D.group = sp.group;
+    D.P = g.P; D.nvox = g.nvox;
+    const double two_pi = 6.283185307179586476925286766559;
+    D.kx = two_pi / (g.nx * gr.h[0]);
+    D.ky = two_pi / (g.ny * gr.h[1]);
+    D.kz = (g.dim == 3) ? two_pi / (g.nz * gr.h[2]) : 0.0;
+    D.inv_nvox = 1.0 / (double)g.nvox;
+    D.lam0 = sp.lam0; D.mu0 = sp.mu0;
+    D.tol = b.tol;
+    D.phase = sp.phase;
+    D.f_in = sp.f;
+    D.S = A + o_S[i];
+    D.U[0] = A + o_U0[i];
+    D.U[1] = cg ? D.U[0] : (void*)(A + o_U1[i]);
+    D.F = A + o_F[sp.leader];
+    D.R = cg ? (void*)(A + o_R[i]) : nullptr;
+    D.Pd = cg ? (void*)(A + o_P[i]) : nullptr;
+    D.Q = cg ? (void*)(A + o_Q[i]) : nullptr;
+    if (b.averaging) {
+      D.out_eps = A + o_oe[i];
+      D.out_sig = nullptr;
+      D.out_u = A + o_ou[i];
+    } else {
+      D.out_eps = sp.eps; D.out_sig = sp.sig; D.out_u = sp.u;
+    }
+    D.partial = reinterpret_cast<double*>(A + o_part[i]);
+    D.history = reinterpret_cast<double*>(A + o_hist[i]);
+    InstState& S = b.state[i];
+    S.status = ST_RUNNING;
+    S.iter = 0;
+  }
+  hipStream_t st = p->stream;
+  LSFFT_TRY(hipMemcpyAsync(b.d_desc, b.desc.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice, st));
+  LSFFT_TRY(hipMemcpyAsync(b.d_state, b.state.data(), sizeof(InstState) * n, hipMemcpyHostToDevice, st));
+  LSFFT_TRY(hipMemcpyAsync(b.d_lame, b.lame.data(), sizeof(double) * b.lame.size(), hipMemcpyHostToDevice, st));
+  std::vector<GroupDesc> gd;
+  for (auto& g : b.groups) gd.push_back(GroupDesc{g.first, g.count, g.incl_phase, 0, g.avg});
+  if (!gd.empty())
+    LSFFT_TRY(hipMemcpyAsync(b.d_groups, gd.data(), sizeof(GroupDesc) * gd.size(), hipMemcpyHostToDevice, st));
+
+  // phase ids must index the tables: one device max per distinct map
+  LSFFT_TRY(hipMemsetAsync(b.d_phasemax, 0, sizeof(int) * n, st));
+  for (int i = 0; i < n; ++i) {
+    bool seen = false;
+    for (int j = 0; j < i && !seen; ++j) seen = (b.specs[j].phase == b.specs[i].phase && b.geo[j].nvox == b.geo[i].nvox);
+    if (!seen) LSFFT_TRY(launch_phase_max(b.specs[i].phase, b.geo[i].nvox, b.d_phasemax + i, st));
+  }
+  std::vector<int> pmax(n, 0);
+  LSFFT_TRY(hipMemcpyAsync(pmax.data(), b.d_phasemax, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  LSFFT_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i) {
+    int m = pmax[i];
+    for (int j = 0; j < i; ++j)
+      if (b.specs[j].phase == b.specs[i].phase && b.geo[j].nvox == b.geo[i].nvox) m = std::max(m, pmax[j]);
+    if (m >= b.specs[i].tab->nphase) return LSFFT_E_ARG;
+  }
+
+  std::vector<int> all(n);
+  for (int i = 0; i < n; ++i) all[i] = i;
+  lsfft_status ls = upload_lists(b, all, true);
+  if (ls != LSFFT_OK) return ls;
+  const bool has3d = std::any_of(b.geo.begin(), b.geo.end(), [](const Geometry& g) { return g.dim == 3; });
+
+  auto X = [&](int list, int mode, int cls) -> hipError_t {
+    if (b.list_len[list] == 0) return hipSuccess;
+    const int t = timed_begin(p, cls);
+    hipError_t e = launch_xpass(f64, largs(b, list), mode);
+    timed_end(p, t);
+    return e;
+  };
+  auto Y = [&](int list, int dir, int which, int extra, int gate, int cls) -> hipError_t {
+    if (!has3d || b.list_len[list] == 0) return hipSuccess;
+    const int t = timed_begin(p, cls);
+    hipError_t e = launch_ypass(f64, largs(b, list), dir, which, extra, gate);
+    timed_end(p, t);
+    return e;
+  };
+  auto Gp = [&](int list, int mode, int cls) -> hipError_t {
+    if (b.list_len[list] == 0) return hipSuccess;
+    const int t = timed_begin(p, cls);
+    hipError_t e = launch_green(f64, largs(b, list), mode);
+    timed_end(p, t);
+    return e;
+  };
+  auto Rd = [&](int mode) -> hipError_t {
+    const int t = timed_begin(p, LSFFT_K_REDUCE);
+    hipError_t e = launch_reduce(largs(b, L_G), b.d_inst, b.n_running, mode);
+    timed_end(p, t);
+    return e;
+  };
+
+  const bool timing = (p->flags & LSFFT_TIMING) != 0;
+  // setup: force transform (once per distinct force), free term, ||P f||
+  p->timing_active = false;
+  LSFFT_TRY(X(L_XLEAD, M_FT, LSFFT_K_OTHER));
+  LSFFT_TRY(Y(L_YLEAD, -1, 1, 0, 0, LSFFT_K_OTHER));
+  LSFFT_TRY(Gp(L_GLEAD, M_FT, LSFFT_K_OTHER));
+  LSFFT_TRY(Gp(L_GALL, M_INIT, LSFFT_K_OTHER));
+  LSFFT_TRY(Rd(M_INIT));
+
+  if (p->flags & LSFFT_STRICT_EQUIL) {
+    LSFFT_TRY(hipMemcpyAsync(b.state.data(), b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost, st));
+    LSFFT_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+      const InstState& L = b.state[b.specs[i].leader];
+      const double fn = std::sqrt(b.state[i].fnorm2 / (double)b.geo[i].nvox);
+      for (int c = 0; c < b.geo[i].dim; ++c) {
+        const double sum = std::fabs(L.removed_mean[c]) * (double)b.geo[i].nvox;
+        if (sum > 1e-12 * std::sqrt((double)b.geo[i].nvox) * std::max(fn, 1e-300)) return LSFFT_E_NONEQUIL;
+      }
+    }
+  }
+
+  p->timing_active = timing;
+  if (cg) {
+    // r0 = P f - A u^b from one operator application on u^b
+    LSFFT_TRY(Y(L_Y, +1, 0, 0, 1, LSFFT_K_YPASS));
+    LSFFT_TRY(X(L_X, M_ITER, LSFFT_K_XPASS));
+    LSFFT_TRY(Y(L_Y, -1, 0, 0, 1, LSFFT_K_YPASS));
+    LSFFT_TRY(Gp(L_G, M_CG_INIT, LSFFT_K_GREEN));
+    LSFFT_TRY(Rd(M_CG_INIT));
+  }
+  std::vector<int> running;
+  for (;;) {
+    for (int k = 0; k < p->poll; ++k) {
+      LSFFT_TRY(Y(L_Y, +1, 0, 0, 1, LSFFT_K_YPASS));
+      LSFFT_TRY(X(L_X, M_ITER, LSFFT_K_XPASS));
+      LSFFT_TRY(Y(L_Y, -1, 0, 0, 1, LSFFT_K_YPASS));
+      if (!cg) {
+        LSFFT_TRY(Gp(L_G, M_ITER, LSFFT_K_GREEN));
+        LSFFT_TRY(Rd(M_ITER));
+      } else {
+        LSFFT_TRY(Gp(L_G, M_CG_AP, LSFFT_K_GREEN));
+        LSFFT_TRY(Rd(M_CG_AP));
+        if (b.list_len[L_CG] > 0) {
+          const int t = timed_begin(p, LSFFT_K_CGUPD);
+          LSFFT_TRY(launch_cg_update(f64, largs(b, L_CG)));
+          timed_end(p, t);
+        }
+        LSFFT_TRY(Rd(M_CG_UPD));
+        LSFFT_TRY(Gp(L_G, M_CG_DIR, LSFFT_K_GREEN));
+      }
+    }
+    LSFFT_TRY(hipMemcpyAsync(b.state.data(), b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost, st));
+    LSFFT_TRY(hipStreamSynchronize(st));
+    running.clear();
+    for (int i = 0; i < n; ++i)
+      if (b.state[i].status == ST_RUNNING) running.push_back(i);
+    if (running.empty()) break;
+    if ((int)running.size() < b.n_running) {
+      ls = upload_lists(b, running, false);
+      if (ls != LSFFT_OK) return ls;
+    }
+  }
+  if (timing) timed_collect(p);
+  p->timing_active = false;
+
+  // materialize u, eps, sigma of the returned iterates
+  LSFFT_TRY(Gp(L_GALL, M_MAT, LSFFT_K_OTHER));
+  LSFFT_TRY(Y(L_YALL, +1, 0, /*extra*/ 3, 0, LSFFT_K_OTHER));
+  LSFFT_TRY(X(L_XALL, M_MAT, LSFFT_K_OTHER));
+  if (b.averaging) {
+    for (int g = 0; g < (int)b.groups.size(); ++g) {
+      const Geometry& G = b.geo[b.groups[g].first];
+      LSFFT_TRY(launch_accumulate(f64, G.dim, largs(b, L_GALL), b.d_groups, g, G.nvox));
+    }
+  }
+  LSFFT_TRY(hipStreamSynchronize(st));
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() - t0_wall;
+
+  lsfft_status worst = LSFFT_OK;
+  auto rank = [](int s) { return s == LSFFT_E_DIVERGED ? 4 : s == LSFFT_E_NOCONV ? 3 : s == LSFFT_W_STAGNATED ? 1 : 0; };
+  for (int i = 0; i < n; ++i) {
+    const InstState& S = b.state[i];
+    lsfft_report& r = rep[b.specs[i].out_index];
+    r.iters = S.iter;
+    r.residual = S.residual;
+    const InstState& L = b.state[b.specs[i].leader];
+    for (int c = 0; c < 3; ++c) r.removed_mean[c] = (c < b.geo[i].dim) ? L.removed_mean[c] : 0.0;
+    r.status = S.status;
+    r.seconds = secs;
+    if (rank(S.status) > rank(worst)) worst = (lsfft_status)S.status;
+  }
+  return worst;
+}
+
+lsfft_status check_plan(lsfft_plan_s* p) { return p ? LSFFT_OK : LSFFT_E_ARG; }
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+lsfft_status worse(lsfft_status a, lsfft_status b) {
+  auto rank = [](int s) {
+    return s < 0 && s != LSFFT_E_NOCONV && s != LSFFT_E_DIVERGED ? 9
+         : s == LSFFT_E_DIVERGED ? 4 : s == LSFFT_E_NOCONV ? 3 : s == LSFFT_W_STAGNATED ? 1 : 0;
+  };
+  return rank(a) >= rank(b) ? a : b;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* lsfft_status_string(lsfft_status s) {
+  switch (s) {
+    case LSFFT_OK: return "ok";
+    case LSFFT_W_STAGNATED: return "stagnated: residual stopped improving above tol";
+    case LSFFT_E_ARG: return "invalid argument";
+    case LSFFT_E_ALLOC: return "device allocation failed";
+    case LSFFT_E_DEVICE: return "HIP runtime error";
+    case LSFFT_E_NOCONV: return "not converged within max_iter";
+    case LSFFT_E_NONEQUIL: return "force is not self-equilibrated";
+    case LSFFT_E_DIVERGED: return "diverged";
+  }
+  return "unknown status";
+}
+
+lsfft_status lsfft_lame_from_young(int nphase, const double* e_nu, double* lame_out) {
+  if (nphase < 1 || !e_nu || !lame_out) return LSFFT_E_ARG;
+  for (int p = 0; p < nphase; ++p) {
+    const double e = e_nu[2 * p], nu = e_nu[2 * p + 1];
+    if (!is_fin(e) || !is_fin(nu) || e <= 0.0 || nu <= -1.0 || nu >= 0.5) return LSFFT_E_ARG;
+  }
+  for (int p = 0; p < nphase; ++p) {
+    const double e = e_nu[2 * p], nu = e_nu[2 * p + 1];
+    lame_out[2 * p] = e * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    lame_out[2 * p + 1] = e / (2.0 * (1.0 + nu));
+  }
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, int max_batch,
+                        lsfft_prec prec, lsfft_scheme scheme, unsigned flags, void* hip_stream) {
+  if (!out) return LSFFT_E_ARG;
+  *out = nullptr;
+  if (!grids || ngrid < 1 || max_batch < 1) return LSFFT_E_ARG;
+  if (prec != LSFFT_F32 && prec != LSFFT_F64) return LSFFT_E_ARG;
+  if (scheme != LSFFT_BASIC && scheme != LSFFT_CG) return LSFFT_E_ARG;
+  if (flags & ~(LSFFT_STRICT_EQUIL | LSFFT_TIMING)) return LSFFT_E_ARG;
+  for (int g = 0; g < ngrid; ++g) {
+    const lsfft_grid& G = grids[g];
+    if (G.dim != 2 && G.dim != 3) return LSFFT_E_ARG;
+    for (int a = 0; a < G.dim; ++a) {
+      if (!supported_len(G.n[a])) return LSFFT_E_ARG;
+      if (!is_fin(G.h[a]) || G.h[a] <= 0.0) return LSFFT_E_ARG;
+    }
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LSFFT_E_DEVICE;
+  lsfft_plan_s* p = new (std::nothrow) lsfft_plan_s();
+  if (!p) return LSFFT_E_ALLOC;
+  p->device = dev;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->f64 = (prec == LSFFT_F64);
+  p->scheme = scheme;
+  p->flags = flags;
+  p->grids.assign(grids, grids + ngrid);
+  for (auto& G : p->grids)
+    if (G.dim == 2) { G.n[2] = 1; G.h[2] = 1.0; }
+  p->max_batch = max_batch;
+  if (const char* e = std::getenv("LSFFT_POLL")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 1024) p->poll = v;
+  }
+  // twiddle table exp(-2 pi i k / L) for every supported length, long double
+  // arithmetic rounded once to the plan precision
+  const int total = tw_total();
+  std::vector<double> twd(2 * (size_t)total);
+  for (int i = 0; i < kNumLens; ++i) {
+    const int L = len_at(i), o = tw_offset(L);
+    for (int k = 0; k < L; ++k) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)L;
+      twd[2 * (o + k)] = (double)cosl(ang);
+      twd[2 * (o + k) + 1] = (double)sinl(ang);
+    }
+  }
+  const size_t bytes = (p->f64 ? sizeof(double) : sizeof(float)) * twd.size();
+  if (!p->tw.ensure(bytes)) {
+    delete p;
+    return LSFFT_E_ALLOC;
+  }
+  hipError_t e;
+  if (p->f64) {
+    e = hipMemcpy(p->tw.p, twd.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> twf(twd.begin(), twd.end());
+    e = hipMemcpy(p->tw.p, twf.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    p->tw.release();
+    delete p;
+    return LSFFT_E_DEVICE;
+  }
+  *out = p;
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_plan_destroy(lsfft_plan_t p) {
+  if (!p) return LSFFT_OK;
+  (void)hipStreamSynchronize(p->stream);
+  p->tw.release();
+  p->arena.release();
+  p->meta.release();
+  p->lists.release();
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  delete p;
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_solve_bfcs(lsfft_plan_t p, int nsolve, const int* grid_idx, const uint8_t* const* phase,
+                              const lsfft_phases* tab, const lsfft_ref* c0, const void* const* f, double tol,
+                              int max_iter, void* const* eps, void* const* sig, void* const* u,
+                              const void* const* u_init, lsfft_report* rep) {
+  if (check_plan(p) != LSFFT_OK) return LSFFT_E_ARG;
+  if (nsolve < 1 || !grid_idx || !phase || !tab || !f || !rep) return LSFFT_E_ARG;
+  if (!is_fin(tol) || tol <= 0.0 || max_iter < 0) return LSFFT_E_ARG;
+  if (u_init) return LSFFT_E_ARG;
+  std::vector<Spec> specs(nsolve);
+  for (int i = 0; i < nsolve; ++i) {
+    const int g = grid_idx[i];
+    if (g < 0 || g >= (int)p->grids.size()) return LSFFT_E_ARG;
+    if (!phase[i] || !f[i]) return LSFFT_E_ARG;
+    if (check_table(&tab[i], p->grids[g].dim) != LSFFT_OK) return LSFFT_E_ARG;
+    Spec& s = specs[i];
+    s.grid = g;
+    s.phase = phase[i];
+    s.tab = &tab[i];
+    if (resolve_ref(&tab[i], c0 ? &c0[i] : nullptr, &s.lam0, &s.mu0) != LSFFT_OK) return LSFFT_E_ARG;
+    s.f = f[i];
+    s.eps = eps ? eps[i] : nullptr;
+    s.sig = sig ? sig[i] : nullptr;
+    s.u = u ? u[i] : nullptr;
+    s.out_index = i;
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return LSFFT_E_DEVICE;
+  lsfft_status worst = LSFFT_OK;
+  for (int start = 0; start < nsolve; start += p->max_batch) {
+    const int cnt = std::min(p->max_batch, nsolve - start);
+    Batch b;
+    b.p = p;
+    b.tol = tol;
+    b.max_iter = max_iter;
+    b.specs.assign(specs.begin() + start, specs.begin() + start + cnt);
+    for (int i = 0; i < cnt; ++i) b.specs[i].leader = i;
+    const double t0 = now_s();
+    lsfft_status s = run_batch(b, rep, t0);
+    if (s == LSFFT_E_ARG || s == LSFFT_E_ALLOC || s == LSFFT_E_DEVICE || s == LSFFT_E_NONEQUIL) return s;
+    worst = worse(worst, s);
+  }
+  return worst;
+}
+
+lsfft_status lsfft_translate_average_batch(lsfft_plan_t p, int ngroup, const lsfft_avg_group* groups,
+                                           double tol, int max_iter, lsfft_report* rep) {
+  if (check_plan(p) != LSFFT_OK) return LSFFT_E_ARG;
+  if (ngroup < 1 || !groups || !rep) return LSFFT_E_ARG;
+  if (!is_fin(tol) || tol <= 0.0 || max_iter < 0) return LSFFT_E_ARG;
+  // expand groups into solves, validating every shift
+  std::vector<Spec> specs;
+  std::vector<int> spec_group;
+  int slot = 0;
+  for (int g = 0; g < ngroup; ++g) {
+    const lsfft_avg_group& G = groups[g];
+    if (G.grid_idx < 0 || G.grid_idx >= (int)p->grids.size()) return LSFFT_E_ARG;
+    const lsfft_grid& gr = p->grids[G.grid_idx];
+    if (!G.phase || !G.f || !G.avg || !G.shifts || G.nshift < 1) return LSFFT_E_ARG;
+    if (check_table(G.tab, gr.dim) != LSFFT_OK) return LSFFT_E_ARG;
+    if (G.incl_phase < 0 || G.incl_phase >= G.tab->nphase) return LSFFT_E_ARG;
+    double lam0, mu0;
+    if (resolve_ref(G.tab, G.c0, &lam0, &mu0) != LSFFT_OK) return LSFFT_E_ARG;
+    for (int k = 0; k < G.nshift; ++k) {
+      Spec s;
+      s.grid = G.grid_idx;
+      s.phase = G.phase;
+      s.tab = G.tab;
+      s.lam0 = lam0;
+      s.mu0 = mu0;
+      s.f = G.f;
+      for (int a = 0; a < gr.dim; ++a) {
+        const int v = G.shifts[(size_t)k * gr.dim + a];
+        if (v < 0 || v >= gr.n[a]) return LSFFT_E_ARG;
+        s.shift[a] = v;
+      }
+      s.out_index = slot++;
+      specs.push_back(s);
+      spec_group.push_back(g);
+    }
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return LSFFT_E_DEVICE;
+  for (int g = 0; g < ngroup; ++g) {
+    const lsfft_grid& gr = p->grids[groups[g].grid_idx];
+    const int d = gr.dim, s = d == 3 ? 6 : 3;
+    const long long nvox = gr.n[0] * gr.n[1] * (d == 3 ? gr.n[2] : 1);
+    if (hipMemsetAsync(groups[g].avg, 0, sizeof(double) * (size_t)(2 * d + 4 * s + 1) * nvox, p->stream) != hipSuccess)
+      return LSFFT_E_DEVICE;
+  }
+  lsfft_status worst = LSFFT_OK;
+  const int total = (int)specs.size();
+  for (int start = 0; start < total; start += p->max_batch) {
+    const int cnt = std::min(p->max_batch, total - start);
+    Batch b;
+    b.p = p;
+    b.tol = tol;
+    b.max_iter = max_iter;
+    b.averaging = true;
+    b.specs.assign(specs.begin() + start, specs.begin() + start + cnt);
+    // sub-groups of this batch: consecutive solves of the same group share
+    // one force spectrum (the first of them transforms it)
+    for (int i = 0; i < cnt; ++i) {
+      const int g = spec_group[start + i];
+      if (i == 0 || spec_group[start + i - 1] != g) {
+        BatchGroup bg;
+        bg.avg = groups[g].avg;
+        bg.incl_phase = groups[g].incl_phase;
+        bg.first = i;
+        bg.count = 0;
+        b.groups.push_back(bg);
+      }
+      b.groups.back().count += 1;
+      b.specs[i].group = (int)b.groups.size() - 1;
+      b.specs[i].leader = b.groups.back().first;
+    }
+    const double t0 = now_s();
+    lsfft_status s = run_batch(b, rep, t0);
+    if (s == LSFFT_E_ARG || s == LSFFT_E_ALLOC || s == LSFFT_E_DEVICE || s == LSFFT_E_NONEQUIL) return s;
+    worst = worse(worst, s);
+  }
+  for (int g = 0; g < ngroup; ++g) {
+    const lsfft_grid& gr = p->grids[groups[g].grid_idx];
+    const int d = gr.dim, s = d == 3 ? 6 : 3;
+    const long long nvox = gr.n[0] * gr.n[1] * (d == 3 ? gr.n[2] : 1);
+    if (launch_scale(groups[g].avg, (long long)(2 * d + 4 * s + 1) * nvox, 1.0 / groups[g].nshift, p->stream) != hipSuccess)
+      return LSFFT_E_DEVICE;
+  }
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return LSFFT_E_DEVICE;
+  return worst;
+}
+
+lsfft_status lsfft_translate_average(lsfft_plan_t p, int grid_idx, const uint8_t* phase, const lsfft_phases* tab,
+                                     const lsfft_ref* c0, const void* f, const int32_t* shifts, int nshift,
+                                     int incl_phase, double tol, int max_iter, double* avg, lsfft_report* rep) {
+  lsfft_avg_group g;
+  g.grid_idx = grid_idx;
+  g.phase = phase;
+  g.tab = tab;
+  g.c0 = c0;
+  g.f = f;
+  g.shifts = shifts;
+  g.nshift = nshift;
+  g.incl_phase = incl_phase;
+  g.avg = avg;
+  return lsfft_translate_average_batch(p, 1, &g, tol, max_iter, rep);
+}
+
+lsfft_status lsfft_kernel_times(lsfft_plan_t p, int kernel_class, double* total_ms, int64_t* launches) {
+  if (!p || kernel_class < 0 || kernel_class >= LSFFT_K_COUNT) return LSFFT_E_ARG;
+  if (total_ms) *total_ms = p->kt_ms[kernel_class];
+  if (launches) *launches = p->kt_n[kernel_class];
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_kernel_times_reset(lsfft_plan_t p) {
+  if (!p) return LSFFT_E_ARG;
+  for (int k = 0; k < LSFFT_K_COUNT; ++k) {
+    p->kt_ms[k] = 0;
+    p->kt_n[k] = 0;
+  }
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_iteration_bytes(lsfft_plan_t p, int grid_idx, int kernel_class, double* bytes) {
+  if (!p || !bytes || grid_idx < 0 || grid_idx >= (int)p->grids.size()) return LSFFT_E_ARG;
+  if (kernel_class < 0 || kernel_class >= LSFFT_K_COUNT) return LSFFT_E_ARG;
+  Geometry g;
+  if (!geometry(p->f64, p->grids[grid_idx], &g)) return LSFFT_E_ARG;
+  const double comp = (double)g.P * (p->f64 ? 16.0 : 8.0);  // one complex half-spectrum stream
+  const double s = g.s, d = g.dim;
+  const bool cg = p->scheme == LSFFT_CG;
+  double b = 0.0;
+  switch (kernel_class) {
+    case LSFFT_K_XPASS: b = 2 * s * comp + (double)g.nvox; break;          // eps^ in, sigma^ out, phase
+    case LSFFT_K_YPASS: b = (g.dim == 3) ? 4 * s * comp : 0.0; break;       // two sweeps, in and out
+    case LSFFT_K_GREEN:
+      b = cg ? (s + 2 * d) * comp + (3 * d + s) * comp                      // A p pass + direction pass
+             : (2 * s + 3 * d) * comp;                                       // sigma^, u^, f^ in; u^, eps^ out
+      break;
+    case LSFFT_K_REDUCE: b = 8.0 * 2 * std::max(g.items_g, g.items_cg); break;
+    case LSFFT_K_CGUPD: b = cg ? 6 * d * comp : 0.0; break;
+    default: b = 0.0;
+  }
+  *bytes = b;
+  return LSFFT_OK;
+}
+
+}  // extern "C"

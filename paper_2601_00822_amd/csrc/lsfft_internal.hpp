@@ -1,0 +1,120 @@
+// Internal structures shared by the host orchestration and the HIP kernels.
+#pragma once
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace lsfft {
+
+constexpr int kThreads = 256;        // workgroup size of every pass kernel
+constexpr int kMaxPhases = 256;      // phase ids are uint8
+constexpr int kMaxLen = 256;         // longest supported axis
+
+// Supported axis lengths (products of 2 and 3, even).  The twiddle table holds
+// exp(-2 pi i k / L) for k < L for each of them, back to back in this order.
+constexpr int kNumLens = 12;
+__host__ __device__ constexpr int len_at(int i) {
+  return i == 0 ? 4 : i == 1 ? 6 : i == 2 ? 8 : i == 3 ? 12 : i == 4 ? 16 : i == 5 ? 24
+       : i == 6 ? 32 : i == 7 ? 48 : i == 8 ? 64 : i == 9 ? 96 : i == 10 ? 128 : 256;
+}
+__host__ __device__ constexpr int tw_offset(int L) {
+  int off = 0;
+  for (int i = 0; i < kNumLens; ++i) {
+    if (len_at(i) == L) return off;
+    off += len_at(i);
+  }
+  return -1;
+}
+__host__ __device__ constexpr int tw_total() {
+  int off = 0;
+  for (int i = 0; i < kNumLens; ++i) off += len_at(i);
+  return off;
+}
+
+// Per-instance lifecycle (device-side, read by every pass kernel).
+enum InstStatus : int {
+  ST_RUNNING = 2,
+  ST_OK = 0,
+  ST_STAGNATED = 1,
+  ST_NOCONV = -4,
+  ST_DIVERGED = -6,
+};
+
+// Modes of the pass kernels.
+enum PassMode : int {
+  M_INIT = 0,    // transform the force, project, free term u^b = N0 f^
+  M_ITER = 1,    // one basic-scheme iteration
+  M_MAT = 2,     // materialize u, eps, sigma from the state
+  M_CG_AP = 3,   // CG: q = A p (forward half) and p.q partials
+  M_CG_UPD = 4,  // CG: u += alpha p, r -= alpha q, z = N0 r, r.z partials
+  M_CG_DIR = 5,  // CG: p = z + beta p, eps^(p) and its inverse transform
+  M_CG_INIT = 6, // CG: r0 = f^ - A u0 from the first operator pass, z0, p0 = z0
+  M_FT = 7,      // force transform: R2C along x, y, then the outer axis and projection
+};
+
+// One solve.  All pointers are device pointers; real and complex buffers are
+// stored in the plan precision (float or double), complex interleaved.
+struct InstDesc {
+  int dim;             // 2 or 3
+  int nx, ny, nz;      // nz = 1 in 2D
+  int nxh;             // nx / 2 + 1
+  int ncomp_s;         // strain components: 3 (2D) or 6 (3D)
+  int items_x, items_y, items_g;   // work items of each pass for this solve
+  int ntile_y, ntile_g;            // kx tiles per line in the y and outer passes
+  int nphase;
+  int lame_off;        // offset (in pairs) into the device Lame table
+  int sx, sy, sz;      // microstructure shift: phase read at (x - s) mod n
+  int max_iter;
+  int group;           // averaging group, -1 if none
+  long long P;         // complex entries of one half-spectrum component
+  long long nvox;      // nx * ny * nz
+  double kx, ky, kz;   // 2 pi / (n h) per axis
+  double inv_nvox;
+  double lam0, mu0;
+  double tol;
+  const uint8_t* phase;
+  const void* f_in;    // real force [d][nvox]
+  void* S;             // spectral work [ncomp_s + d][P]
+  void* U[2];          // displacement spectrum, double-buffered [d][P]
+  void* F;             // force spectrum [d][P] (may be shared)
+  void* R;             // CG residual [d][P]
+  void* Pd;            // CG direction [d][P]
+  void* Q;             // CG A p [d][P]
+  void* out_eps;       // real [s][nvox] or null
+  void* out_sig;       // real [s][nvox] or null
+  void* out_u;         // real [d][nvox] or null
+  double* partial;     // per work item FP64 partial sums [max items][2]
+  double* history;     // optional residual history [max_iter + 1] or null
+};
+
+struct InstState {
+  int iter;
+  int status;
+  int mark_iter;       // iteration of the last >= 1% improvement
+  int grow;            // consecutive iterations with a growing residual
+  double residual;
+  double fnorm2;
+  double mark;         // residual at mark_iter
+  double prev;
+  double removed_mean[3];
+  double rz;           // CG: r.z of the current iterate
+  double alpha;
+  double beta;
+  double pq;
+};
+
+struct WorkItem {
+  int inst;
+  int local;
+};
+
+// Averaging group: solves of one (microstructure, force) pair over shifts.
+struct GroupDesc {
+  int first;           // first instance index of the group in the batch
+  int count;           // number of instances (shifts) of the group
+  int incl_phase;
+  int pad;
+  double* avg;         // [2d + 4s + 1][nvox] FP64 accumulator
+};
+
+}  // namespace lsfft

@@ -1,0 +1,331 @@
+"""ctypes binding of liblsfft (argument marshalling only).
+
+Every step of the solver runs in the HIP kernels of ``liblsfft.so``; this
+module checks tensor shapes, dtypes and devices, converts array-order shapes
+and shifts to the library's (x, y, z) order, passes raw device pointers and
+the current HIP stream, and turns status codes into exceptions.  Torch is
+used for device memory and streams only.  There is no fallback: if the
+library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsfft.so")
+
+OK, W_STAGNATED = 0, 1
+E_ARG, E_ALLOC, E_DEVICE, E_NOCONV, E_NONEQUIL, E_DIVERGED = -1, -2, -3, -4, -5, -6
+F32, F64 = 0, 1
+BASIC, CG = 0, 1
+STRICT_EQUIL, TIMING = 0x1, 0x2
+K_XPASS, K_YPASS, K_GREEN, K_REDUCE, K_CGUPD, K_OTHER = range(6)
+
+EXPORTS = [
+    "lsfft_plan", "lsfft_solve_bfcs", "lsfft_translate_average", "lsfft_translate_average_batch",
+    "lsfft_plan_destroy", "lsfft_status_string", "lsfft_lame_from_young", "lsfft_kernel_times",
+    "lsfft_kernel_times_reset", "lsfft_iteration_bytes",
+]
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int64 * 3), ("h", C.c_double * 3)]
+
+
+class Phases(C.Structure):
+    _fields_ = [("nphase", C.c_int), ("lame", C.POINTER(C.c_double))]
+
+
+class Ref(C.Structure):
+    _fields_ = [("lambda0", C.c_double), ("mu0", C.c_double)]
+
+
+class Report(C.Structure):
+    _fields_ = [("iters", C.c_int), ("residual", C.c_double), ("removed_mean", C.c_double * 3),
+                ("status", C.c_int), ("seconds", C.c_double)]
+
+
+class AvgGroup(C.Structure):
+    _fields_ = [("grid_idx", C.c_int), ("phase", C.c_void_p), ("tab", C.POINTER(Phases)),
+                ("c0", C.POINTER(Ref)), ("f", C.c_void_p), ("shifts", C.POINTER(C.c_int32)),
+                ("nshift", C.c_int), ("incl_phase", C.c_int), ("avg", C.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblsfft.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "or python paper_2601_00822_amd/build_lib.py")
+    lib = C.CDLL(path)
+    vp, ip, dp = C.c_void_p, C.c_int, C.c_double
+    lib.lsfft_plan.argtypes = [C.POINTER(vp), C.POINTER(Grid), ip, ip, ip, ip, C.c_uint, vp]
+    lib.lsfft_plan.restype = ip
+    lib.lsfft_solve_bfcs.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(vp), C.POINTER(Phases), C.POINTER(Ref),
+                                     C.POINTER(vp), dp, ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                     C.POINTER(vp), C.POINTER(Report)]
+    lib.lsfft_solve_bfcs.restype = ip
+    lib.lsfft_translate_average.argtypes = [vp, ip, vp, C.POINTER(Phases), C.POINTER(Ref), vp,
+                                            C.POINTER(C.c_int32), ip, ip, dp, ip, vp, C.POINTER(Report)]
+    lib.lsfft_translate_average.restype = ip
+    lib.lsfft_translate_average_batch.argtypes = [vp, ip, C.POINTER(AvgGroup), dp, ip, C.POINTER(Report)]
+    lib.lsfft_translate_average_batch.restype = ip
+    lib.lsfft_plan_destroy.argtypes = [vp]
+    lib.lsfft_plan_destroy.restype = ip
+    lib.lsfft_status_string.argtypes = [ip]
+    lib.lsfft_status_string.restype = C.c_char_p
+    lib.lsfft_lame_from_young.argtypes = [ip, C.POINTER(dp), C.POINTER(dp)]
+    lib.lsfft_lame_from_young.restype = ip
+    lib.lsfft_kernel_times.argtypes = [vp, ip, C.POINTER(dp), C.POINTER(C.c_int64)]
+    lib.lsfft_kernel_times.restype = ip
+    lib.lsfft_kernel_times_reset.argtypes = [vp]
+    lib.lsfft_kernel_times_reset.restype = ip
+    lib.lsfft_iteration_bytes.argtypes = [vp, ip, ip, C.POINTER(dp)]
+    lib.lsfft_iteration_bytes.restype = ip
+    _lib = lib
+    return lib
+
+
+class LsfftError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load_library().lsfft_status_string(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+def status_string(status: int) -> str:
+    return load_library().lsfft_status_string(status).decode()
+
+
+def lame_from_young(table) -> np.ndarray:
+    """``[nphase][2]`` (E, nu) to (lambda, mu), computed by the library."""
+    t = np.ascontiguousarray(np.asarray(table, dtype=np.float64))
+    out = np.zeros_like(t)
+    st = load_library().lsfft_lame_from_young(
+        t.shape[0], t.ctypes.data_as(C.POINTER(C.c_double)), out.ctypes.data_as(C.POINTER(C.c_double)))
+    if st != OK:
+        raise LsfftError(st, "lame_from_young")
+    return out
+
+
+@dataclass
+class SolveReport:
+    iters: int
+    residual: float
+    removed_mean: tuple
+    status: int
+    seconds: float
+
+
+def _report(r: Report, d: int) -> SolveReport:
+    return SolveReport(r.iters, r.residual, tuple(r.removed_mean[:d]), r.status, r.seconds)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """A solver plan for one or more grids (array-order shapes)."""
+
+    def __init__(self, shapes, prec: str = "f64", scheme: str = "basic", max_batch: int = 1,
+                 strict_equil: bool = False, timing: bool = False, spacing=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblsfft needs a HIP GPU; none is visible")
+        self.lib = load_library()
+        if isinstance(shapes[0], int):
+            shapes = [shapes]
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.prec = prec
+        self.dtype = torch.float64 if prec == "f64" else torch.float32
+        grids = (Grid * len(self.shapes))()
+        for g, shp in enumerate(self.shapes):
+            d = len(shp)
+            if d not in (2, 3):
+                raise ValueError("grids are 2D or 3D")
+            grids[g].dim = d
+            rev = list(reversed(shp)) + [1] * (3 - d)
+            for a in range(3):
+                grids[g].n[a] = rev[a]
+                grids[g].h[a] = 1.0 if spacing is None else float(list(reversed(spacing[g]))[a] if a < d else 1.0)
+        flags = (STRICT_EQUIL if strict_equil else 0) | (TIMING if timing else 0)
+        self.stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = self.lib.lsfft_plan(C.byref(h), grids, len(self.shapes), int(max_batch),
+                                 F64 if prec == "f64" else F32, CG if scheme == "cg" else BASIC,
+                                 flags, C.c_void_p(self.stream.cuda_stream))
+        if st != OK:
+            raise LsfftError(st, "lsfft_plan")
+        self.handle = h
+
+    # ------------------------------------------------------------------ utils
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.lsfft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, t, shape, dtype, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a GPU tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return C.c_void_p(t.data_ptr())
+
+    @staticmethod
+    def _phases(lame):
+        arr = np.ascontiguousarray(np.asarray(lame, dtype=np.float64).reshape(-1, 2))
+        ph = Phases(arr.shape[0], arr.ctypes.data_as(C.POINTER(C.c_double)))
+        return ph, arr
+
+    @staticmethod
+    def _ref(c0):
+        if c0 is None:
+            return Ref(float("nan"), float("nan"))
+        return Ref(float(c0[0]), float(c0[1]))
+
+    # ------------------------------------------------------------------ solves
+    def solve_batch(self, problems, tol=1e-8, max_iter=10000, outputs=("eps", "sig", "u")):
+        """``problems``: list of dicts with keys grid (index), phase (uint8 GPU
+        tensor), lame ([nphase][2]), f ([d][...] GPU tensor), optional c0.
+        Returns (list of {eps, sig, u} tensors, list of SolveReport, status)."""
+        torch = _torch()
+        n = len(problems)
+        gidx = (C.c_int * n)()
+        ph_p = (C.c_void_p * n)()
+        f_p = (C.c_void_p * n)()
+        tabs = (Phases * n)()
+        refs = (Ref * n)()
+        eps_p = (C.c_void_p * n)()
+        sig_p = (C.c_void_p * n)()
+        u_p = (C.c_void_p * n)()
+        keep = []
+        outs = []
+        for i, pb in enumerate(problems):
+            g = int(pb.get("grid", 0))
+            shp = self.shapes[g]
+            d = len(shp)
+            s = 6 if d == 3 else 3
+            gidx[i] = g
+            ph_p[i] = self._check(pb["phase"], shp, torch.uint8, "phase")
+            f_p[i] = self._check(pb["f"], (d,) + shp, self.dtype, "f")
+            tabs[i], arr = self._phases(pb["lame"])
+            keep.append(arr)
+            refs[i] = self._ref(pb.get("c0"))
+            o = {}
+            dev = pb["f"].device
+            if "eps" in outputs:
+                o["eps"] = torch.empty((s,) + shp, dtype=self.dtype, device=dev)
+                eps_p[i] = o["eps"].data_ptr()
+            if "sig" in outputs:
+                o["sig"] = torch.empty((s,) + shp, dtype=self.dtype, device=dev)
+                sig_p[i] = o["sig"].data_ptr()
+            if "u" in outputs:
+                o["u"] = torch.empty((d,) + shp, dtype=self.dtype, device=dev)
+                u_p[i] = o["u"].data_ptr()
+            outs.append(o)
+        reps = (Report * n)()
+        st = self.lib.lsfft_solve_bfcs(self.handle, n, gidx, ph_p, tabs, refs, f_p, float(tol), int(max_iter),
+                                       eps_p, sig_p, u_p, None, reps)
+        if st not in (OK, W_STAGNATED, E_NOCONV, E_DIVERGED):
+            raise LsfftError(st, "lsfft_solve_bfcs")
+        return outs, [_report(reps[i], len(self.shapes[gidx[i]])) for i in range(n)], st
+
+    def solve(self, phase, lame, f, tol=1e-8, max_iter=10000, c0=None, grid=0,
+              outputs=("eps", "sig", "u")):
+        """One solve; returns ({eps, sig, u}, SolveReport)."""
+        outs, reps, _ = self.solve_batch([dict(grid=grid, phase=phase, lame=lame, f=f, c0=c0)],
+                                         tol=tol, max_iter=max_iter, outputs=outputs)
+        return outs[0], reps[0]
+
+    # ------------------------------------------------------------------ averaging
+    def translate_average_batch(self, groups, tol=1e-8, max_iter=10000):
+        """``groups``: list of dicts with keys grid, phase, lame, f, shifts
+        (array order ``[n][d]``), optional incl_phase (default 1) and c0.
+        Returns (list of FP64 averages ``[2d + 4s + 1][...]``, reports, status)."""
+        torch = _torch()
+        ng = len(groups)
+        arr = (AvgGroup * ng)()
+        keep = []
+        avgs = []
+        total = 0
+        for k, gr in enumerate(groups):
+            g = int(gr.get("grid", 0))
+            shp = self.shapes[g]
+            d = len(shp)
+            s = 6 if d == 3 else 3
+            tab, lame_arr = self._phases(gr["lame"])
+            ref = self._ref(gr.get("c0"))
+            sh = np.ascontiguousarray(np.asarray(gr["shifts"], dtype=np.int32).reshape(-1, d)[:, ::-1])
+            avg = torch.empty((2 * d + 4 * s + 1,) + shp, dtype=torch.float64, device=gr["f"].device)
+            keep += [tab, lame_arr, ref, sh]
+            arr[k].grid_idx = g
+            arr[k].phase = self._check(gr["phase"], shp, torch.uint8, "phase")
+            arr[k].tab = C.pointer(tab)
+            arr[k].c0 = C.pointer(ref)
+            arr[k].f = self._check(gr["f"], (d,) + shp, self.dtype, "f")
+            arr[k].shifts = sh.ctypes.data_as(C.POINTER(C.c_int32))
+            arr[k].nshift = sh.shape[0]
+            arr[k].incl_phase = int(gr.get("incl_phase", 1))
+            arr[k].avg = avg.data_ptr()
+            avgs.append(avg)
+            total += sh.shape[0]
+        reps = (Report * total)()
+        st = self.lib.lsfft_translate_average_batch(self.handle, ng, arr, float(tol), int(max_iter), reps)
+        if st not in (OK, W_STAGNATED, E_NOCONV, E_DIVERGED):
+            raise LsfftError(st, "lsfft_translate_average_batch")
+        out_reps = []
+        k = 0
+        for gr in groups:
+            d = len(self.shapes[int(gr.get("grid", 0))])
+            for _ in range(np.asarray(gr["shifts"]).reshape(-1, d).shape[0]):
+                out_reps.append(_report(reps[k], d))
+                k += 1
+        return avgs, out_reps, st
+
+    def translate_average(self, phase, lame, f, shifts, incl_phase=1, tol=1e-8, max_iter=10000,
+                          c0=None, grid=0):
+        avgs, reps, st = self.translate_average_batch(
+            [dict(grid=grid, phase=phase, lame=lame, f=f, shifts=shifts, incl_phase=incl_phase, c0=c0)],
+            tol=tol, max_iter=max_iter)
+        return avgs[0], reps
+
+    # ------------------------------------------------------------------ timing
+    def kernel_times(self, kclass: int):
+        ms = C.c_double()
+        n = C.c_int64()
+        st = self.lib.lsfft_kernel_times(self.handle, kclass, C.byref(ms), C.byref(n))
+        if st != OK:
+            raise LsfftError(st, "lsfft_kernel_times")
+        return ms.value, n.value
+
+    def kernel_times_reset(self):
+        self.lib.lsfft_kernel_times_reset(self.handle)
+
+    def iteration_bytes(self, kclass: int, grid: int = 0) -> float:
+        b = C.c_double()
+        st = self.lib.lsfft_iteration_bytes(self.handle, grid, kclass, C.byref(b))
+        if st != OK:
+            raise LsfftError(st, "lsfft_iteration_bytes")
+        return b.value
