@@ -1,18 +1,26 @@
 // Mixed-radix Stockham FFT building blocks for gfx950 (MI355X).
 //
-// A workgroup transforms a tile of MP independent pencils of length N held in
-// LDS as split real/imaginary arrays.  Element (pencil m, index n) lives at
-// m*SM + n*SN, so the same code serves pencils that are strided in HBM (the y
-// and z passes: SN = MP, SM = 1, lanes walk consecutive pencils) and pencils
-// that are rows in HBM (the x pass: SN = 1, SM = odd row pitch, lanes walk
-// rows).  Each pass reads R inputs spaced N/R apart, applies the twiddles of
-// the current span, a radix-R butterfly, and writes the autosorted outputs
-// (Stockham formulation, no bit reversal).  Transforms are unnormalised:
-// forward uses exp(-2 pi i k n / N), inverse exp(+2 pi i k n / N)
-// (the DFT of Sec. 4, Eqs. 4.3-4.5; the 1/|N| of Eq. 4.4 is applied once by
-// the caller).
+// A workgroup transforms a tile of MP independent pencils of length N.  The
+// first pass takes its inputs from registers (the caller loads them straight
+// from HBM), the middle passes exchange data through one LDS buffer in place
+// (gather into registers, barrier, butterfly, scatter, barrier), and the last
+// pass leaves its outputs in registers, so a transform costs np - 1 LDS round
+// trips for np passes.  Butterfly b of a pass maps to pencil m and index j;
+// with JF = false pencils vary fastest across lanes (pencils strided in HBM:
+// lanes read runs of consecutive pencils), with JF = true the index varies
+// fastest (pencils contiguous in HBM: lanes read runs along the pencil).
 //
-// Twiddles come from an LDS table tw[k] = exp(-2 pi i k / NT) read with a
+// A pass of radix R over span NS reads the R inputs j + r N/R, multiplies by
+// the twiddles of the current span, applies a radix-R butterfly and writes
+// the autosorted outputs (j / NS) NS R + j % NS + r NS (Stockham form, no bit
+// reversal).  In the last pass the outputs sit at j + r N/R, which are the
+// input positions of a first pass of the same radix: the reversed plan of the
+// inverse transform consumes the forward outputs where they are.
+// Transforms are unnormalised: forward exp(-2 pi i k n / N), inverse
+// exp(+2 pi i k n / N) (the DFT of Sec. 4, Eqs. 4.3-4.5; the 1/|N| of Eq. 4.4
+// is applied once by the caller).
+//
+// Twiddles come from an LDS table tw[k] = exp(-2 pi i k / NTAB) read with
 // stride TWS, so the table of a length-2N real transform also serves its
 // length-N complex core.
 #pragma once
@@ -21,13 +29,13 @@
 namespace lsfft {
 
 // ---------------------------------------------------------------------------
-// radix plans: product of the radices is N, radices in {2, 3, 4, 8}
+// radix plans (forward order): product of the radices is N
 // ---------------------------------------------------------------------------
 template <int N> struct Plan;
 #define LSFFT_PLAN(N_, NP_, R0, R1, R2)                                  \
   template <> struct Plan<N_> {                                            \
     static constexpr int np = NP_;                                         \
-    static constexpr int r[3] = {R0, R1, R2};                              \
+    static constexpr int r0 = R0, r1 = R1, r2 = R2;                        \
   };
 LSFFT_PLAN(2, 1, 2, 1, 1)
 LSFFT_PLAN(3, 1, 3, 1, 1)
@@ -37,13 +45,31 @@ LSFFT_PLAN(8, 1, 8, 1, 1)
 LSFFT_PLAN(12, 2, 4, 3, 1)
 LSFFT_PLAN(16, 2, 4, 4, 1)
 LSFFT_PLAN(24, 2, 8, 3, 1)
-LSFFT_PLAN(32, 2, 8, 4, 1)
+LSFFT_PLAN(32, 2, 4, 8, 1)
 LSFFT_PLAN(48, 3, 4, 4, 3)
 LSFFT_PLAN(64, 2, 8, 8, 1)
-LSFFT_PLAN(96, 3, 8, 4, 3)
-LSFFT_PLAN(128, 3, 8, 4, 4)
-LSFFT_PLAN(256, 3, 8, 8, 4)
+LSFFT_PLAN(96, 3, 4, 8, 3)
+LSFFT_PLAN(128, 3, 4, 4, 8)
+LSFFT_PLAN(256, 3, 4, 8, 8)
 #undef LSFFT_PLAN
+
+// radix of pass p, in forward order or reversed
+template <int N, bool REV> struct PlanSeq {
+  using P = Plan<N>;
+  static constexpr int np = P::np;
+  static constexpr int fwd(int p) { return p == 0 ? P::r0 : p == 1 ? P::r1 : P::r2; }
+  static constexpr int r(int p) { return REV ? fwd(np - 1 - p) : fwd(p); }
+  // span before pass p
+  static constexpr int ns(int p) {
+    int s = 1;
+    for (int q = 0; q < p; ++q) s *= r(q);
+    return s;
+  }
+  static constexpr int first() { return r(0); }
+  static constexpr int last() { return r(np - 1); }
+  static_assert(np == 1 ? P::r0 == N : np == 2 ? P::r0 * P::r1 == N : P::r0 * P::r1 * P::r2 == N,
+                "radix plan does not multiply to N");
+};
 
 // ---------------------------------------------------------------------------
 // complex helpers on split (re, im) scalars
@@ -71,7 +97,6 @@ __device__ __forceinline__ void bfly4_vals(T& x0r, T& x0i, T& x1r, T& x1i,
   T cr = x1r + x3r, ci = x1i + x3i;
   T dr = x1r - x3r, di = x1i - x3i;
   // forward: y1 = b - i d, y3 = b + i d ; inverse: y1 = b + i d, y3 = b - i d
-  // (-i)*(dr + i di) = di - i dr ; (+i)*(dr + i di) = -di + i dr
   T er, ei;
   if (DIR < 0) { er = di; ei = -dr; } else { er = -di; ei = dr; }
   x0r = ar + cr; x0i = ai + ci;
@@ -92,7 +117,7 @@ __device__ __forceinline__ void bfly3(T* vr, T* vi) {
   T dr = vr[1] - vr[2], di = vi[1] - vi[2];
   T mr = vr[0] - T(0.5) * sr, mi = vi[0] - T(0.5) * si;
   // forward: y1 = m - i s3 d ; y2 = m + i s3 d  (inverse swaps)
-  T tr, ti;  // (-i s3) * d = s3*di - i s3*dr
+  T tr, ti;
   if (DIR < 0) { tr = s3 * di; ti = -s3 * dr; } else { tr = -s3 * di; ti = s3 * dr; }
   vr[0] = vr[0] + sr; vi[0] = vi[0] + si;
   vr[1] = mr + tr; vi[1] = mi + ti;
@@ -102,26 +127,22 @@ __device__ __forceinline__ void bfly3(T* vr, T* vi) {
 template <typename T, int DIR>
 __device__ __forceinline__ void bfly8(T* vr, T* vi) {
   const T h = T(0.70710678118654752440084436210484904);  // sqrt(2)/2
-  // even and odd radix-4 halves
   bfly4_vals<T, DIR>(vr[0], vi[0], vr[2], vi[2], vr[4], vi[4], vr[6], vi[6]);
   bfly4_vals<T, DIR>(vr[1], vi[1], vr[3], vi[3], vr[5], vi[5], vr[7], vi[7]);
-  // twiddle the odd half by W8^k, W8 = exp(DIR * 2 pi i / 8)
-  {  // k = 1: (h, DIR*h)
+  {  // W8^1
     T r = vr[3], i = vi[3];
     if (DIR < 0) { vr[3] = h * (r + i); vi[3] = h * (i - r); }
     else         { vr[3] = h * (r - i); vi[3] = h * (i + r); }
   }
-  {  // k = 2: DIR*i
+  {  // W8^2
     T r = vr[5], i = vi[5];
     if (DIR < 0) { vr[5] = i; vi[5] = -r; } else { vr[5] = -i; vi[5] = r; }
   }
-  {  // k = 3: (-h, DIR*h)
+  {  // W8^3
     T r = vr[7], i = vi[7];
     if (DIR < 0) { vr[7] = h * (i - r); vi[7] = -h * (r + i); }
     else         { vr[7] = -h * (r + i); vi[7] = h * (r - i); }
   }
-  // combine: y[k] = E[k] + W^k O[k], y[k+4] = E[k] - W^k O[k]
-  // E[k] sits in slot 2k, O[k] (twiddled) in slot 2k+1
   T er[4] = {vr[0], vr[2], vr[4], vr[6]}, ei[4] = {vi[0], vi[2], vi[4], vi[6]};
   T orr[4] = {vr[1], vr[3], vr[5], vr[7]}, oi[4] = {vi[1], vi[3], vi[5], vi[7]};
 #pragma unroll
@@ -140,29 +161,38 @@ __device__ __forceinline__ void bfly(T* vr, T* vi) {
 }
 
 // ---------------------------------------------------------------------------
-// one Stockham pass over an LDS tile
+// tile transform with register input and register output
 // ---------------------------------------------------------------------------
-template <typename T, int N, int R, int NS, int DIR, int MP, int SM, int SN, int TWS, int NT>
-__device__ __forceinline__ void stockham_pass(const T* __restrict__ ir, const T* __restrict__ ii,
-                                              T* __restrict__ orr, T* __restrict__ oi,
-                                              const T* __restrict__ twr, const T* __restrict__ twi,
-                                              int tid) {
-  constexpr int NB = N / R;
-  constexpr int TOT = MP * NB;
-  constexpr int TSTEP = N / (NS * R);  // twiddle index step in units of N-th roots
-#pragma unroll 2
-  for (int b = tid; b < TOT; b += NT) {
-    const int m = b % MP;
-    const int j = b / MP;
-    const int k = j % NS;
-    T vr[R], vi[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int idx = m * SM + (j + r * NB) * SN;
-      vr[r] = ir[idx];
-      vi[r] = ii[idx];
-    }
+// T: float/double; N: length; DIR: -1/+1; REV: reversed radix order;
+// MP: pencils; SM, SN: LDS strides of pencil and index; TWS: twiddle stride;
+// JF: index-fastest butterfly mapping; NTH: threads.
+template <typename T, int N, int DIR, bool REV, int MP, int SM, int SN, int TWS, bool JF, int NTH>
+struct TileFft {
+  using S = PlanSeq<N, REV>;
+  static constexpr int np = S::np;
+  static constexpr int R0 = S::first();
+  static constexpr int RL = S::last();
+  static constexpr int TOT0 = MP * (N / R0);
+  static constexpr int TOTL = MP * (N / RL);
+  static constexpr int B0 = (TOT0 + NTH - 1) / NTH;   // butterflies per thread, first pass
+  static constexpr int BL = (TOTL + NTH - 1) / NTH;   // last pass
+
+  // butterfly -> (pencil, index)
+  template <int R>
+  __device__ static __forceinline__ void bj(int b, int& m, int& j) {
+    constexpr int NB = N / R;
+    if constexpr (JF) { m = b / NB; j = b - m * NB; }
+    else { m = b % MP; j = b / MP; }
+  }
+  // first-pass input position r of butterfly (m, j): index j + r N/R0
+  template <int R>
+  __device__ static __forceinline__ int in_idx(int j, int r) { return j + r * (N / R); }
+
+  template <int R, int NS>
+  __device__ static __forceinline__ void twiddle(T* vr, T* vi, int j, const T* twr, const T* twi) {
     if constexpr (NS > 1) {
+      constexpr int TSTEP = N / (NS * R);
+      const int k = j % NS;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         const int t = r * k * TSTEP * TWS;
@@ -171,49 +201,105 @@ __device__ __forceinline__ void stockham_pass(const T* __restrict__ ir, const T*
         cmul(vr[r], vi[r], wr, wi);
       }
     }
-    bfly<T, R, DIR>(vr, vi);
-    const int base = (j / NS) * NS * R + k;
+  }
+
+  template <int P>
+  __device__ static __forceinline__ void scatter_pass(T (&vr)[(MP * N / S::r(P) + NTH - 1) / NTH][S::r(P)],
+                                                      T (&vi)[(MP * N / S::r(P) + NTH - 1) / NTH][S::r(P)],
+                                                      T* re, T* im, const T* twr, const T* twi, int tid) {
+    constexpr int R = S::r(P), NS = S::ns(P), TOT = MP * (N / R), BPT = (TOT + NTH - 1) / NTH;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int idx = m * SM + (base + r * NS) * SN;
-      orr[idx] = vr[r];
-      oi[idx] = vi[r];
+    for (int q = 0; q < BPT; ++q) {
+      const int b = tid + q * NTH;
+      if (TOT % NTH == 0 || b < TOT) {
+        int m, j;
+        bj<R>(b, m, j);
+        twiddle<R, NS>(vr[q], vi[q], j, twr, twi);
+        bfly<T, R, DIR>(vr[q], vi[q]);
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int idx = m * SM + (base + r * NS) * SN;
+          re[idx] = vr[q][r];
+          im[idx] = vi[q][r];
+        }
+      }
     }
   }
-}
 
-// Full transform of the tile.  Input in buffer 0 (ar, ai); passes ping-pong
-// with buffer 1 (br, bi).  Returns 0 if the result is in buffer 0, 1 if in
-// buffer 1.  Every pass ends with a workgroup barrier.
-template <typename T, int N, int DIR, int MP, int SM, int SN, int TWS, int NT>
-__device__ __forceinline__ int fft_tile(T* ar, T* ai, T* br, T* bi,
-                                        const T* twr, const T* twi, int tid) {
-  using P = Plan<N>;
-  constexpr int R0 = P::r[0];
-  stockham_pass<T, N, R0, 1, DIR, MP, SM, SN, TWS, NT>(ar, ai, br, bi, twr, twi, tid);
-  __syncthreads();
-  if constexpr (P::np == 1) {
-    return 1;
-  } else {
-    constexpr int R1 = P::r[1];
-    stockham_pass<T, N, R1, R0, DIR, MP, SM, SN, TWS, NT>(br, bi, ar, ai, twr, twi, tid);
-    __syncthreads();
-    if constexpr (P::np == 2) {
-      return 0;
-    } else {
-      constexpr int R2 = P::r[2];
-      stockham_pass<T, N, R2, R0 * R1, DIR, MP, SM, SN, TWS, NT>(ar, ai, br, bi, twr, twi, tid);
+  template <int P>
+  __device__ static __forceinline__ void gather_pass(T (&vr)[(MP * N / S::r(P) + NTH - 1) / NTH][S::r(P)],
+                                                     T (&vi)[(MP * N / S::r(P) + NTH - 1) / NTH][S::r(P)],
+                                                     const T* re, const T* im, int tid) {
+    constexpr int R = S::r(P), TOT = MP * (N / R), BPT = (TOT + NTH - 1) / NTH;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int b = tid + q * NTH;
+      if (TOT % NTH == 0 || b < TOT) {
+        int m, j;
+        bj<R>(b, m, j);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int idx = m * SM + (j + r * (N / R)) * SN;
+          vr[q][r] = re[idx];
+          vi[q][r] = im[idx];
+        }
+      }
+    }
+  }
+
+  template <int P>
+  __device__ static __forceinline__ void compute_pass(T (&vr)[(MP * N / S::r(P) + NTH - 1) / NTH][S::r(P)],
+                                                      T (&vi)[(MP * N / S::r(P) + NTH - 1) / NTH][S::r(P)],
+                                                      const T* twr, const T* twi, int tid) {
+    constexpr int R = S::r(P), NS = S::ns(P), TOT = MP * (N / R), BPT = (TOT + NTH - 1) / NTH;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int b = tid + q * NTH;
+      if (TOT % NTH == 0 || b < TOT) {
+        int m, j;
+        bj<R>(b, m, j);
+        twiddle<R, NS>(vr[q], vi[q], j, twr, twi);
+        bfly<T, R, DIR>(vr[q], vi[q]);
+      }
+    }
+  }
+
+  // Whole transform.  `in` holds first-pass inputs (position j + r N/R0 of
+  // butterfly tid + q NTH), `out` receives last-pass outputs (position
+  // j + r N/RL).  Uses LDS (re, im) as staging; contains the barriers it
+  // needs between its own passes.  The caller must make sure no thread still
+  // reads (re, im) from a previous use when this starts (alternating two
+  // buffers between consecutive transforms is enough when np >= 2).
+  __device__ static __forceinline__ void run(T (&in_r)[B0][R0], T (&in_i)[B0][R0],
+                                             T (&out_r)[BL][RL], T (&out_i)[BL][RL],
+                                             T* re, T* im, const T* twr, const T* twi, int tid) {
+    if constexpr (np == 1) {
+      compute_pass<0>(in_r, in_i, twr, twi, tid);
+#pragma unroll
+      for (int q = 0; q < BL; ++q)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) { out_r[q][r] = in_r[q][r]; out_i[q][r] = in_i[q][r]; }
+    } else if constexpr (np == 2) {
+      scatter_pass<0>(in_r, in_i, re, im, twr, twi, tid);
       __syncthreads();
-      return 1;
+      gather_pass<1>(out_r, out_i, re, im, tid);
+      compute_pass<1>(out_r, out_i, twr, twi, tid);
+    } else {
+      scatter_pass<0>(in_r, in_i, re, im, twr, twi, tid);
+      __syncthreads();
+      {
+        constexpr int R1 = S::r(1), BP1 = (MP * (N / R1) + NTH - 1) / NTH;
+        T mr[BP1][R1], mi[BP1][R1];
+        gather_pass<1>(mr, mi, re, im, tid);
+        __syncthreads();
+        scatter_pass<1>(mr, mi, re, im, twr, twi, tid);
+      }
+      __syncthreads();
+      gather_pass<2>(out_r, out_i, re, im, tid);
+      compute_pass<2>(out_r, out_i, twr, twi, tid);
     }
   }
-}
-
-template <int N> struct PlanCheck {
-  static constexpr int prod = Plan<N>::np == 1 ? Plan<N>::r[0]
-                            : Plan<N>::np == 2 ? Plan<N>::r[0] * Plan<N>::r[1]
-                                               : Plan<N>::r[0] * Plan<N>::r[1] * Plan<N>::r[2];
-  static_assert(prod == N, "radix plan does not multiply to N");
 };
 
 }  // namespace lsfft
