@@ -18,8 +18,11 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblsfft.so")
 
-SOURCES = ["k_g_f32.hip", "k_g_f64.hip", "k_x_f32.hip", "k_x_f64.hip", "k_y_f32.hip",
-           "k_y_f64.hip", "k_misc.hip", "lsfft.cpp"]
+def sources():
+    """Every HIP translation unit in csrc/ (largest first) plus the host code."""
+    hips = sorted((f for f in os.listdir(CSRC) if f.endswith(".hip")),
+                  key=lambda f: (not f.startswith("k_g_"), f))
+    return hips + ["lsfft.cpp"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -48,8 +51,9 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    srcs = sources()
+    with cf.ThreadPoolExecutor(max_workers=min(len(srcs), os.cpu_count() or 4)) as ex:
+        objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

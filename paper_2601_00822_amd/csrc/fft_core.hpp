@@ -51,11 +51,33 @@ LSFFT_PLAN(64, 2, 8, 8, 1)
 LSFFT_PLAN(96, 3, 4, 8, 3)
 LSFFT_PLAN(128, 3, 4, 4, 8)
 LSFFT_PLAN(256, 3, 4, 8, 8)
+
+// Plans whose last forward radix is at most 4, for tiles held at 4 (or 3)
+// points per thread between the forward and the inverse transform.
+template <int N> struct PlanG;
+#define LSFFT_PLANG(N_, NP_, R0, R1, R2)                                 \
+  template <> struct PlanG<N_> {                                           \
+    static constexpr int np = NP_;                                         \
+    static constexpr int r0 = R0, r1 = R1, r2 = R2;                        \
+  };
+LSFFT_PLANG(4, 1, 4, 1, 1)
+LSFFT_PLANG(6, 2, 2, 3, 1)
+LSFFT_PLANG(8, 2, 2, 4, 1)
+LSFFT_PLANG(12, 2, 4, 3, 1)
+LSFFT_PLANG(16, 2, 4, 4, 1)
+LSFFT_PLANG(24, 2, 8, 3, 1)
+LSFFT_PLANG(32, 2, 8, 4, 1)
+LSFFT_PLANG(48, 3, 4, 4, 3)
+LSFFT_PLANG(64, 3, 4, 4, 4)
+LSFFT_PLANG(96, 3, 4, 8, 3)
+LSFFT_PLANG(128, 3, 8, 4, 4)
+LSFFT_PLANG(256, 3, 8, 8, 4)
 #undef LSFFT_PLAN
+#undef LSFFT_PLANG
 
 // radix of pass p, in forward order or reversed
-template <int N, bool REV> struct PlanSeq {
-  using P = Plan<N>;
+template <template <int> class PL, int N, bool REV> struct PlanSeq {
+  using P = PL<N>;
   static constexpr int np = P::np;
   static constexpr int fwd(int p) { return p == 0 ? P::r0 : p == 1 ? P::r1 : P::r2; }
   static constexpr int r(int p) { return REV ? fwd(np - 1 - p) : fwd(p); }
@@ -165,10 +187,11 @@ __device__ __forceinline__ void bfly(T* vr, T* vi) {
 // ---------------------------------------------------------------------------
 // T: float/double; N: length; DIR: -1/+1; REV: reversed radix order;
 // MP: pencils; SM, SN: LDS strides of pencil and index; TWS: twiddle stride;
-// JF: index-fastest butterfly mapping; NTH: threads.
-template <typename T, int N, int DIR, bool REV, int MP, int SM, int SN, int TWS, bool JF, int NTH>
+// JF: index-fastest butterfly mapping; NTH: threads; PL: radix plan family.
+template <typename T, int N, int DIR, bool REV, int MP, int SM, int SN, int TWS, bool JF, int NTH,
+          template <int> class PL = Plan>
 struct TileFft {
-  using S = PlanSeq<N, REV>;
+  using S = PlanSeq<PL, N, REV>;
   static constexpr int np = S::np;
   static constexpr int R0 = S::first();
   static constexpr int RL = S::last();

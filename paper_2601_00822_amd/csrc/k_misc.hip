@@ -7,20 +7,21 @@
 namespace lsfft {
 
 template <typename T>
-static size_t geom_query(int kind, int len, int* per_line) {
+static size_t geom_query(int kind, int len, int* per_tile) {
   size_t bytes = 0;
   int q = 0;
   switch (len) {
 #define X(L)                                                                    \
   case L:                                                                       \
-    if (kind == 0) { bytes = lds_x<T, L>(); q = RowGeom<T, L / 2>::MR; }        \
-    else { bytes = lds_strided<T, L>(); q = StridedGeom<T, L>::MP; }            \
+    if (kind == 0) { bytes = lds_x<T, L>(); q = XGeom<T, L / 2>::MR; }          \
+    else if (kind == 1) { bytes = lds_y<T, L>(); q = SGeom<T, L>::MP; }         \
+    else { bytes = lds_g<T, L>(); q = SGeom<T, L>::MPG; }                        \
     break;
     LSFFT_LEN_CASES(X)
 #undef X
     default: return 0;
   }
-  if (per_line) *per_line = q;
+  if (per_tile) *per_tile = q;
   return bytes;
 }
 
@@ -28,57 +29,71 @@ size_t query_geometry(bool f64, int kind, int len, int* per_tile) {
   return f64 ? geom_query<double>(kind, len, per_tile) : geom_query<float>(kind, len, per_tile);
 }
 
-hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode) {
-  return f64 ? launch_xpass_f64(a, mode) : launch_xpass_f32(a, mode);
+int threads_per_block(bool f64) { return f64 ? Cfg<double>::NTH : Cfg<float>::NTH; }
+int threads_per_block_green(bool f64) { return f64 ? Cfg<double>::NTH_G : Cfg<float>::NTH_G; }
+
+hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode, int dim, int len) {
+  if (f64) return dim == 3 ? launch_xpass_f64_3d(a, mode, len) : launch_xpass_f64_2d(a, mode, len);
+  return dim == 3 ? launch_xpass_f32_3d(a, mode, len) : launch_xpass_f32_2d(a, mode, len);
 }
 
-hipError_t launch_ypass(bool f64, const LaunchArgs& a, int dir, int which, int extra, int gate) {
-  return f64 ? launch_ypass_f64(a, dir, which, extra, gate) : launch_ypass_f32(a, dir, which, extra, gate);
+hipError_t launch_ypass(bool f64, const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len) {
+  return f64 ? launch_ypass_f64(a, dir, which, ncomp, gate, len) : launch_ypass_f32(a, dir, which, ncomp, gate, len);
 }
 
-hipError_t launch_green(bool f64, const LaunchArgs& a, int mode) {
-  return f64 ? launch_green_f64(a, mode) : launch_green_f32(a, mode);
+hipError_t launch_green(bool f64, const LaunchArgs& a, int mode, int dim, int len) {
+  const bool small = len < 32;
+  if (f64) {
+    if (dim == 3) return small ? launch_green_f64_3d_s(a, mode, len) : launch_green_f64_3d_l(a, mode, len);
+    return small ? launch_green_f64_2d_s(a, mode, len) : launch_green_f64_2d_l(a, mode, len);
+  }
+  if (dim == 3) return small ? launch_green_f32_3d_s(a, mode, len) : launch_green_f32_3d_l(a, mode, len);
+  return small ? launch_green_f32_2d_s(a, mode, len) : launch_green_f32_2d_l(a, mode, len);
 }
 
 hipError_t launch_cg_update(bool f64, const LaunchArgs& a) {
-  if (f64) hipLaunchKernelGGL((k_cg_update<double>), a.grid, NT, sizeof(double) * 8, a.stream, a.desc, a.state, a.items, a.count);
-  else hipLaunchKernelGGL((k_cg_update<float>), a.grid, NT, sizeof(double) * 8, a.stream, a.desc, a.state, a.items, a.count);
+  if (f64)
+    hipLaunchKernelGGL((k_cg_update<double>), a.grid, Cfg<double>::NTH, sizeof(double) * 16, a.stream, a.desc, a.state,
+                       a.items, a.count);
+  else
+    hipLaunchKernelGGL((k_cg_update<float>), a.grid, Cfg<float>::NTH, sizeof(double) * 16, a.stream, a.desc, a.state,
+                       a.items, a.count);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const LaunchArgs& a, const int* inst_list, int ninst, int mode) {
+hipError_t launch_reduce(const LaunchArgs& a, const int* inst_list, const int* d_ninst, int ninst, int mode) {
   if (ninst <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(ninst), NT, 0, a.stream, a.desc, a.state, inst_list, ninst, mode);
+  hipLaunchKernelGGL(k_reduce, dim3(ninst), NTR, 0, a.stream, a.desc, a.state, inst_list, d_ninst, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_phase_max(const uint8_t* phase, long long n, int* out, hipStream_t s) {
-  long long blocks = (n + NT - 1) / NT;
+  long long blocks = (n + NTR - 1) / NTR;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_phase_max, dim3((unsigned)blocks), NT, 0, s, phase, n, out);
+  hipLaunchKernelGGL(k_phase_max, dim3((unsigned)blocks), NTR, 0, s, phase, n, out);
   return hipGetLastError();
 }
 
 hipError_t launch_accumulate(bool f64, int dim, const LaunchArgs& a, const GroupDesc* groups, int g, long long nvox) {
-  long long blocks = (nvox + NT - 1) / NT;
+  long long blocks = (nvox + NTR - 1) / NTR;
   if (blocks > 4096) blocks = 4096;
   const dim3 grid((unsigned)blocks);
   if (f64) {
-    if (dim == 3) hipLaunchKernelGGL((k_accumulate<double, 3>), grid, NT, 0, a.stream, a.desc, groups, g, a.lame);
-    else hipLaunchKernelGGL((k_accumulate<double, 2>), grid, NT, 0, a.stream, a.desc, groups, g, a.lame);
+    if (dim == 3) hipLaunchKernelGGL((k_accumulate<double, 3>), grid, NTR, 0, a.stream, a.desc, groups, g, a.lame);
+    else hipLaunchKernelGGL((k_accumulate<double, 2>), grid, NTR, 0, a.stream, a.desc, groups, g, a.lame);
   } else {
-    if (dim == 3) hipLaunchKernelGGL((k_accumulate<float, 3>), grid, NT, 0, a.stream, a.desc, groups, g, a.lame);
-    else hipLaunchKernelGGL((k_accumulate<float, 2>), grid, NT, 0, a.stream, a.desc, groups, g, a.lame);
+    if (dim == 3) hipLaunchKernelGGL((k_accumulate<float, 3>), grid, NTR, 0, a.stream, a.desc, groups, g, a.lame);
+    else hipLaunchKernelGGL((k_accumulate<float, 2>), grid, NTR, 0, a.stream, a.desc, groups, g, a.lame);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_scale(double* a, long long n, double s, hipStream_t st) {
-  long long blocks = (n + NT - 1) / NT;
+  long long blocks = (n + NTR - 1) / NTR;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), NT, 0, st, a, n, s);
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), NTR, 0, st, a, n, s);
   return hipGetLastError();
 }
 

@@ -3,23 +3,29 @@
 // One basic-scheme iteration is four sweeps over HBM (3D), each a persistent
 // kernel walking a device work list of (solve, tile) items:
 //
-//   ypass<inv>  : inverse y transforms of the strain spectrum (3D only)
-//   xpass<ITER> : per x-row: half-spectrum -> real (C2R), Hooke's law
-//                 sigma = lam(x) tr(eps) I + 2 mu(x) eps (Eq. 2.2), real ->
-//                 half-spectrum (R2C); the real fields never reach HBM
+//   ypass<inv>  : inverse y transforms of the strain spectrum (3D only),
+//                 one component per item
+//   xpass<ITER> : per block of x rows: half spectrum -> real (C2R), Hooke's
+//                 law sigma = lam(x) tr(eps) I + 2 mu(x) eps (Eq. 2.2) on the
+//                 real values held in registers, real -> half spectrum (R2C);
+//                 the real fields never reach HBM
 //   ypass<fwd>  : forward y transforms of the stress spectrum (3D only)
 //   green<ITER> : along the outermost axis: forward transform of sigma, the
 //                 equilibrium residual r = i xi . sigma^ + f^ with its FP64
-//                 Parseval partial sum, the update u^ += N0(xi) r (the
-//                 displacement form of Eqs. 5.7-5.10, see the solver notes),
-//                 the next strain spectrum sym(i xi (x) u^) / |N| and its
-//                 inverse transform
+//                 Parseval partial sum, the update u^ += N0(xi) r (Algorithm 1
+//                 in displacement form), the next strain spectrum
+//                 sym(i xi (x) u^) / |N| and its inverse transform
 //
 // followed by a one-block-per-solve FP64 reduction that evaluates the stopping
 // rule and retires converged solves.  2D grids skip the y sweeps (the outer
 // axis is y).  The same kernels, in other modes, transform the force, form the
 // free term u^b = N0 f^ (Eqs. 2.8-2.9), run the conjugate-gradient variant and
 // materialize u, eps and sigma.
+//
+// Transform stages: the first pass of every transform reads its inputs from
+// HBM (or from the pointwise stage) straight into registers, and the last
+// pass leaves its outputs in registers, which the next stage consumes where
+// they are; only the middle passes go through LDS.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -31,8 +37,6 @@
 
 namespace lsfft {
 
-constexpr int NT = kThreads;
-
 // ---------------------------------------------------------------------------
 // tile geometry
 // ---------------------------------------------------------------------------
@@ -43,29 +47,38 @@ constexpr int pow2floor(int v) {
 }
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// elements of one component tile held in LDS / registers
-template <typename T> struct TileBudget { static constexpr int value = 2048; };
-template <> struct TileBudget<double> { static constexpr int value = 1024; };
-
-// pencils per tile for a strided pass of length N
-template <typename T, int N> struct StridedGeom {
-  static constexpr int MP = clampi(pow2floor(TileBudget<T>::value / N), 1, 64);
-  static constexpr int ELEMS = MP * N;
-  static constexpr int PPT = (ELEMS + NT - 1) / NT;
+// Threads per workgroup and tile elements per component, per kernel family:
+// x and y passes hold 8 (FP32) / 4 (FP64) points per thread, the outer pass 4.
+template <typename T> struct Cfg;
+template <> struct Cfg<float> {
+  static constexpr int NTH = 256, E = 2048, EX = 2048;   // x and y passes
+  static constexpr int NTH_G = 512, E_G = 2048;          // outer pass
+};
+template <> struct Cfg<double> {
+  static constexpr int NTH = 128, E = 1024, EX = 512;
+  static constexpr int NTH_G = 256, E_G = 1024;
 };
 
-// rows per tile for the x pass (H = nx / 2 complex points per row); the x
-// pass keeps every strain component of its points in registers, so it uses
-// half the budget
-template <typename T, int H> struct RowGeom {
-  static constexpr int MR = clampi(pow2floor(TileBudget<T>::value / 2 / H), 1, 64);
-  static constexpr int SM = ((H + 1) % 2 == 1) ? (H + 1) : (H + 2);  // odd pitch
-  static constexpr int PPT = (MR * H + NT - 1) / NT;
+// pencils per strided tile of length N (y pass, outer pass)
+template <typename T, int N> struct SGeom {
+  static constexpr int MP = clampi(pow2floor(Cfg<T>::E / N), 1, 64);
+  static constexpr int MPG = clampi(pow2floor(Cfg<T>::E_G / N), 1, 64);
+};
+
+// rows per x tile (H = nx / 2 complex points per row); odd LDS pitches
+template <typename T, int H> struct XGeom {
+  static constexpr int MR = clampi(pow2floor(Cfg<T>::EX / H), 1, 64);
+  static constexpr int SM = ((H + 1) % 2 == 1) ? (H + 1) : (H + 2);  // fold tile, H + 1 entries
+  static constexpr int SM2 = (H % 2 == 1) ? H : (H + 1);             // transform staging
 };
 
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+// scheduling fence: the compiler may not move instructions across it, which
+// bounds how many loads it hoists ahead (and so the live registers)
+#define LSFFT_FENCE() __builtin_amdgcn_sched_barrier(0)
+
 template <typename T> struct C2;
 template <> struct C2<float> { using type = float2; };
 template <> struct C2<double> { using type = double2; };
@@ -81,6 +94,14 @@ __device__ __forceinline__ void stc(void* base, long long i, T re, T im) {
   v.y = im;
   reinterpret_cast<typename C2<T>::type*>(base)[i] = v;
 }
+template <typename T>
+__device__ __forceinline__ const char* cptr(const void* base, long long comp_stride, int c) {
+  return static_cast<const char*>(base) + (size_t)c * comp_stride * sizeof(T) * 2;
+}
+template <typename T>
+__device__ __forceinline__ char* mptr(void* base, long long comp_stride, int c) {
+  return static_cast<char*>(base) + (size_t)c * comp_stride * sizeof(T) * 2;
+}
 
 // signed wavevector component of index k on an axis of n points; zero on the
 // Nyquist index
@@ -90,18 +111,24 @@ __device__ __forceinline__ double wavenum(int k, int n, double scale) {
   return scale * double(k < h ? k : k - n);
 }
 
+__device__ __forceinline__ int wrap(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
 // load exp(-2 pi i k / L), k < L, into LDS from the plan's twiddle table
-template <typename T, int L>
+template <typename T, int L, int NTH>
 __device__ __forceinline__ void load_tw(T* twr, T* twi, const T* table, int tid) {
   constexpr int off = tw_offset(L);
   static_assert(off >= 0, "unsupported transform length");
-  for (int k = tid; k < L; k += NT) {
+  for (int k = tid; k < L; k += NTH) {
     twr[k] = table[2 * (off + k)];
     twi[k] = table[2 * (off + k) + 1];
   }
 }
 
-// block-wide FP64 sum (deterministic for a fixed block size)
+// block-wide FP64 sum (deterministic for a fixed block size), valid in thread 0
+template <int NTH>
 __device__ inline double block_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -110,313 +137,10 @@ __device__ inline double block_sum(double v, double* red) {
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0) {
-    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    for (int w = 0; w < NTH / 64; ++w) s += red[w];
   }
-  return s;  // valid in thread 0
+  return s;
 }
-
-
-// ---------------------------------------------------------------------------
-// real <-> half-spectrum folding of a length-NX real row through a
-// length-H = NX/2 complex transform (z[n] = a[2n] + i a[2n+1])
-// ---------------------------------------------------------------------------
-
-// Z (transform of the packed row, in rr/ri) -> X[k], k = 0..H, written to
-// global row `row` of `out` (complex, nxh entries per row).
-//   E = (Z[k] + conj Z[H-k]) / 2,  O = -i (Z[k] - conj Z[H-k]) / 2,
-//   X[k] = E + exp(-2 pi i k / NX) O
-template <typename T, int H, int MR, int SM>
-__device__ __forceinline__ void fold_r2c_store(const T* rr, const T* ri, const T* twr, const T* twi,
-                                               void* out, int row0, int nrows, int nxh, int tid) {
-  for (int e = tid; e < MR * (H + 1); e += NT) {
-    const int m = e / (H + 1);
-    const int k = e - m * (H + 1);
-    const int row = row0 + m;
-    if (row >= nrows) continue;
-    const int k1 = (k == H) ? 0 : k;
-    const int k2 = (k == 0) ? 0 : H - k;
-    const T zr = rr[m * SM + k1], zi = ri[m * SM + k1];
-    const T wr = rr[m * SM + k2], wi = ri[m * SM + k2];
-    const T er = T(0.5) * (zr + wr), ei = T(0.5) * (zi - wi);
-    const T dr = T(0.5) * (zr - wr), di = T(0.5) * (zi + wi);
-    const T orr = di, oi = -dr;                 // O = -i D
-    const T cr = twr[k], ci = twi[k];
-    stc<T>(out, (long long)row * nxh + k, er + cr * orr - ci * oi, ei + cr * oi + ci * orr);
-  }
-}
-
-// X[k] (k = 0..H, rows in ar/ai) -> Z'[k] (k < H) in br/bi such that the
-// unnormalised inverse length-H transform of Z' is NX * (a[2n] + i a[2n+1]):
-//   Z' = (X[k] + conj X[H-k]) + i exp(+2 pi i k / NX) (X[k] - conj X[H-k])
-template <typename T, int H, int MR, int SM>
-__device__ __forceinline__ void fold_c2r_prep(const T* ar, const T* ai, T* br, T* bi,
-                                              const T* twr, const T* twi, int tid) {
-  for (int e = tid; e < MR * H; e += NT) {
-    const int m = e / H;
-    const int k = e - m * H;
-    const T xr = ar[m * SM + k], xi = ai[m * SM + k];
-    const T yr = ar[m * SM + (H - k)], yi = -ai[m * SM + (H - k)];   // conj X[H-k]
-    const T dr = xr - yr, di = xi - yi;
-    const T cr = twr[k], ci = -twi[k];                                // exp(+2 pi i k / NX)
-    const T tr = cr * dr - ci * di, ti = cr * di + ci * dr;
-    br[m * SM + k] = xr + yr - ti;
-    bi[m * SM + k] = xi + yi + tr;
-  }
-}
-
-__device__ __forceinline__ int wrap(int v, int n) {
-  v %= n;
-  return v < 0 ? v + n : v;
-}
-
-// ---------------------------------------------------------------------------
-// x pass
-// ---------------------------------------------------------------------------
-template <typename T, int NX, int DIM, int MODE>
-__device__ void xpass_item(const InstDesc& D, int local, const double* __restrict__ lame,
-                           const T* __restrict__ twtab, unsigned char* smem) {
-  constexpr int H = NX / 2;
-  using G = RowGeom<T, H>;
-  constexpr int MR = G::MR, SM = G::SM, PPT = G::PPT;
-  constexpr int TILE = MR * SM;
-  constexpr int S = (DIM == 3) ? 6 : 3;
-  T* ar = reinterpret_cast<T*>(smem);
-  T* ai = ar + TILE;
-  T* br = ai + TILE;
-  T* bi = br + TILE;
-  T* twr = bi + TILE;
-  T* twi = twr + NX;
-  T* lam_s = twi + NX;
-  T* mu_s = lam_s + kMaxPhases;
-  const int tid = threadIdx.x;
-  load_tw<T, NX>(twr, twi, twtab, tid);
-  if constexpr (MODE != M_FT) {
-    for (int p = tid; p < D.nphase; p += NT) {
-      lam_s[p] = T(lame[2 * (D.lame_off + p)]);
-      mu_s[p] = T(lame[2 * (D.lame_off + p) + 1]);
-    }
-  }
-  __syncthreads();
-  const int nrows = D.ny * D.nz;
-  const int row0 = local * MR;
-  const long long P = D.P;
-  const int nxh = D.nxh;
-  const size_t cbytes = sizeof(T) * 2;
-
-  if constexpr (MODE == M_FT) {
-    // forward real-to-half-spectrum of the force rows into F
-    for (int c = 0; c < DIM; ++c) {
-      const T* src = reinterpret_cast<const T*>(D.f_in) + (long long)c * D.nvox;
-      for (int e = tid; e < MR * H; e += NT) {
-        const int m = e / H, n = e - (e / H) * H;
-        const int row = row0 + m;
-        T re = T(0), im = T(0);
-        if (row < nrows) {
-          const typename C2<T>::type v =
-              reinterpret_cast<const typename C2<T>::type*>(src + (long long)row * NX)[n];
-          re = v.x;
-          im = v.y;
-        }
-        ar[m * SM + n] = re;
-        ai[m * SM + n] = im;
-      }
-      __syncthreads();
-      const int where = fft_tile<T, H, -1, MR, SM, 1, 2, NT>(ar, ai, br, bi, twr, twi, tid);
-      fold_r2c_store<T, H, MR, SM>(where ? br : ar, where ? bi : ai, twr, twi,
-                                   static_cast<char*>(D.F) + c * P * cbytes, row0, nrows, nxh, tid);
-      __syncthreads();
-    }
-    return;
-  } else {
-    // strain components of this thread's points, real pairs (x = 2n, 2n + 1)
-    T er[S][PPT], ei[S][PPT];
-    constexpr int ncu = (MODE == M_MAT) ? S + DIM : S;
-#pragma unroll
-    for (int c = 0; c < ncu; ++c) {
-      const char* src = static_cast<const char*>(D.S) + c * P * cbytes;
-      for (int e = tid; e < MR * (H + 1); e += NT) {
-        const int m = e / (H + 1), k = e - (e / (H + 1)) * (H + 1);
-        const int row = row0 + m;
-        T re = T(0), im = T(0);
-        if (row < nrows) {
-          const typename C2<T>::type v = ldc<T>(src, (long long)row * nxh + k);
-          re = v.x;
-          im = v.y;
-        }
-        ar[m * SM + k] = re;
-        ai[m * SM + k] = im;
-      }
-      __syncthreads();
-      fold_c2r_prep<T, H, MR, SM>(ar, ai, br, bi, twr, twi, tid);
-      __syncthreads();
-      const int where = fft_tile<T, H, +1, MR, SM, 1, 2, NT>(br, bi, ar, ai, twr, twi, tid);
-      const T* rr = where ? ar : br;
-      const T* ri = where ? ai : bi;
-      if (c < S) {
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          const int e = tid + p * NT;
-          if (e < MR * H) {
-            const int m = e / H, n = e - (e / H) * H;
-            er[c][p] = rr[m * SM + n];
-            ei[c][p] = ri[m * SM + n];
-          }
-        }
-      } else if (D.out_u) {
-        // MAT: displacement component c - S written straight out
-        T* dst = reinterpret_cast<T*>(D.out_u) + (long long)(c - S) * D.nvox;
-        for (int e = tid; e < MR * H; e += NT) {
-          const int m = e / H, n = e - (e / H) * H;
-          const int row = row0 + m;
-          if (row < nrows) {
-            typename C2<T>::type v;
-            v.x = rr[m * SM + n];
-            v.y = ri[m * SM + n];
-            reinterpret_cast<typename C2<T>::type*>(dst + (long long)row * NX)[n] = v;
-          }
-        }
-      }
-      __syncthreads();
-    }
-    if constexpr (MODE == M_MAT) {
-      if (D.out_eps) {
-#pragma unroll
-        for (int c = 0; c < S; ++c) {
-          T* dst = reinterpret_cast<T*>(D.out_eps) + (long long)c * D.nvox;
-#pragma unroll
-          for (int p = 0; p < PPT; ++p) {
-            const int e = tid + p * NT;
-            const int m = e / H, n = e - (e / H) * H;
-            if (e < MR * H && row0 + m < nrows) {
-              typename C2<T>::type v;
-              v.x = er[c][p];
-              v.y = ei[c][p];
-              reinterpret_cast<typename C2<T>::type*>(dst + (long long)(row0 + m) * NX)[n] = v;
-            }
-          }
-        }
-      }
-    }
-    // Hooke's law at every point of the tile, microstructure shifted by s
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      const int e = tid + p * NT;
-      const int m = e / H, n = e - (e / H) * H;
-      const int row = row0 + m;
-      if (e < MR * H && row < nrows) {
-        const int z = row / D.ny, y = row - (row / D.ny) * D.ny;
-        const long long rbase =
-            ((long long)wrap(z - D.sz, D.nz) * D.ny + wrap(y - D.sy, D.ny)) * (long long)NX;
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          const int x = 2 * n + half;
-          const int ph = D.phase[rbase + wrap(x - D.sx, NX)];
-          const T lam = lam_s[ph], mu2 = T(2) * mu_s[ph];
-          T ev[S];
-#pragma unroll
-          for (int c = 0; c < S; ++c) ev[c] = half ? ei[c][p] : er[c][p];
-          T tr = ev[0] + ev[1];
-          if constexpr (DIM == 3) tr += ev[2];
-#pragma unroll
-          for (int c = 0; c < S; ++c) {
-            const T sv = mu2 * ev[c] + ((c < DIM) ? lam * tr : T(0));
-            if (half) ei[c][p] = sv; else er[c][p] = sv;
-          }
-        }
-      }
-    }
-    if constexpr (MODE == M_MAT) {
-      if (D.out_sig) {
-#pragma unroll
-        for (int c = 0; c < S; ++c) {
-          T* dst = reinterpret_cast<T*>(D.out_sig) + (long long)c * D.nvox;
-#pragma unroll
-          for (int p = 0; p < PPT; ++p) {
-            const int e = tid + p * NT;
-            const int m = e / H, n = e - (e / H) * H;
-            if (e < MR * H && row0 + m < nrows) {
-              typename C2<T>::type v;
-              v.x = er[c][p];
-              v.y = ei[c][p];
-              reinterpret_cast<typename C2<T>::type*>(dst + (long long)(row0 + m) * NX)[n] = v;
-            }
-          }
-        }
-      }
-      return;
-    } else {
-      // forward transform of each stress component back to the half spectrum
-#pragma unroll
-      for (int c = 0; c < S; ++c) {
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          const int e = tid + p * NT;
-          if (e < MR * H) {
-            const int m = e / H, n = e - (e / H) * H;
-            ar[m * SM + n] = er[c][p];
-            ai[m * SM + n] = ei[c][p];
-          }
-        }
-        __syncthreads();
-        const int where = fft_tile<T, H, -1, MR, SM, 1, 2, NT>(ar, ai, br, bi, twr, twi, tid);
-        fold_r2c_store<T, H, MR, SM>(where ? br : ar, where ? bi : ai, twr, twi,
-                                     static_cast<char*>(D.S) + c * P * cbytes, row0, nrows, nxh, tid);
-        __syncthreads();
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// y pass (3D): complex transforms along y of `ncomp` components of `buf`
-// ---------------------------------------------------------------------------
-template <typename T, int NY, int DIR>
-__device__ void ypass_item(const InstDesc& D, int local, void* buf, int ncomp,
-                           const T* __restrict__ twtab, unsigned char* smem) {
-  using G = StridedGeom<T, NY>;
-  constexpr int MP = G::MP, E = G::ELEMS;
-  T* ar = reinterpret_cast<T*>(smem);
-  T* ai = ar + E;
-  T* br = ai + E;
-  T* bi = br + E;
-  T* twr = bi + E;
-  T* twi = twr + NY;
-  const int tid = threadIdx.x;
-  load_tw<T, NY>(twr, twi, twtab, tid);
-  __syncthreads();
-  const int z = local / D.ntile_y;
-  const int kx0 = (local - z * D.ntile_y) * MP;
-  const int nxh = D.nxh;
-  const long long base = (long long)z * NY * nxh + kx0;
-  const size_t cbytes = sizeof(T) * 2;
-  for (int c = 0; c < ncomp; ++c) {
-    char* cb = static_cast<char*>(buf) + c * D.P * cbytes;
-    for (int e = tid; e < E; e += NT) {
-      const int m = e % MP, n = e / MP;
-      T re = T(0), im = T(0);
-      if (kx0 + m < nxh) {
-        const typename C2<T>::type v = ldc<T>(cb, base + (long long)n * nxh + m);
-        re = v.x;
-        im = v.y;
-      }
-      ar[e] = re;
-      ai[e] = im;
-    }
-    __syncthreads();
-    const int where = fft_tile<T, NY, DIR, MP, 1, MP, 1, NT>(ar, ai, br, bi, twr, twi, tid);
-    const T* rr = where ? br : ar;
-    const T* ri = where ? bi : ai;
-    for (int e = tid; e < E; e += NT) {
-      const int m = e % MP, n = e / MP;
-      if (kx0 + m < nxh) stc<T>(cb, base + (long long)n * nxh + m, rr[e], ri[e]);
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Green / body-force pass along the outermost axis (z in 3D, y in 2D)
-// ---------------------------------------------------------------------------
 
 // N0(xi) v = (v - c0 xi (xi . v) / |xi|^2) / (mu0 |xi|^2); zero where xi = 0
 template <typename T, int DIM>
@@ -439,538 +163,20 @@ __device__ __forceinline__ void apply_n0(const T* xi, T xi2, T c0, T mu0, T* vr,
 }
 
 // Voigt index pairs, (11,22,33,23,13,12) in 3D and (11,22,12) in 2D
-template <int DIM> __device__ __forceinline__ int va(int c) {
+template <int DIM> __host__ __device__ constexpr int va(int c) {
   if constexpr (DIM == 3) return c < 3 ? c : (c == 3 ? 1 : 0);
   else return c < 2 ? c : 0;
 }
-template <int DIM> __device__ __forceinline__ int vb(int c) {
+template <int DIM> __host__ __device__ constexpr int vb(int c) {
   if constexpr (DIM == 3) return c < 3 ? c : (c == 3 ? 2 : (c == 4 ? 2 : 1));
   else return c < 2 ? c : 1;
 }
 
-template <typename T, int NG, int DIM, int MODE>
-__device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int local,
-                           const T* __restrict__ twtab, unsigned char* smem) {
-  using G = StridedGeom<T, NG>;
-  constexpr int MP = G::MP, E = G::ELEMS, PPT = G::PPT;
-  constexpr int S = (DIM == 3) ? 6 : 3;
-  T* ar = reinterpret_cast<T*>(smem);
-  T* ai = ar + E;
-  T* br = ai + E;
-  T* bi = br + E;
-  T* twr = bi + E;
-  T* twi = twr + NG;
-  double* red = reinterpret_cast<double*>(twi + NG + (NG & 1));
-  const int tid = threadIdx.x;
-  load_tw<T, NG>(twr, twi, twtab, tid);
-  __syncthreads();
-
-  const int nxh = D.nxh;
-  int ymid = 0, tile;
-  long long stride, base;
-  if constexpr (DIM == 3) {
-    ymid = local / D.ntile_g;
-    tile = local - ymid * D.ntile_g;
-    stride = (long long)D.ny * nxh;
-    base = (long long)ymid * nxh + tile * MP;
-  } else {
-    tile = local;
-    stride = nxh;
-    base = (long long)tile * MP;
-  }
-  const int kx0 = tile * MP;
-  const size_t cbytes = sizeof(T) * 2;
-  const long long P = D.P;
-  const T inv_n = T(D.inv_nvox);
-  const T mu0 = T(D.mu0);
-  const T c0 = T((D.lam0 + D.mu0) / (D.lam0 + 2.0 * D.mu0));
-
-  // this thread's points: e = tid + p * NT, pencil m = e % MP, index n = e / MP
-  T vr[DIM][PPT], vi[DIM][PPT];
-  double part = 0.0, part2 = 0.0;
-
-  auto point_xi = [&](int p, T* xi, T& xi2, bool& valid, long long& gidx, T& wgt, int& n) {
-    const int e = tid + p * NT;
-    const int m = e % MP;
-    n = e / MP;
-    const int kx = kx0 + m;
-    valid = (e < E) && (kx < nxh);
-    xi[0] = T(wavenum(kx, D.nx, D.kx));
-    if constexpr (DIM == 3) {
-      xi[1] = T(wavenum(ymid, D.ny, D.ky));
-      xi[2] = T(wavenum(n, D.nz, D.kz));
-    } else {
-      xi[1] = T(wavenum(n, D.ny, D.ky));
-    }
-    xi2 = T(0);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) xi2 += xi[a] * xi[a];
-    gidx = base + (long long)n * stride + m;
-    wgt = (kx == 0 || kx == (D.nx >> 1)) ? T(1) : T(2);
-  };
-
-  // forward transform of NC components of `src` along the outer axis; calls
-  // fn(c, p, re, im) for every point of this thread (c is a compile-time
-  // constant after unrolling, so register arrays stay in registers)
-  auto forward = [&](const void* src, auto nc_tag, auto&& fn) {
-    constexpr int NC = decltype(nc_tag)::value;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const char* cb = static_cast<const char*>(src) + c * P * cbytes;
-      for (int e = tid; e < E; e += NT) {
-        const int m = e % MP, n = e / MP;
-        T re = T(0), im = T(0);
-        if (kx0 + m < nxh) {
-          const typename C2<T>::type v = ldc<T>(cb, base + (long long)n * stride + m);
-          re = v.x;
-          im = v.y;
-        }
-        ar[e] = re;
-        ai[e] = im;
-      }
-      __syncthreads();
-      const int where = fft_tile<T, NG, -1, MP, 1, MP, 1, NT>(ar, ai, br, bi, twr, twi, tid);
-      const T* rr = where ? br : ar;
-      const T* ri = where ? bi : ai;
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        const int e = tid + p * NT;
-        if (e < E) fn(c, p, rr[e], ri[e]);
-      }
-      __syncthreads();
-    }
-  };
-
-  // inverse transform of values produced per point by gen(c, p, re&, im&)
-  // into NC components of `dst`
-  auto inverse = [&](void* dst, auto nc_tag, auto&& gen) {
-    constexpr int NC = decltype(nc_tag)::value;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        const int e = tid + p * NT;
-        if (e < E) {
-          T re, im;
-          gen(c, p, re, im);
-          ar[e] = re;
-          ai[e] = im;
-        }
-      }
-      __syncthreads();
-      const int where = fft_tile<T, NG, +1, MP, 1, MP, 1, NT>(ar, ai, br, bi, twr, twi, tid);
-      const T* rr = where ? br : ar;
-      const T* ri = where ? bi : ai;
-      char* cb = static_cast<char*>(dst) + c * P * cbytes;
-      for (int e = tid; e < E; e += NT) {
-        const int m = e % MP, n = e / MP;
-        if (kx0 + m < nxh) stc<T>(cb, base + (long long)n * stride + m, rr[e], ri[e]);
-      }
-      __syncthreads();
-    }
-  };
-
-  // strain spectrum / |N| from the displacement spectrum held in vr/vi:
-  // eps^_ab = (i/2)(xi_a u^_b + xi_b u^_a)
-  auto strain_gen = [&](int c, int p, T& re, T& im) {
-    T xi[DIM], xi2, wgt;
-    bool valid;
-    long long gidx;
-    int n;
-    point_xi(p, xi, xi2, valid, gidx, wgt, n);
-    const int a = va<DIM>(c), b = vb<DIM>(c);
-    // i/2 (xi_a u_b + xi_b u_a) = (-(xi_a ub.i + xi_b ua.i)/2, (xi_a ub.r + xi_b ua.r)/2)
-    const T sr = T(0.5) * (xi[a] * vr[b][p] + xi[b] * vr[a][p]);
-    const T si = T(0.5) * (xi[a] * vi[b][p] + xi[b] * vi[a][p]);
-    re = -si * inv_n;
-    im = sr * inv_n;
-  };
-
-  const int cur = St->iter & 1;
-
-  if constexpr (MODE == M_FT) {
-    // finish the force transform, record the removed mean, project off Z
-    forward(D.F, std::integral_constant<int, DIM>{}, [&](int c, int p, T re, T im) { vr[c][p] = re; vi[c][p] = im; });
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      T xi[DIM], xi2, wgt;
-      bool valid;
-      long long gidx;
-      int n;
-      point_xi(p, xi, xi2, valid, gidx, wgt, n);
-      if (!valid) continue;
-      const bool origin = (kx0 + (tid + p * NT) % MP == 0) && n == 0 && (DIM == 2 || ymid == 0);
-#pragma unroll
-      for (int c = 0; c < DIM; ++c) {
-        if (origin) St->removed_mean[c] = double(vr[c][p]) * D.inv_nvox;
-        if (xi2 == T(0)) { vr[c][p] = T(0); vi[c][p] = T(0); }
-        stc<T>(static_cast<char*>(D.F) + c * P * cbytes, gidx, vr[c][p], vi[c][p]);
-      }
-    }
-    return;
-  } else if constexpr (MODE == M_INIT || MODE == M_ITER || MODE == M_CG_INIT) {
-    if constexpr (MODE == M_INIT) {
-#pragma unroll
-      for (int p = 0; p < PPT; ++p)
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) { vr[a][p] = T(0); vi[a][p] = T(0); }
-    } else {
-      // residual r = i xi . sigma^ accumulated component by component
-#pragma unroll
-      for (int p = 0; p < PPT; ++p)
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) { vr[a][p] = T(0); vi[a][p] = T(0); }
-      forward(D.S, std::integral_constant<int, S>{}, [&](int c, int p, T re, T im) {
-        T xi[DIM], xi2, wgt;
-        bool valid;
-        long long gidx;
-        int n;
-        point_xi(p, xi, xi2, valid, gidx, wgt, n);
-        const int a = va<DIM>(c), b = vb<DIM>(c);
-        // i xi_b s -> (-xi_b im, xi_b re)
-        vr[a][p] -= xi[b] * im;
-        vi[a][p] += xi[b] * re;
-        if (a != b) {
-          vr[b][p] -= xi[a] * im;
-          vi[b][p] += xi[a] * re;
-        }
-      });
-    }
-    // + f^ (already projected off Z), Parseval partial, update
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      T xi[DIM], xi2, wgt;
-      bool valid;
-      long long gidx;
-      int n;
-      point_xi(p, xi, xi2, valid, gidx, wgt, n);
-      if (!valid) {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) { vr[a][p] = T(0); vi[a][p] = T(0); }
-        continue;
-      }
-      T ur[DIM], ui[DIM];
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const typename C2<T>::type f = ldc<T>(static_cast<const char*>(D.F) + a * P * cbytes, gidx);
-        vr[a][p] += f.x;
-        vi[a][p] += f.y;
-        part += double(wgt) * (double(vr[a][p]) * double(vr[a][p]) + double(vi[a][p]) * double(vi[a][p]));
-        ur[a] = vr[a][p];
-        ui[a] = vi[a][p];
-      }
-      apply_n0<T, DIM>(xi, xi2, c0, mu0, ur, ui);   // N0 r
-      if constexpr (MODE == M_CG_INIT) {
-        // r0 stored, z0 = N0 r0 = p0 stored, r.z partial; p0 drives the next
-        // operator application
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          stc<T>(static_cast<char*>(D.R) + a * P * cbytes, gidx, vr[a][p], vi[a][p]);
-          stc<T>(static_cast<char*>(D.Pd) + a * P * cbytes, gidx, ur[a], ui[a]);
-          part2 += double(wgt) * (double(vr[a][p]) * double(ur[a]) + double(vi[a][p]) * double(ui[a]));
-          vr[a][p] = ur[a];
-          vi[a][p] = ui[a];
-        }
-      } else {
-        const void* uin = D.U[cur];
-        void* uout = (MODE == M_INIT) ? D.U[0] : D.U[cur ^ 1];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          T nr = ur[a], ni = ui[a];
-          if constexpr (MODE == M_ITER) {
-            const typename C2<T>::type u0 = ldc<T>(static_cast<const char*>(uin) + a * P * cbytes, gidx);
-            nr += u0.x;
-            ni += u0.y;
-          }
-          stc<T>(static_cast<char*>(uout) + a * P * cbytes, gidx, nr, ni);
-          vr[a][p] = nr;
-          vi[a][p] = ni;
-        }
-      }
-    }
-    // next strain spectrum and its inverse transform
-    inverse(D.S, std::integral_constant<int, S>{}, strain_gen);
-  } else if constexpr (MODE == M_MAT) {
-    const void* uin = D.U[cur];
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      T xi[DIM], xi2, wgt;
-      bool valid;
-      long long gidx;
-      int n;
-      point_xi(p, xi, xi2, valid, gidx, wgt, n);
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        T re = T(0), im = T(0);
-        if (valid) {
-          const typename C2<T>::type u0 = ldc<T>(static_cast<const char*>(uin) + a * P * cbytes, gidx);
-          re = u0.x;
-          im = u0.y;
-        }
-        vr[a][p] = re;
-        vi[a][p] = im;
-      }
-    }
-    inverse(D.S, std::integral_constant<int, S>{}, strain_gen);
-    inverse(static_cast<char*>(D.S) + S * P * cbytes, std::integral_constant<int, DIM>{}, [&](int c, int p, T& re, T& im) {
-      re = vr[c][p] * inv_n;
-      im = vi[c][p] * inv_n;
-    });
-    return;
-  } else if constexpr (MODE == M_CG_AP) {
-    // q = A p = -i xi . sigma^(p): stored, and the partial p.q
-#pragma unroll
-    for (int p = 0; p < PPT; ++p)
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) { vr[a][p] = T(0); vi[a][p] = T(0); }
-    forward(D.S, std::integral_constant<int, S>{}, [&](int c, int p, T re, T im) {
-      T xi[DIM], xi2, wgt;
-      bool valid;
-      long long gidx;
-      int n;
-      point_xi(p, xi, xi2, valid, gidx, wgt, n);
-      const int a = va<DIM>(c), b = vb<DIM>(c);
-      // -i xi_b s -> (xi_b im, -xi_b re)
-      vr[a][p] += xi[b] * im;
-      vi[a][p] -= xi[b] * re;
-      if (a != b) {
-        vr[b][p] += xi[a] * im;
-        vi[b][p] -= xi[a] * re;
-      }
-    });
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      T xi[DIM], xi2, wgt;
-      bool valid;
-      long long gidx;
-      int n;
-      point_xi(p, xi, xi2, valid, gidx, wgt, n);
-      if (!valid) continue;
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const typename C2<T>::type pd = ldc<T>(static_cast<const char*>(D.Pd) + a * P * cbytes, gidx);
-        stc<T>(static_cast<char*>(D.Q) + a * P * cbytes, gidx, vr[a][p], vi[a][p]);
-        part += double(wgt) * (double(pd.x) * double(vr[a][p]) + double(pd.y) * double(vi[a][p]));
-      }
-    }
-  } else if constexpr (MODE == M_CG_DIR) {
-    // p = N0 r + beta p, stored, then eps^(p) / |N| and its inverse transform
-    const T beta = T(St->beta);
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      T xi[DIM], xi2, wgt;
-      bool valid;
-      long long gidx;
-      int n;
-      point_xi(p, xi, xi2, valid, gidx, wgt, n);
-      if (!valid) {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) { vr[a][p] = T(0); vi[a][p] = T(0); }
-        continue;
-      }
-      T zr[DIM], zi[DIM];
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const typename C2<T>::type r = ldc<T>(static_cast<const char*>(D.R) + a * P * cbytes, gidx);
-        zr[a] = r.x;
-        zi[a] = r.y;
-      }
-      apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const typename C2<T>::type pd = ldc<T>(static_cast<const char*>(D.Pd) + a * P * cbytes, gidx);
-        const T nr = zr[a] + beta * pd.x, ni = zi[a] + beta * pd.y;
-        stc<T>(static_cast<char*>(D.Pd) + a * P * cbytes, gidx, nr, ni);
-        vr[a][p] = nr;
-        vi[a][p] = ni;
-      }
-    }
-    inverse(D.S, std::integral_constant<int, S>{}, strain_gen);
-  }
-
-  // FP64 partial sums of this item, one slot per item (fixed order later)
-  if constexpr (MODE == M_INIT || MODE == M_ITER || MODE == M_CG_INIT || MODE == M_CG_AP) {
-    const double s1 = block_sum(part, red);
-    if constexpr (MODE == M_CG_INIT) {
-      const double s2 = block_sum(part2, red);
-      if (tid == 0) {
-        D.partial[2 * local] = s1;
-        D.partial[2 * local + 1] = s2;
-      }
-    } else {
-      if (tid == 0) D.partial[2 * local] = s1;
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// CG pointwise update: u += alpha p, r -= alpha q, partials r.z and r.r
+// stopping rule and the fused FP64 reduction
 // ---------------------------------------------------------------------------
-template <typename T, int DIM>
-__device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsigned char* smem) {
-  // one item = NT * 4 consecutive half-spectrum points
-  const int tid = threadIdx.x;
-  double* red = reinterpret_cast<double*>(smem);
-  const T alpha = T(St->alpha);
-  const T mu0 = T(D.mu0);
-  const T c0 = T((D.lam0 + D.mu0) / (D.lam0 + 2.0 * D.mu0));
-  const size_t cbytes = sizeof(T) * 2;
-  const long long P = D.P;
-  double prz = 0.0, prr = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    const long long g = (long long)local * NT * 4 + q * NT + tid;
-    if (g >= P) break;
-    const int kx = int(g % D.nxh);
-    const long long rest = g / D.nxh;
-    T xi[DIM];
-    xi[0] = T(wavenum(kx, D.nx, D.kx));
-    if constexpr (DIM == 3) {
-      xi[1] = T(wavenum(int(rest % D.ny), D.ny, D.ky));
-      xi[2] = T(wavenum(int(rest / D.ny), D.nz, D.kz));
-    } else {
-      xi[1] = T(wavenum(int(rest), D.ny, D.ky));
-    }
-    T xi2 = T(0);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) xi2 += xi[a] * xi[a];
-    const double wgt = (kx == 0 || kx == (D.nx >> 1)) ? 1.0 : 2.0;
-    T rr[DIM], ri[DIM];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const typename C2<T>::type u = ldc<T>(static_cast<const char*>(D.U[0]) + a * P * cbytes, g);
-      const typename C2<T>::type pd = ldc<T>(static_cast<const char*>(D.Pd) + a * P * cbytes, g);
-      const typename C2<T>::type r = ldc<T>(static_cast<const char*>(D.R) + a * P * cbytes, g);
-      const typename C2<T>::type qv = ldc<T>(static_cast<const char*>(D.Q) + a * P * cbytes, g);
-      stc<T>(static_cast<char*>(D.U[0]) + a * P * cbytes, g, u.x + alpha * pd.x, u.y + alpha * pd.y);
-      rr[a] = r.x - alpha * qv.x;
-      ri[a] = r.y - alpha * qv.y;
-      stc<T>(static_cast<char*>(D.R) + a * P * cbytes, g, rr[a], ri[a]);
-      prr += wgt * (double(rr[a]) * double(rr[a]) + double(ri[a]) * double(ri[a]));
-    }
-    T zr[DIM], zi[DIM];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) { zr[a] = rr[a]; zi[a] = ri[a]; }
-    apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) prz += wgt * (double(rr[a]) * double(zr[a]) + double(ri[a]) * double(zi[a]));
-  }
-  const double s1 = block_sum(prz, red);
-  const double s2 = block_sum(prr, red);
-  if (tid == 0) {
-    D.partial[2 * local] = s1;
-    D.partial[2 * local + 1] = s2;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// kernels
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool gated(int mode) {
-  return mode == M_ITER || mode == M_CG_AP || mode == M_CG_UPD || mode == M_CG_DIR || mode == M_CG_INIT;
-}
-
-#define LSFFT_LEN_CASES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void k_xpass(const InstDesc* __restrict__ descs, InstState* __restrict__ states,
-                                              const WorkItem* __restrict__ items, const int* __restrict__ nitems,
-                                              const double* __restrict__ lame, const T* __restrict__ tw) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int n_items = *nitems;
-  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
-    const WorkItem it = items[w];
-    const InstDesc& D = descs[it.inst];
-    if (gated(MODE) && states[it.inst].status != ST_RUNNING) continue;
-    if (D.dim == 3) {
-      switch (D.nx) {
-#define X(L) case L: xpass_item<T, L, 3, MODE>(D, it.local, lame, tw, smem); break;
-        LSFFT_LEN_CASES(X)
-#undef X
-        default: break;
-      }
-    } else {
-      switch (D.nx) {
-#define X(L) case L: xpass_item<T, L, 2, MODE>(D, it.local, lame, tw, smem); break;
-        LSFFT_LEN_CASES(X)
-#undef X
-        default: break;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-template <typename T, int DIR>
-__global__ __launch_bounds__(NT) void k_ypass(const InstDesc* __restrict__ descs, InstState* __restrict__ states,
-                                              const WorkItem* __restrict__ items, const int* __restrict__ nitems,
-                                              const T* __restrict__ tw, int which, int ncomp_extra, int gate) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int n_items = *nitems;
-  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
-    const WorkItem it = items[w];
-    const InstDesc& D = descs[it.inst];
-    if (gate && states[it.inst].status != ST_RUNNING) continue;
-    void* buf = (which == 0) ? D.S : D.F;
-    const int ncomp = (which == 0) ? D.ncomp_s + ncomp_extra : D.dim;
-    switch (D.ny) {
-#define X(L) case L: ypass_item<T, L, DIR>(D, it.local, buf, ncomp, tw, smem); break;
-      LSFFT_LEN_CASES(X)
-#undef X
-      default: break;
-    }
-    __syncthreads();
-  }
-}
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void k_green(const InstDesc* __restrict__ descs, InstState* __restrict__ states,
-                                              const WorkItem* __restrict__ items, const int* __restrict__ nitems,
-                                              const T* __restrict__ tw) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int n_items = *nitems;
-  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
-    const WorkItem it = items[w];
-    const InstDesc& D = descs[it.inst];
-    InstState* St = states + it.inst;
-    if (gated(MODE) && St->status != ST_RUNNING) continue;
-    if (D.dim == 3) {
-      switch (D.nz) {
-#define X(L) case L: green_item<T, L, 3, MODE>(D, St, it.local, tw, smem); break;
-        LSFFT_LEN_CASES(X)
-#undef X
-        default: break;
-      }
-    } else {
-      switch (D.ny) {
-#define X(L) case L: green_item<T, L, 2, MODE>(D, St, it.local, tw, smem); break;
-        LSFFT_LEN_CASES(X)
-#undef X
-        default: break;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(NT) void k_cg_update(const InstDesc* __restrict__ descs, InstState* __restrict__ states,
-                                                  const WorkItem* __restrict__ items, const int* __restrict__ nitems) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int n_items = *nitems;
-  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
-    const WorkItem it = items[w];
-    const InstDesc& D = descs[it.inst];
-    InstState* St = states + it.inst;
-    if (St->status != ST_RUNNING) continue;
-    if (D.dim == 3) cg_update_item<T, 3>(D, St, it.local, smem);
-    else cg_update_item<T, 2>(D, St, it.local, smem);
-    __syncthreads();
-  }
-}
-
-#ifdef LSFFT_MISC_TU
-// Stopping rule and lifecycle of one solve after a residual evaluation.
-__device__ void judge(const InstDesc& D, InstState& St, double delta) {
+// Lifecycle of one solve after a residual evaluation (basic scheme).
+__device__ inline void judge(const InstDesc& D, InstState& St, double delta) {
   St.residual = delta;
   if (D.history) D.history[St.iter] = delta;
   if (!(delta == delta) || delta > 1e300) { St.status = ST_DIVERGED; return; }
@@ -989,24 +195,8 @@ __device__ void judge(const InstDesc& D, InstState& St, double delta) {
   St.iter += 1;
 }
 
-// One block per solve: fixed-order FP64 sums of the per-item partials.
-__global__ __launch_bounds__(NT) void k_reduce(const InstDesc* __restrict__ descs, InstState* __restrict__ states,
-                                               const int* __restrict__ inst_list, int ninst, int mode) {
-  __shared__ double red[NT / 64];
-  if ((int)blockIdx.x >= ninst) return;
-  const int i = inst_list[blockIdx.x];
-  const InstDesc& D = descs[i];
-  InstState& St = states[i];
-  if (mode != M_INIT && St.status != ST_RUNNING) return;
-  const int nslot = (mode == M_CG_UPD) ? (int)((D.P + NT * 4 - 1) / (NT * 4)) : D.items_g;
-  double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < nslot; k += NT) {
-    a += D.partial[2 * k];
-    if (mode == M_CG_INIT || mode == M_CG_UPD) b += D.partial[2 * k + 1];
-  }
-  a = block_sum(a, red);
-  b = block_sum(b, red);
-  if (threadIdx.x != 0) return;
+// Apply the totals (a, b) of a launch's partial sums to the solve's state.
+__device__ inline void finalize(const InstDesc& D, InstState& St, int mode, double a, double b) {
   if (mode == M_INIT) {
     St.fnorm2 = a;
     St.iter = 0;
@@ -1038,7 +228,6 @@ __global__ __launch_bounds__(NT) void k_reduce(const InstDesc* __restrict__ desc
     const double rz_new = a;
     St.beta = rz_new / St.rz;
     St.rz = rz_new;
-    // the update produced iterate iter + 1
     St.iter += 1;
     const double delta = sqrt(b / St.fnorm2);
     St.residual = delta;
@@ -1057,36 +246,1014 @@ __global__ __launch_bounds__(NT) void k_reduce(const InstDesc* __restrict__ desc
   }
 }
 
-// Largest phase id of each solve's map (argument validation on the device).
-__global__ __launch_bounds__(NT) void k_phase_max(const uint8_t* __restrict__ phase, long long n, int* __restrict__ out) {
-  __shared__ int red[NT];
+// ---------------------------------------------------------------------------
+// x pass
+// ---------------------------------------------------------------------------
+// Row block of MR rows (row = z * ny + y).  Per component: the H + 1 half
+// spectrum entries of each row (H from the main block, the last from the
+// Nyquist plane) are staged in LDS; the fold
+//   Z'[k] = (X[k] + conj X[H-k]) + i exp(+2 pi i k / NX) (X[k] - conj X[H-k])
+// feeds a length-H inverse transform whose output is NX (a[2n] + i a[2n+1]);
+// the forward direction is the mirror image:
+//   X[k] = E + exp(-2 pi i k / NX) O, E = (Z[k] + conj Z[H-k]) / 2,
+//   O = -i (Z[k] - conj Z[H-k]) / 2.
+template <typename T, int NX, int DIM, int MODE>
+__device__ void xpass_item(const InstDesc& D, int local, const double* __restrict__ lame,
+                           const T* __restrict__ twtab, unsigned char* smem) {
+  constexpr int NTH = Cfg<T>::NTH;
+  constexpr int H = NX / 2;
+  using G = XGeom<T, H>;
+  constexpr int MR = G::MR, SM = G::SM, SM2 = G::SM2;
+  constexpr int S = (DIM == 3) ? 6 : 3;
+  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH>;   // C2R core
+  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH>;  // R2C core
+  static_assert(FI::RL == FF::R0 && FI::BL == FF::B0, "x transforms must chain in registers");
+  constexpr int BP = FI::BL, RP = FI::RL;          // points held per thread: BP x RP
+  constexpr int TOTP = FI::TOTL;
+
+  T* ar = reinterpret_cast<T*>(smem);              // fold tile MR x SM
+  T* ai = ar + MR * SM;
+  T* br = ai + MR * SM;                            // transform staging MR x SM2
+  T* bi = br + MR * SM2;
+  T* twr = bi + MR * SM2;
+  T* twi = twr + NX;
+  T* lam_s = twi + NX;
+  T* mu_s = lam_s + kMaxPhases;
+  const int tid = threadIdx.x;
+  load_tw<T, NX, NTH>(twr, twi, twtab, tid);
+  if constexpr (MODE != M_FT) {
+    for (int p = tid; p < D.nphase; p += NTH) {
+      lam_s[p] = T(lame[2 * (D.lame_off + p)]);
+      mu_s[p] = T(lame[2 * (D.lame_off + p) + 1]);
+    }
+  }
+  __syncthreads();
+  const int nrows = D.ny * D.nz;
+  // work item = (row tile, part): the part selects the component group, so
+  // independent components of one row block run in parallel workgroups
+  const int part = local / D.xtiles;
+  const int row0 = (local - part * D.xtiles) * MR;
+  const long long Pm = D.Pm, Pc = D.Pc;
+
+  // forward core on registers `in` (positions j + r H/R0 of butterfly tid + q NTH),
+  // then unfold through LDS and store component c of `dst`
+  auto forward_store = [&](T (&in_r)[FF::B0][FF::R0], T (&in_i)[FF::B0][FF::R0], void* dst, int c) {
+    T o_r[FF::BL][FF::RL], o_i[FF::BL][FF::RL];
+    __syncthreads();   // staging buffer free
+    FF::run(in_r, in_i, o_r, o_i, br, bi, twr, twi, tid);
+    __syncthreads();   // previous users of the fold tile are done
+#pragma unroll
+    for (int q = 0; q < FF::BL; ++q) {
+      const int b = tid + q * NTH;
+      if (FF::TOTL % NTH == 0 || b < FF::TOTL) {
+        int m, j;
+        FF::template bj<FF::RL>(b, m, j);
+#pragma unroll
+        for (int r = 0; r < FF::RL; ++r) {
+          const int n = j + r * (H / FF::RL);
+          ar[m * SM + n] = o_r[q][r];
+          ai[m * SM + n] = o_i[q][r];
+        }
+      }
+    }
+    __syncthreads();
+    char* base = mptr<T>(dst, Pc, c);
+    for (int e = tid; e < MR * (H + 1); e += NTH) {
+      const int m = e / (H + 1);
+      const int k = e - m * (H + 1);
+      const int row = row0 + m;
+      if (row >= nrows) continue;
+      const int k1 = (k == H) ? 0 : k;
+      const int k2 = (k == 0) ? 0 : H - k;
+      const T zr = ar[m * SM + k1], zi = ai[m * SM + k1];
+      const T wr = ar[m * SM + k2], wi = ai[m * SM + k2];
+      const T er = T(0.5) * (zr + wr), ei = T(0.5) * (zi - wi);
+      const T dr = T(0.5) * (zr - wr), di = T(0.5) * (zi + wi);
+      const T orr = di, oi = -dr;
+      const T cr = twr[k], ci = twi[k];
+      const T xr = er + cr * orr - ci * oi, xi = ei + cr * oi + ci * orr;
+      if (k < H) stc<T>(base, row * H + k, xr, xi);
+      else stc<T>(base, (int)Pm + row, xr, xi);
+    }
+  };
+
+  if constexpr (MODE == M_FT) {
+    // real force rows -> half spectrum of F, component `part`
+    {
+      const int c = part;
+      const T* src = reinterpret_cast<const T*>(D.f_in) + (long long)c * D.nvox;
+      T in_r[FF::B0][FF::R0], in_i[FF::B0][FF::R0];
+#pragma unroll
+      for (int q = 0; q < FF::B0; ++q) {
+        const int b = tid + q * NTH;
+        int m, j;
+        FF::template bj<FF::R0>(b, m, j);
+        const bool ok = (FF::TOT0 % NTH == 0 || b < FF::TOT0) && row0 + m < nrows;
+#pragma unroll
+        for (int r = 0; r < FF::R0; ++r) {
+          const int n = j + r * (H / FF::R0);
+          T re = T(0), im = T(0);
+          if (ok) {
+            const typename C2<T>::type v =
+                reinterpret_cast<const typename C2<T>::type*>(src + (row0 + m) * NX)[n];
+            re = v.x;
+            im = v.y;
+          }
+          in_r[q][r] = re;
+          in_i[q][r] = im;
+        }
+      }
+      forward_store(in_r, in_i, D.F, c);
+    }
+    return;
+  } else {
+    // C2R of component c of S into registers (real pairs at x = 2n, 2n + 1)
+    auto c2r = [&](int c, T (&o_r)[BP][RP], T (&o_i)[BP][RP]) {
+      const char* src = cptr<T>(D.S, Pc, c);
+      __syncthreads();   // fold tile and staging free
+      for (int e = tid; e < MR * (H + 1); e += NTH) {
+        const int m = e / (H + 1);
+        const int k = e - m * (H + 1);
+        const int row = row0 + m;
+        T re = T(0), im = T(0);
+        if (row < nrows) {
+          const typename C2<T>::type v = (k < H) ? ldc<T>(src, row * H + k) : ldc<T>(src, (int)Pm + row);
+          re = v.x;
+          im = v.y;
+        }
+        ar[m * SM + k] = re;
+        ai[m * SM + k] = im;
+      }
+      __syncthreads();
+      T in_r[FI::B0][FI::R0], in_i[FI::B0][FI::R0];
+#pragma unroll
+      for (int q = 0; q < FI::B0; ++q) {
+        const int b = tid + q * NTH;
+        int m, j;
+        FI::template bj<FI::R0>(b, m, j);
+        if (FI::TOT0 % NTH != 0 && b >= FI::TOT0) m = 0;
+#pragma unroll
+        for (int r = 0; r < FI::R0; ++r) {
+          const int k = j + r * (H / FI::R0);
+          const T xr = ar[m * SM + k], xi = ai[m * SM + k];
+          const T yr = ar[m * SM + (H - k)], yi = -ai[m * SM + (H - k)];
+          const T dr = xr - yr, di = xi - yi;
+          const T cr = twr[k], ci = -twi[k];
+          const T tr = cr * dr - ci * di, ti = cr * di + ci * dr;
+          in_r[q][r] = xr + yr - ti;
+          in_i[q][r] = xi + yi + tr;
+        }
+      }
+      FI::run(in_r, in_i, o_r, o_i, br, bi, twr, twi, tid);
+    };
+    // write real pairs held in registers to component c of a real field
+    auto write_real = [&](void* field, int c, const T (&v_r)[BP][RP], const T (&v_i)[BP][RP]) {
+      T* dst = reinterpret_cast<T*>(field) + (long long)c * D.nvox;
+#pragma unroll
+      for (int q = 0; q < BP; ++q) {
+        const int b = tid + q * NTH;
+        int m, j;
+        FI::template bj<RP>(b, m, j);
+        if ((TOTP % NTH == 0 || b < TOTP) && row0 + m < nrows) {
+#pragma unroll
+          for (int r = 0; r < RP; ++r) {
+            const int n = j + r * (H / RP);
+            typename C2<T>::type v;
+            v.x = v_r[q][r];
+            v.y = v_i[q][r];
+            reinterpret_cast<typename C2<T>::type*>(dst + (row0 + m) * NX)[n] = v;
+          }
+        }
+      }
+    };
+    // phase id of the microstructure shifted by s, at real index x of a row
+    auto phase_at = [&](int row, int x) -> int {
+      const int z = row / D.ny, y = row - (row / D.ny) * D.ny;
+      const int rbase = (wrap(z - D.sz, D.nz) * D.ny + wrap(y - D.sy, D.ny)) * NX;
+      return D.phase[rbase + ((D.sx == 0) ? x : wrap(x - D.sx, NX))];
+    };
+    // apply fn(point value&, lam, mu, half) at every point of this thread
+    auto each_point = [&](auto&& fn) {
+#pragma unroll
+      for (int q = 0; q < BP; ++q) {
+        const int b = tid + q * NTH;
+        int m, j;
+        FI::template bj<RP>(b, m, j);
+        const int row = row0 + m;
+        if ((TOTP % NTH == 0 || b < TOTP) && row < nrows) {
+#pragma unroll
+          for (int r = 0; r < RP; ++r) {
+            const int n = j + r * (H / RP);
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+              const int ph = phase_at(row, 2 * n + half);
+              fn(q, r, half, lam_s[ph], mu_s[ph]);
+            }
+          }
+        }
+      }
+    };
+
+    if (part >= 1 && part <= S - DIM) {
+      // shear component: sigma_ab = 2 mu eps_ab
+      const int c = DIM + part - 1;
+      T e_r[BP][RP], e_i[BP][RP];
+      c2r(c, e_r, e_i);
+      if constexpr (MODE == M_MAT) {
+        if (D.out_eps) write_real(D.out_eps, c, e_r, e_i);
+      }
+      each_point([&](int q, int r, int half, T lam, T mu) {
+        if (half) e_i[q][r] *= T(2) * mu; else e_r[q][r] *= T(2) * mu;
+      });
+      if constexpr (MODE == M_MAT) {
+        if (D.out_sig) write_real(D.out_sig, c, e_r, e_i);
+      } else {
+        forward_store(e_r, e_i, D.S, c);
+      }
+      return;
+    }
+    if constexpr (MODE == M_MAT) {
+      if (part > S - DIM) {
+        // displacement component, written straight out
+        const int c = part - (S - DIM) - 1;
+        if (D.out_u) {
+          T e_r[BP][RP], e_i[BP][RP];
+          c2r(S + c, e_r, e_i);
+          write_real(D.out_u, c, e_r, e_i);
+        }
+        return;
+      }
+    }
+    // part 0: normal components, coupled through the trace
+    T n_r[DIM][BP][RP], n_i[DIM][BP][RP];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) c2r(c, n_r[c], n_i[c]);
+    if constexpr (MODE == M_MAT) {
+      if (D.out_eps) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) write_real(D.out_eps, c, n_r[c], n_i[c]);
+      }
+    }
+    each_point([&](int q, int r, int half, T lam, T mu) {
+      T ev[DIM];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) ev[c] = half ? n_i[c][q][r] : n_r[c][q][r];
+      T tr = T(0);
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) tr += ev[c];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        const T sv = T(2) * mu * ev[c] + lam * tr;
+        if (half) n_i[c][q][r] = sv; else n_r[c][q][r] = sv;
+      }
+    });
+    if constexpr (MODE == M_MAT) {
+      if (D.out_sig) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) write_real(D.out_sig, c, n_r[c], n_i[c]);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) forward_store(n_r[c], n_i[c], D.S, c);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// strided tiles (y pass and outer pass)
+// ---------------------------------------------------------------------------
+// A tile is MP pencils of length N.  Main tiles take mpk consecutive kx
+// columns times MP / mpk consecutive lines of the other axis; Nyquist tiles
+// take MP consecutive lines of the Nyquist plane.  Element (m, n) of
+// component c lives at c Pc + off(m) + n sn.
+struct TileAddr {
+  int sn;              // stride along the pencil (elements)
+  int base;            // offset of pencil 0 within a component
+  int so;              // stride between lines of the other axis
+  int mpk, lg;         // kx pencils per line (power of 2), log2
+  int kx0, o0, nother; // first kx, first line, lines in the grid
+  bool nyq;
+  int H;
+  __device__ __forceinline__ int off(int m) const {
+    if (nyq) return base + m * so;
+    return base + (m >> lg) * so + (m & (mpk - 1));
+  }
+  __device__ __forceinline__ bool valid(int m) const {
+    if (nyq) return o0 + m < nother;
+    return o0 + (m >> lg) < nother;
+  }
+  __device__ __forceinline__ int kx(int m) const { return nyq ? H : kx0 + (m & (mpk - 1)); }
+  __device__ __forceinline__ int other(int m) const { return nyq ? o0 + m : o0 + (m >> lg); }
+};
+
+// y pass (3D): pencils along y; other axis = z.
+__device__ __forceinline__ TileAddr ytile(const InstDesc& D, int local, int MP) {
+  TileAddr t;
+  t.H = D.H;
+  if (local < D.ymain) {
+    const int per = MP >> D.lg_y;                    // z lines per tile
+    const int tz = local / D.ntk_y, tk = local - (local / D.ntk_y) * D.ntk_y;
+    t.nyq = false;
+    t.mpk = D.mpk_y;
+    t.lg = D.lg_y;
+    t.kx0 = tk * D.mpk_y;
+    t.o0 = tz * per;
+    t.nother = D.nz;
+    t.sn = D.H;
+    t.so = D.ny * D.H;
+    t.base = t.o0 * t.so + t.kx0;
+  } else {
+    const int tn = local - D.ymain;
+    t.nyq = true;
+    t.mpk = 1;
+    t.lg = 0;
+    t.kx0 = D.H;
+    t.o0 = tn * MP;
+    t.nother = D.nz;
+    t.sn = 1;
+    t.so = D.ny;
+    t.base = (int)D.Pm + t.o0 * D.ny;
+  }
+  return t;
+}
+
+// outer pass: pencils along z (3D, other axis y) or y (2D, no other axis)
+template <int DIM>
+__device__ __forceinline__ TileAddr gtile(const InstDesc& D, int local, int MP) {
+  TileAddr t;
+  t.H = D.H;
+  if (local < D.gmain) {
+    t.nyq = false;
+    t.mpk = D.mpk_g;
+    t.lg = D.lg_g;
+    if constexpr (DIM == 3) {
+      const int per = MP >> D.lg_g;
+      const int ty = local / D.ntk_g, tk = local - (local / D.ntk_g) * D.ntk_g;
+      t.kx0 = tk * D.mpk_g;
+      t.o0 = ty * per;
+      t.nother = D.ny;
+      t.sn = D.ny * D.H;
+      t.so = D.H;
+      t.base = t.o0 * D.H + t.kx0;
+    } else {
+      t.kx0 = local * D.mpk_g;
+      t.o0 = 0;
+      t.nother = 1;                                 // only m < mpk are valid
+      t.sn = D.H;
+      t.so = D.H;
+      t.base = t.kx0;
+    }
+  } else {
+    const int tn = local - D.gmain;
+    t.nyq = true;
+    t.mpk = 1;
+    t.lg = 0;
+    t.kx0 = D.H;
+    if constexpr (DIM == 3) {
+      t.o0 = tn * MP;
+      t.nother = D.ny;
+      t.sn = D.ny;
+      t.so = 1;
+      t.base = (int)D.Pm + t.o0;
+    } else {
+      t.o0 = 0;
+      t.nother = 1;                                 // a single pencil
+      t.sn = 1;
+      t.so = 1;
+      t.base = (int)D.Pm;
+    }
+  }
+  return t;
+}
+
+template <typename T, int NY, int DIR>
+__device__ void ypass_item(const InstDesc& D, int local, int c, void* buf, const T* __restrict__ twtab,
+                           unsigned char* smem) {
+  constexpr int NTH = Cfg<T>::NTH;
+  constexpr int MP = SGeom<T, NY>::MP;
+  constexpr int E = MP * NY;
+  using F = TileFft<T, NY, DIR, (DIR > 0), MP, 1, MP, 1, false, NTH>;
+  T* re = reinterpret_cast<T*>(smem);
+  T* im = re + E;
+  T* twr = im + E;
+  T* twi = twr + NY;
+  const int tid = threadIdx.x;
+  load_tw<T, NY, NTH>(twr, twi, twtab, tid);
+  __syncthreads();
+  const TileAddr t = ytile(D, local, MP);
+  char* cb = mptr<T>(buf, D.Pc, c);
+  T in_r[F::B0][F::R0], in_i[F::B0][F::R0];
+#pragma unroll
+  for (int q = 0; q < F::B0; ++q) {
+    const int b = tid + q * NTH;
+    int m, j;
+    F::template bj<F::R0>(b, m, j);
+    const bool ok = (F::TOT0 % NTH == 0 || b < F::TOT0) && t.valid(m);
+    const int o = t.off(m);
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      T re_ = T(0), im_ = T(0);
+      if (ok) {
+        const typename C2<T>::type v = ldc<T>(cb, o + (j + r * (NY / F::R0)) * t.sn);
+        re_ = v.x;
+        im_ = v.y;
+      }
+      in_r[q][r] = re_;
+      in_i[q][r] = im_;
+    }
+  }
+  T o_r[F::BL][F::RL], o_i[F::BL][F::RL];
+  F::run(in_r, in_i, o_r, o_i, re, im, twr, twi, tid);
+#pragma unroll
+  for (int q = 0; q < F::BL; ++q) {
+    const int b = tid + q * NTH;
+    int m, j;
+    F::template bj<F::RL>(b, m, j);
+    if ((F::TOTL % NTH == 0 || b < F::TOTL) && t.valid(m)) {
+      const int o = t.off(m);
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r)
+        stc<T>(cb, o + (j + r * (NY / F::RL)) * t.sn, o_r[q][r], o_i[q][r]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Green / body-force pass along the outermost axis
+// ---------------------------------------------------------------------------
+template <typename T, int NG, int DIM, int MODE>
+__device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int local,
+                           const T* __restrict__ twtab, unsigned char* smem) {
+  constexpr int NTH = Cfg<T>::NTH_G;
+  constexpr int MP = SGeom<T, NG>::MPG;
+  constexpr int E = MP * NG;
+  constexpr int S = (DIM == 3) ? 6 : 3;
+  using FF = TileFft<T, NG, -1, false, MP, 1, MP, 1, false, NTH, PlanG>;
+  using FI = TileFft<T, NG, +1, true, MP, 1, MP, 1, false, NTH, PlanG>;
+  static_assert(FF::RL == FI::R0 && FF::BL == FI::B0, "outer transforms must chain in registers");
+  constexpr int BP = FF::BL, RP = FF::RL, TOTP = FF::TOTL;
+  constexpr int NSTEP = NG / RP;                 // index step between a butterfly's points
+
+  T* lre[2];
+  T* lim[2];
+  lre[0] = reinterpret_cast<T*>(smem);
+  lim[0] = lre[0] + E;
+  lre[1] = lim[0] + E;
+  lim[1] = lre[1] + E;
+  T* twr = lim[1] + E;
+  T* twi = twr + NG;
+  double* red = reinterpret_cast<double*>(twi + NG + (NG & 1));
+  const int tid = threadIdx.x;
+  load_tw<T, NG, NTH>(twr, twi, twtab, tid);
+  __syncthreads();
+
+  const TileAddr t = gtile<DIM>(D, local, MP);
+  const long long Pc = D.Pc;
+  const T inv_n = T(D.inv_nvox);
+  const T mu0 = T(D.mu0);
+  const T c0 = T((D.lam0 + D.mu0) / (D.lam0 + 2.0 * D.mu0));
+
+  // per last-pass butterfly q of this thread: pencil m, first index j
+  bool pv[BP];
+  int poff[BP];
+  int pj[BP];
+  T pxi0[BP], pxi1[BP];   // xi_x, and xi_y in 3D
+  T pw[BP];               // Parseval weight
+#pragma unroll
+  for (int q = 0; q < BP; ++q) {
+    const int b = tid + q * NTH;
+    int m, j;
+    FF::template bj<RP>(b, m, j);
+    pv[q] = (TOTP % NTH == 0 || b < TOTP) && t.valid(m);
+    poff[q] = t.off(m);
+    pj[q] = j;
+    const int kx = t.kx(m);
+    pxi0[q] = T(wavenum(kx, D.nx, D.kx));
+    pxi1[q] = (DIM == 3) ? T(wavenum(t.other(m) < D.ny ? t.other(m) : 0, D.ny, D.ky)) : T(0);
+    pw[q] = (kx == 0 || kx == D.H) ? T(1) : T(2);
+  }
+  auto point_xi = [&](int q, int r, T* xi, T& xi2) {
+    const int n = pj[q] + r * NSTEP;
+    xi[0] = pxi0[q];
+    if constexpr (DIM == 3) {
+      xi[1] = pxi1[q];
+      xi[2] = T(wavenum(n, D.nz, D.kz));
+    } else {
+      xi[1] = T(wavenum(n, D.ny, D.ky));
+    }
+    xi2 = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) xi2 += xi[a] * xi[a];
+  };
+  auto gidx = [&](int q, int r) -> int { return poff[q] + (pj[q] + r * NSTEP) * t.sn; };
+
+  // first-pass loads of component c of src into (in_r, in_i)
+  auto load_first = [&](const void* src, int c, T (&in_r)[FF::B0][FF::R0], T (&in_i)[FF::B0][FF::R0]) {
+    const char* cb = cptr<T>(src, Pc, c);
+#pragma unroll
+    for (int q = 0; q < FF::B0; ++q) {
+      const int b = tid + q * NTH;
+      int m, j;
+      FF::template bj<FF::R0>(b, m, j);
+      const bool ok = (FF::TOT0 % NTH == 0 || b < FF::TOT0) && t.valid(m);
+      const int o = t.off(m);
+#pragma unroll
+      for (int r = 0; r < FF::R0; ++r) {
+        T re_ = T(0), im_ = T(0);
+        if (ok) {
+          const typename C2<T>::type v = ldc<T>(cb, o + (j + r * (NG / FF::R0)) * t.sn);
+          re_ = v.x;
+          im_ = v.y;
+        }
+        in_r[q][r] = re_;
+        in_i[q][r] = im_;
+      }
+    }
+  };
+
+  // forward transforms of NC components of src; fn(c, q, r, re, im) per point
+  int buf = 0;
+  auto forward_all = [&](const void* src, auto nc_tag, auto&& fn) {
+    constexpr int NC = decltype(nc_tag)::value;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T cur_r[FF::B0][FF::R0], cur_i[FF::B0][FF::R0];
+      load_first(src, c, cur_r, cur_i);
+      T o_r[BP][RP], o_i[BP][RP];
+      FF::run(cur_r, cur_i, o_r, o_i, lre[buf], lim[buf], twr, twi, tid);
+      buf ^= 1;
+#pragma unroll
+      for (int q = 0; q < BP; ++q)
+#pragma unroll
+        for (int r = 0; r < RP; ++r) fn(c, q, r, o_r[q][r], o_i[q][r]);
+      LSFFT_FENCE();   // keep the next component's loads after this one
+    }
+  };
+
+  // inverse transforms of NC components produced per point by gen(c, q, r, re&, im&),
+  // stored to dst (component offset c0_ in the destination)
+  auto inverse_all = [&](void* dst, int cfirst, auto nc_tag, auto&& gen) {
+    constexpr int NC = decltype(nc_tag)::value;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T in_r[FI::B0][FI::R0], in_i[FI::B0][FI::R0];
+#pragma unroll
+      for (int q = 0; q < BP; ++q)
+#pragma unroll
+        for (int r = 0; r < RP; ++r) gen(c, q, r, in_r[q][r], in_i[q][r]);
+      T o_r[FI::BL][FI::RL], o_i[FI::BL][FI::RL];
+      FI::run(in_r, in_i, o_r, o_i, lre[buf], lim[buf], twr, twi, tid);
+      buf ^= 1;
+      char* cb = mptr<T>(dst, Pc, cfirst + c);
+      LSFFT_FENCE();
+#pragma unroll
+      for (int q = 0; q < FI::BL; ++q) {
+        const int b = tid + q * NTH;
+        int m, j;
+        FI::template bj<FI::RL>(b, m, j);
+        if ((FI::TOTL % NTH == 0 || b < FI::TOTL) && t.valid(m)) {
+          const int o = t.off(m);
+#pragma unroll
+          for (int r = 0; r < FI::RL; ++r)
+            stc<T>(cb, o + (j + r * (NG / FI::RL)) * t.sn, o_r[q][r], o_i[q][r]);
+        }
+      }
+    }
+  };
+
+  // displacement-like vector per point (residual, then state)
+  T vr[DIM][BP][RP], vi[DIM][BP][RP];
+
+  // strain spectrum / |N| from the vector held in vr/vi:
+  // eps^_ab = (i/2)(xi_a u^_b + xi_b u^_a)
+  auto strain_gen = [&](int c, int q, int r, T& re, T& im) {
+    T xi[DIM], xi2;
+    point_xi(q, r, xi, xi2);
+    const int a = va<DIM>(c), b = vb<DIM>(c);
+    const T sr = T(0.5) * (xi[a] * vr[b][q][r] + xi[b] * vr[a][q][r]);
+    const T si = T(0.5) * (xi[a] * vi[b][q][r] + xi[b] * vi[a][q][r]);
+    re = -si * inv_n;
+    im = sr * inv_n;
+  };
+  // accumulate sgn * i xi . sigma^ component c into vr/vi
+  auto div_acc = [&](int c, int q, int r, T re, T im, T sgn) {
+    T xi[DIM], xi2;
+    point_xi(q, r, xi, xi2);
+    const int a = va<DIM>(c), b = vb<DIM>(c);
+    // i xi_b s -> (-xi_b im, xi_b re)
+    vr[a][q][r] -= sgn * xi[b] * im;
+    vi[a][q][r] += sgn * xi[b] * re;
+    if (a != b) {
+      vr[b][q][r] -= sgn * xi[a] * im;
+      vi[b][q][r] += sgn * xi[a] * re;
+    }
+  };
+  auto zero_v = [&]() {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int q = 0; q < BP; ++q)
+#pragma unroll
+        for (int r = 0; r < RP; ++r) { vr[a][q][r] = T(0); vi[a][q][r] = T(0); }
+  };
+
+  double part = 0.0, part2 = 0.0;
+  const int cur = St->iter & 1;
+
+  if constexpr (MODE == M_FT) {
+    // finish the force transform, record the removed mean, project off Z
+    forward_all(D.F, std::integral_constant<int, DIM>{}, [&](int c, int q, int r, T re, T im) {
+      vr[c][q][r] = re;
+      vi[c][q][r] = im;
+    });
+#pragma unroll
+    for (int q = 0; q < BP; ++q) {
+      if (!pv[q]) continue;
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        T xi[DIM], xi2;
+        point_xi(q, r, xi, xi2);
+        const int g = gidx(q, r);
+        const bool origin = (g == 0);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          if (origin) St->removed_mean[c] = double(vr[c][q][r]) * D.inv_nvox;
+          if (xi2 == T(0)) { vr[c][q][r] = T(0); vi[c][q][r] = T(0); }
+          stc<T>(mptr<T>(D.F, Pc, c), g, vr[c][q][r], vi[c][q][r]);
+        }
+      }
+    }
+    return;
+  } else if constexpr (MODE == M_INIT || MODE == M_ITER || MODE == M_CG_INIT) {
+    zero_v();
+    if constexpr (MODE != M_INIT) {
+      forward_all(D.S, std::integral_constant<int, S>{},
+                  [&](int c, int q, int r, T re, T im) { div_acc(c, q, r, re, im, T(1)); });
+    }
+#pragma unroll
+    for (int q = 0; q < BP; ++q) {
+      if (!pv[q]) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int r = 0; r < RP; ++r) { vr[a][q][r] = T(0); vi[a][q][r] = T(0); }
+        continue;
+      }
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        T xi[DIM], xi2;
+        point_xi(q, r, xi, xi2);
+        const int g = gidx(q, r);
+        T ur[DIM], ui[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const typename C2<T>::type f = ldc<T>(cptr<T>(D.F, Pc, a), g);
+          vr[a][q][r] += f.x;
+          vi[a][q][r] += f.y;
+          part += double(pw[q]) * (double(vr[a][q][r]) * double(vr[a][q][r]) +
+                                   double(vi[a][q][r]) * double(vi[a][q][r]));
+          ur[a] = vr[a][q][r];
+          ui[a] = vi[a][q][r];
+        }
+        apply_n0<T, DIM>(xi, xi2, c0, mu0, ur, ui);   // N0 r
+        LSFFT_FENCE();
+        if constexpr (MODE == M_CG_INIT) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            stc<T>(mptr<T>(D.R, Pc, a), g, vr[a][q][r], vi[a][q][r]);
+            stc<T>(mptr<T>(D.Pd, Pc, a), g, ur[a], ui[a]);
+            part2 += double(pw[q]) * (double(vr[a][q][r]) * double(ur[a]) + double(vi[a][q][r]) * double(ui[a]));
+            vr[a][q][r] = ur[a];
+            vi[a][q][r] = ui[a];
+          }
+        } else {
+          void* uout = (MODE == M_INIT) ? D.U[0] : D.U[cur ^ 1];
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            T nr = ur[a], ni = ui[a];
+            if constexpr (MODE == M_ITER) {
+              const typename C2<T>::type u0 = ldc<T>(cptr<T>(D.U[cur], Pc, a), g);
+              nr += u0.x;
+              ni += u0.y;
+            }
+            stc<T>(mptr<T>(uout, Pc, a), g, nr, ni);
+            vr[a][q][r] = nr;
+            vi[a][q][r] = ni;
+          }
+        }
+      }
+    }
+    inverse_all(D.S, 0, std::integral_constant<int, S>{}, strain_gen);
+  } else if constexpr (MODE == M_MAT) {
+#pragma unroll
+    for (int q = 0; q < BP; ++q)
+#pragma unroll
+      for (int r = 0; r < RP; ++r)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          T re = T(0), im = T(0);
+          if (pv[q]) {
+            const typename C2<T>::type u0 = ldc<T>(cptr<T>(D.U[cur], Pc, a), gidx(q, r));
+            re = u0.x;
+            im = u0.y;
+          }
+          vr[a][q][r] = re;
+          vi[a][q][r] = im;
+        }
+    inverse_all(D.S, 0, std::integral_constant<int, S>{}, strain_gen);
+    inverse_all(D.S, S, std::integral_constant<int, DIM>{}, [&](int c, int q, int r, T& re, T& im) {
+      re = vr[c][q][r] * inv_n;
+      im = vi[c][q][r] * inv_n;
+    });
+    return;
+  } else if constexpr (MODE == M_CG_AP) {
+    // q = A p = -i xi . sigma^(p): stored, and the partial p.q
+    zero_v();
+    forward_all(D.S, std::integral_constant<int, S>{},
+                [&](int c, int q, int r, T re, T im) { div_acc(c, q, r, re, im, T(-1)); });
+#pragma unroll
+    for (int q = 0; q < BP; ++q) {
+      if (!pv[q]) continue;
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const int g = gidx(q, r);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const typename C2<T>::type pd = ldc<T>(cptr<T>(D.Pd, Pc, a), g);
+          stc<T>(mptr<T>(D.Q, Pc, a), g, vr[a][q][r], vi[a][q][r]);
+          part += double(pw[q]) * (double(pd.x) * double(vr[a][q][r]) + double(pd.y) * double(vi[a][q][r]));
+        }
+      }
+    }
+  } else if constexpr (MODE == M_CG_DIR) {
+    // p = N0 r + beta p, stored, then eps^(p) / |N| and its inverse transform
+    const T beta = T(St->beta);
+#pragma unroll
+    for (int q = 0; q < BP; ++q) {
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        if (!pv[q]) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) { vr[a][q][r] = T(0); vi[a][q][r] = T(0); }
+          continue;
+        }
+        T xi[DIM], xi2;
+        point_xi(q, r, xi, xi2);
+        const int g = gidx(q, r);
+        T zr[DIM], zi[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const typename C2<T>::type rv = ldc<T>(cptr<T>(D.R, Pc, a), g);
+          zr[a] = rv.x;
+          zi[a] = rv.y;
+        }
+        apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const typename C2<T>::type pd = ldc<T>(cptr<T>(D.Pd, Pc, a), g);
+          const T nr = zr[a] + beta * pd.x, ni = zi[a] + beta * pd.y;
+          stc<T>(mptr<T>(D.Pd, Pc, a), g, nr, ni);
+          vr[a][q][r] = nr;
+          vi[a][q][r] = ni;
+        }
+      }
+    }
+    inverse_all(D.S, 0, std::integral_constant<int, S>{}, strain_gen);
+  }
+
+  // FP64 partial sums of this item, one slot per item; a separate one-block
+  // kernel sums the slots in a fixed order (bitwise reproducible)
+  if constexpr (MODE == M_INIT || MODE == M_ITER || MODE == M_CG_INIT || MODE == M_CG_AP) {
+    const double s1 = block_sum<NTH>(part, red);
+    if constexpr (MODE == M_CG_INIT) {
+      const double s2 = block_sum<NTH>(part2, red);
+      if (tid == 0) {
+        D.partial[2 * local] = s1;
+        D.partial[2 * local + 1] = s2;
+      }
+    } else {
+      if (tid == 0) D.partial[2 * local] = s1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CG pointwise update: u += alpha p, r -= alpha q, partials r.z and r.r
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsigned char* smem) {
+  constexpr int NTH = Cfg<T>::NTH;
+  const int tid = threadIdx.x;
+  double* red = reinterpret_cast<double*>(smem);
+  const T alpha = T(St->alpha);
+  const T mu0 = T(D.mu0);
+  const T c0 = T((D.lam0 + D.mu0) / (D.lam0 + 2.0 * D.mu0));
+  const long long Pc = D.Pc;
+  double prz = 0.0, prr = 0.0;
+  for (int qq = 0; qq < 4; ++qq) {
+    const long long g = (long long)local * NTH * 4 + qq * NTH + tid;
+    if (g >= Pc) break;
+    int kx, ky, kz;
+    if (g < D.Pm) {
+      kx = int(g % D.H);
+      const long long rest = g / D.H;
+      ky = int(rest % D.ny);
+      kz = int(rest / D.ny);
+    } else {
+      kx = D.H;
+      const long long rest = g - D.Pm;
+      ky = int(rest % D.ny);
+      kz = int(rest / D.ny);
+    }
+    T xi[DIM];
+    xi[0] = T(wavenum(kx, D.nx, D.kx));
+    xi[1] = T(wavenum(ky, D.ny, D.ky));
+    if constexpr (DIM == 3) xi[2] = T(wavenum(kz, D.nz, D.kz));
+    T xi2 = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) xi2 += xi[a] * xi[a];
+    const double wgt = (kx == 0 || kx == D.H) ? 1.0 : 2.0;
+    T rr[DIM], ri[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const typename C2<T>::type u = ldc<T>(cptr<T>(D.U[0], Pc, a), g);
+      const typename C2<T>::type pd = ldc<T>(cptr<T>(D.Pd, Pc, a), g);
+      const typename C2<T>::type r = ldc<T>(cptr<T>(D.R, Pc, a), g);
+      const typename C2<T>::type qv = ldc<T>(cptr<T>(D.Q, Pc, a), g);
+      stc<T>(mptr<T>(D.U[0], Pc, a), g, u.x + alpha * pd.x, u.y + alpha * pd.y);
+      rr[a] = r.x - alpha * qv.x;
+      ri[a] = r.y - alpha * qv.y;
+      stc<T>(mptr<T>(D.R, Pc, a), g, rr[a], ri[a]);
+      prr += wgt * (double(rr[a]) * double(rr[a]) + double(ri[a]) * double(ri[a]));
+    }
+    T zr[DIM], zi[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) { zr[a] = rr[a]; zi[a] = ri[a]; }
+    apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) prz += wgt * (double(rr[a]) * double(zr[a]) + double(ri[a]) * double(zi[a]));
+  }
+  const double s1 = block_sum<NTH>(prz, red);
+  const double s2 = block_sum<NTH>(prr, red);
+  if (tid == 0) {
+    D.partial[2 * local] = s1;
+    D.partial[2 * local + 1] = s2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool gated(int mode) {
+  return mode == M_ITER || mode == M_CG_AP || mode == M_CG_UPD || mode == M_CG_DIR || mode == M_CG_INIT;
+}
+
+// occupancy targets (waves per SIMD) that bound the register allocation
+template <typename T> struct WavesG { static constexpr int value = 4; };
+template <> struct WavesG<double> { static constexpr int value = 2; };
+#ifndef LSFFT_WAVES_G
+#define LSFFT_WAVES_G WavesG<T>::value
+#endif
+#ifndef LSFFT_WAVES_X
+#define LSFFT_WAVES_X 3
+#endif
+#ifndef LSFFT_WAVES_Y
+#define LSFFT_WAVES_Y 4
+#endif
+
+#ifdef LSFFT_ONLY_LEN
+#define LSFFT_LEN_CASES(X) X(LSFFT_ONLY_LEN)
+#else
+#define LSFFT_LEN_CASES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
+#endif
+
+// One kernel per (precision, length, dimension, mode): every work item of a
+// launch has the same transform length, so register allocation and LDS
+// layout are those of that length alone.
+template <typename T, int NX, int DIM, int MODE>
+__global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_X))) void k_xpass(
+    const InstDesc* __restrict__ descs, InstState* __restrict__ states, const WorkItem* __restrict__ items,
+    const int* __restrict__ nitems, const double* __restrict__ lame, const T* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n_items = *nitems;
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const WorkItem it = items[w];
+    const InstDesc& D = descs[it.inst];
+    if (gated(MODE) && states[it.inst].status != ST_RUNNING) continue;
+    xpass_item<T, NX, DIM, MODE>(D, it.local, lame, tw, smem);
+    __syncthreads();
+  }
+}
+
+// one component per work unit: unit w covers item w % n_items, component w / n_items
+template <typename T, int NY, int DIR>
+__global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_Y))) void k_ypass(
+    const InstDesc* __restrict__ descs, InstState* __restrict__ states, const WorkItem* __restrict__ items,
+    const int* __restrict__ nitems, const T* __restrict__ tw, int which, int ncomp, int gate) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n_items = *nitems;
+  const int n_units = n_items * ncomp;
+  for (int w = blockIdx.x; w < n_units; w += gridDim.x) {
+    const int c = w / n_items;
+    const WorkItem it = items[w - c * n_items];
+    const InstDesc& D = descs[it.inst];
+    if (gate && states[it.inst].status != ST_RUNNING) continue;
+    void* buf = (which == 0) ? D.S : D.F;
+    ypass_item<T, NY, DIR>(D, it.local, c, buf, tw, smem);
+    __syncthreads();
+  }
+}
+
+template <typename T, int NG, int DIM, int MODE>
+__global__ __launch_bounds__(Cfg<T>::NTH_G) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_G))) void k_green(
+    const InstDesc* __restrict__ descs, InstState* __restrict__ states, const WorkItem* __restrict__ items,
+    const int* __restrict__ nitems, const T* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n_items = *nitems;
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const WorkItem it = items[w];
+    const InstDesc& D = descs[it.inst];
+    InstState* St = states + it.inst;
+    if (gated(MODE) && St->status != ST_RUNNING) continue;
+    green_item<T, NG, DIM, MODE>(D, St, it.local, tw, smem);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(Cfg<T>::NTH) void k_cg_update(const InstDesc* __restrict__ descs,
+                                                           InstState* __restrict__ states,
+                                                           const WorkItem* __restrict__ items,
+                                                           const int* __restrict__ nitems) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n_items = *nitems;
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const WorkItem it = items[w];
+    const InstDesc& D = descs[it.inst];
+    InstState* St = states + it.inst;
+    if (St->status != ST_RUNNING) continue;
+    if (D.dim == 3) cg_update_item<T, 3>(D, St, it.local, smem);
+    else cg_update_item<T, 2>(D, St, it.local, smem);
+    __syncthreads();
+  }
+}
+
+#ifdef LSFFT_MISC_TU
+constexpr int NTR = 256;   // reduction, validation and averaging kernels
+
+// One block per solve: fixed-order FP64 sums of the per-item partials, then
+// the stopping rule.
+__global__ __launch_bounds__(NTR) void k_reduce(const InstDesc* __restrict__ descs, InstState* __restrict__ states,
+                                                const int* __restrict__ inst_list, const int* __restrict__ ninst,
+                                                int mode) {
+  __shared__ double red[NTR / 64];
+  // the number of listed solves is read on the device: a captured launch
+  // keeps its grid while solves retire
+  if ((int)blockIdx.x >= *ninst) return;
+  const int i = inst_list[blockIdx.x];
+  const InstDesc& D = descs[i];
+  InstState& St = states[i];
+  if (mode != M_INIT && St.status != ST_RUNNING) return;
+  const int nslot = (mode == M_CG_UPD) ? D.items_cg : D.items_g;
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nslot; k += NTR) {
+    a += D.partial[2 * k];
+    if (mode == M_CG_INIT || mode == M_CG_UPD) b += D.partial[2 * k + 1];
+  }
+  a = block_sum<NTR>(a, red);
+  b = block_sum<NTR>(b, red);
+  if (threadIdx.x == 0) finalize(D, St, mode, a, b);
+}
+
+// Largest phase id of a phase map (argument validation on the device).
+__global__ __launch_bounds__(NTR) void k_phase_max(const uint8_t* __restrict__ phase, long long n, int* __restrict__ out) {
+  __shared__ int red[NTR];
   int m = 0;
-  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+  for (long long i = (long long)blockIdx.x * NTR + threadIdx.x; i < n; i += (long long)gridDim.x * NTR)
     m = max(m, (int)phase[i]);
   red[threadIdx.x] = m;
   __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
+  for (int s = NTR / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
   if (threadIdx.x == 0) atomicMax(out, red[0]);
 }
 
-#endif  // LSFFT_MISC_TU
-
 // Translated averaging (Eqs. 3.5-3.6): for every voxel, in the fixed order of
 // the group's shifts, sum u, u V, eps, eps V, sigma, sigma V and V, V the
 // indicator of the inclusion phase in the shifted microstructure.  Sums are
 // added to the FP64 accumulator; no atomics, one thread per voxel.
 template <typename T, int DIM>
-__global__ __launch_bounds__(NT) void k_accumulate(const InstDesc* __restrict__ descs, const GroupDesc* __restrict__ groups,
-                                                   int g, const double* __restrict__ lame) {
+__global__ __launch_bounds__(NTR) void k_accumulate(const InstDesc* __restrict__ descs,
+                                                    const GroupDesc* __restrict__ groups, int g,
+                                                    const double* __restrict__ lame) {
   constexpr int S = (DIM == 3) ? 6 : 3;
   constexpr int NC = 2 * DIM + 4 * S + 1;
   const GroupDesc G = groups[g];
   const InstDesc& D0 = descs[G.first];
   const long long nvox = D0.nvox;
-  for (long long v = (long long)blockIdx.x * NT + threadIdx.x; v < nvox; v += (long long)gridDim.x * NT) {
+  for (long long v = (long long)blockIdx.x * NTR + threadIdx.x; v < nvox; v += (long long)gridDim.x * NTR) {
     const int x = int(v % D0.nx);
     const long long rest = v / D0.nx;
     const int y = int(rest % D0.ny);
@@ -1130,9 +1297,8 @@ __global__ __launch_bounds__(NT) void k_accumulate(const InstDesc* __restrict__ 
   }
 }
 
-#ifdef LSFFT_MISC_TU
-__global__ __launch_bounds__(NT) void k_scale(double* __restrict__ a, long long n, double s) {
-  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) a[i] *= s;
+__global__ __launch_bounds__(NTR) void k_scale(double* __restrict__ a, long long n, double s) {
+  for (long long i = (long long)blockIdx.x * NTR + threadIdx.x; i < n; i += (long long)gridDim.x * NTR) a[i] *= s;
 }
 #endif  // LSFFT_MISC_TU
 
@@ -1140,16 +1306,14 @@ __global__ __launch_bounds__(NT) void k_scale(double* __restrict__ a, long long 
 // LDS requirements (bytes) of one work item, per precision and length
 // ---------------------------------------------------------------------------
 template <typename T, int L> constexpr size_t lds_x() {
-  using G = RowGeom<T, L / 2>;
-  return sizeof(T) * (4 * G::MR * G::SM + 2 * L + 2 * kMaxPhases);
+  using G = XGeom<T, L / 2>;
+  return sizeof(T) * (2 * G::MR * G::SM + 2 * G::MR * G::SM2 + 2 * L + 2 * kMaxPhases);
 }
-template <typename T, int L> constexpr size_t lds_strided() {
-  using G = StridedGeom<T, L>;
-  return sizeof(T) * (4 * G::ELEMS + 2 * L + 2) + sizeof(double) * 8;
+template <typename T, int L> constexpr size_t lds_y() {
+  return sizeof(T) * (2 * SGeom<T, L>::MP * L + 2 * L);
 }
-template <typename T, int L> constexpr int tiles_strided(int nxh) {
-  return (nxh + StridedGeom<T, L>::MP - 1) / StridedGeom<T, L>::MP;
+template <typename T, int L> constexpr size_t lds_g() {
+  return sizeof(T) * (4 * SGeom<T, L>::MPG * L + 2 * L + 2) + sizeof(double) * 16;
 }
 
 }  // namespace lsfft
-

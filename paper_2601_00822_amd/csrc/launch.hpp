@@ -8,6 +8,7 @@ namespace lsfft {
 
 struct LaunchArgs {
   dim3 grid;
+  int block;              // threads per workgroup (precision dependent)
   size_t lds;
   hipStream_t stream;
   const InstDesc* desc;
@@ -18,23 +19,35 @@ struct LaunchArgs {
   const void* tw;         // device twiddle table in the plan precision
 };
 
-// kind 0: x pass (len = nx); kind 1: strided pass (len = ny or nz).
-// Returns the LDS bytes of one work item (0 if unsupported) and the rows or
-// pencils per tile.
+// kind 0: x pass (len = nx); kind 1: y pass (len = ny); kind 2: outer pass
+// (len = nz in 3D, ny in 2D).  Returns the LDS bytes of one work item (0 if
+// unsupported) and the rows or pencils per tile.
 size_t query_geometry(bool f64, int kind, int len, int* per_tile);
+int threads_per_block(bool f64);
+int threads_per_block_green(bool f64);
 
-hipError_t launch_xpass_f32(const LaunchArgs& a, int mode);
-hipError_t launch_xpass_f64(const LaunchArgs& a, int mode);
-hipError_t launch_ypass_f32(const LaunchArgs& a, int dir, int which, int extra, int gate);
-hipError_t launch_ypass_f64(const LaunchArgs& a, int dir, int which, int extra, int gate);
-hipError_t launch_green_f32(const LaunchArgs& a, int mode);
-hipError_t launch_green_f64(const LaunchArgs& a, int mode);
+// per precision / dimension / length group (one translation unit each)
+hipError_t launch_xpass_f32_2d(const LaunchArgs& a, int mode, int len);
+hipError_t launch_xpass_f32_3d(const LaunchArgs& a, int mode, int len);
+hipError_t launch_xpass_f64_2d(const LaunchArgs& a, int mode, int len);
+hipError_t launch_xpass_f64_3d(const LaunchArgs& a, int mode, int len);
+hipError_t launch_ypass_f32(const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len);
+hipError_t launch_ypass_f64(const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len);
+hipError_t launch_green_f32_2d_s(const LaunchArgs& a, int mode, int len);
+hipError_t launch_green_f32_2d_l(const LaunchArgs& a, int mode, int len);
+hipError_t launch_green_f32_3d_s(const LaunchArgs& a, int mode, int len);
+hipError_t launch_green_f32_3d_l(const LaunchArgs& a, int mode, int len);
+hipError_t launch_green_f64_2d_s(const LaunchArgs& a, int mode, int len);
+hipError_t launch_green_f64_2d_l(const LaunchArgs& a, int mode, int len);
+hipError_t launch_green_f64_3d_s(const LaunchArgs& a, int mode, int len);
+hipError_t launch_green_f64_3d_l(const LaunchArgs& a, int mode, int len);
 
-hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode);
-hipError_t launch_ypass(bool f64, const LaunchArgs& a, int dir, int which, int extra, int gate);
-hipError_t launch_green(bool f64, const LaunchArgs& a, int mode);
+// dispatch on (precision, dimension, transform length)
+hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode, int dim, int len);
+hipError_t launch_ypass(bool f64, const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len);
+hipError_t launch_green(bool f64, const LaunchArgs& a, int mode, int dim, int len);
 hipError_t launch_cg_update(bool f64, const LaunchArgs& a);
-hipError_t launch_reduce(const LaunchArgs& a, const int* inst_list, int ninst, int mode);
+hipError_t launch_reduce(const LaunchArgs& a, const int* inst_list, const int* d_ninst, int ninst, int mode);
 hipError_t launch_phase_max(const uint8_t* phase, long long n, int* out, hipStream_t s);
 hipError_t launch_accumulate(bool f64, int dim, const LaunchArgs& a, const GroupDesc* groups, int g, long long nvox);
 hipError_t launch_scale(double* a, long long n, double s, hipStream_t st);

@@ -75,11 +75,25 @@ struct BatchGroup {
 
 enum ListId { L_XLEAD, L_YLEAD, L_GLEAD, L_X, L_Y, L_G, L_CG, L_XALL, L_YALL, L_GALL, L_NUM };
 
+// A contiguous run of work items of one list that share the kernel
+// specialization (dimension and transform length) and therefore one launch.
+struct Seg {
+  int dim = 0, len = 0;
+  int off = 0, cap = 0, count = 0;
+  size_t lds = 0;
+  int cidx = 0;        // slot of its item count in the device count array
+};
+
+constexpr int kMaxSegs = 512;
+
 }  // namespace
 
 struct lsfft_plan_s {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t ustream = nullptr;  // caller's stream (inputs are ordered on it)
+  hipStream_t stream = nullptr;   // plan-owned work stream (capturable)
+  hipEvent_t ev_in = nullptr;
+  bool graphs = true;
   bool f64 = false;
   lsfft_scheme scheme = LSFFT_BASIC;
   unsigned flags = 0;
@@ -144,34 +158,70 @@ lsfft_status resolve_ref(const lsfft_phases* t, const lsfft_ref* c0, double* lam
 }
 
 struct Geometry {
-  int nx, ny, nz, nxh, dim, s;
-  long long P, nvox;
-  int items_x, items_y, items_g, items_cg, ntile_y, ntile_g;
+  int nx, ny, nz, H, dim, s;
+  long long Pm, Pc, nvox;
+  int xtiles, items_x, items_xall, items_xft, items_y, ymain, mpk_y, ntk_y, items_g, gmain, mpk_g, ntk_g, items_cg;
   size_t lds_x, lds_y, lds_g;
 };
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
+
+// largest power of two <= mp that divides h
+int kx_pencils(int mp, int h) {
+  int k = 1;
+  while (k * 2 <= mp && h % (k * 2) == 0) k *= 2;
+  return k;
+}
 
 bool geometry(bool f64, const lsfft_grid& g, Geometry* o) {
   o->dim = g.dim;
   o->nx = (int)gnx(g);
   o->ny = (int)gny(g);
   o->nz = (int)gnz(g);
-  o->nxh = o->nx / 2 + 1;
+  o->H = o->nx / 2;
   o->s = g.dim == 3 ? 6 : 3;
-  o->P = (long long)o->nz * o->ny * o->nxh;
+  o->Pm = (long long)o->nz * o->ny * o->H;
+  o->Pc = o->Pm + (long long)o->nz * o->ny;
   o->nvox = (long long)o->nz * o->ny * o->nx;
   int mr = 0, mpy = 0, mpg = 0;
   o->lds_x = query_geometry(f64, 0, o->nx, &mr);
   o->lds_y = (g.dim == 3) ? query_geometry(f64, 1, o->ny, &mpy) : 0;
   const int outer = (g.dim == 3) ? o->nz : o->ny;
-  o->lds_g = query_geometry(f64, 1, outer, &mpg);
+  o->lds_g = query_geometry(f64, 2, outer, &mpg);
   if (!o->lds_x || !o->lds_g || (g.dim == 3 && !o->lds_y)) return false;
   const int rows = o->ny * o->nz;
-  o->items_x = (rows + mr - 1) / mr;
-  o->ntile_y = (g.dim == 3) ? (o->nxh + mpy - 1) / mpy : 0;
-  o->items_y = (g.dim == 3) ? o->nz * o->ntile_y : 0;
-  o->ntile_g = (o->nxh + mpg - 1) / mpg;
-  o->items_g = ((g.dim == 3) ? o->ny : 1) * o->ntile_g;
-  o->items_cg = (int)((o->P + kThreads * 4 - 1) / (kThreads * 4));
+  o->xtiles = (rows + mr - 1) / mr;
+  o->items_x = o->xtiles * (1 + o->s - o->dim);          // normal group + shear components
+  o->items_xall = o->xtiles * (1 + o->s);                 // + displacement components
+  o->items_xft = o->xtiles * o->dim;                      // force components
+  if (g.dim == 3) {
+    o->mpk_y = kx_pencils(mpy, o->H);
+    const int per = mpy / o->mpk_y;
+    o->ntk_y = o->H / o->mpk_y;
+    o->ymain = o->ntk_y * ((o->nz + per - 1) / per);
+    o->items_y = o->ymain + (o->nz + mpy - 1) / mpy;
+  } else {
+    o->mpk_y = 1;
+    o->ntk_y = 0;
+    o->ymain = 0;
+    o->items_y = 0;
+  }
+  o->mpk_g = kx_pencils(mpg, o->H);
+  o->ntk_g = o->H / o->mpk_g;
+  if (g.dim == 3) {
+    const int per = mpg / o->mpk_g;
+    o->gmain = o->ntk_g * ((o->ny + per - 1) / per);
+    o->items_g = o->gmain + (o->ny + mpg - 1) / mpg;
+  } else {
+    o->gmain = o->ntk_g;
+    o->items_g = o->gmain + 1;
+  }
+  const int nth = threads_per_block(f64);
+  o->items_cg = (int)((o->Pc + nth * 4 - 1) / (nth * 4));
   return true;
 }
 
@@ -230,82 +280,137 @@ struct Batch {
   int* d_phasemax = nullptr;
   WorkItem* d_lists[L_NUM] = {nullptr};
   int list_cap[L_NUM] = {0};
-  int list_len[L_NUM] = {0};
-  size_t list_lds[L_NUM] = {0};
+  std::vector<Seg> segs[L_NUM];   // per list: one segment per (dim, transform length)
+  int nseg_total = 0;
   int n_running = 0;
   double tol = 1e-8;
   int max_iter = 0;
   bool averaging = false;
 };
 
-LaunchArgs largs(Batch& b, int list) {
+LaunchArgs largs(Batch& b, int list, const Seg& sg, int units = 1) {
   LaunchArgs a;
-  const int n = std::max(1, b.list_len[list]);
+  const int n = std::max(1, sg.count * units);
   a.grid = dim3((unsigned)std::min(n, kMaxGrid));
-  a.lds = b.list_lds[list];
+  a.block = threads_per_block(b.p->f64);
+  a.lds = sg.lds;
   a.stream = b.p->stream;
   a.desc = b.d_desc;
   a.state = b.d_state;
-  a.items = b.d_lists[list];
-  a.count = b.d_counts + list;
+  a.items = b.d_lists[list] + sg.off;
+  a.count = b.d_counts + sg.cidx;
   a.lame = b.d_lame;
   a.tw = b.p->tw.p;
   return a;
 }
 
-// Build work lists for the given instance subset; host copies into device.
+LaunchArgs base_args(Batch& b) {
+  LaunchArgs a{};
+  a.grid = dim3(1);
+  a.block = threads_per_block(b.p->f64);
+  a.stream = b.p->stream;
+  a.desc = b.d_desc;
+  a.state = b.d_state;
+  a.lame = b.d_lame;
+  a.tw = b.p->tw.p;
+  return a;
+}
+
+// Work-list key of solve i for list l: the kernel specialization it needs.
+void list_key(const Batch& b, int l, int i, int* dim, int* len, int* items, size_t* lds) {
+  const Geometry& g = b.geo[i];
+  *dim = g.dim;
+  switch (l) {
+    case L_X: *len = g.nx; *items = g.items_x; *lds = g.lds_x; break;
+    case L_XALL: *len = g.nx; *items = g.items_xall; *lds = g.lds_x; break;
+    case L_XLEAD: *len = g.nx; *items = g.items_xft; *lds = g.lds_x; break;
+    case L_Y: case L_YALL: case L_YLEAD: *len = g.ny; *items = g.items_y; *lds = g.lds_y; break;
+    case L_G: case L_GALL: case L_GLEAD: *len = (g.dim == 3) ? g.nz : g.ny; *items = g.items_g; *lds = g.lds_g; break;
+    default: *len = 0; *items = g.items_cg; *lds = 0; break;   // L_CG
+  }
+}
+
+bool is_dynamic(int l) { return l == L_X || l == L_Y || l == L_G || l == L_CG; }
+
+// Lay out every list as segments (first call), then fill the dynamic lists
+// with the items of the running solves (every call) and upload lists and
+// counts.  Segment offsets and capacities never change within a batch.
 lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_too) {
-  std::vector<WorkItem> lists[L_NUM];
-  std::vector<size_t> lds(L_NUM, 0);
-  auto add = [&](int id, int inst, int n, size_t l) {
-    for (int k = 0; k < n; ++k) lists[id].push_back({inst, k});
-    if (n > 0) lds[id] = std::max(lds[id], l);
-  };
-  for (int i : running) {
-    const Geometry& g = b.geo[i];
-    add(L_X, i, g.items_x, g.lds_x);
-    add(L_Y, i, g.items_y, g.lds_y);
-    add(L_G, i, g.items_g, g.lds_g);
-    add(L_CG, i, g.items_cg, 0);
-  }
+  const int n = (int)b.specs.size();
   if (all_too) {
-    for (int i = 0; i < (int)b.specs.size(); ++i) {
-      const Geometry& g = b.geo[i];
-      add(L_XALL, i, g.items_x, g.lds_x);
-      add(L_YALL, i, g.items_y, g.lds_y);
-      add(L_GALL, i, g.items_g, g.lds_g);
-      if (b.specs[i].leader == i) {
-        add(L_XLEAD, i, g.items_x, g.lds_x);
-        add(L_YLEAD, i, g.items_y, g.lds_y);
-        add(L_GLEAD, i, g.items_g, g.lds_g);
+    int cidx = 0;
+    for (int l = 0; l < L_NUM; ++l) {
+      b.segs[l].clear();
+      int off = 0;
+      for (int i = 0; i < n; ++i) {
+        if ((l == L_XLEAD || l == L_YLEAD || l == L_GLEAD) && b.specs[i].leader != i) continue;
+        int dim, len, items;
+        size_t lds;
+        list_key(b, l, i, &dim, &len, &items, &lds);
+        if (items == 0) continue;
+        Seg* sg = nullptr;
+        for (auto& x : b.segs[l])
+          if (x.dim == dim && x.len == len) sg = &x;
+        if (!sg) {
+          b.segs[l].push_back(Seg{});
+          sg = &b.segs[l].back();
+          sg->dim = dim;
+          sg->len = len;
+          sg->cidx = cidx++;
+        }
+        sg->cap += items;
+        sg->lds = std::max(sg->lds, lds);
       }
+      for (auto& x : b.segs[l]) {
+        x.off = off;
+        off += x.cap;
+      }
+      if (off > b.list_cap[l]) return LSFFT_E_ALLOC;
     }
+    if (cidx > kMaxSegs - 1) return LSFFT_E_ALLOC;
+    b.nseg_total = cidx;
   }
-  std::vector<int> counts(L_NUM);
+  std::vector<int> counts(kMaxSegs, 0);
   for (int l = 0; l < L_NUM; ++l) {
-    const bool dynamic = (l == L_X || l == L_Y || l == L_G || l == L_CG);
-    if (!dynamic && !all_too) {
-      counts[l] = b.list_len[l];
+    if (!all_too && !is_dynamic(l)) {
+      for (auto& x : b.segs[l]) counts[x.cidx] = x.count;
       continue;
     }
-    if ((int)lists[l].size() > b.list_cap[l]) return LSFFT_E_ALLOC;  // capacities sized up front
-    b.list_len[l] = (int)lists[l].size();
-    if (dynamic && !all_too) {
-      // keep the LDS size of the full list: launches need the max anyway
-    } else {
-      b.list_lds[l] = lds[l];
+    std::vector<WorkItem> items(b.list_cap[l] > 0 ? b.list_cap[l] : 1);
+    for (auto& x : b.segs[l]) {
+      int fill = 0;
+      const std::vector<int>* src = &running;
+      std::vector<int> all_ids;
+      if (!is_dynamic(l)) {
+        all_ids.resize(n);
+        for (int i = 0; i < n; ++i) all_ids[i] = i;
+        src = &all_ids;
+      }
+      for (int i : *src) {
+        if ((l == L_XLEAD || l == L_YLEAD || l == L_GLEAD) && b.specs[i].leader != i) continue;
+        int dim, len, cnt;
+        size_t lds;
+        list_key(b, l, i, &dim, &len, &cnt, &lds);
+        if (cnt == 0 || dim != x.dim || len != x.len) continue;
+        for (int k = 0; k < cnt; ++k) items[x.off + fill + k] = WorkItem{i, k};
+        fill += cnt;
+      }
+      x.count = fill;
+      counts[x.cidx] = fill;
+      if (fill > 0)
+        LSFFT_TRY(hipMemcpyAsync(b.d_lists[l] + x.off, items.data() + x.off, sizeof(WorkItem) * fill,
+                                 hipMemcpyHostToDevice, b.p->stream));
     }
-    counts[l] = b.list_len[l];
-    if (!lists[l].empty())
-      LSFFT_TRY(hipMemcpyAsync(b.d_lists[l], lists[l].data(), lists[l].size() * sizeof(WorkItem),
-                               hipMemcpyHostToDevice, b.p->stream));
+    // the host vector dies at the end of this iteration: wait for its copies
+    LSFFT_TRY(hipStreamSynchronize(b.p->stream));
   }
-  LSFFT_TRY(hipMemcpyAsync(b.d_counts, counts.data(), sizeof(int) * L_NUM, hipMemcpyHostToDevice, b.p->stream));
   std::vector<int> inst(running.begin(), running.end());
+  counts[kMaxSegs - 1] = (int)inst.size();   // solves listed for the reduction
+  LSFFT_TRY(hipMemcpyAsync(b.d_counts, counts.data(), sizeof(int) * counts.size(), hipMemcpyHostToDevice,
+                           b.p->stream));
   if (!inst.empty())
     LSFFT_TRY(hipMemcpyAsync(b.d_inst, inst.data(), sizeof(int) * inst.size(), hipMemcpyHostToDevice, b.p->stream));
   b.n_running = (int)inst.size();
-  // the host vectors above die at return: wait for the copies
   LSFFT_TRY(hipStreamSynchronize(b.p->stream));
   return LSFFT_OK;
 }
@@ -332,7 +437,7 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
   std::vector<size_t> o_S(n), o_U0(n), o_U1(n), o_F(n), o_R(n), o_P(n), o_Q(n), o_oe(n), o_ou(n), o_part(n), o_hist(n);
   for (int i = 0; i < n; ++i) {
     const Geometry& g = b.geo[i];
-    const size_t comp = (size_t)g.P * cs;
+    const size_t comp = (size_t)g.Pc * cs;
     o_S[i] = off; off = align_up(off + comp * (g.s + g.dim));
     o_U0[i] = off; off = align_up(off + comp * g.dim);
     if (!cg) { o_U1[i] = off; off = align_up(off + comp * g.dim); }
@@ -359,7 +464,12 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
     list_need[L_X] += g.items_x; list_need[L_Y] += g.items_y; list_need[L_G] += g.items_g;
     list_need[L_CG] += g.items_cg;
   }
-  list_need[L_XALL] = list_need[L_XLEAD] = list_need[L_X];
+  if (list_need[L_X] == 0) list_need[L_X] = 1;
+  list_need[L_XALL] = list_need[L_XLEAD] = 0;
+  for (int i = 0; i < n; ++i) {
+    list_need[L_XALL] += b.geo[i].items_xall;
+    list_need[L_XLEAD] += b.geo[i].items_xft;
+  }
   list_need[L_YALL] = list_need[L_YLEAD] = list_need[L_Y];
   list_need[L_GALL] = list_need[L_GLEAD] = list_need[L_G];
   size_t total_lame = 0;
@@ -369,7 +479,7 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
   const size_t m_state = moff; moff = align_up(moff + sizeof(InstState) * n);
   const size_t m_lame = moff; moff = align_up(moff + sizeof(double) * total_lame);
   const size_t m_groups = moff; moff = align_up(moff + sizeof(GroupDesc) * std::max<size_t>(1, b.groups.size()));
-  const size_t m_counts = moff; moff = align_up(moff + sizeof(int) * L_NUM);
+  const size_t m_counts = moff; moff = align_up(moff + sizeof(int) * kMaxSegs);
   const size_t m_inst = moff; moff = align_up(moff + sizeof(int) * n);
   const size_t m_pmax = moff; moff = align_up(moff + sizeof(int) * n);
   size_t m_list[L_NUM];
@@ -397,16 +507,19 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
     const Geometry& g = b.geo[i];
     const lsfft_grid& gr = p->grids[sp.grid];
     InstDesc& D = b.desc[i];
-    D.dim = g.dim; D.nx = g.nx; D.ny = g.ny; D.nz = g.nz; D.nxh = g.nxh; D.ncomp_s = g.s;
-    D.items_x = g.items_x; D.items_y = g.items_y; D.items_g = g.items_g;
-    D.ntile_y = g.ntile_y; D.ntile_g = g.ntile_g;
+    D.dim = g.dim; D.nx = g.nx; D.ny = g.ny; D.nz = g.nz; D.H = g.H; D.ncomp_s = g.s;
+    D.xtiles = g.xtiles; D.items_y = g.items_y; D.ymain = g.ymain;
+    D.mpk_y = g.mpk_y; D.lg_y = ilog2(g.mpk_y); D.ntk_y = g.ntk_y;
+    D.items_g = g.items_g; D.gmain = g.gmain;
+    D.mpk_g = g.mpk_g; D.lg_g = ilog2(g.mpk_g); D.ntk_g = g.ntk_g;
+    D.items_cg = g.items_cg;
     D.nphase = sp.tab->nphase;
     D.lame_off = (int)(b.lame.size() / 2);
     for (int q = 0; q < 2 * sp.tab->nphase; ++q) b.lame.push_back(sp.tab->lame[q]);
     D.sx = sp.shift[0]; D.sy = sp.shift[1]; D.sz = sp.shift[2];
     D.max_iter = b.max_iter;
     D.group = sp.group;
-    D.P = g.P; D.nvox = g.nvox;
+    D.Pm = g.Pm; D.Pc = g.Pc; D.nvox = g.nvox;
     const double two_pi = 6.283185307179586476925286766559;
     D.kx = two_pi / (g.nx * gr.h[0]);
     D.ky = two_pi / (g.ny * gr.h[1]);
@@ -466,41 +579,59 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
   for (int i = 0; i < n; ++i) all[i] = i;
   lsfft_status ls = upload_lists(b, all, true);
   if (ls != LSFFT_OK) return ls;
-  const bool has3d = std::any_of(b.geo.begin(), b.geo.end(), [](const Geometry& g) { return g.dim == 3; });
 
   auto X = [&](int list, int mode, int cls) -> hipError_t {
-    if (b.list_len[list] == 0) return hipSuccess;
-    const int t = timed_begin(p, cls);
-    hipError_t e = launch_xpass(f64, largs(b, list), mode);
-    timed_end(p, t);
-    return e;
+    for (const Seg& sg : b.segs[list]) {
+      if (sg.count == 0) continue;
+      const int t = timed_begin(p, cls);
+      hipError_t e = launch_xpass(f64, largs(b, list, sg), mode, sg.dim, sg.len);
+      timed_end(p, t);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   };
-  auto Y = [&](int list, int dir, int which, int extra, int gate, int cls) -> hipError_t {
-    if (!has3d || b.list_len[list] == 0) return hipSuccess;
-    const int t = timed_begin(p, cls);
-    hipError_t e = launch_ypass(f64, largs(b, list), dir, which, extra, gate);
-    timed_end(p, t);
-    return e;
+  auto Y = [&](int list, int dir, int which, int ncomp, int gate, int cls) -> hipError_t {
+    for (const Seg& sg : b.segs[list]) {
+      if (sg.count == 0) continue;
+      const int t = timed_begin(p, cls);
+      hipError_t e = launch_ypass(f64, largs(b, list, sg, ncomp), dir, which, ncomp, gate, sg.len);
+      timed_end(p, t);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   };
   auto Gp = [&](int list, int mode, int cls) -> hipError_t {
-    if (b.list_len[list] == 0) return hipSuccess;
-    const int t = timed_begin(p, cls);
-    hipError_t e = launch_green(f64, largs(b, list), mode);
-    timed_end(p, t);
-    return e;
+    for (const Seg& sg : b.segs[list]) {
+      if (sg.count == 0) continue;
+      const int t = timed_begin(p, cls);
+      hipError_t e = launch_green(f64, largs(b, list, sg), mode, sg.dim, sg.len);
+      timed_end(p, t);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   };
   auto Rd = [&](int mode) -> hipError_t {
     const int t = timed_begin(p, LSFFT_K_REDUCE);
-    hipError_t e = launch_reduce(largs(b, L_G), b.d_inst, b.n_running, mode);
+    hipError_t e = launch_reduce(base_args(b), b.d_inst, b.d_counts + kMaxSegs - 1, b.n_running, mode);
     timed_end(p, t);
     return e;
+  };
+  auto CGU = [&]() -> hipError_t {
+    for (const Seg& sg : b.segs[L_CG]) {
+      if (sg.count == 0) continue;
+      const int t = timed_begin(p, LSFFT_K_CGUPD);
+      hipError_t e = launch_cg_update(f64, largs(b, L_CG, sg));
+      timed_end(p, t);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   };
 
   const bool timing = (p->flags & LSFFT_TIMING) != 0;
   // setup: force transform (once per distinct force), free term, ||P f||
   p->timing_active = false;
   LSFFT_TRY(X(L_XLEAD, M_FT, LSFFT_K_OTHER));
-  LSFFT_TRY(Y(L_YLEAD, -1, 1, 0, 0, LSFFT_K_OTHER));
+  LSFFT_TRY(Y(L_YLEAD, -1, 1, 3, 0, LSFFT_K_OTHER));
   LSFFT_TRY(Gp(L_GLEAD, M_FT, LSFFT_K_OTHER));
   LSFFT_TRY(Gp(L_GALL, M_INIT, LSFFT_K_OTHER));
   LSFFT_TRY(Rd(M_INIT));
@@ -521,32 +652,64 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
   p->timing_active = timing;
   if (cg) {
     // r0 = P f - A u^b from one operator application on u^b
-    LSFFT_TRY(Y(L_Y, +1, 0, 0, 1, LSFFT_K_YPASS));
+    LSFFT_TRY(Y(L_Y, +1, 0, 6, 1, LSFFT_K_YPASS));
     LSFFT_TRY(X(L_X, M_ITER, LSFFT_K_XPASS));
-    LSFFT_TRY(Y(L_Y, -1, 0, 0, 1, LSFFT_K_YPASS));
+    LSFFT_TRY(Y(L_Y, -1, 0, 6, 1, LSFFT_K_YPASS));
     LSFFT_TRY(Gp(L_G, M_CG_INIT, LSFFT_K_GREEN));
     LSFFT_TRY(Rd(M_CG_INIT));
   }
+  // one polling round: `poll` iterations of every running solve
+  auto round = [&]() -> hipError_t {
+    for (int k = 0; k < p->poll; ++k) {
+      hipError_t e;
+      if ((e = Y(L_Y, +1, 0, 6, 1, LSFFT_K_YPASS)) != hipSuccess) return e;
+      if ((e = X(L_X, M_ITER, LSFFT_K_XPASS)) != hipSuccess) return e;
+      if ((e = Y(L_Y, -1, 0, 6, 1, LSFFT_K_YPASS)) != hipSuccess) return e;
+      if (!cg) {
+        if ((e = Gp(L_G, M_ITER, LSFFT_K_GREEN)) != hipSuccess) return e;
+        if ((e = Rd(M_ITER)) != hipSuccess) return e;
+      } else {
+        if ((e = Gp(L_G, M_CG_AP, LSFFT_K_GREEN)) != hipSuccess) return e;
+        if ((e = Rd(M_CG_AP)) != hipSuccess) return e;
+        if ((e = CGU()) != hipSuccess) return e;
+        if ((e = Rd(M_CG_UPD)) != hipSuccess) return e;
+        if ((e = Gp(L_G, M_CG_DIR, LSFFT_K_GREEN)) != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
+  };
+  // Without per-launch timing the round is captured once as a HIP graph and
+  // replayed: launch grids are fixed at capture (the largest work lists), the
+  // kernels read the current item counts from device memory, so retiring
+  // solves later needs no recapture.
+  hipGraphExec_t gexec = nullptr;
+  struct GraphGuard {
+    hipGraphExec_t* g;
+    ~GraphGuard() { if (*g) (void)hipGraphExecDestroy(*g); }
+  } guard{&gexec};
+  const bool use_graph = p->graphs && !timing;
   std::vector<int> running;
   for (;;) {
-    for (int k = 0; k < p->poll; ++k) {
-      LSFFT_TRY(Y(L_Y, +1, 0, 0, 1, LSFFT_K_YPASS));
-      LSFFT_TRY(X(L_X, M_ITER, LSFFT_K_XPASS));
-      LSFFT_TRY(Y(L_Y, -1, 0, 0, 1, LSFFT_K_YPASS));
-      if (!cg) {
-        LSFFT_TRY(Gp(L_G, M_ITER, LSFFT_K_GREEN));
-        LSFFT_TRY(Rd(M_ITER));
-      } else {
-        LSFFT_TRY(Gp(L_G, M_CG_AP, LSFFT_K_GREEN));
-        LSFFT_TRY(Rd(M_CG_AP));
-        if (b.list_len[L_CG] > 0) {
-          const int t = timed_begin(p, LSFFT_K_CGUPD);
-          LSFFT_TRY(launch_cg_update(f64, largs(b, L_CG)));
-          timed_end(p, t);
+    if (use_graph) {
+      if (!gexec) {
+        hipGraph_t graph = nullptr;
+        LSFFT_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const hipError_t ce = round();
+        const hipError_t ee = hipStreamEndCapture(st, &graph);
+        if (ce != hipSuccess || ee != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return LSFFT_E_DEVICE;
         }
-        LSFFT_TRY(Rd(M_CG_UPD));
-        LSFFT_TRY(Gp(L_G, M_CG_DIR, LSFFT_K_GREEN));
+        const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+          gexec = nullptr;
+          return LSFFT_E_DEVICE;
+        }
       }
+      LSFFT_TRY(hipGraphLaunch(gexec, st));
+    } else {
+      LSFFT_TRY(round());
     }
     LSFFT_TRY(hipMemcpyAsync(b.state.data(), b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost, st));
     LSFFT_TRY(hipStreamSynchronize(st));
@@ -564,12 +727,12 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
 
   // materialize u, eps, sigma of the returned iterates
   LSFFT_TRY(Gp(L_GALL, M_MAT, LSFFT_K_OTHER));
-  LSFFT_TRY(Y(L_YALL, +1, 0, /*extra*/ 3, 0, LSFFT_K_OTHER));
+  LSFFT_TRY(Y(L_YALL, +1, 0, /*eps + u*/ 9, 0, LSFFT_K_OTHER));
   LSFFT_TRY(X(L_XALL, M_MAT, LSFFT_K_OTHER));
   if (b.averaging) {
     for (int g = 0; g < (int)b.groups.size(); ++g) {
       const Geometry& G = b.geo[b.groups[g].first];
-      LSFFT_TRY(launch_accumulate(f64, G.dim, largs(b, L_GALL), b.d_groups, g, G.nvox));
+      LSFFT_TRY(launch_accumulate(f64, G.dim, base_args(b), b.d_groups, g, G.nvox));
     }
   }
   LSFFT_TRY(hipStreamSynchronize(st));
@@ -593,6 +756,15 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
 }
 
 lsfft_status check_plan(lsfft_plan_s* p) { return p ? LSFFT_OK : LSFFT_E_ARG; }
+
+// Order the plan's work stream after everything already enqueued on the
+// caller's stream (the inputs).
+lsfft_status enter(lsfft_plan_s* p) {
+  if (hipSetDevice(p->device) != hipSuccess) return LSFFT_E_DEVICE;
+  if (hipEventRecord(p->ev_in, p->ustream) != hipSuccess) return LSFFT_E_DEVICE;
+  if (hipStreamWaitEvent(p->stream, p->ev_in, 0) != hipSuccess) return LSFFT_E_DEVICE;
+  return LSFFT_OK;
+}
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -662,7 +834,17 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
   lsfft_plan_s* p = new (std::nothrow) lsfft_plan_s();
   if (!p) return LSFFT_E_ALLOC;
   p->device = dev;
-  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->ustream = static_cast<hipStream_t>(hip_stream);
+  if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete p;
+    return LSFFT_E_DEVICE;
+  }
+  if (hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(p->stream);
+    delete p;
+    return LSFFT_E_DEVICE;
+  }
+  if (std::getenv("LSFFT_NO_GRAPH")) p->graphs = false;
   p->f64 = (prec == LSFFT_F64);
   p->scheme = scheme;
   p->flags = flags;
@@ -710,6 +892,8 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
 lsfft_status lsfft_plan_destroy(lsfft_plan_t p) {
   if (!p) return LSFFT_OK;
   (void)hipStreamSynchronize(p->stream);
+  (void)hipStreamDestroy(p->stream);
+  (void)hipEventDestroy(p->ev_in);
   p->tw.release();
   p->arena.release();
   p->meta.release();
@@ -744,7 +928,7 @@ lsfft_status lsfft_solve_bfcs(lsfft_plan_t p, int nsolve, const int* grid_idx, c
     s.u = u ? u[i] : nullptr;
     s.out_index = i;
   }
-  if (hipSetDevice(p->device) != hipSuccess) return LSFFT_E_DEVICE;
+  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
   lsfft_status worst = LSFFT_OK;
   for (int start = 0; start < nsolve; start += p->max_batch) {
     const int cnt = std::min(p->max_batch, nsolve - start);
@@ -798,7 +982,7 @@ lsfft_status lsfft_translate_average_batch(lsfft_plan_t p, int ngroup, const lsf
       spec_group.push_back(g);
     }
   }
-  if (hipSetDevice(p->device) != hipSuccess) return LSFFT_E_DEVICE;
+  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
   for (int g = 0; g < ngroup; ++g) {
     const lsfft_grid& gr = p->grids[groups[g].grid_idx];
     const int d = gr.dim, s = d == 3 ? 6 : 3;
@@ -885,7 +1069,7 @@ lsfft_status lsfft_iteration_bytes(lsfft_plan_t p, int grid_idx, int kernel_clas
   if (kernel_class < 0 || kernel_class >= LSFFT_K_COUNT) return LSFFT_E_ARG;
   Geometry g;
   if (!geometry(p->f64, p->grids[grid_idx], &g)) return LSFFT_E_ARG;
-  const double comp = (double)g.P * (p->f64 ? 16.0 : 8.0);  // one complex half-spectrum stream
+  const double comp = (double)g.Pc * (p->f64 ? 16.0 : 8.0);  // one complex half-spectrum stream
   const double s = g.s, d = g.dim;
   const bool cg = p->scheme == LSFFT_CG;
   double b = 0.0;

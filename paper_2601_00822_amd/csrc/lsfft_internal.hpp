@@ -6,7 +6,6 @@
 
 namespace lsfft {
 
-constexpr int kThreads = 256;        // workgroup size of every pass kernel
 constexpr int kMaxPhases = 256;      // phase ids are uint8
 constexpr int kMaxLen = 256;         // longest supported axis
 
@@ -54,19 +53,31 @@ enum PassMode : int {
 
 // One solve.  All pointers are device pointers; real and complex buffers are
 // stored in the plan precision (float or double), complex interleaved.
+//
+// Spectral layout ("split half spectrum"): component c of a spectral buffer
+// starts at c * Pc and holds the modes kx = 0 .. H-1 (H = nx / 2) as a
+// [nz][ny][H] block of Pm complex entries, followed by the Nyquist plane
+// kx = H as a [nz][ny] block of Pn entries (Pc = Pm + Pn).  Rows of the main
+// block are H entries long, so every tile of the strided passes is full.
 struct InstDesc {
   int dim;             // 2 or 3
   int nx, ny, nz;      // nz = 1 in 2D
-  int nxh;             // nx / 2 + 1
+  int H;               // nx / 2
   int ncomp_s;         // strain components: 3 (2D) or 6 (3D)
-  int items_x, items_y, items_g;   // work items of each pass for this solve
-  int ntile_y, ntile_g;            // kx tiles per line in the y and outer passes
+  int xtiles;          // x-pass row tiles (work items = row tiles x component groups)
+  int items_y;         // y-pass tiles per component (main + Nyquist)
+  int ymain;           // y-pass main tiles per component
+  int mpk_y, lg_y, ntk_y;  // y tiles: kx pencils per tile, log2, kx tiles per plane
+  int items_g;         // outer-pass tiles (main + Nyquist)
+  int gmain;           // outer-pass main tiles
+  int mpk_g, lg_g, ntk_g;  // outer tiles: kx pencils per tile, log2, kx tiles per line
+  int items_cg;        // CG update items
   int nphase;
   int lame_off;        // offset (in pairs) into the device Lame table
   int sx, sy, sz;      // microstructure shift: phase read at (x - s) mod n
   int max_iter;
   int group;           // averaging group, -1 if none
-  long long P;         // complex entries of one half-spectrum component
+  long long Pm, Pc;    // complex entries: main block, component stride
   long long nvox;      // nx * ny * nz
   double kx, ky, kz;   // 2 pi / (n h) per axis
   double inv_nvox;
@@ -74,22 +85,24 @@ struct InstDesc {
   double tol;
   const uint8_t* phase;
   const void* f_in;    // real force [d][nvox]
-  void* S;             // spectral work [ncomp_s + d][P]
-  void* U[2];          // displacement spectrum, double-buffered [d][P]
-  void* F;             // force spectrum [d][P] (may be shared)
-  void* R;             // CG residual [d][P]
-  void* Pd;            // CG direction [d][P]
-  void* Q;             // CG A p [d][P]
+  void* S;             // spectral work [ncomp_s + d][Pc]
+  void* U[2];          // displacement spectrum, double-buffered [d][Pc]
+  void* F;             // force spectrum [d][Pc] (may be shared)
+  void* R;             // CG residual [d][Pc]
+  void* Pd;            // CG direction [d][Pc]
+  void* Q;             // CG A p [d][Pc]
   void* out_eps;       // real [s][nvox] or null
   void* out_sig;       // real [s][nvox] or null
   void* out_u;         // real [d][nvox] or null
   double* partial;     // per work item FP64 partial sums [max items][2]
-  double* history;     // optional residual history [max_iter + 1] or null
+  double* history;     // optional residual history [max_iter + 2] or null
 };
 
 struct InstState {
   int iter;
   int status;
+  int done;            // work items of the current launch finished (last one reduces)
+  int pad_;
   int mark_iter;       // iteration of the last >= 1% improvement
   int grow;            // consecutive iterations with a growing residual
   double residual;
