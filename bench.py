@@ -107,6 +107,9 @@ def main() -> int:
     ap.add_argument("--scheme", default="basic", choices=["basic", "cg"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the solves, run one plain device-to-device copy of this many MiB "
+                         "(reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the solver path is single-GPU (requested --gpus {args.gpus}); "
@@ -124,6 +127,14 @@ def main() -> int:
     dt = torch.float32 if args.prec == "f32" else torch.float64
     phase_d = torch.from_numpy(phase).to(dev)
     f_d = torch.from_numpy(f).to(dev).to(dt)
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # timed region: iterations replayed as captured HIP graphs
     plan = Plan([wl["shape"]], prec=args.prec, scheme=args.scheme)
     # kernel-duration region: the same solves with a HIP event pair around

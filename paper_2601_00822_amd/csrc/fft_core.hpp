@@ -189,8 +189,14 @@ __device__ __forceinline__ void bfly(T* vr, T* vi) {
 // MP: pencils; SM, SN: LDS strides of pencil and index; TWS: twiddle stride;
 // JF: index-fastest butterfly mapping; NTH: threads; PL: radix plan family.
 template <typename T, int N, int DIR, bool REV, int MP, int SM, int SN, int TWS, bool JF, int NTH,
-          template <int> class PL = Plan>
+          template <int> class PL = Plan, bool SKEW = false>
 struct TileFft {
+  // LDS word of element (pencil m, index n); with SKEW one padding word is
+  // inserted every 32 indices, which breaks the power-of-two strides of the
+  // Stockham scatters across LDS banks
+  __device__ static __forceinline__ int lidx(int m, int n) {
+    return m * SM + n * SN + (SKEW ? (n >> 5) : 0);
+  }
   using S = PlanSeq<PL, N, REV>;
   static constexpr int np = S::np;
   static constexpr int R0 = S::first();
@@ -242,7 +248,7 @@ struct TileFft {
         const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int idx = m * SM + (base + r * NS) * SN;
+          const int idx = lidx(m, base + r * NS);
           re[idx] = vr[q][r];
           im[idx] = vi[q][r];
         }
@@ -263,7 +269,7 @@ struct TileFft {
         bj<R>(b, m, j);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int idx = m * SM + (j + r * (N / R)) * SN;
+          const int idx = lidx(m, j + r * (N / R));
           vr[q][r] = re[idx];
           vi[q][r] = im[idx];
         }

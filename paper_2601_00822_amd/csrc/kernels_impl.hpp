@@ -52,7 +52,7 @@ constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi 
 template <typename T> struct Cfg;
 template <> struct Cfg<float> {
   static constexpr int NTH = 256, E = 2048, EX = 2048;   // x and y passes
-  static constexpr int NTH_G = 512, E_G = 2048;          // outer pass
+  static constexpr int NTH_G = 256, E_G = 1024;          // outer pass
 };
 template <> struct Cfg<double> {
   static constexpr int NTH = 128, E = 1024, EX = 512;
@@ -69,7 +69,8 @@ template <typename T, int N> struct SGeom {
 template <typename T, int H> struct XGeom {
   static constexpr int MR = clampi(pow2floor(Cfg<T>::EX / H), 1, 64);
   static constexpr int SM = ((H + 1) % 2 == 1) ? (H + 1) : (H + 2);  // fold tile, H + 1 entries
-  static constexpr int SM2 = (H % 2 == 1) ? H : (H + 1);             // transform staging
+  static constexpr int SKW = H + (H >> 5) + 1;                        // skewed row length
+  static constexpr int SM2 = (SKW % 2 == 1) ? SKW : (SKW + 1);         // transform staging
 };
 
 // ---------------------------------------------------------------------------
@@ -83,16 +84,35 @@ template <typename T> struct C2;
 template <> struct C2<float> { using type = float2; };
 template <> struct C2<double> { using type = double2; };
 
+// HBM accesses go through pointers in the global address space.  The
+// buffers are reached through pointers stored in the solve descriptor, whose
+// address space the compiler cannot infer; generic (flat) accesses would
+// also count against the LDS wait counter, so every LDS barrier would wait
+// for all loads in flight.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LSFFT_GLOBAL __attribute__((address_space(1)))
+#else
+#define LSFFT_GLOBAL
+#endif
+template <typename V>
+__device__ __forceinline__ V gld(const void* base, long long i) {
+  return ((const LSFFT_GLOBAL V*)base)[i];
+}
+template <typename V>
+__device__ __forceinline__ void gst(void* base, long long i, V v) {
+  ((LSFFT_GLOBAL V*)base)[i] = v;
+}
+
 template <typename T>
 __device__ __forceinline__ typename C2<T>::type ldc(const void* base, long long i) {
-  return reinterpret_cast<const typename C2<T>::type*>(base)[i];
+  return gld<typename C2<T>::type>(base, i);
 }
 template <typename T>
 __device__ __forceinline__ void stc(void* base, long long i, T re, T im) {
   typename C2<T>::type v;
   v.x = re;
   v.y = im;
-  reinterpret_cast<typename C2<T>::type*>(base)[i] = v;
+  gst<typename C2<T>::type>(base, i, v);
 }
 template <typename T>
 __device__ __forceinline__ const char* cptr(const void* base, long long comp_stride, int c) {
@@ -265,8 +285,8 @@ __device__ void xpass_item(const InstDesc& D, int local, const double* __restric
   using G = XGeom<T, H>;
   constexpr int MR = G::MR, SM = G::SM, SM2 = G::SM2;
   constexpr int S = (DIM == 3) ? 6 : 3;
-  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH>;   // C2R core
-  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH>;  // R2C core
+  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, Plan, true>;   // C2R core
+  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, Plan, true>;  // R2C core
   static_assert(FI::RL == FF::R0 && FI::BL == FF::B0, "x transforms must chain in registers");
   constexpr int BP = FI::BL, RP = FI::RL;          // points held per thread: BP x RP
   constexpr int TOTP = FI::TOTL;
@@ -283,8 +303,8 @@ __device__ void xpass_item(const InstDesc& D, int local, const double* __restric
   load_tw<T, NX, NTH>(twr, twi, twtab, tid);
   if constexpr (MODE != M_FT) {
     for (int p = tid; p < D.nphase; p += NTH) {
-      lam_s[p] = T(lame[2 * (D.lame_off + p)]);
-      mu_s[p] = T(lame[2 * (D.lame_off + p) + 1]);
+      lam_s[p] = T(gld<double>(lame, 2 * (D.lame_off + p)));
+      mu_s[p] = T(gld<double>(lame, 2 * (D.lame_off + p) + 1));
     }
   }
   __syncthreads();
@@ -355,7 +375,7 @@ __device__ void xpass_item(const InstDesc& D, int local, const double* __restric
           T re = T(0), im = T(0);
           if (ok) {
             const typename C2<T>::type v =
-                reinterpret_cast<const typename C2<T>::type*>(src + (row0 + m) * NX)[n];
+                gld<typename C2<T>::type>(src + (row0 + m) * NX, n);
             re = v.x;
             im = v.y;
           }
@@ -421,7 +441,7 @@ __device__ void xpass_item(const InstDesc& D, int local, const double* __restric
             typename C2<T>::type v;
             v.x = v_r[q][r];
             v.y = v_i[q][r];
-            reinterpret_cast<typename C2<T>::type*>(dst + (row0 + m) * NX)[n] = v;
+            gst<typename C2<T>::type>(dst + (row0 + m) * NX, n, v);
           }
         }
       }
@@ -430,7 +450,7 @@ __device__ void xpass_item(const InstDesc& D, int local, const double* __restric
     auto phase_at = [&](int row, int x) -> int {
       const int z = row / D.ny, y = row - (row / D.ny) * D.ny;
       const int rbase = (wrap(z - D.sz, D.nz) * D.ny + wrap(y - D.sy, D.ny)) * NX;
-      return D.phase[rbase + ((D.sx == 0) ? x : wrap(x - D.sx, NX))];
+      return gld<uint8_t>(D.phase, rbase + ((D.sx == 0) ? x : wrap(x - D.sx, NX)));
     };
     // apply fn(point value&, lam, mu, half) at every point of this thread
     auto each_point = [&](auto&& fn) {
@@ -631,8 +651,9 @@ __device__ void ypass_item(const InstDesc& D, int local, int c, void* buf, const
                            unsigned char* smem) {
   constexpr int NTH = Cfg<T>::NTH;
   constexpr int MP = SGeom<T, NY>::MP;
-  constexpr int E = MP * NY;
-  using F = TileFft<T, NY, DIR, (DIR > 0), MP, 1, MP, 1, false, NTH>;
+  constexpr int LP = (MP > 1) ? MP + 1 : 1;     // padded LDS row (one index, all pencils)
+  constexpr int E = LP * NY;
+  using F = TileFft<T, NY, DIR, (DIR > 0), MP, 1, LP, 1, false, NTH>;
   T* re = reinterpret_cast<T*>(smem);
   T* im = re + E;
   T* twr = im + E;
@@ -686,10 +707,11 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
                            const T* __restrict__ twtab, unsigned char* smem) {
   constexpr int NTH = Cfg<T>::NTH_G;
   constexpr int MP = SGeom<T, NG>::MPG;
-  constexpr int E = MP * NG;
+  constexpr int LP = (MP > 1) ? MP + 1 : 1;     // padded LDS row
+  constexpr int E = LP * NG;
   constexpr int S = (DIM == 3) ? 6 : 3;
-  using FF = TileFft<T, NG, -1, false, MP, 1, MP, 1, false, NTH, PlanG>;
-  using FI = TileFft<T, NG, +1, true, MP, 1, MP, 1, false, NTH, PlanG>;
+  using FF = TileFft<T, NG, -1, false, MP, 1, LP, 1, false, NTH, PlanG>;
+  using FI = TileFft<T, NG, +1, true, MP, 1, LP, 1, false, NTH, PlanG>;
   static_assert(FF::RL == FI::R0 && FF::BL == FI::B0, "outer transforms must chain in registers");
   constexpr int BP = FF::BL, RP = FF::RL, TOTP = FF::TOTL;
   constexpr int NSTEP = NG / RP;                 // index step between a butterfly's points
@@ -775,10 +797,13 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
   int buf = 0;
   auto forward_all = [&](const void* src, auto nc_tag, auto&& fn) {
     constexpr int NC = decltype(nc_tag)::value;
+    T cur_r[FF::B0][FF::R0], cur_i[FF::B0][FF::R0];
+    load_first(src, 0, cur_r, cur_i);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      T cur_r[FF::B0][FF::R0], cur_i[FF::B0][FF::R0];
-      load_first(src, c, cur_r, cur_i);
+      // the next component's loads are issued before this one's transform
+      T nxt_r[FF::B0][FF::R0], nxt_i[FF::B0][FF::R0];
+      if (c + 1 < NC) load_first(src, c + 1, nxt_r, nxt_i);
       T o_r[BP][RP], o_i[BP][RP];
       FF::run(cur_r, cur_i, o_r, o_i, lre[buf], lim[buf], twr, twi, tid);
       buf ^= 1;
@@ -786,7 +811,13 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
       for (int q = 0; q < BP; ++q)
 #pragma unroll
         for (int r = 0; r < RP; ++r) fn(c, q, r, o_r[q][r], o_i[q][r]);
-      LSFFT_FENCE();   // keep the next component's loads after this one
+      LSFFT_FENCE();
+      if (c + 1 < NC) {
+#pragma unroll
+        for (int q = 0; q < FF::B0; ++q)
+#pragma unroll
+          for (int r = 0; r < FF::R0; ++r) { cur_r[q][r] = nxt_r[q][r]; cur_i[q][r] = nxt_i[q][r]; }
+      }
     }
   };
 
@@ -1028,11 +1059,11 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
     if constexpr (MODE == M_CG_INIT) {
       const double s2 = block_sum<NTH>(part2, red);
       if (tid == 0) {
-        D.partial[2 * local] = s1;
-        D.partial[2 * local + 1] = s2;
+        gst<double>(D.partial, 2 * local, s1);
+        gst<double>(D.partial, 2 * local + 1, s2);
       }
     } else {
-      if (tid == 0) D.partial[2 * local] = s1;
+      if (tid == 0) gst<double>(D.partial, 2 * local, s1);
     }
   }
 }
@@ -1096,8 +1127,8 @@ __device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsi
   const double s1 = block_sum<NTH>(prz, red);
   const double s2 = block_sum<NTH>(prr, red);
   if (tid == 0) {
-    D.partial[2 * local] = s1;
-    D.partial[2 * local + 1] = s2;
+    gst<double>(D.partial, 2 * local, s1);
+    gst<double>(D.partial, 2 * local + 1, s2);
   }
 }
 
@@ -1109,7 +1140,7 @@ __device__ __forceinline__ bool gated(int mode) {
 }
 
 // occupancy targets (waves per SIMD) that bound the register allocation
-template <typename T> struct WavesG { static constexpr int value = 4; };
+template <typename T> struct WavesG { static constexpr int value = 3; };
 template <> struct WavesG<double> { static constexpr int value = 2; };
 #ifndef LSFFT_WAVES_G
 #define LSFFT_WAVES_G WavesG<T>::value
@@ -1309,11 +1340,12 @@ template <typename T, int L> constexpr size_t lds_x() {
   using G = XGeom<T, L / 2>;
   return sizeof(T) * (2 * G::MR * G::SM + 2 * G::MR * G::SM2 + 2 * L + 2 * kMaxPhases);
 }
+template <int MP> constexpr int padded(int mp) { return mp > 1 ? mp + 1 : 1; }
 template <typename T, int L> constexpr size_t lds_y() {
-  return sizeof(T) * (2 * SGeom<T, L>::MP * L + 2 * L);
+  return sizeof(T) * (2 * padded<0>(SGeom<T, L>::MP) * L + 2 * L);
 }
 template <typename T, int L> constexpr size_t lds_g() {
-  return sizeof(T) * (4 * SGeom<T, L>::MPG * L + 2 * L + 2) + sizeof(double) * 16;
+  return sizeof(T) * (4 * padded<0>(SGeom<T, L>::MPG) * L + 2 * L + 2) + sizeof(double) * 16;
 }
 
 }  // namespace lsfft
