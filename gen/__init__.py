@@ -123,12 +123,12 @@ def rsa_cell(cell: int, d: int, vf: float, rmin: float, rmax: float, seed: int,
             if not ok:
                 fails += 1
                 continue
-            fails = 0
             trial = mask | _cell_ball_mask(cshape, c, r)
             if trial.mean() > vf + 0.5 * (trial.mean() - mask.mean()) and balls:
                 # overshoot by more than half of this ball: try a smaller one
                 fails += 1
                 continue
+            fails = 0
             balls.append((c, r))
             mask = trial
         if mask.mean() >= vf - 0.02:
