@@ -64,6 +64,20 @@ typedef enum { LSFFT_BASIC = 0, LSFFT_CG = 1 } lsfft_scheme;
 /* plan flags */
 #define LSFFT_STRICT_EQUIL 0x1u  /* reject forces whose voxel sum is not ~0 (Eq. 2.5) instead of projecting */
 #define LSFFT_TIMING       0x2u  /* record HIP events around every kernel launch (see lsfft_kernel_times) */
+/* LSFFT_REFINE64 (LSFFT_F32 plans only): mixed-precision defect correction.
+ * The displacement state is kept in FP64; each outer step evaluates the FP64
+ * residual P f + div(L sym grad u) of that state (the stopping rule below is
+ * applied to it), solves the correction equation with that residual as its
+ * force in FP32 with the plan's scheme to a relative residual of 1e-3, and
+ * adds the correction in FP64.  The FP32 rounding floor then limits only the
+ * progress per step, so tol = 1e-8 is reachable at any contrast.  Reports:
+ * iters = FP32 iterations summed over the inner solves, residual = FP64
+ * residual of the returned state, at most 40 outer steps (else
+ * LSFFT_E_NOCONV).  Outputs are the FP64 state rounded once to FP32 and
+ * materialized in FP32.  The plan holds an FP64 companion workspace
+ * (about 18 complex FP64 half-spectrum fields per solve) and max_batch must
+ * not exceed 65535. */
+#define LSFFT_REFINE64     0x4u
 
 typedef struct {
   int dim;          /* 2 or 3 */
@@ -99,8 +113,9 @@ typedef struct lsfft_plan_s* lsfft_plan_t;
  *  max_batch  largest number of solves (or shifts) run concurrently; larger
  *             requests are processed in successive batches (>= 1)
  *  hip_stream hipStream_t to enqueue on (NULL = the null stream)
- * Errors: LSFFT_E_ARG for an unsupported grid, ngrid < 1, max_batch < 1;
- * LSFFT_E_DEVICE if no HIP device is usable.
+ * Errors: LSFFT_E_ARG for an unsupported grid, ngrid < 1, max_batch < 1,
+ * unknown flags, LSFFT_REFINE64 on an LSFFT_F64 plan or with max_batch >
+ * 65535; LSFFT_E_DEVICE if no HIP device is usable.
  */
 lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, int max_batch,
                         lsfft_prec prec, lsfft_scheme scheme, unsigned flags, void* hip_stream);

@@ -97,4 +97,45 @@ hipError_t launch_scale(double* a, long long n, double s, hipStream_t st) {
   return hipGetLastError();
 }
 
+// grid.x strides over the half spectrum of one solve, grid.y = solve slot
+// (callers keep count <= 65535)
+static dim3 spectrum_grid(long long max_pc, int count, int dims) {
+  long long bx = (max_pc * dims + NTR - 1) / NTR;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  return dim3((unsigned)bx, (unsigned)count);
+}
+
+hipError_t launch_widen(const float* src, double* dst, long long n, hipStream_t st) {
+  long long blocks = (n + NTR - 1) / NTR;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_widen, dim3((unsigned)blocks), NTR, 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_defect(const InstDesc* d64, const InstState* s64, const InstDesc* d32, const int* inst, int count,
+                         long long max_pc, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_defect, spectrum_grid(max_pc, count, 1), NTR, 0, st, d64, s64, d32, inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_correct(const InstDesc* d64, const InstState* s64, const InstDesc* d32, const InstState* s32,
+                          const int* inst, int count, bool cg, long long max_pc, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_correct, spectrum_grid(max_pc, count, 3), NTR, 0, st, d64, s64, d32, s32, inst, cg ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_narrow(const InstDesc* d64, const InstState* s64, const InstDesc* d32, const int* inst, int count,
+                         long long max_pc, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_narrow, spectrum_grid(max_pc, count, 3), NTR, 0, st, d64, s64, d32, inst);
+  return hipGetLastError();
+}
+
 }  // namespace lsfft

@@ -1331,6 +1331,91 @@ __global__ __launch_bounds__(NTR) void k_accumulate(const InstDesc* __restrict__
 __global__ __launch_bounds__(NTR) void k_scale(double* __restrict__ a, long long n, double s) {
   for (long long i = (long long)blockIdx.x * NTR + threadIdx.x; i < n; i += (long long)gridDim.x * NTR) a[i] *= s;
 }
+
+// ---- mixed-precision defect correction: FP64 state, FP32 inner solves ----
+// Wavevector of entry g of the split half spectrum (main block, then the
+// x-Nyquist plane).
+__device__ inline void spectrum_xi(const InstDesc& D, long long g, double xi[3]) {
+  int kx;
+  long long rest;
+  if (g < D.Pm) {
+    kx = int(g % D.H);
+    rest = g / D.H;
+  } else {
+    kx = D.H;
+    rest = g - D.Pm;
+  }
+  xi[0] = wavenum(kx, D.nx, D.kx);
+  xi[1] = wavenum(int(rest % D.ny), D.ny, D.ky);
+  xi[2] = (D.dim == 3) ? wavenum(int(rest / D.ny), D.nz, D.kz) : 0.0;
+}
+
+__global__ __launch_bounds__(NTR) void k_widen(const float* __restrict__ src, double* __restrict__ dst, long long n) {
+  for (long long i = (long long)blockIdx.x * NTR + threadIdx.x; i < n; i += (long long)gridDim.x * NTR)
+    dst[i] = double(src[i]);
+}
+
+// FP32 force of the inner solve: r = K0 (N0 r), K0 = mu0 |xi|^2 I + (lam0 +
+// mu0) xi xi^T the reference acoustic tensor, from the two FP64 state buffers
+// of the outer step (u + N0 r and u).  Zero on the xi = 0 set.
+__global__ __launch_bounds__(NTR) void k_defect(const InstDesc* __restrict__ d64, const InstState* __restrict__ s64,
+                                                const InstDesc* __restrict__ d32, const int* __restrict__ inst) {
+  const int i = inst[blockIdx.y];
+  const InstDesc& C = d64[i];
+  const int cur = s64[i].iter & 1;
+  const double2* un = static_cast<const double2*>(C.U[cur]);
+  const double2* uo = static_cast<const double2*>(C.U[cur ^ 1]);
+  float2* F = static_cast<float2*>(d32[i].F);
+  const long long Pc = C.Pc;
+  const double b = C.lam0 + C.mu0;
+  for (long long g = (long long)blockIdx.x * NTR + threadIdx.x; g < Pc; g += (long long)gridDim.x * NTR) {
+    double xi[3];
+    spectrum_xi(C, g, xi);
+    const double xi2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+    double dr[3] = {0, 0, 0}, di[3] = {0, 0, 0}, pr = 0.0, pi = 0.0;
+    for (int a = 0; a < C.dim; ++a) {
+      const double2 x = un[a * Pc + g], y = uo[a * Pc + g];
+      dr[a] = x.x - y.x;
+      di[a] = x.y - y.y;
+      pr += xi[a] * dr[a];
+      pi += xi[a] * di[a];
+    }
+    for (int a = 0; a < C.dim; ++a)
+      F[a * Pc + g] = make_float2(float(C.mu0 * xi2 * dr[a] + b * xi[a] * pr), float(C.mu0 * xi2 * di[a] + b * xi[a] * pi));
+  }
+}
+
+// u += d: the FP64 state buffer that the next outer step reads becomes the
+// previous state plus the returned iterate of the FP32 inner solve.
+__global__ __launch_bounds__(NTR) void k_correct(const InstDesc* __restrict__ d64, const InstState* __restrict__ s64,
+                                                 const InstDesc* __restrict__ d32, const InstState* __restrict__ s32,
+                                                 const int* __restrict__ inst, int cg) {
+  const int i = inst[blockIdx.y];
+  const InstDesc& C = d64[i];
+  const int cur = s64[i].iter & 1;
+  const int sel = cg ? 0 : (s32[i].iter & 1);
+  double2* dst = static_cast<double2*>(C.U[cur]);
+  const double2* src = static_cast<const double2*>(C.U[cur ^ 1]);
+  const float2* d = static_cast<const float2*>(d32[i].U[sel]);
+  const long long n = (long long)C.dim * C.Pc;
+  for (long long g = (long long)blockIdx.x * NTR + threadIdx.x; g < n; g += (long long)gridDim.x * NTR) {
+    const double2 s = src[g];
+    const float2 e = d[g];
+    dst[g] = make_double2(s.x + double(e.x), s.y + double(e.y));
+  }
+}
+
+// The returned FP64 iterate rounded once into the FP32 state buffer 0.
+__global__ __launch_bounds__(NTR) void k_narrow(const InstDesc* __restrict__ d64, const InstState* __restrict__ s64,
+                                                const InstDesc* __restrict__ d32, const int* __restrict__ inst) {
+  const int i = inst[blockIdx.y];
+  const InstDesc& C = d64[i];
+  const double2* src = static_cast<const double2*>(C.U[s64[i].iter & 1]);
+  float2* dst = static_cast<float2*>(d32[i].U[0]);
+  const long long n = (long long)C.dim * C.Pc;
+  for (long long g = (long long)blockIdx.x * NTR + threadIdx.x; g < n; g += (long long)gridDim.x * NTR)
+    dst[g] = make_float2(float(src[g].x), float(src[g].y));
+}
 #endif  // LSFFT_MISC_TU
 
 // ---------------------------------------------------------------------------

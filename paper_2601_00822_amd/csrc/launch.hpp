@@ -52,4 +52,14 @@ hipError_t launch_phase_max(const uint8_t* phase, long long n, int* out, hipStre
 hipError_t launch_accumulate(bool f64, int dim, const LaunchArgs& a, const GroupDesc* groups, int g, long long nvox);
 hipError_t launch_scale(double* a, long long n, double s, hipStream_t st);
 
+// mixed-precision defect correction; `inst` lists `count` solves, `max_pc`
+// is the largest half spectrum among them
+hipError_t launch_widen(const float* src, double* dst, long long n, hipStream_t st);
+hipError_t launch_defect(const InstDesc* d64, const InstState* s64, const InstDesc* d32, const int* inst, int count,
+                         long long max_pc, hipStream_t st);
+hipError_t launch_correct(const InstDesc* d64, const InstState* s64, const InstDesc* d32, const InstState* s32,
+                          const int* inst, int count, bool cg, long long max_pc, hipStream_t st);
+hipError_t launch_narrow(const InstDesc* d64, const InstState* s64, const InstDesc* d32, const int* inst, int count,
+                         long long max_pc, hipStream_t st);
+
 }  // namespace lsfft

@@ -100,7 +100,12 @@ struct lsfft_plan_s {
   std::vector<lsfft_grid> grids;
   int max_batch = 1;
   int poll = 8;
+  bool owns_stream = true;
   DevBuf tw, arena, meta, lists;
+  // LSFFT_REFINE64: FP64 companion (same grids, shares the work stream) and
+  // the FP64 copies of the forces
+  lsfft_plan_s* sub = nullptr;
+  DevBuf fwide;
   // timing
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, int>> ev_pending;  // (class, index of start event)
@@ -415,7 +420,21 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
   return LSFFT_OK;
 }
 
-lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
+// Largest half-spectrum size among the listed solves (grid of the
+// defect-correction kernels).
+long long max_pc(const Batch& b, const std::vector<int>& ids) {
+  long long m = 1;
+  for (int i : ids) m = std::max(m, (long long)b.geo[i].Pc);
+  return m;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Workspace layout, descriptors, Lame tables, phase validation and the
+// initial work lists of a batch.
+lsfft_status prepare(Batch& b) {
   lsfft_plan_s* p = b.p;
   const bool f64 = p->f64;
   const size_t rs = f64 ? 8 : 4;   // real scalar
@@ -577,68 +596,77 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
 
   std::vector<int> all(n);
   for (int i = 0; i < n; ++i) all[i] = i;
-  lsfft_status ls = upload_lists(b, all, true);
-  if (ls != LSFFT_OK) return ls;
+  return upload_lists(b, all, true);
+}
 
-  auto X = [&](int list, int mode, int cls) -> hipError_t {
-    for (const Seg& sg : b.segs[list]) {
-      if (sg.count == 0) continue;
-      const int t = timed_begin(p, cls);
-      hipError_t e = launch_xpass(f64, largs(b, list, sg), mode, sg.dim, sg.len);
-      timed_end(p, t);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  };
-  auto Y = [&](int list, int dir, int which, int ncomp, int gate, int cls) -> hipError_t {
-    for (const Seg& sg : b.segs[list]) {
-      if (sg.count == 0) continue;
-      const int t = timed_begin(p, cls);
-      hipError_t e = launch_ypass(f64, largs(b, list, sg, ncomp), dir, which, ncomp, gate, sg.len);
-      timed_end(p, t);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  };
-  auto Gp = [&](int list, int mode, int cls) -> hipError_t {
-    for (const Seg& sg : b.segs[list]) {
-      if (sg.count == 0) continue;
-      const int t = timed_begin(p, cls);
-      hipError_t e = launch_green(f64, largs(b, list, sg), mode, sg.dim, sg.len);
-      timed_end(p, t);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  };
-  auto Rd = [&](int mode) -> hipError_t {
-    const int t = timed_begin(p, LSFFT_K_REDUCE);
-    hipError_t e = launch_reduce(base_args(b), b.d_inst, b.d_counts + kMaxSegs - 1, b.n_running, mode);
-    timed_end(p, t);
-    return e;
-  };
-  auto CGU = [&]() -> hipError_t {
-    for (const Seg& sg : b.segs[L_CG]) {
-      if (sg.count == 0) continue;
-      const int t = timed_begin(p, LSFFT_K_CGUPD);
-      hipError_t e = launch_cg_update(f64, largs(b, L_CG, sg));
-      timed_end(p, t);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  };
+// ---- launches of one pass kind over the segments of a work list ----------
+hipError_t pass_x(Batch& b, int list, int mode, int cls) {
+  for (const Seg& sg : b.segs[list]) {
+    if (sg.count == 0) continue;
+    const int t = timed_begin(b.p, cls);
+    hipError_t e = launch_xpass(b.p->f64, largs(b, list, sg), mode, sg.dim, sg.len);
+    timed_end(b.p, t);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+hipError_t pass_y(Batch& b, int list, int dir, int which, int ncomp, int gate, int cls) {
+  for (const Seg& sg : b.segs[list]) {
+    if (sg.count == 0) continue;
+    const int t = timed_begin(b.p, cls);
+    hipError_t e = launch_ypass(b.p->f64, largs(b, list, sg, ncomp), dir, which, ncomp, gate, sg.len);
+    timed_end(b.p, t);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+hipError_t pass_g(Batch& b, int list, int mode, int cls) {
+  for (const Seg& sg : b.segs[list]) {
+    if (sg.count == 0) continue;
+    const int t = timed_begin(b.p, cls);
+    hipError_t e = launch_green(b.p->f64, largs(b, list, sg), mode, sg.dim, sg.len);
+    timed_end(b.p, t);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+hipError_t pass_reduce(Batch& b, int mode) {
+  const int t = timed_begin(b.p, LSFFT_K_REDUCE);
+  hipError_t e = launch_reduce(base_args(b), b.d_inst, b.d_counts + kMaxSegs - 1, b.n_running, mode);
+  timed_end(b.p, t);
+  return e;
+}
+hipError_t pass_cg_update(Batch& b) {
+  for (const Seg& sg : b.segs[L_CG]) {
+    if (sg.count == 0) continue;
+    const int t = timed_begin(b.p, LSFFT_K_CGUPD);
+    hipError_t e = launch_cg_update(b.p->f64, largs(b, L_CG, sg));
+    timed_end(b.p, t);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
-  const bool timing = (p->flags & LSFFT_TIMING) != 0;
-  // setup: force transform (once per distinct force), free term, ||P f||
+// Force transform, free term u^b = N0 P f^ and ||P f||.  With `spectral_force`
+// the force spectra are already in place (one per solve) and only the solves
+// on the current dynamic lists are (re)started.
+lsfft_status setup(Batch& b, bool spectral_force) {
+  lsfft_plan_s* p = b.p;
+  const int n = (int)b.specs.size();
   p->timing_active = false;
-  LSFFT_TRY(X(L_XLEAD, M_FT, LSFFT_K_OTHER));
-  LSFFT_TRY(Y(L_YLEAD, -1, 1, 3, 0, LSFFT_K_OTHER));
-  LSFFT_TRY(Gp(L_GLEAD, M_FT, LSFFT_K_OTHER));
-  LSFFT_TRY(Gp(L_GALL, M_INIT, LSFFT_K_OTHER));
-  LSFFT_TRY(Rd(M_INIT));
+  if (!spectral_force) {
+    LSFFT_TRY(pass_x(b, L_XLEAD, M_FT, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_y(b, L_YLEAD, -1, 1, 3, 0, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_g(b, L_GLEAD, M_FT, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_g(b, L_GALL, M_INIT, LSFFT_K_OTHER));
+  } else {
+    LSFFT_TRY(pass_g(b, L_G, M_INIT, LSFFT_K_OTHER));
+  }
+  LSFFT_TRY(pass_reduce(b, M_INIT));
 
-  if (p->flags & LSFFT_STRICT_EQUIL) {
-    LSFFT_TRY(hipMemcpyAsync(b.state.data(), b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost, st));
-    LSFFT_TRY(hipStreamSynchronize(st));
+  if (!spectral_force && (p->flags & LSFFT_STRICT_EQUIL)) {
+    LSFFT_TRY(hipMemcpyAsync(b.state.data(), b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost, p->stream));
+    LSFFT_TRY(hipStreamSynchronize(p->stream));
     for (int i = 0; i < n; ++i) {
       const InstState& L = b.state[b.specs[i].leader];
       const double fn = std::sqrt(b.state[i].fnorm2 / (double)b.geo[i].nvox);
@@ -648,32 +676,54 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
       }
     }
   }
+  return LSFFT_OK;
+}
 
+// Copy the solve states to the host and list the running ones.
+lsfft_status read_states(Batch& b, std::vector<int>& running) {
+  const int n = (int)b.specs.size();
+  LSFFT_TRY(hipMemcpyAsync(b.state.data(), b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost, b.p->stream));
+  LSFFT_TRY(hipStreamSynchronize(b.p->stream));
+  running.clear();
+  for (int i = 0; i < n; ++i)
+    if (b.state[i].status == ST_RUNNING) running.push_back(i);
+  return LSFFT_OK;
+}
+
+// Iterate every solve on the dynamic lists until none is running.  With
+// `max_rounds` > 0 at most that many single-iteration rounds are run, without
+// a graph (the mixed-precision outer step).
+lsfft_status iterate(Batch& b, int max_rounds = 0) {
+  lsfft_plan_s* p = b.p;
+  const bool cg = p->scheme == LSFFT_CG;
+  hipStream_t st = p->stream;
+  const bool timing = (p->flags & LSFFT_TIMING) != 0;
   p->timing_active = timing;
   if (cg) {
     // r0 = P f - A u^b from one operator application on u^b
-    LSFFT_TRY(Y(L_Y, +1, 0, 6, 1, LSFFT_K_YPASS));
-    LSFFT_TRY(X(L_X, M_ITER, LSFFT_K_XPASS));
-    LSFFT_TRY(Y(L_Y, -1, 0, 6, 1, LSFFT_K_YPASS));
-    LSFFT_TRY(Gp(L_G, M_CG_INIT, LSFFT_K_GREEN));
-    LSFFT_TRY(Rd(M_CG_INIT));
+    LSFFT_TRY(pass_y(b, L_Y, +1, 0, 6, 1, LSFFT_K_YPASS));
+    LSFFT_TRY(pass_x(b, L_X, M_ITER, LSFFT_K_XPASS));
+    LSFFT_TRY(pass_y(b, L_Y, -1, 0, 6, 1, LSFFT_K_YPASS));
+    LSFFT_TRY(pass_g(b, L_G, M_CG_INIT, LSFFT_K_GREEN));
+    LSFFT_TRY(pass_reduce(b, M_CG_INIT));
   }
-  // one polling round: `poll` iterations of every running solve
+  const int per_round = max_rounds > 0 ? 1 : p->poll;
+  // one polling round: `per_round` iterations of every running solve
   auto round = [&]() -> hipError_t {
-    for (int k = 0; k < p->poll; ++k) {
+    for (int k = 0; k < per_round; ++k) {
       hipError_t e;
-      if ((e = Y(L_Y, +1, 0, 6, 1, LSFFT_K_YPASS)) != hipSuccess) return e;
-      if ((e = X(L_X, M_ITER, LSFFT_K_XPASS)) != hipSuccess) return e;
-      if ((e = Y(L_Y, -1, 0, 6, 1, LSFFT_K_YPASS)) != hipSuccess) return e;
+      if ((e = pass_y(b, L_Y, +1, 0, 6, 1, LSFFT_K_YPASS)) != hipSuccess) return e;
+      if ((e = pass_x(b, L_X, M_ITER, LSFFT_K_XPASS)) != hipSuccess) return e;
+      if ((e = pass_y(b, L_Y, -1, 0, 6, 1, LSFFT_K_YPASS)) != hipSuccess) return e;
       if (!cg) {
-        if ((e = Gp(L_G, M_ITER, LSFFT_K_GREEN)) != hipSuccess) return e;
-        if ((e = Rd(M_ITER)) != hipSuccess) return e;
+        if ((e = pass_g(b, L_G, M_ITER, LSFFT_K_GREEN)) != hipSuccess) return e;
+        if ((e = pass_reduce(b, M_ITER)) != hipSuccess) return e;
       } else {
-        if ((e = Gp(L_G, M_CG_AP, LSFFT_K_GREEN)) != hipSuccess) return e;
-        if ((e = Rd(M_CG_AP)) != hipSuccess) return e;
-        if ((e = CGU()) != hipSuccess) return e;
-        if ((e = Rd(M_CG_UPD)) != hipSuccess) return e;
-        if ((e = Gp(L_G, M_CG_DIR, LSFFT_K_GREEN)) != hipSuccess) return e;
+        if ((e = pass_g(b, L_G, M_CG_AP, LSFFT_K_GREEN)) != hipSuccess) return e;
+        if ((e = pass_reduce(b, M_CG_AP)) != hipSuccess) return e;
+        if ((e = pass_cg_update(b)) != hipSuccess) return e;
+        if ((e = pass_reduce(b, M_CG_UPD)) != hipSuccess) return e;
+        if ((e = pass_g(b, L_G, M_CG_DIR, LSFFT_K_GREEN)) != hipSuccess) return e;
       }
     }
     return hipSuccess;
@@ -687,9 +737,9 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
     hipGraphExec_t* g;
     ~GraphGuard() { if (*g) (void)hipGraphExecDestroy(*g); }
   } guard{&gexec};
-  const bool use_graph = p->graphs && !timing;
+  const bool use_graph = p->graphs && !timing && max_rounds == 0;
   std::vector<int> running;
-  for (;;) {
+  for (int r = 0; max_rounds == 0 || r < max_rounds; ++r) {
     if (use_graph) {
       if (!gexec) {
         hipGraph_t graph = nullptr;
@@ -711,11 +761,8 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
     } else {
       LSFFT_TRY(round());
     }
-    LSFFT_TRY(hipMemcpyAsync(b.state.data(), b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost, st));
-    LSFFT_TRY(hipStreamSynchronize(st));
-    running.clear();
-    for (int i = 0; i < n; ++i)
-      if (b.state[i].status == ST_RUNNING) running.push_back(i);
+    lsfft_status ls = read_states(b, running);
+    if (ls != LSFFT_OK) return ls;
     if (running.empty()) break;
     if ((int)running.size() < b.n_running) {
       ls = upload_lists(b, running, false);
@@ -724,24 +771,38 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
   }
   if (timing) timed_collect(p);
   p->timing_active = false;
+  return LSFFT_OK;
+}
 
-  // materialize u, eps, sigma of the returned iterates
-  LSFFT_TRY(Gp(L_GALL, M_MAT, LSFFT_K_OTHER));
-  LSFFT_TRY(Y(L_YALL, +1, 0, /*eps + u*/ 9, 0, LSFFT_K_OTHER));
-  LSFFT_TRY(X(L_XALL, M_MAT, LSFFT_K_OTHER));
+// u, eps, sigma of the returned iterates; the averaging accumulation.
+lsfft_status materialize(Batch& b) {
+  LSFFT_TRY(pass_g(b, L_GALL, M_MAT, LSFFT_K_OTHER));
+  LSFFT_TRY(pass_y(b, L_YALL, +1, 0, /*eps + u*/ 9, 0, LSFFT_K_OTHER));
+  LSFFT_TRY(pass_x(b, L_XALL, M_MAT, LSFFT_K_OTHER));
   if (b.averaging) {
     for (int g = 0; g < (int)b.groups.size(); ++g) {
       const Geometry& G = b.geo[b.groups[g].first];
-      LSFFT_TRY(launch_accumulate(f64, G.dim, base_args(b), b.d_groups, g, G.nvox));
+      LSFFT_TRY(launch_accumulate(b.p->f64, G.dim, base_args(b), b.d_groups, g, G.nvox));
     }
   }
-  LSFFT_TRY(hipStreamSynchronize(st));
-  const double secs =
-      std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() - t0_wall;
+  LSFFT_TRY(hipStreamSynchronize(b.p->stream));
+  return LSFFT_OK;
+}
 
+lsfft_status rank_worst(lsfft_status worst, int s) {
+  auto rank = [](int v) { return v == LSFFT_E_DIVERGED ? 4 : v == LSFFT_E_NOCONV ? 3 : v == LSFFT_W_STAGNATED ? 1 : 0; };
+  return rank(s) > rank(worst) ? (lsfft_status)s : worst;
+}
+
+lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
+  lsfft_status ls = prepare(b);
+  if (ls != LSFFT_OK) return ls;
+  if ((ls = setup(b, false)) != LSFFT_OK) return ls;
+  if ((ls = iterate(b)) != LSFFT_OK) return ls;
+  if ((ls = materialize(b)) != LSFFT_OK) return ls;
+  const double secs = now_s() - t0_wall;
   lsfft_status worst = LSFFT_OK;
-  auto rank = [](int s) { return s == LSFFT_E_DIVERGED ? 4 : s == LSFFT_E_NOCONV ? 3 : s == LSFFT_W_STAGNATED ? 1 : 0; };
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < (int)b.specs.size(); ++i) {
     const InstState& S = b.state[i];
     lsfft_report& r = rep[b.specs[i].out_index];
     r.iters = S.iter;
@@ -750,7 +811,111 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
     for (int c = 0; c < 3; ++c) r.removed_mean[c] = (c < b.geo[i].dim) ? L.removed_mean[c] : 0.0;
     r.status = S.status;
     r.seconds = secs;
-    if (rank(S.status) > rank(worst)) worst = (lsfft_status)S.status;
+    worst = rank_worst(worst, S.status);
+  }
+  return worst;
+}
+
+// Mixed-precision defect correction (FP32 plans with LSFFT_REFINE64).  The
+// state u lives in FP64 on the companion FP64 plan; each outer step
+//   1. evaluates the FP64 residual r = P f + div(L sym grad u) and its norm
+//      (one FP64 basic iteration: the stopping test runs on this residual),
+//   2. solves A d = r in FP32 with the plan's scheme to a relative residual
+//      of kInnerTol (A = -div(L sym grad .), the same operator),
+//   3. sets u += d in FP64.
+// The FP32 floor of the inner solves bounds only the reduction per step, not
+// the final accuracy.  The returned fields are materialized in FP32 from the
+// FP64 state rounded once.
+constexpr double kInnerTol = 1e-3;
+constexpr int kMaxOuter = 40;
+
+lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
+  lsfft_plan_s* p = b.p;
+  lsfft_plan_s* q = p->sub;
+  const int n = (int)b.specs.size();
+  const bool cg = p->scheme == LSFFT_CG;
+  hipStream_t st = p->stream;
+
+  // FP64 copies of the forces (exact widening), one per leader
+  size_t need = 0;
+  std::vector<size_t> foff(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (b.specs[i].leader != i) continue;
+    const lsfft_grid& g = p->grids[b.specs[i].grid];
+    foff[i] = need;
+    need = align_up(need + sizeof(double) * (size_t)g.dim * (size_t)(gnx(g) * gny(g) * gnz(g)));
+  }
+  if (!q->fwide.ensure(need)) return LSFFT_E_ALLOC;
+  Batch c;   // FP64 companion: state, force spectrum, residual
+  c.p = q;
+  c.tol = b.tol;
+  c.max_iter = kMaxOuter;
+  c.averaging = false;
+  c.specs = b.specs;
+  for (int i = 0; i < n; ++i) {
+    Spec& s = c.specs[i];
+    s.eps = s.sig = s.u = nullptr;
+    s.group = -1;
+    const lsfft_grid& g = p->grids[s.grid];
+    const long long cnt = (long long)g.dim * gnx(g) * gny(g) * gnz(g);
+    double* w = reinterpret_cast<double*>(static_cast<char*>(q->fwide.p) + foff[s.leader]);
+    if (s.leader == i) LSFFT_TRY(launch_widen(static_cast<const float*>(b.specs[i].f), w, cnt, st));
+    s.f = w;
+  }
+  lsfft_status ls = prepare(c);
+  if (ls != LSFFT_OK) return ls;
+  if ((ls = setup(c, false)) != LSFFT_OK) return ls;
+
+  // FP32 inner solves: one force spectrum per solve (the defects differ)
+  Batch in = b;
+  in.tol = kInnerTol;
+  for (int i = 0; i < n; ++i) in.specs[i].leader = i;
+  if ((ls = prepare(in)) != LSFFT_OK) return ls;
+  std::vector<long long> inner_iters(n, 0);
+  std::vector<int> running;
+  for (;;) {
+    // outer step 1: FP64 residual and stopping test at the current state
+    if ((ls = iterate(c, 1)) != LSFFT_OK) return ls;
+    if ((ls = read_states(c, running)) != LSFFT_OK) return ls;
+    if (running.empty()) break;
+    if ((ls = upload_lists(c, running, false)) != LSFFT_OK) return ls;
+    if ((ls = upload_lists(in, running, false)) != LSFFT_OK) return ls;
+    // step 2: defect as FP32 force, inner solve
+    LSFFT_TRY(launch_defect(c.d_desc, c.d_state, in.d_desc, c.d_inst, c.n_running, max_pc(c, running), st));
+    if ((ls = setup(in, true)) != LSFFT_OK) return ls;
+    if ((ls = iterate(in)) != LSFFT_OK) return ls;
+    std::vector<int> none;
+    if ((ls = read_states(in, none)) != LSFFT_OK) return ls;
+    for (int i : running) inner_iters[i] += in.state[i].iter;
+    // step 3: u += d in FP64
+    LSFFT_TRY(launch_correct(c.d_desc, c.d_state, in.d_desc, in.d_state, c.d_inst, c.n_running, cg,
+                             max_pc(c, running), st));
+    // strain spectrum of the corrected state, the input of the next residual
+    LSFFT_TRY(pass_g(c, L_G, M_MAT, LSFFT_K_OTHER));
+  }
+  // round the FP64 iterates once and materialize them in FP32
+  std::vector<int> all(n);
+  for (int i = 0; i < n; ++i) all[i] = i;
+  if ((ls = upload_lists(c, all, false)) != LSFFT_OK) return ls;
+  LSFFT_TRY(launch_narrow(c.d_desc, c.d_state, in.d_desc, c.d_inst, n, max_pc(c, all), st));
+  for (int i = 0; i < n; ++i) {
+    in.state[i].iter = 0;
+    in.state[i].status = c.state[i].status;
+  }
+  LSFFT_TRY(hipMemcpyAsync(in.d_state, in.state.data(), sizeof(InstState) * n, hipMemcpyHostToDevice, st));
+  if ((ls = materialize(in)) != LSFFT_OK) return ls;
+  const double secs = now_s() - t0_wall;
+  lsfft_status worst = LSFFT_OK;
+  for (int i = 0; i < n; ++i) {
+    const InstState& S = c.state[i];
+    lsfft_report& r = rep[b.specs[i].out_index];
+    r.iters = (int)std::min<long long>(inner_iters[i], 0x7fffffff);
+    r.residual = S.residual;
+    const InstState& L = c.state[c.specs[i].leader];
+    for (int k = 0; k < 3; ++k) r.removed_mean[k] = (k < c.geo[i].dim) ? L.removed_mean[k] : 0.0;
+    r.status = S.status;
+    r.seconds = secs;
+    worst = rank_worst(worst, S.status);
   }
   return worst;
 }
@@ -766,16 +931,56 @@ lsfft_status enter(lsfft_plan_s* p) {
   return LSFFT_OK;
 }
 
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
 lsfft_status worse(lsfft_status a, lsfft_status b) {
   auto rank = [](int s) {
     return s < 0 && s != LSFFT_E_NOCONV && s != LSFFT_E_DIVERGED ? 9
          : s == LSFFT_E_DIVERGED ? 4 : s == LSFFT_E_NOCONV ? 3 : s == LSFFT_W_STAGNATED ? 1 : 0;
   };
   return rank(a) >= rank(b) ? a : b;
+}
+
+// Twiddle table exp(-2 pi i k / L) for every supported length, long double
+// arithmetic rounded once to the plan precision.
+bool upload_twiddles(lsfft_plan_s* p) {
+  const int total = tw_total();
+  std::vector<double> twd(2 * (size_t)total);
+  for (int i = 0; i < kNumLens; ++i) {
+    const int L = len_at(i), o = tw_offset(L);
+    for (int k = 0; k < L; ++k) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)L;
+      twd[2 * (o + k)] = (double)cosl(ang);
+      twd[2 * (o + k) + 1] = (double)sinl(ang);
+    }
+  }
+  const size_t bytes = (p->f64 ? sizeof(double) : sizeof(float)) * twd.size();
+  if (!p->tw.ensure(bytes)) return false;
+  hipError_t e;
+  if (p->f64) {
+    e = hipMemcpy(p->tw.p, twd.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> twf(twd.begin(), twd.end());
+    e = hipMemcpy(p->tw.p, twf.data(), bytes, hipMemcpyHostToDevice);
+  }
+  return e == hipSuccess;
+}
+
+// Release a plan, its companion and every buffer they own.
+void free_plan(lsfft_plan_s* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->sub) free_plan(p->sub);
+  p->sub = nullptr;
+  if (p->owns_stream) {
+    if (p->stream) (void)hipStreamDestroy(p->stream);
+    if (p->ev_in) (void)hipEventDestroy(p->ev_in);
+  }
+  p->tw.release();
+  p->arena.release();
+  p->meta.release();
+  p->lists.release();
+  p->fwide.release();
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  delete p;
 }
 
 }  // namespace
@@ -820,7 +1025,8 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
   if (!grids || ngrid < 1 || max_batch < 1) return LSFFT_E_ARG;
   if (prec != LSFFT_F32 && prec != LSFFT_F64) return LSFFT_E_ARG;
   if (scheme != LSFFT_BASIC && scheme != LSFFT_CG) return LSFFT_E_ARG;
-  if (flags & ~(LSFFT_STRICT_EQUIL | LSFFT_TIMING)) return LSFFT_E_ARG;
+  if (flags & ~(LSFFT_STRICT_EQUIL | LSFFT_TIMING | LSFFT_REFINE64)) return LSFFT_E_ARG;
+  if ((flags & LSFFT_REFINE64) && (prec != LSFFT_F32 || max_batch > 65535)) return LSFFT_E_ARG;
   for (int g = 0; g < ngrid; ++g) {
     const lsfft_grid& G = grids[g];
     if (G.dim != 2 && G.dim != 3) return LSFFT_E_ARG;
@@ -856,34 +1062,31 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
     const int v = std::atoi(e);
     if (v >= 1 && v <= 1024) p->poll = v;
   }
-  // twiddle table exp(-2 pi i k / L) for every supported length, long double
-  // arithmetic rounded once to the plan precision
-  const int total = tw_total();
-  std::vector<double> twd(2 * (size_t)total);
-  for (int i = 0; i < kNumLens; ++i) {
-    const int L = len_at(i), o = tw_offset(L);
-    for (int k = 0; k < L; ++k) {
-      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)L;
-      twd[2 * (o + k)] = (double)cosl(ang);
-      twd[2 * (o + k) + 1] = (double)sinl(ang);
-    }
-  }
-  const size_t bytes = (p->f64 ? sizeof(double) : sizeof(float)) * twd.size();
-  if (!p->tw.ensure(bytes)) {
-    delete p;
+  if (!upload_twiddles(p)) {
+    free_plan(p);
     return LSFFT_E_ALLOC;
   }
-  hipError_t e;
-  if (p->f64) {
-    e = hipMemcpy(p->tw.p, twd.data(), bytes, hipMemcpyHostToDevice);
-  } else {
-    std::vector<float> twf(twd.begin(), twd.end());
-    e = hipMemcpy(p->tw.p, twf.data(), bytes, hipMemcpyHostToDevice);
-  }
-  if (e != hipSuccess) {
-    p->tw.release();
-    delete p;
-    return LSFFT_E_DEVICE;
+  if (flags & LSFFT_REFINE64) {
+    lsfft_plan_s* q = new (std::nothrow) lsfft_plan_s();
+    if (!q) {
+      free_plan(p);
+      return LSFFT_E_ALLOC;
+    }
+    q->device = dev;
+    q->ustream = p->ustream;
+    q->stream = p->stream;
+    q->owns_stream = false;
+    q->graphs = p->graphs;
+    q->f64 = true;
+    q->scheme = LSFFT_BASIC;
+    q->flags = flags & LSFFT_STRICT_EQUIL;   // the force check runs on the FP64 force transform
+    q->grids = p->grids;
+    q->max_batch = p->max_batch;
+    p->sub = q;
+    if (!upload_twiddles(q)) {
+      free_plan(p);
+      return LSFFT_E_ALLOC;
+    }
   }
   *out = p;
   return LSFFT_OK;
@@ -891,15 +1094,7 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
 
 lsfft_status lsfft_plan_destroy(lsfft_plan_t p) {
   if (!p) return LSFFT_OK;
-  (void)hipStreamSynchronize(p->stream);
-  (void)hipStreamDestroy(p->stream);
-  (void)hipEventDestroy(p->ev_in);
-  p->tw.release();
-  p->arena.release();
-  p->meta.release();
-  p->lists.release();
-  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-  delete p;
+  free_plan(p);
   return LSFFT_OK;
 }
 
@@ -939,7 +1134,7 @@ lsfft_status lsfft_solve_bfcs(lsfft_plan_t p, int nsolve, const int* grid_idx, c
     b.specs.assign(specs.begin() + start, specs.begin() + start + cnt);
     for (int i = 0; i < cnt; ++i) b.specs[i].leader = i;
     const double t0 = now_s();
-    lsfft_status s = run_batch(b, rep, t0);
+    lsfft_status s = p->sub ? run_refined(b, rep, t0) : run_batch(b, rep, t0);
     if (s == LSFFT_E_ARG || s == LSFFT_E_ALLOC || s == LSFFT_E_DEVICE || s == LSFFT_E_NONEQUIL) return s;
     worst = worse(worst, s);
   }
@@ -1017,7 +1212,7 @@ lsfft_status lsfft_translate_average_batch(lsfft_plan_t p, int ngroup, const lsf
       b.specs[i].leader = b.groups.back().first;
     }
     const double t0 = now_s();
-    lsfft_status s = run_batch(b, rep, t0);
+    lsfft_status s = p->sub ? run_refined(b, rep, t0) : run_batch(b, rep, t0);
     if (s == LSFFT_E_ARG || s == LSFFT_E_ALLOC || s == LSFFT_E_DEVICE || s == LSFFT_E_NONEQUIL) return s;
     worst = worse(worst, s);
   }

@@ -22,7 +22,7 @@ OK, W_STAGNATED = 0, 1
 E_ARG, E_ALLOC, E_DEVICE, E_NOCONV, E_NONEQUIL, E_DIVERGED = -1, -2, -3, -4, -5, -6
 F32, F64 = 0, 1
 BASIC, CG = 0, 1
-STRICT_EQUIL, TIMING = 0x1, 0x2
+STRICT_EQUIL, TIMING, REFINE64 = 0x1, 0x2, 0x4
 K_XPASS, K_YPASS, K_GREEN, K_REDUCE, K_CGUPD, K_OTHER = range(6)
 
 EXPORTS = [
@@ -139,7 +139,7 @@ class Plan:
     """A solver plan for one or more grids (array-order shapes)."""
 
     def __init__(self, shapes, prec: str = "f64", scheme: str = "basic", max_batch: int = 1,
-                 strict_equil: bool = False, timing: bool = False, spacing=None):
+                 strict_equil: bool = False, timing: bool = False, spacing=None, refine: bool = False):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("liblsfft needs a HIP GPU; none is visible")
@@ -159,7 +159,7 @@ class Plan:
             for a in range(3):
                 grids[g].n[a] = rev[a]
                 grids[g].h[a] = 1.0 if spacing is None else float(list(reversed(spacing[g]))[a] if a < d else 1.0)
-        flags = (STRICT_EQUIL if strict_equil else 0) | (TIMING if timing else 0)
+        flags = (STRICT_EQUIL if strict_equil else 0) | (TIMING if timing else 0) | (REFINE64 if refine else 0)
         self.stream = torch.cuda.current_stream()
         h = C.c_void_p()
         st = self.lib.lsfft_plan(C.byref(h), grids, len(self.shapes), int(max_batch),

@@ -90,6 +90,8 @@ def test_plan_rejects_bad_scalars(lib):
     assert lib.lsfft_plan(C.byref(out), C.byref(g), 1, 1, 2, 0, 0, None) == -1   # precision
     assert lib.lsfft_plan(C.byref(out), C.byref(g), 1, 1, 0, 5, 0, None) == -1   # scheme
     assert lib.lsfft_plan(C.byref(out), C.byref(g), 1, 1, 0, 0, 0x80, None) == -1  # flags
+    assert lib.lsfft_plan(C.byref(out), C.byref(g), 1, 1, 1, 0, 0x4, None) == -1   # FP64 refinement
+    assert lib.lsfft_plan(C.byref(out), C.byref(g), 1, 70000, 0, 0, 0x4, None) == -1  # batch too large
 
 
 def test_calls_on_null_plan(lib):
