@@ -22,7 +22,7 @@ def sources():
     """Every HIP translation unit in csrc/ (largest first) plus the host code."""
     hips = sorted((f for f in os.listdir(CSRC) if f.endswith(".hip")),
                   key=lambda f: (not f.startswith("k_g_"), f))
-    return hips + ["lsfft.cpp"]
+    return hips + ["lsfft.cpp", "fno.cpp"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

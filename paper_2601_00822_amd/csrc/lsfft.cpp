@@ -291,6 +291,16 @@ struct Batch {
   double tol = 1e-8;
   int max_iter = 0;
   bool averaging = false;
+  // the captured polling round, kept for the batch's lifetime (the inner
+  // solves of the defect correction replay it once per outer step)
+  struct GraphHolder {
+    hipGraphExec_t exec = nullptr;
+    GraphHolder() = default;
+    GraphHolder(const GraphHolder&) {}              // copies start without a graph
+    GraphHolder& operator=(const GraphHolder&) { return *this; }
+    ~GraphHolder() { if (exec) (void)hipGraphExecDestroy(exec); }
+  } graph;
+  std::vector<WorkItem> host_items[L_NUM];         // staging of the uploaded lists
 };
 
 LaunchArgs largs(Batch& b, int list, const Seg& sg, int units = 1) {
@@ -381,7 +391,8 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
       for (auto& x : b.segs[l]) counts[x.cidx] = x.count;
       continue;
     }
-    std::vector<WorkItem> items(b.list_cap[l] > 0 ? b.list_cap[l] : 1);
+    std::vector<WorkItem>& items = b.host_items[l];
+    items.resize(b.list_cap[l] > 0 ? b.list_cap[l] : 1);
     for (auto& x : b.segs[l]) {
       int fill = 0;
       const std::vector<int>* src = &running;
@@ -406,8 +417,6 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
         LSFFT_TRY(hipMemcpyAsync(b.d_lists[l] + x.off, items.data() + x.off, sizeof(WorkItem) * fill,
                                  hipMemcpyHostToDevice, b.p->stream));
     }
-    // the host vector dies at the end of this iteration: wait for its copies
-    LSFFT_TRY(hipStreamSynchronize(b.p->stream));
   }
   std::vector<int> inst(running.begin(), running.end());
   counts[kMaxSegs - 1] = (int)inst.size();   // solves listed for the reduction
@@ -732,11 +741,7 @@ lsfft_status iterate(Batch& b, int max_rounds = 0) {
   // replayed: launch grids are fixed at capture (the largest work lists), the
   // kernels read the current item counts from device memory, so retiring
   // solves later needs no recapture.
-  hipGraphExec_t gexec = nullptr;
-  struct GraphGuard {
-    hipGraphExec_t* g;
-    ~GraphGuard() { if (*g) (void)hipGraphExecDestroy(*g); }
-  } guard{&gexec};
+  hipGraphExec_t& gexec = b.graph.exec;
   const bool use_graph = p->graphs && !timing && max_rounds == 0;
   std::vector<int> running;
   for (int r = 0; max_rounds == 0 || r < max_rounds; ++r) {

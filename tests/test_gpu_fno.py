@@ -1,0 +1,144 @@
+"""GPU parity of the surrogate kernels (through the C ABI) against the FP64
+oracle of the same network with its matrix-product operands rounded to
+bf16 like the kernels' MFMA operands.
+
+What remains between the two is fp32 arithmetic (transforms, accumulation
+order, GELU, loss) and the rare operand whose bf16 rounding flips because
+the fp32 activation differs from the fp64 one in its last bits: both are far
+below the bars used here (relative L2 1e-3 for outputs, 5e-3 per gradient
+tensor).  The unrounded fp64 network is checked at the bf16 level (3e-2).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fno_oracle as F
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_00822_amd import load_library
+    load_library()
+    return torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def random_params(arch, seed):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shp in arch.layout():
+        if name.startswith("r"):
+            s = 1.0 / arch.width
+            p[name] = rng.uniform(-s, s, size=shp) + 1j * rng.uniform(-s, s, size=shp)
+        elif name.endswith("_b") or name.startswith("b"):
+            p[name] = rng.normal(size=shp) * 0.1
+        else:
+            p[name] = rng.uniform(-1, 1, size=shp) / np.sqrt(shp[1])
+    # the kernels see fp32 parameters
+    return {k: (v.astype(np.complex64).astype(np.complex128) if np.iscomplexobj(v)
+                else v.astype(np.float32).astype(np.float64)) for k, v in p.items()}
+
+
+def oracle_arch(a):
+    return F.Arch(n=a.n, modes=a.modes, width=a.width, hidden=a.hidden, cin=a.cin, cout=a.cout, layers=a.layers)
+
+
+SMALL = dict(n=16, modes=4, hidden=64, layers=2)
+FULL = dict()
+
+
+@pytest.mark.parametrize("kw,batch", [(SMALL, 5), (SMALL, 33), (FULL, 2)])
+def test_forward_and_gradients(torch_mod, kw, batch):
+    torch = torch_mod
+    from paper_2601_00822_amd.fno import FnoArch, Surrogate, pack, unpack
+    arch = FnoArch(**kw)
+    say(f"surrogate forward/backward {arch} batch {batch}")
+    oa = oracle_arch(arch)
+    p = random_params(arch, 1)
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=(batch, arch.cin) + (arch.n,) * 3).astype(np.float32)
+    t = rng.normal(size=(batch, arch.cout) + (arch.n,) * 3).astype(np.float32)
+    s = Surrogate(arch, max_batch=batch)
+    s.set_params(pack(arch, p))
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    y = s.forward(xd).cpu().numpy().astype(np.float64)
+    yo = F.forward(p, x.astype(np.float64), oa, bf16=True)
+    y64 = F.forward(p, x.astype(np.float64), oa, bf16=False)
+    e_bf, e_64 = rel(y, yo), rel(y, y64)
+    print(f"forward: vs bf16-operand oracle {e_bf:.2e}, vs fp64 oracle {e_64:.2e}")
+    assert e_bf < 1e-3 and e_64 < 3e-2
+    loss, g = s.loss_grad(xd, td)
+    lo, go = F.backward(p, x.astype(np.float64), t.astype(np.float64), oa, bf16=True)
+    print(f"loss gpu {loss:.8f} oracle {lo:.8f}")
+    assert abs(loss - lo) <= 1e-4 * abs(lo)
+    gg = unpack(arch, g.cpu().numpy())
+    worst = max((rel(gg[k], go[k]), k) for k in go)
+    print(f"worst gradient tensor {worst[1]}: {worst[0]:.2e}")
+    for k in go:
+        assert rel(gg[k], go[k]) < 5e-3, (k, rel(gg[k], go[k]))
+    s.close()
+
+
+def test_adam_step(torch_mod):
+    torch = torch_mod
+    from paper_2601_00822_amd.fno import FnoArch, Surrogate, pack, unpack
+    arch = FnoArch(**SMALL)
+    say("surrogate Adam: two steps against the oracle update on the kernels' gradients")
+    p = random_params(arch, 3)
+    rng = np.random.default_rng(4)
+    x = torch.from_numpy(rng.normal(size=(3, arch.cin) + (arch.n,) * 3).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.normal(size=(3, arch.cout) + (arch.n,) * 3).astype(np.float32)).cuda()
+    s = Surrogate(arch, max_batch=3)
+    s.set_params(pack(arch, p))
+    ref = {k: v.copy() for k, v in p.items()}
+    state = {}
+    for step in (1, 2):
+        _, g = s.loss_grad(x, t)
+        s.adam(1e-3)
+        gd = unpack(arch, g.cpu().numpy())
+        F.adam_step(ref, gd, state, lr=1e-3, step=step)
+        got = unpack(arch, s.get_params().cpu().numpy())
+        for k in ref:
+            assert np.abs(got[k] - ref[k]).max() <= 1e-6, (step, k)
+    s.close()
+
+
+def test_training_reduces_the_loss(torch_mod):
+    """Fit a fixed linear Fourier-space map on random inputs: the loss after
+    a few dozen steps must be well below its start (kernels and Adam work
+    together)."""
+    torch = torch_mod
+    from paper_2601_00822_amd.fno import FnoArch, Surrogate, pack
+    arch = FnoArch(n=16, modes=4, hidden=64, layers=2, cin=3, cout=6)
+    say("surrogate training smoke: 60 steps")
+    p = random_params(arch, 5)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(16, arch.cin) + (arch.n,) * 3)
+    # target: smooth linear response of the inputs (low-pass, channel mix)
+    xh = np.fft.rfftn(x, axes=(2, 3, 4))
+    k = np.fft.fftfreq(arch.n)[:, None, None] ** 2 + np.fft.fftfreq(arch.n)[None, :, None] ** 2 + \
+        np.fft.rfftfreq(arch.n)[None, None, :] ** 2
+    mix = rng.normal(size=(arch.cout, arch.cin))
+    t = np.fft.irfftn(np.einsum("oi,bi...->bo...", mix, xh) * np.exp(-40 * k), s=(arch.n,) * 3, axes=(2, 3, 4))
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    td = torch.from_numpy((t / t.std()).astype(np.float32)).cuda()
+    s = Surrogate(arch, max_batch=16)
+    s.set_params(pack(arch, p))
+    losses = [s.train_step(xd, td, 3e-3) for _ in range(60)]
+    print(f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.5 * losses[0]
+    s.close()
