@@ -42,6 +42,11 @@ WORKLOADS = {
     "bfcs256soft": dict(shape=(256, 256, 256), cell=16, vf=0.30, contrast=0.01, radius=12.0, rsa=True,
                         desc="3D 256^3 (16^3 cells of 16^3), RSA spheres vf 0.3 r 3-6, soft inclusions "
                              "contrast 0.01, vector bump R=12, to 1e-8"),
+    "surrogate": dict(surrogate=True, desc="learned surrogate: 64^3 grid, one sphere per 16^3 cell (vf 0.25, "
+                                            "contrast 10); forces of 1-3 bumps R 4-12; targets = translation "
+                                            "averages over all 4096 intra-cell shifts (FP64 solver kernel) "
+                                            "restricted to 32^3; Fourier neural operator 4 layers, width 32, "
+                                            "12 modes, bf16 MFMA training and inference"),
     "batch512": dict(batch=True, desc="512 solves in one call: 8 microstructures (48^3, 64^3, 96^3 "
                                       "round robin, cells of 16^3, RSA spheres r 3-6, vf U[0.10,0.35], "
                                       "contrast log-uniform [2,100]) x 64 seeded intra-cell shifts, "
@@ -131,6 +136,117 @@ def run_batch_workload(args, wl):
     }
 
 
+def run_surrogate_workload(args, wl):
+    """Averaged-strain kernel from the FP64 solver, dataset, training,
+    held-out error against the solver, and the surrogate-vs-solver speedup."""
+    import numpy as np
+    import torch
+    import gen
+    from paper_2601_00822_amd import Plan, lame_from_young
+    from paper_2601_00822_amd import surrogate as S
+    from paper_2601_00822_amd.fno import FnoArch, Surrogate
+
+    def log(msg):
+        print(f"[surrogate] {msg}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    n, cell = 64, 16
+    phase_np, vf = gen.inclusion_per_cell((n, n, n), cell, 0.25)
+    lame = lame_from_young(gen.Material.two_phase(1.0, 10.0).table())
+    phase = torch.from_numpy(phase_np).to(dev)
+    t0 = time.perf_counter()
+    K, kreps = S.averaged_strain_kernel(phase, lame, cell, prec="f64", max_batch=512)
+    torch.cuda.synchronize()
+    t_kernel = time.perf_counter() - t0
+    log(f"averaged-strain kernel: {len(kreps)} FP64 solves in {t_kernel:.1f} s, "
+        f"max residual {max(r.residual for r in kreps):.2e}")
+    Khat = S.kernel_spectrum(K)
+
+    def make(count, seed):
+        params = gen.bump_set_params(n, count, seed)
+        X, T = [], []
+        for k in range(0, count, 64):
+            f = gen.bump_set_torch(n, params[k:k + 64], dev)
+            e = S.averaged_strain_from_kernel(Khat, f)
+            X.append(S.restrict2(f).float())
+            T.append(S.restrict2(e).float())
+        return torch.cat(X).contiguous(), torch.cat(T).contiguous(), params
+
+    t0 = time.perf_counter()
+    Xtr, Ttr, _ = make(args.train_samples, 1)
+    Xte, Tte, pte = make(args.test_samples, 2)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    xs, ts = float(Xtr.std()), float(Ttr.std())
+    log(f"dataset: {Xtr.shape[0]} train / {Xte.shape[0]} held-out pairs in {t_data:.1f} s")
+    arch = FnoArch()
+    model = Surrogate(arch, max_batch=args.fno_batch)
+    model.set_params(S.init_params(arch, 0))
+    tr = S.train(model, Xtr / xs, Ttr / ts, epochs=args.epochs, batch=args.fno_batch, lr=args.lr,
+                 seed=3, log_every=200, printer=log)
+    log(f"training: {tr.steps} steps in {tr.seconds:.1f} s ({1e3 * tr.seconds / max(tr.steps, 1):.2f} ms/step)")
+    Y = S.predict(model, (Xte / xs).contiguous(), args.fno_batch) * ts
+    err = S.relative_l2(Y, Tte)
+    log(f"held-out relative L2: mean {err.mean():.4f} max {err.max():.4f}")
+
+    # the FP64 solver as judge: direct translation averages of held-out forces
+    plan64 = Plan([(n, n, n)], prec="f64", max_batch=512)
+    checks = []
+    t_direct = 0.0
+    for i in range(args.direct_checks):
+        f = gen.bump_set_torch(n, [pte[i]], dev)[0].contiguous()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        avg, _ = plan64.translate_average(phase, lame, f, S.cell_shifts(cell), tol=1e-8)
+        torch.cuda.synchronize()
+        t_direct = time.perf_counter() - t1
+        direct = S.restrict2(avg[6:12]).float()
+        checks.append({"surrogate_vs_direct": float(S.relative_l2(Y[i:i + 1], direct[None])[0]),
+                       "kernel_target_vs_direct": float(S.relative_l2(Tte[i:i + 1], direct[None])[0])})
+        log(f"direct FP64 check {i}: {checks[-1]} ({t_direct:.1f} s)")
+    plan64.close()
+    # solver time for one averaged field with the benchmark solver (FP32 + FP64 correction)
+    plan32 = Plan([(n, n, n)], prec="f32", max_batch=512, refine=True)
+    f = gen.bump_set_torch(n, [pte[0]], dev, dtype=torch.float32)[0].contiguous()
+    plan32.translate_average(phase, lame, f, S.cell_shifts(cell)[:64], tol=1e-8)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan32.translate_average(phase, lame, f, S.cell_shifts(cell), tol=1e-8)
+    torch.cuda.synchronize()
+    t_solver = time.perf_counter() - t1
+    plan32.close()
+    # surrogate inference time per averaged field (batched)
+    xb = (Xte[:args.fno_batch] / xs).contiguous()
+    model.forward(xb)
+    torch.cuda.synchronize()
+    reps = 20
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        model.forward(xb)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t1) / (reps * xb.shape[0])
+    speedup = t_solver / t_inf
+    log(f"solver {t_solver:.2f} s per averaged field, surrogate {1e6 * t_inf:.1f} us per field")
+    model.close()
+    return {
+        "metric": METRIC, "value": speedup, "unit": "x (solver s / surrogate s per averaged field)",
+        "n_gpus": 1, "steps": tr.steps, "warmup": 0, "ms_per_step": 1e3 * tr.seconds / max(tr.steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "surrogate", "description": wl["desc"], "grid": [n, n, n], "coarse": [32, 32, 32],
+                   "train_samples": int(Xtr.shape[0]), "heldout_samples": int(Xte.shape[0]),
+                   "epochs": args.epochs, "batch": args.fno_batch, "lr": args.lr,
+                   "arch": {"layers": arch.layers, "width": arch.width, "modes": arch.modes,
+                            "hidden": arch.hidden}},
+        "heldout_rel_l2": {"mean": float(err.mean()), "median": float(np.median(err)), "max": float(err.max())},
+        "direct_fp64_checks": checks,
+        "final_train_loss": float(np.mean(tr.losses[-50:])),
+        "seconds": {"kernel_solves": t_kernel, "dataset": t_data, "training": tr.seconds,
+                    "solver_per_field_f32": t_solver, "solver_per_field_f64": t_direct,
+                    "surrogate_per_field": t_inf},
+    }
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for name in ("kernels_impl.hpp", "fft_core.hpp"):
@@ -197,6 +313,12 @@ def main() -> int:
     ap.add_argument("--no-refine", action="store_true",
                     help="FP32 without the FP64 defect correction (stops at the FP32 stagnation floor)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-samples", type=int, default=20000)
+    ap.add_argument("--test-samples", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--fno-batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--direct-checks", type=int, default=2)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the solves, run one plain device-to-device copy of this many MiB "
@@ -214,6 +336,9 @@ def main() -> int:
     wl = WORKLOADS[args.workload]
     if wl.get("batch"):
         print(json.dumps(run_batch_workload(args, wl)))
+        return 0
+    if wl.get("surrogate"):
+        print(json.dumps(run_surrogate_workload(args, wl)))
         return 0
     dev = torch.device("cuda:0")
     phase, f, table, _ = make_inputs(wl)

@@ -25,6 +25,7 @@ __all__ = [
     "Material", "inclusion_per_cell", "rsa_cell", "tile_cell", "laminate",
     "bump_force", "dipole_force", "multi_bump_force", "sample_shifts",
     "all_shifts", "random_direction", "random_center", "grid_positions",
+    "bump_set_params", "bump_set_torch", "point_force",
 ]
 
 
@@ -235,3 +236,55 @@ def sample_shifts(cell: int, d: int, n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(len(full), size=n, replace=False))
     return np.ascontiguousarray(full[idx])
+
+
+def point_force(shape, direction_index: int) -> np.ndarray:
+    """Unit force at the origin voxel along one axis (component-major)."""
+    f = np.zeros((len(shape),) + tuple(shape))
+    f[(direction_index,) + (0,) * len(shape)] = 1.0
+    return f
+
+
+def bump_set_params(n: int, count: int, seed: int, nmin: int = 1, nmax: int = 3,
+                    rmin: float = 4.0, rmax: float = 12.0) -> list:
+    """Seeded parameters of ``count`` forces on an ``n^3`` grid, each a sum of
+    ``nmin..nmax`` vector bumps with uniform centres, radii uniform in
+    ``[rmin, rmax]`` and directions uniform on the sphere.  Returns a list of
+    lists of ``(center[3] array order, radius, direction[3] x first)``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        k = int(rng.integers(nmin, nmax + 1))
+        bumps = []
+        for _ in range(k):
+            c = rng.uniform(0.0, n, size=3)
+            r = float(rng.uniform(rmin, rmax))
+            v = rng.normal(size=3)
+            bumps.append((c, r, v / np.linalg.norm(v)))
+        out.append(bumps)
+    return out
+
+
+def bump_set_torch(n: int, params: list, device, dtype=None):
+    """Evaluate forces from ``bump_set_params`` on the GPU: returns a tensor
+    ``[len(params)][3][n][n][n]`` with the same bump profile as
+    ``bump_force`` (periodic minimum image)."""
+    import torch
+    dtype = dtype or torch.float64
+    ax = torch.arange(n, device=device, dtype=torch.float64)
+    out = torch.zeros((len(params), 3, n, n, n), device=device, dtype=dtype)
+    for i, bumps in enumerate(params):
+        for c, r, v in bumps:
+            r2 = 0.0
+            for a in range(3):
+                t = torch.remainder(ax - float(c[a]), float(n))
+                t = torch.where(t > n / 2.0, t - n, t)
+                shp = [1, 1, 1]
+                shp[a] = n
+                r2 = r2 + (t * t).view(shp)
+            q = r2 / (r * r)
+            b = torch.where(q < 1.0, torch.exp(-1.0 / (1.0 - torch.clamp(q, max=1.0 - 1e-12))),
+                            torch.zeros_like(q))
+            for comp in range(3):
+                out[i, comp] += (b * float(v[comp])).to(dtype)
+    return out
