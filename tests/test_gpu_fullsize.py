@@ -4,7 +4,9 @@ launch configuration bench.py times.
 
 * FP64: the complete oracle solve (Algorithm 1, NumPy FP64) at full size,
   iterate count and strain compared to the GPU (about a minute of CPU).
-* FP32: relative strain error against the FP64 result <= 1e-5.
+* FP32: relative strain error against the FP64 result <= 1e-5; with the FP64
+  defect correction (the configuration bench.py times) the FP64-evaluated
+  residual meets 1e-8 and the error is <= 1e-6, also at contrast 100.
 * Properties that hold at any size, computed on the CPU in FP64 from the
   GPU fields: the equilibrium residual equals the reported one, sigma = L eps,
   eps = sym grad u.
@@ -43,9 +45,10 @@ def gpu_results(setup):
     torch, dev, phase, f, lame = setup
     from paper_2601_00822_amd import Plan
     out = {}
-    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+    for prec, dt, refine in (("f64", torch.float64, False), ("f32", torch.float32, False),
+                             ("f32r", torch.float32, True)):
         say(f"128^3 solve {prec}")
-        plan = Plan([SHAPE], prec=prec)
+        plan = Plan([SHAPE], prec=prec[:3], refine=refine)
         res, rep = plan.solve(torch.from_numpy(phase).to(dev), lame, torch.from_numpy(f).to(dev).to(dt), tol=1e-8)
         torch.cuda.synchronize()
         out[prec] = ({k: v.double().cpu().numpy() for k, v in res.items()}, rep)
@@ -103,3 +106,38 @@ def test_fp64_against_full_oracle(setup, gpu_results):
     assert rep.iters == ref.iters
     assert err < 1e-10
     assert np.abs(res["u"] - ref.u).max() < 1e-10 * np.abs(ref.u).max()
+
+
+def test_fp32_refined_against_fp64(setup, gpu_results):
+    torch, dev, phase, f, lame = setup
+    r64, _ = gpu_results["f64"]
+    r32, rep = gpu_results["f32r"]
+    err = O.relative_strain_error_voigt(r32["eps"], r64["eps"])
+    r = independent_residual(phase, lame, f, r32["sig"])
+    say(f"fp32+fp64 correction iters={rep.iters} residual={rep.residual:.3e} cpu residual of the fp32 "
+        f"fields={r:.3e} strain err vs fp64={err:.3e}")
+    assert rep.status == 0 and rep.residual <= 1e-8
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("scheme", ["basic", "cg"])
+def test_refined_high_contrast_128(setup, scheme):
+    """128^3, random spheres vf 0.3 (r 3-6) in 16^3 cells, contrast 100, bump
+    R = 12: FP32 with the FP64 correction against the FP64 basic solve."""
+    torch, dev, _, _, _ = setup
+    from paper_2601_00822_amd import Plan
+    say(f"128^3 contrast 100 FP32+FP64 correction, {scheme}")
+    phase = gen.tile_cell(gen.rsa_cell(16, 3, 0.3, 3.0, 6.0, seed=11)[0], SHAPE)
+    f = gen.bump_force(SHAPE, gen.random_center(SHAPE, 5), 12.0, gen.random_direction(3, 6))
+    lame = O.lame_from_young(gen.Material.two_phase(1.0, 100.0).table())
+    ph, fd = torch.from_numpy(phase).to(dev), torch.from_numpy(f).to(dev)
+    p64 = Plan([SHAPE], prec="f64")
+    o64, r64 = p64.solve(ph, lame, fd, tol=1e-8, max_iter=20000)
+    p64.close()
+    p32 = Plan([SHAPE], prec="f32", scheme=scheme, refine=True)
+    o32, r32 = p32.solve(ph, lame, fd.float(), tol=1e-8, max_iter=20000)
+    p32.close()
+    e = O.relative_strain_error_voigt(o32["eps"].double().cpu().numpy(), o64["eps"].cpu().numpy())
+    print(f"fp64 iters {r64.iters}; fp32 {scheme} iters {r32.iters} residual {r32.residual:.3e} err {e:.3e}")
+    assert r64.status == 0 and r32.status == 0 and r32.residual <= 1e-8
+    assert e < 1e-6
