@@ -60,6 +60,8 @@ template <int N> struct PlanG;
     static constexpr int np = NP_;                                         \
     static constexpr int r0 = R0, r1 = R1, r2 = R2;                        \
   };
+LSFFT_PLANG(2, 1, 2, 1, 1)
+LSFFT_PLANG(3, 1, 3, 1, 1)
 LSFFT_PLANG(4, 1, 4, 1, 1)
 LSFFT_PLANG(6, 2, 2, 3, 1)
 LSFFT_PLANG(8, 2, 2, 4, 1)

@@ -106,7 +106,7 @@ hipError_t launch_pointwise(const PwArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // pointwise weight gradient: MFMA over 16-voxel chunks, per-block partials
 // ---------------------------------------------------------------------------
-constexpr int kWgBlocks = 512;
+constexpr int kWgBlocks = 256;
 int wgrad_blocks(int B, long long V) {
   const long long chunks = (long long)B * (V / 16);
   long long nb = (chunks + 3) / 4;
@@ -186,19 +186,28 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   }
 }
 
+// Fixed-order sum of the per-block partials: a block covers 64 consecutive
+// packed outputs, its four waves sum interleaved quarters of the partials,
+// and the quarters are added in a fixed order.
 __global__ __launch_bounds__(NTB) void k_wgrad_reduce(const float* __restrict__ part, int nblk, int O, int I,
                                                       int opad, int ipad, float* __restrict__ gw,
                                                       float* __restrict__ gb) {
+  __shared__ float red[4][64];
   const int n = O * I + O;
   const int stride = opad * ipad + opad;
-  for (int k = blockIdx.x * NTB + threadIdx.x; k < n; k += gridDim.x * NTB) {
-    int src;
-    if (k < O * I) src = (k / I) * ipad + (k % I);
-    else src = opad * ipad + (k - O * I);
-    float s = 0.0f;
-    for (int blk = 0; blk < nblk; ++blk) s += part[(size_t)blk * stride + src];
-    if (k < O * I) gw[k] = s;
-    else gb[k - O * I] = s;
+  const int k = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;
+  float s = 0.0f;
+  if (k < n) {
+    const int src = (k < O * I) ? (k / I) * ipad + (k % I) : opad * ipad + (k - O * I);
+    for (int blk = q; blk < nblk; blk += 4) s += part[(size_t)blk * stride + src];
+  }
+  red[q][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (q == 0 && k < n) {
+    const float t = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    if (k < O * I) gw[k] = t;
+    else gb[k - O * I] = t;
   }
 }
 
@@ -217,7 +226,7 @@ hipError_t launch_wgrad(const WgArgs& a, float* gw, float* gb, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = a.O * a.I + a.O;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + NTB - 1) / NTB)), NTB, 0, s, a.part, a.nblk, a.O, a.I,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), NTB, 0, s, a.part, a.nblk, a.O, a.I,
                      a.opad, a.ipad, gw, gb);
   return hipGetLastError();
 }
@@ -586,12 +595,13 @@ __global__ __launch_bounds__(NTB) void k_loss_part(const float* __restrict__ y, 
   }
 }
 
-// per-sample coefficients 1 / (||e_b|| ||t_b|| B) and the mean loss
-__global__ void k_loss_final(const double* __restrict__ part, int B, int nchunk, double* __restrict__ coef,
-                             double* __restrict__ loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// per-sample coefficients 1 / (||e_b|| ||t_b|| B) and the mean loss (one
+// block; a thread per sample, then a fixed-order sum)
+__global__ __launch_bounds__(NTB) void k_loss_final(const double* __restrict__ part, int B, int nchunk,
+                                                    double* __restrict__ coef, double* __restrict__ loss) {
+  __shared__ double red[NTB];
   double acc = 0.0;
-  for (int b = 0; b < B; ++b) {
+  for (int b = threadIdx.x; b < B; b += NTB) {
     double e = 0.0, n = 0.0;
     for (int c = 0; c < nchunk; ++c) {
       e += part[((size_t)b * nchunk + c) * 2];
@@ -601,7 +611,13 @@ __global__ void k_loss_final(const double* __restrict__ part, int B, int nchunk,
     acc += en / tn;
     coef[b] = 1.0 / (fmax(en, 1e-300) * tn * (double)B);
   }
-  *loss = acc / (double)B;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < NTB; ++k) s += red[k];
+    *loss = s / (double)B;
+  }
 }
 
 __global__ __launch_bounds__(NTB) void k_loss_grad(const float* __restrict__ y, const float* __restrict__ t,
@@ -616,7 +632,7 @@ hipError_t launch_loss(const float* y, const float* t, float* dy, int B, long lo
                        int nchunk, double* loss_dev, hipStream_t s) {
   double* coef = part + (size_t)B * nchunk * 2;
   hipLaunchKernelGGL(k_loss_part, dim3((unsigned)nchunk, (unsigned)B), NTB, 0, s, y, t, per_sample, nchunk, part);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), 64, 0, s, part, B, nchunk, coef, loss_dev);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), NTB, 0, s, part, B, nchunk, coef, loss_dev);
   long long blocks = ((long long)B * per_sample + NTB - 1) / NTB;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)blocks), NTB, 0, s, y, t, coef, dy, B, per_sample);

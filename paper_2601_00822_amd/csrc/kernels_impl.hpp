@@ -50,12 +50,29 @@ constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi 
 // Threads per workgroup and tile elements per component, per kernel family:
 // x and y passes hold 8 (FP32) / 4 (FP64) points per thread, the outer pass 4.
 template <typename T> struct Cfg;
+#ifndef LSFFT_XPLAN
+#define LSFFT_XPLAN Plan
+#endif
+#ifndef LSFFT_XNTH_F32
+#define LSFFT_XNTH_F32 256
+#endif
+#ifndef LSFFT_XE_F32
+#define LSFFT_XE_F32 2048
+#endif
+#ifndef LSFFT_XNTH_F64
+#define LSFFT_XNTH_F64 128
+#endif
+#ifndef LSFFT_XE_F64
+#define LSFFT_XE_F64 512
+#endif
 template <> struct Cfg<float> {
-  static constexpr int NTH = 256, E = 2048, EX = 2048;   // x and y passes
+  static constexpr int NTH = 256, E = 2048;              // y pass
+  static constexpr int NTH_X = LSFFT_XNTH_F32, EX = LSFFT_XE_F32;   // x pass
   static constexpr int NTH_G = 256, E_G = 1024;          // outer pass
 };
 template <> struct Cfg<double> {
-  static constexpr int NTH = 128, E = 1024, EX = 512;
+  static constexpr int NTH = 128, E = 1024;
+  static constexpr int NTH_X = LSFFT_XNTH_F64, EX = LSFFT_XE_F64;
   static constexpr int NTH_G = 256, E_G = 1024;
 };
 
@@ -280,13 +297,13 @@ __device__ inline void finalize(const InstDesc& D, InstState& St, int mode, doub
 template <typename T, int NX, int DIM, int MODE>
 __device__ void xpass_item(const InstDesc& D, int local, const double* __restrict__ lame,
                            const T* __restrict__ twtab, unsigned char* smem) {
-  constexpr int NTH = Cfg<T>::NTH;
+  constexpr int NTH = Cfg<T>::NTH_X;
   constexpr int H = NX / 2;
   using G = XGeom<T, H>;
   constexpr int MR = G::MR, SM = G::SM, SM2 = G::SM2;
   constexpr int S = (DIM == 3) ? 6 : 3;
-  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, Plan, true>;   // C2R core
-  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, Plan, true>;  // R2C core
+  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true>;   // C2R core
+  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true>;  // R2C core
   static_assert(FI::RL == FF::R0 && FI::BL == FF::B0, "x transforms must chain in registers");
   constexpr int BP = FI::BL, RP = FI::RL;          // points held per thread: BP x RP
   constexpr int TOTP = FI::TOTL;
@@ -387,22 +404,42 @@ __device__ void xpass_item(const InstDesc& D, int local, const double* __restric
     }
     return;
   } else {
-    // C2R of component c of S into registers (real pairs at x = 2n, 2n + 1)
+    // C2R of component c of S into registers (real pairs at x = 2n, 2n + 1).
+    // The H + 1 entries of each row of the block (element e = tid + u NTH)
+    // are loaded into registers with every load issued before the first use,
+    // then staged in LDS for the fold.
+    constexpr int XE = MR * (H + 1);
+    constexpr int XL = (XE + NTH - 1) / NTH;
     auto c2r = [&](int c, T (&o_r)[BP][RP], T (&o_i)[BP][RP]) {
       const char* src = cptr<T>(D.S, Pc, c);
-      __syncthreads();   // fold tile and staging free
-      for (int e = tid; e < MR * (H + 1); e += NTH) {
-        const int m = e / (H + 1);
-        const int k = e - m * (H + 1);
-        const int row = row0 + m;
+      T pr[XL], pi[XL];
+#pragma unroll
+      for (int u = 0; u < XL; ++u) {
+        const int e = tid + u * NTH;
         T re = T(0), im = T(0);
-        if (row < nrows) {
-          const typename C2<T>::type v = (k < H) ? ldc<T>(src, row * H + k) : ldc<T>(src, (int)Pm + row);
-          re = v.x;
-          im = v.y;
+        if (XE % NTH == 0 || e < XE) {
+          const int m = e / (H + 1);
+          const int k = e - m * (H + 1);
+          const int row = row0 + m;
+          if (row < nrows) {
+            const typename C2<T>::type v = (k < H) ? ldc<T>(src, row * H + k) : ldc<T>(src, (int)Pm + row);
+            re = v.x;
+            im = v.y;
+          }
         }
-        ar[m * SM + k] = re;
-        ai[m * SM + k] = im;
+        pr[u] = re;
+        pi[u] = im;
+      }
+      __syncthreads();   // fold tile and staging free
+#pragma unroll
+      for (int u = 0; u < XL; ++u) {
+        const int e = tid + u * NTH;
+        if (XE % NTH == 0 || e < XE) {
+          const int m = e / (H + 1);
+          const int k = e - m * (H + 1);
+          ar[m * SM + k] = pr[u];
+          ai[m * SM + k] = pi[u];
+        }
       }
       __syncthreads();
       T in_r[FI::B0][FI::R0], in_i[FI::B0][FI::R0];
@@ -1162,7 +1199,7 @@ template <> struct WavesG<double> { static constexpr int value = 2; };
 // launch has the same transform length, so register allocation and LDS
 // layout are those of that length alone.
 template <typename T, int NX, int DIM, int MODE>
-__global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_X))) void k_xpass(
+__global__ __launch_bounds__(Cfg<T>::NTH_X) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_X))) void k_xpass(
     const InstDesc* __restrict__ descs, InstState* __restrict__ states, const WorkItem* __restrict__ items,
     const int* __restrict__ nitems, const double* __restrict__ lame, const T* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem[];
