@@ -972,19 +972,30 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
         T xi[DIM], xi2;
         point_xi(q, r, xi, xi2);
         const int g = gidx(q, r);
+        // the force and (basic iteration, FP32) the current state of this
+        // point, loaded together: the stores below may alias these buffers
+        // as far as the compiler knows, so a load placed after a store would
+        // wait for its own round trip.  FP64 tiles have no registers to spare
+        // for it and load the state at its use.
+        constexpr bool early_u = (MODE == M_ITER) && std::is_same<T, float>::value;
+        typename C2<T>::type fv[DIM], u0v[early_u ? DIM : 1];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          fv[a] = ldc<T>(cptr<T>(D.F, Pc, a), g);
+          if constexpr (early_u) u0v[a] = ldc<T>(cptr<T>(D.U[cur], Pc, a), g);
+        }
         T ur[DIM], ui[DIM];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-          const typename C2<T>::type f = ldc<T>(cptr<T>(D.F, Pc, a), g);
-          vr[a][q][r] += f.x;
-          vi[a][q][r] += f.y;
+          vr[a][q][r] += fv[a].x;
+          vi[a][q][r] += fv[a].y;
           part += double(pw[q]) * (double(vr[a][q][r]) * double(vr[a][q][r]) +
                                    double(vi[a][q][r]) * double(vi[a][q][r]));
           ur[a] = vr[a][q][r];
           ui[a] = vi[a][q][r];
         }
         apply_n0<T, DIM>(xi, xi2, c0, mu0, ur, ui);   // N0 r
-        LSFFT_FENCE();
+        if constexpr (!early_u) LSFFT_FENCE();
         if constexpr (MODE == M_CG_INIT) {
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
@@ -999,7 +1010,10 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
             T nr = ur[a], ni = ui[a];
-            if constexpr (MODE == M_ITER) {
+            if constexpr (early_u) {
+              nr += u0v[a].x;
+              ni += u0v[a].y;
+            } else if constexpr (MODE == M_ITER) {
               const typename C2<T>::type u0 = ldc<T>(cptr<T>(D.U[cur], Pc, a), g);
               nr += u0.x;
               ni += u0.y;
@@ -1111,6 +1125,9 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
 template <typename T, int DIM>
 __device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsigned char* smem) {
   constexpr int NTH = Cfg<T>::NTH;
+  // entries per batch whose loads are all issued before the batch's stores
+  constexpr int QB = (sizeof(T) == 4) ? 4 : 2;
+  using V2 = typename C2<T>::type;
   const int tid = threadIdx.x;
   double* red = reinterpret_cast<double*>(smem);
   const T alpha = T(St->alpha);
@@ -1118,48 +1135,61 @@ __device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsi
   const T c0 = T((D.lam0 + D.mu0) / (D.lam0 + 2.0 * D.mu0));
   const long long Pc = D.Pc;
   double prz = 0.0, prr = 0.0;
-  for (int qq = 0; qq < 4; ++qq) {
-    const long long g = (long long)local * NTH * 4 + qq * NTH + tid;
-    if (g >= Pc) break;
-    int kx, ky, kz;
-    if (g < D.Pm) {
-      kx = int(g % D.H);
-      const long long rest = g / D.H;
-      ky = int(rest % D.ny);
-      kz = int(rest / D.ny);
-    } else {
-      kx = D.H;
-      const long long rest = g - D.Pm;
-      ky = int(rest % D.ny);
-      kz = int(rest / D.ny);
+  for (int q0 = 0; q0 < 4; q0 += QB) {
+    V2 uv[QB][DIM], pv[QB][DIM], rv[QB][DIM], qv[QB][DIM];
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) {
+      const long long g = (long long)local * NTH * 4 + (q0 + qq) * NTH + tid;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        if (g < Pc) {
+          uv[qq][a] = ldc<T>(cptr<T>(D.U[0], Pc, a), g);
+          pv[qq][a] = ldc<T>(cptr<T>(D.Pd, Pc, a), g);
+          rv[qq][a] = ldc<T>(cptr<T>(D.R, Pc, a), g);
+          qv[qq][a] = ldc<T>(cptr<T>(D.Q, Pc, a), g);
+        }
+      }
     }
-    T xi[DIM];
-    xi[0] = T(wavenum(kx, D.nx, D.kx));
-    xi[1] = T(wavenum(ky, D.ny, D.ky));
-    if constexpr (DIM == 3) xi[2] = T(wavenum(kz, D.nz, D.kz));
-    T xi2 = T(0);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) xi2 += xi[a] * xi[a];
-    const double wgt = (kx == 0 || kx == D.H) ? 1.0 : 2.0;
-    T rr[DIM], ri[DIM];
+    for (int qq = 0; qq < QB; ++qq) {
+      const long long g = (long long)local * NTH * 4 + (q0 + qq) * NTH + tid;
+      if (g >= Pc) continue;
+      int kx, ky, kz;
+      if (g < D.Pm) {
+        kx = int(g % D.H);
+        const long long rest = g / D.H;
+        ky = int(rest % D.ny);
+        kz = int(rest / D.ny);
+      } else {
+        kx = D.H;
+        const long long rest = g - D.Pm;
+        ky = int(rest % D.ny);
+        kz = int(rest / D.ny);
+      }
+      T xi[DIM];
+      xi[0] = T(wavenum(kx, D.nx, D.kx));
+      xi[1] = T(wavenum(ky, D.ny, D.ky));
+      if constexpr (DIM == 3) xi[2] = T(wavenum(kz, D.nz, D.kz));
+      T xi2 = T(0);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const typename C2<T>::type u = ldc<T>(cptr<T>(D.U[0], Pc, a), g);
-      const typename C2<T>::type pd = ldc<T>(cptr<T>(D.Pd, Pc, a), g);
-      const typename C2<T>::type r = ldc<T>(cptr<T>(D.R, Pc, a), g);
-      const typename C2<T>::type qv = ldc<T>(cptr<T>(D.Q, Pc, a), g);
-      stc<T>(mptr<T>(D.U[0], Pc, a), g, u.x + alpha * pd.x, u.y + alpha * pd.y);
-      rr[a] = r.x - alpha * qv.x;
-      ri[a] = r.y - alpha * qv.y;
-      stc<T>(mptr<T>(D.R, Pc, a), g, rr[a], ri[a]);
-      prr += wgt * (double(rr[a]) * double(rr[a]) + double(ri[a]) * double(ri[a]));
+      for (int a = 0; a < DIM; ++a) xi2 += xi[a] * xi[a];
+      const double wgt = (kx == 0 || kx == D.H) ? 1.0 : 2.0;
+      T rr[DIM], ri[DIM];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        stc<T>(mptr<T>(D.U[0], Pc, a), g, uv[qq][a].x + alpha * pv[qq][a].x, uv[qq][a].y + alpha * pv[qq][a].y);
+        rr[a] = rv[qq][a].x - alpha * qv[qq][a].x;
+        ri[a] = rv[qq][a].y - alpha * qv[qq][a].y;
+        stc<T>(mptr<T>(D.R, Pc, a), g, rr[a], ri[a]);
+        prr += wgt * (double(rr[a]) * double(rr[a]) + double(ri[a]) * double(ri[a]));
+      }
+      T zr[DIM], zi[DIM];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) { zr[a] = rr[a]; zi[a] = ri[a]; }
+      apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) prz += wgt * (double(rr[a]) * double(zr[a]) + double(ri[a]) * double(zi[a]));
     }
-    T zr[DIM], zi[DIM];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) { zr[a] = rr[a]; zi[a] = ri[a]; }
-    apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) prz += wgt * (double(rr[a]) * double(zr[a]) + double(ri[a]) * double(zi[a]));
   }
   const double s1 = block_sum<NTH>(prz, red);
   const double s2 = block_sum<NTH>(prr, red);
@@ -1283,10 +1313,23 @@ __global__ __launch_bounds__(NTR) void k_reduce(const InstDesc* __restrict__ des
   InstState& St = states[i];
   if (mode != M_INIT && St.status != ST_RUNNING) return;
   const int nslot = (mode == M_CG_UPD) ? D.items_cg : D.items_g;
+  const bool two = (mode == M_CG_INIT || mode == M_CG_UPD);
+  // eight slots per thread and step, all loads issued before the adds
+  constexpr int U = 8;
   double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < nslot; k += NTR) {
-    a += D.partial[2 * k];
-    if (mode == M_CG_INIT || mode == M_CG_UPD) b += D.partial[2 * k + 1];
+  for (int k0 = threadIdx.x; k0 < nslot; k0 += NTR * U) {
+    double va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * NTR;
+      va[u] = (k < nslot) ? D.partial[2 * k] : 0.0;
+      vb[u] = (two && k < nslot) ? D.partial[2 * k + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a += va[u];
+      b += vb[u];
+    }
   }
   a = block_sum<NTR>(a, red);
   b = block_sum<NTR>(b, red);
