@@ -47,6 +47,9 @@ WORKLOADS = {
                                             "averages over all 4096 intra-cell shifts (FP64 solver kernel) "
                                             "restricted to 32^3; Fourier neural operator 4 layers, width 32, "
                                             "12 modes, bf16 MFMA training and inference"),
+    "fno_step": dict(fno_step=True, desc="surrogate kernels alone: training steps and inference batches of the "
+                                          "4-layer, width-32, 12-mode operator on 32^3 inputs (seeded random "
+                                          "data, batch 32)"),
     "batch512": dict(batch=True, desc="512 solves in one call: 8 microstructures (48^3, 64^3, 96^3 "
                                       "round robin, cells of 16^3, RSA spheres r 3-6, vf U[0.10,0.35], "
                                       "contrast log-uniform [2,100]) x 64 seeded intra-cell shifts, "
@@ -247,6 +250,44 @@ def run_surrogate_workload(args, wl):
     }
 
 
+def run_fno_step_workload(args, wl):
+    """Time the surrogate's training step and batched inference on seeded
+    random data (the kernels alone, no dataset construction)."""
+    import numpy as np
+    import torch
+    from paper_2601_00822_amd import surrogate as S
+    from paper_2601_00822_amd.fno import FnoArch, Surrogate
+    arch = FnoArch()
+    B = args.fno_batch
+    model = Surrogate(arch, max_batch=B)
+    model.set_params(S.init_params(arch, 0))
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.normal(size=(B, arch.cin) + (arch.n,) * 3).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.normal(size=(B, arch.cout) + (arch.n,) * 3).astype(np.float32)).cuda()
+    for _ in range(args.warmup):
+        model.train_step(x, t, 1e-4)
+        model.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        model.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        model.forward(x)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / args.steps
+    model.close()
+    return {
+        "metric": METRIC, "value": B / t_inf, "unit": "surrogate fields/s (inference)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_train, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "fno_step", "description": wl["desc"], "batch": B},
+        "train_ms_per_step": 1e3 * t_train, "inference_ms_per_batch": 1e3 * t_inf,
+    }
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for name in ("kernels_impl.hpp", "fft_core.hpp"):
@@ -339,6 +380,9 @@ def main() -> int:
         return 0
     if wl.get("surrogate"):
         print(json.dumps(run_surrogate_workload(args, wl)))
+        return 0
+    if wl.get("fno_step"):
+        print(json.dumps(run_fno_step_workload(args, wl)))
         return 0
     dev = torch.device("cuda:0")
     phase, f, table, _ = make_inputs(wl)

@@ -1202,6 +1202,17 @@ __device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsi
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched to the eight XCDs in turn.  Map workgroup b of
+// a grid of G to a slot such that each XCD runs one contiguous range of
+// slots: neighbouring tiles of the outer pass, which share 128-byte lines
+// along kx, then meet in the same L2 instead of each XCD fetching the lines.
+__device__ __forceinline__ int xcd_slot(int b, int G) {
+  constexpr int X = 8;
+  const int q = G / X, r = G - (G / X) * X;
+  const int x = b - (b / X) * X, k = b / X;
+  return x * q + (x < r ? x : r) + k;
+}
+
 __device__ __forceinline__ bool gated(int mode) {
   return mode == M_ITER || mode == M_CG_AP || mode == M_CG_UPD || mode == M_CG_DIR || mode == M_CG_INIT;
 }
@@ -1268,7 +1279,7 @@ __global__ __launch_bounds__(Cfg<T>::NTH_G) __attribute__((amdgpu_waves_per_eu(L
     const int* __restrict__ nitems, const T* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n_items = *nitems;
-  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+  for (int w = xcd_slot(blockIdx.x, gridDim.x); w < n_items; w += gridDim.x) {
     const WorkItem it = items[w];
     const InstDesc& D = descs[it.inst];
     InstState* St = states + it.inst;
