@@ -435,11 +435,15 @@ def main() -> int:
     ktimes = {k: plan_t.kernel_times(c) for k, c in classes.items()}
     dom = max(("green", "xpass", "ypass"), key=lambda k: ktimes[k][0])
     ms, launches = ktimes[dom]
-    per_launch_s = ms / 1e3 / max(launches, 1)
     bytes_per_iter = plan_t.iteration_bytes(classes[dom])
-    if dom == "ypass":
-        bytes_per_iter /= 2.0                      # two y launches per iteration
-    achieved = bytes_per_iter / per_launch_s / 1e9
+    launches_per_iter = 2.0 if dom == "ypass" else 1.0   # two y launches per iteration
+    bytes_per_launch = bytes_per_iter / launches_per_iter
+    # launches past a solve's convergence inside a polling round are gated
+    # and nearly empty: time per working launch = all launch time of the
+    # class over the launches that did an iteration's work
+    working = iters_t * launches_per_iter
+    per_launch_s = ms / 1e3 / max(working, 1)
+    achieved = bytes_per_launch / per_launch_s / 1e9
     traffic = measured_traffic(dom, args.workload, args.prec)
 
     out = {
@@ -468,8 +472,9 @@ def main() -> int:
                                   "kernel durations and the roofline come from this region"},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bytes_per_iter,
-                     "mean_launch_us": per_launch_s * 1e6, "launches": launches},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "mean_launch_us": per_launch_s * 1e6, "launches": launches,
+                     "working_launches": int(working)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, phase, f, table, args.cpu_budget)

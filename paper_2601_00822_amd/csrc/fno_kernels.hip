@@ -38,66 +38,128 @@ __device__ __forceinline__ bf16x8 neg8(bf16x8 a) {
 // ---------------------------------------------------------------------------
 // pointwise layer
 // ---------------------------------------------------------------------------
-// One wave per 32-voxel column tile of one sample; the B operand (the input
-// channels of the tile) is converted to bf16 once and reused for every
-// 32-row tile of output channels.
+// One wave per block of 32 NT voxels of one sample, computed as NT
+// interleaved 32-column MFMA tiles: tile k holds voxels v0 + NT c + k
+// (c = lane % 32), so every lane moves NT consecutive voxels, one per tile,
+// in one vector access, and each half-wave reads or writes 128 NT
+// contiguous bytes of one channel.  The B operand (input channels) is
+// converted to bf16 once per block and reused for every 32-row tile of
+// output channels.  NT shrinks as the input width grows (register budget).
 constexpr int kMaxKs = 16;   // ipad <= 256
 
-template <int KS>
+template <int NT> struct VecF;
+template <> struct VecF<1> { using type = float; };
+template <> struct VecF<2> { using type = float2; };
+template <> struct VecF<4> { using type = float4; };
+
+template <int NT>
+__device__ __forceinline__ void vload(const float* p, float (&v)[NT]) {
+  const typename VecF<NT>::type x = *reinterpret_cast<const typename VecF<NT>::type*>(p);
+  if constexpr (NT == 1) v[0] = x;
+  else if constexpr (NT == 2) { v[0] = x.x; v[1] = x.y; }
+  else { v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w; }
+}
+template <int NT>
+__device__ __forceinline__ void vstore(float* p, const float (&v)[NT]) {
+  typename VecF<NT>::type x;
+  if constexpr (NT == 1) x = v[0];
+  else if constexpr (NT == 2) { x.x = v[0]; x.y = v[1]; }
+  else { x.x = v[0]; x.y = v[1]; x.z = v[2]; x.w = v[3]; }
+  *reinterpret_cast<typename VecF<NT>::type*>(p) = x;
+}
+
+template <int KS, int NT>
 __global__ __launch_bounds__(256) void k_pointwise(PwArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int half = lane >> 5, col = lane & 31;
+  constexpr int BV = 32 * NT;   // voxels per wave block
   const long long V = a.V;
-  const long long tiles = (long long)a.B * (V / 32);
+  const long long blocks = (long long)a.B * (V / BV);
   const bf16x8* w8 = reinterpret_cast<const bf16x8*>(a.w);
-  for (long long t = (long long)blockIdx.x * 4 + wave; t < tiles; t += (long long)gridDim.x * 4) {
-    const int b = int(t / (V / 32));
-    const long long v = (t % (V / 32)) * 32 + col;
-    bf16x8 bop[KS];
+  for (long long t = (long long)blockIdx.x * 4 + wave; t < blocks; t += (long long)gridDim.x * 4) {
+    const int b = int(t / (V / BV));
+    const long long v = (t % (V / BV)) * BV + NT * col;
+    bf16x8 bop[KS][NT];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int i = s * 16 + half * 8 + j;
-        const float x = (i < a.I) ? a.in[((long long)b * a.I + i) * V + v] : 0.0f;
-        bop[s][j] = (__bf16)x;
+        float x[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) x[k] = 0.0f;
+        if (i < a.I) vload<NT>(a.in + ((long long)b * a.I + i) * V + v, x);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) bop[s][k][j] = (__bf16)x[k];
       }
     }
     for (int ot = 0; ot < a.opad / 32; ++ot) {
-      f32x16 acc = {0};
+      f32x16 acc[NT];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) acc[k] = f32x16{0};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const bf16x8 aop = w8[((long long)(ot * 32 + col) * a.ipad + s * 16 + half * 8) / 8];
-        acc = mfma(aop, bop[s], acc);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) acc[k] = mfma(aop, bop[s][k], acc[k]);
       }
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int o = ot * 32 + 8 * (e / 4) + 4 * half + (e % 4);
         if (o >= a.O) continue;
         const long long idx = ((long long)b * a.O + o) * V + v;
-        float val = acc[e];
-        if (a.bias) val += a.bias[o];
-        if (a.add) val += a.add[idx];
-        if (a.aux) val *= gelu_grad(a.aux[idx]);
-        a.out[idx] = val;
-        if (a.out_act) a.out_act[idx] = gelu(val);
+        float val[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) val[k] = acc[k][e];
+        if (a.bias) {
+          const float bo = a.bias[o];
+#pragma unroll
+          for (int k = 0; k < NT; ++k) val[k] += bo;
+        }
+        if (a.add) {
+          float ad[NT];
+          vload<NT>(a.add + idx, ad);
+#pragma unroll
+          for (int k = 0; k < NT; ++k) val[k] += ad[k];
+        }
+        if (a.aux) {
+          float ax[NT];
+          vload<NT>(a.aux + idx, ax);
+#pragma unroll
+          for (int k = 0; k < NT; ++k) val[k] *= gelu_grad(ax[k]);
+        }
+        vstore<NT>(a.out + idx, val);
+        if (a.out_act) {
+          float g[NT];
+#pragma unroll
+          for (int k = 0; k < NT; ++k) g[k] = gelu(val[k]);
+          vstore<NT>(a.out_act + idx, g);
+        }
       }
     }
   }
 }
 
 hipError_t launch_pointwise(const PwArgs& a, hipStream_t s) {
-  if (a.ipad % 16 || a.opad % 32 || a.ipad > 16 * kMaxKs || a.V % 32) return hipErrorInvalidValue;
-  const long long tiles = (long long)a.B * (a.V / 32);
-  long long blocks = (tiles + 3) / 4;
+  if (a.ipad % 16 || a.opad % 32 || a.ipad > 16 * kMaxKs || a.V % 128) return hipErrorInvalidValue;
+  const int ks = a.ipad / 16;
+  const int nt = ks <= 2 ? 4 : (ks <= 8 ? 2 : 1);
+  const long long nblk = (long long)a.B * (a.V / (32 * nt));
+  long long blocks = (nblk + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   const dim3 g((unsigned)blocks);
-  switch (a.ipad / 16) {
-#define PW(K) case K: hipLaunchKernelGGL(k_pointwise<K>, g, 256, 0, s, a); break;
-    PW(1) PW(2) PW(4) PW(6) PW(8) PW(10) PW(12) PW(14) PW(16)
-#undef PW
+  switch (ks) {
+    case 1: hipLaunchKernelGGL((k_pointwise<1, 4>), g, 256, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pointwise<2, 4>), g, 256, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pointwise<4, 2>), g, 256, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_pointwise<6, 2>), g, 256, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_pointwise<8, 2>), g, 256, 0, s, a); break;
+    case 10: hipLaunchKernelGGL((k_pointwise<10, 1>), g, 256, 0, s, a); break;
+    case 12: hipLaunchKernelGGL((k_pointwise<12, 1>), g, 256, 0, s, a); break;
+    case 14: hipLaunchKernelGGL((k_pointwise<14, 1>), g, 256, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_pointwise<16, 1>), g, 256, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -333,6 +395,14 @@ hipError_t launch_modemix(int mode, const float2* x, const __hip_bfloat16* r, co
 // ---------------------------------------------------------------------------
 // truncated transforms: direct sums along one axis at a time, fp32
 // ---------------------------------------------------------------------------
+// Every kernel stages a contiguous block of its input in LDS with coalesced
+// loads, sums from LDS (odd pitches keep the strided reads conflict free),
+// and writes a contiguous block of output.  Layouts (BC = batch x channels,
+// P = 2M M):
+//   h   [BC][z][y][x]           real
+//   t1  [BC][z][y][kx]          kx < M
+//   t2  [BC][z][iy][kx]         iy < 2M (signed ky)
+//   md  [iz P + iy M + kx][BC]  the kept modes, mode-major
 // Kept array index of the signed wavenumber slot s in [0, 2M): s for s < M,
 // n - 2M + s for the negative ones.
 template <int N> __device__ __forceinline__ int kidx(int s, int M) { return s < M ? s : N - 2 * M + s; }
@@ -340,131 +410,124 @@ template <int N> __device__ __forceinline__ int kidx(int s, int M) { return s < 
 template <int N>
 __device__ __forceinline__ void load_tw(float2* tw, const float2* twg) {
   if (threadIdx.x < N) tw[threadIdx.x] = twg[threadIdx.x];
-  __syncthreads();
 }
 
-// x: real rows of N -> M complex (e^{-i})
+constexpr int kRows = 64;    // rows of N per x-transform block
+constexpr int kSlabs = 8;    // (bc, z) slabs per y-transform block
+constexpr int kZbc = 16;     // bc per z-transform block
+constexpr int kZyx = 8;      // (iy, kx) pairs per z-transform block
+
+// x forward: kRows real rows -> M complex each (e^{-i})
 template <int N>
 __global__ __launch_bounds__(NTB) void k_dft_x_fwd(const float* __restrict__ h, float2* __restrict__ t1, long long rows,
                                                    int M, const float2* __restrict__ twg) {
   __shared__ float2 tw[N];
+  __shared__ float tile[kRows * (N + 1)];
+  __shared__ float2 res[kRows * (N / 2 + 1)];
   load_tw<N>(tw, twg);
-  const long long row = (long long)blockIdx.x * NTB + threadIdx.x;
-  if (row >= rows) return;
-  float v[N];
-  const float4* src = reinterpret_cast<const float4*>(h + row * N);
-#pragma unroll
-  for (int q = 0; q < N / 4; ++q) {
-    const float4 f = src[q];
-    v[4 * q] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
+  const long long row0 = (long long)blockIdx.x * kRows;
+  const int nr = (int)((rows - row0) < kRows ? (rows - row0) : kRows);
+  for (int e = threadIdx.x; e < kRows * N / 4; e += NTB) {
+    const int r = (4 * e) / N, x = (4 * e) % N;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r < nr) v = reinterpret_cast<const float4*>(h + row0 * N)[e];
+    float* d = tile + r * (N + 1) + x;
+    d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
   }
-  for (int kx = 0; kx < M; ++kx) {
+  __syncthreads();
+  const int r = threadIdx.x % kRows;
+  for (int kx = threadIdx.x / kRows; kx < M; kx += NTB / kRows) {
     float re = 0.f, im = 0.f;
 #pragma unroll
     for (int x = 0; x < N; ++x) {
-      const float2 t = tw[(kx * x) & (N - 1)];
-      re += v[x] * t.x;
-      im -= v[x] * t.y;
+      const float a = tile[r * (N + 1) + x];
+      const float2 w = tw[(kx * x) & (N - 1)];
+      re += a * w.x;
+      im -= a * w.y;
     }
-    t1[row * M + kx] = make_float2(re, im);
+    res[r * (N / 2 + 1) + kx] = make_float2(re, im);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nr * M; e += NTB) t1[row0 * M + e] = res[(e / M) * (N / 2 + 1) + e % M];
+}
+
+// x inverse: out[row][x] = sum_kx c(kx) Re(t1[row][kx] e^{+i kx x})
+template <int N>
+__global__ __launch_bounds__(NTB) void k_dft_x_inv(const float2* __restrict__ t1, float* __restrict__ out, long long rows,
+                                                   int M, float c0, float c1, const float2* __restrict__ twg) {
+  __shared__ float2 tw[N];
+  __shared__ float2 tin[kRows * (N / 2 + 1)];
+  __shared__ float tile[kRows * (N + 1)];
+  load_tw<N>(tw, twg);
+  const long long row0 = (long long)blockIdx.x * kRows;
+  const int nr = (int)((rows - row0) < kRows ? (rows - row0) : kRows);
+  for (int e = threadIdx.x; e < nr * M; e += NTB) {
+    const int kx = e % M;
+    const float c = (kx == 0) ? c0 : c1;
+    const float2 v = t1[row0 * M + e];
+    tin[(e / M) * (N / 2 + 1) + kx] = make_float2(c * v.x, c * v.y);
+  }
+  __syncthreads();
+  const int r = threadIdx.x % kRows;
+  for (int x = threadIdx.x / kRows; x < N; x += NTB / kRows) {
+    float acc = 0.f;
+    for (int kx = 0; kx < M; ++kx) {
+      const float2 a = tin[r * (N / 2 + 1) + kx];
+      const float2 w = tw[(kx * x) & (N - 1)];
+      acc += a.x * w.x - a.y * w.y;
+    }
+    tile[r * (N + 1) + x] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nr * N / 4; e += NTB) {
+    const int rr = (4 * e) / N, x = (4 * e) % N;
+    const float* sft = tile + rr * (N + 1) + x;
+    reinterpret_cast<float4*>(out + row0 * N)[e] = make_float4(sft[0], sft[1], sft[2], sft[3]);
   }
 }
 
-// y: t1[bz][y][kx] -> t2[bz][iy][kx], iy in [0, 2M) (e^{-i})
+// y forward: slabs t1[bz][y][kx] -> t2[bz][iy][kx] (e^{-i})
 template <int N>
 __global__ __launch_bounds__(NTB) void k_dft_y_fwd(const float2* __restrict__ t1, float2* __restrict__ t2, long long nbz,
                                                    int M, const float2* __restrict__ twg) {
   __shared__ float2 tw[N];
+  __shared__ float2 slab[kSlabs * N * (N / 2 + 1)];
   load_tw<N>(tw, twg);
-  const long long t = (long long)blockIdx.x * NTB + threadIdx.x;
-  if (t >= nbz * M) return;
-  const int kx = int(t % M);
-  const long long bz = t / M;
-  float2 acc[N];
-#pragma unroll
-  for (int s = 0; s < N; ++s) acc[s] = make_float2(0.f, 0.f);
-  for (int y = 0; y < N; ++y) {
-    const float2 a = t1[(bz * N + y) * M + kx];
-#pragma unroll
-    for (int s = 0; s < N; ++s) {
-      if (s < 2 * M) {
-        const float2 w = tw[(kidx<N>(s, M) * y) & (N - 1)];
-        acc[s].x += a.x * w.x + a.y * w.y;
-        acc[s].y += a.y * w.x - a.x * w.y;
-      }
-    }
+  const long long bz0 = (long long)blockIdx.x * kSlabs;
+  const int ns = (int)((nbz - bz0) < kSlabs ? (nbz - bz0) : kSlabs);
+  const int per_in = N * M;
+  for (int e = threadIdx.x; e < ns * per_in; e += NTB) {
+    const int sl = e / per_in, rem = e % per_in;
+    slab[sl * N * (N / 2 + 1) + (rem / M) * (N / 2 + 1) + rem % M] = t1[bz0 * per_in + e];
   }
+  __syncthreads();
+  const int per_out = 2 * M * M;
+  for (int o = threadIdx.x; o < ns * per_out; o += NTB) {
+    const int sl = o / per_out, rem = o % per_out;
+    const int iy = rem / M, kx = rem % M;
+    const int k = kidx<N>(iy, M);
+    const float2* src = slab + sl * N * (N / 2 + 1) + kx;
+    float re = 0.f, im = 0.f;
 #pragma unroll
-  for (int s = 0; s < N; ++s)
-    if (s < 2 * M) t2[(bz * 2 * M + s) * M + kx] = acc[s];
+    for (int y = 0; y < N; ++y) {
+      const float2 a = src[y * (N / 2 + 1)];
+      const float2 w = tw[(k * y) & (N - 1)];
+      re += a.x * w.x + a.y * w.y;
+      im += a.y * w.x - a.x * w.y;
+    }
+    t2[bz0 * per_out + o] = make_float2(re, im);
+  }
 }
 
-// z: t2[bc][z][iy][kx] -> modes[(iz 2M + iy) M + kx][bc] * scale(kx) (e^{-i})
-template <int N>
-__global__ __launch_bounds__(NTB) void k_dft_z_fwd(const float2* __restrict__ t2, float2* __restrict__ md, int BC, int M,
-                                                   float sc0, float sc1, const float2* __restrict__ twg) {
-  __shared__ float2 tw[N];
-  load_tw<N>(tw, twg);
-  const long long t = (long long)blockIdx.x * NTB + threadIdx.x;
-  const int P = 2 * M * M;
-  if (t >= (long long)BC * P) return;
-  const int bc = int(t / P);
-  const int yx = int(t % P);   // iy * M + kx
-  const int kx = yx % M;
-  float2 acc[N];
-#pragma unroll
-  for (int s = 0; s < N; ++s) acc[s] = make_float2(0.f, 0.f);
-  for (int z = 0; z < N; ++z) {
-    const float2 a = t2[((long long)bc * N + z) * P + yx];
-#pragma unroll
-    for (int s = 0; s < N; ++s) {
-      if (s < 2 * M) {
-        const float2 w = tw[(kidx<N>(s, M) * z) & (N - 1)];
-        acc[s].x += a.x * w.x + a.y * w.y;
-        acc[s].y += a.y * w.x - a.x * w.y;
-      }
-    }
-  }
-  const float sc = (kx == 0) ? sc0 : sc1;
-#pragma unroll
-  for (int s = 0; s < N; ++s)
-    if (s < 2 * M) md[((long long)s * P + yx) * BC + bc] = make_float2(acc[s].x * sc, acc[s].y * sc);
-}
-
-// inverse z: modes -> t2[bc][z][iy][kx] (e^{+i})
-template <int N>
-__global__ __launch_bounds__(NTB) void k_dft_z_inv(const float2* __restrict__ md, float2* __restrict__ t2, int BC, int M,
-                                                   const float2* __restrict__ twg) {
-  __shared__ float2 tw[N];
-  load_tw<N>(tw, twg);
-  const long long t = (long long)blockIdx.x * NTB + threadIdx.x;
-  const int P = 2 * M * M;
-  if (t >= (long long)BC * P) return;
-  const int bc = int(t / P);
-  const int yx = int(t % P);
-  float2 acc[N];
-#pragma unroll
-  for (int z = 0; z < N; ++z) acc[z] = make_float2(0.f, 0.f);
-  for (int s = 0; s < 2 * M; ++s) {
-    const float2 a = md[((long long)s * P + yx) * BC + bc];
-    const int k = kidx<N>(s, M);
-#pragma unroll
-    for (int z = 0; z < N; ++z) {
-      const float2 w = tw[(k * z) & (N - 1)];
-      acc[z].x += a.x * w.x - a.y * w.y;
-      acc[z].y += a.y * w.x + a.x * w.y;
-    }
-  }
-#pragma unroll
-  for (int z = 0; z < N; ++z) t2[((long long)bc * N + z) * P + yx] = acc[z];
-}
-
-// inverse y: t2[bz][iy][kx] -> t1[bz][y][kx] (e^{+i})
+// y inverse: t2[bz][iy][kx] -> t1[bz][y][kx] (e^{+i}); one thread per
+// (bz, kx) holding the N outputs in registers, so every input is read once
+// and the twiddle index is the same across the wave
 template <int N>
 __global__ __launch_bounds__(NTB) void k_dft_y_inv(const float2* __restrict__ t2, float2* __restrict__ t1, long long nbz,
                                                    int M, const float2* __restrict__ twg) {
   __shared__ float2 tw[N];
   load_tw<N>(tw, twg);
+  __syncthreads();
   const long long t = (long long)blockIdx.x * NTB + threadIdx.x;
   if (t >= nbz * M) return;
   const int kx = int(t % M);
@@ -472,9 +535,9 @@ __global__ __launch_bounds__(NTB) void k_dft_y_inv(const float2* __restrict__ t2
   float2 acc[N];
 #pragma unroll
   for (int y = 0; y < N; ++y) acc[y] = make_float2(0.f, 0.f);
-  for (int s = 0; s < 2 * M; ++s) {
-    const float2 a = t2[(bz * 2 * M + s) * M + kx];
-    const int k = kidx<N>(s, M);
+  for (int s2 = 0; s2 < 2 * M; ++s2) {
+    const float2 a = t2[(bz * 2 * M + s2) * M + kx];
+    const int k = kidx<N>(s2, M);
 #pragma unroll
     for (int y = 0; y < N; ++y) {
       const float2 w = tw[(k * y) & (N - 1)];
@@ -486,53 +549,99 @@ __global__ __launch_bounds__(NTB) void k_dft_y_inv(const float2* __restrict__ t2
   for (int y = 0; y < N; ++y) t1[(bz * N + y) * M + kx] = acc[y];
 }
 
-// inverse x: out[row][x] = sum_kx c(kx) Re(t1[row][kx] e^{+i kx x})
+// z forward: t2[bc][z][yx] -> md[(iz P + yx) BC + bc] * scale(kx) (e^{-i}),
+// one block per kZbc x kZyx tile of (bc, yx)
 template <int N>
-__global__ __launch_bounds__(NTB) void k_dft_x_inv(const float2* __restrict__ t1, float* __restrict__ out, long long rows,
-                                                   int M, float c0, float c1, const float2* __restrict__ twg) {
+__global__ __launch_bounds__(NTB) void k_dft_z_fwd(const float2* __restrict__ t2, float2* __restrict__ md, int BC, int M,
+                                                   float sc0, float sc1, const float2* __restrict__ twg) {
   __shared__ float2 tw[N];
+  constexpr int BP = N * (kZyx + 1) + 1;   // odd pitch between bc: the sums read one bc per lane
+  __shared__ float2 tile[kZbc * BP];
   load_tw<N>(tw, twg);
-  const long long row = (long long)blockIdx.x * NTB + threadIdx.x;
-  if (row >= rows) return;
-  float acc[N];
-#pragma unroll
-  for (int x = 0; x < N; ++x) acc[x] = 0.f;
-  for (int kx = 0; kx < M; ++kx) {
-    const float2 a = t1[row * M + kx];
-    const float c = (kx == 0) ? c0 : c1;
-    const float ar = c * a.x, ai = c * a.y;
-#pragma unroll
-    for (int x = 0; x < N; ++x) {
-      const float2 w = tw[(kx * x) & (N - 1)];
-      acc[x] += ar * w.x - ai * w.y;
-    }
+  const int P = 2 * M * M;
+  const int nyx = (P + kZyx - 1) / kZyx;
+  const int bc0 = (blockIdx.x / nyx) * kZbc, yx0 = (blockIdx.x % nyx) * kZyx;
+  for (int e = threadIdx.x; e < kZbc * N * kZyx; e += NTB) {
+    const int j = e % kZyx, z = (e / kZyx) % N, b = e / (kZyx * N);
+    float2 v = make_float2(0.f, 0.f);
+    if (bc0 + b < BC && yx0 + j < P) v = t2[((long long)(bc0 + b) * N + z) * P + yx0 + j];
+    tile[b * BP + z * (kZyx + 1) + j] = v;
   }
-  float4* dst = reinterpret_cast<float4*>(out + row * N);
+  __syncthreads();
+  for (int o = threadIdx.x; o < 2 * M * kZyx * kZbc; o += NTB) {
+    const int b = o % kZbc, j = (o / kZbc) % kZyx, iz = o / (kZbc * kZyx);
+    if (bc0 + b >= BC || yx0 + j >= P) continue;
+    const int k = kidx<N>(iz, M);
+    const float2* src = tile + b * BP + j;
+    float re = 0.f, im = 0.f;
 #pragma unroll
-  for (int q = 0; q < N / 4; ++q) dst[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+    for (int z = 0; z < N; ++z) {
+      const float2 a = src[z * (kZyx + 1)];
+      const float2 w = tw[(k * z) & (N - 1)];
+      re += a.x * w.x + a.y * w.y;
+      im += a.y * w.x - a.x * w.y;
+    }
+    const float sc = ((yx0 + j) % M == 0) ? sc0 : sc1;
+    md[((long long)iz * P + yx0 + j) * BC + bc0 + b] = make_float2(re * sc, im * sc);
+  }
 }
 
-static unsigned nblocks(long long work) { return (unsigned)((work + NTB - 1) / NTB); }
+// z inverse: md -> t2[bc][z][yx] (e^{+i}), same tiles
+template <int N>
+__global__ __launch_bounds__(NTB) void k_dft_z_inv(const float2* __restrict__ md, float2* __restrict__ t2, int BC, int M,
+                                                   const float2* __restrict__ twg) {
+  __shared__ float2 tw[N];
+  __shared__ float2 tile[N * kZyx * (kZbc + 1)];
+  load_tw<N>(tw, twg);
+  const int P = 2 * M * M;
+  const int nyx = (P + kZyx - 1) / kZyx;
+  const int bc0 = (blockIdx.x / nyx) * kZbc, yx0 = (blockIdx.x % nyx) * kZyx;
+  for (int e = threadIdx.x; e < 2 * M * kZyx * kZbc; e += NTB) {
+    const int b = e % kZbc, j = (e / kZbc) % kZyx, iz = e / (kZbc * kZyx);
+    float2 v = make_float2(0.f, 0.f);
+    if (bc0 + b < BC && yx0 + j < P) v = md[((long long)iz * P + yx0 + j) * BC + bc0 + b];
+    tile[(iz * kZyx + j) * (kZbc + 1) + b] = v;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < kZbc * N * kZyx; o += NTB) {
+    const int j = o % kZyx, z = (o / kZyx) % N, b = o / (kZyx * N);
+    if (bc0 + b >= BC || yx0 + j >= P) continue;
+    float re = 0.f, im = 0.f;
+    for (int iz = 0; iz < 2 * M; ++iz) {
+      const float2 a = tile[(iz * kZyx + j) * (kZbc + 1) + b];
+      const float2 w = tw[(kidx<N>(iz, M) * z) & (N - 1)];
+      re += a.x * w.x - a.y * w.y;
+      im += a.y * w.x + a.x * w.y;
+    }
+    t2[((long long)(bc0 + b) * N + z) * P + yx0 + j] = make_float2(re, im);
+  }
+}
+
+static unsigned nblocks(long long work, int per) { return (unsigned)((work + per - 1) / per); }
 
 template <int N>
 static hipError_t dft_fwd_n(int M, int BC, const float* h, float2* t1, float2* t2, float2* md, float sc0, float sc1,
                             const float2* tw, hipStream_t s) {
   const long long rows = (long long)BC * N * N;
-  hipLaunchKernelGGL(k_dft_x_fwd<N>, dim3(nblocks(rows)), NTB, 0, s, h, t1, rows, M, tw);
+  hipLaunchKernelGGL(k_dft_x_fwd<N>, dim3(nblocks(rows, kRows)), NTB, 0, s, h, t1, rows, M, tw);
   const long long nbz = (long long)BC * N;
-  hipLaunchKernelGGL(k_dft_y_fwd<N>, dim3(nblocks(nbz * M)), NTB, 0, s, t1, t2, nbz, M, tw);
-  hipLaunchKernelGGL(k_dft_z_fwd<N>, dim3(nblocks((long long)BC * 2 * M * M)), NTB, 0, s, t2, md, BC, M, sc0, sc1, tw);
+  hipLaunchKernelGGL(k_dft_y_fwd<N>, dim3(nblocks(nbz, kSlabs)), NTB, 0, s, t1, t2, nbz, M, tw);
+  const int P = 2 * M * M;
+  const unsigned nz = nblocks(BC, kZbc) * nblocks(P, kZyx);
+  hipLaunchKernelGGL(k_dft_z_fwd<N>, dim3(nz), NTB, 0, s, t2, md, BC, M, sc0, sc1, tw);
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t dft_inv_n(int M, int BC, const float2* md, float2* t2, float2* t1, float* out, float c0, float c1,
                             const float2* tw, hipStream_t s) {
-  hipLaunchKernelGGL(k_dft_z_inv<N>, dim3(nblocks((long long)BC * 2 * M * M)), NTB, 0, s, md, t2, BC, M, tw);
+  const int P = 2 * M * M;
+  const unsigned nz = nblocks(BC, kZbc) * nblocks(P, kZyx);
+  hipLaunchKernelGGL(k_dft_z_inv<N>, dim3(nz), NTB, 0, s, md, t2, BC, M, tw);
   const long long nbz = (long long)BC * N;
-  hipLaunchKernelGGL(k_dft_y_inv<N>, dim3(nblocks(nbz * M)), NTB, 0, s, t2, t1, nbz, M, tw);
+  hipLaunchKernelGGL(k_dft_y_inv<N>, dim3(nblocks(nbz * M, NTB)), NTB, 0, s, t2, t1, nbz, M, tw);
   const long long rows = (long long)BC * N * N;
-  hipLaunchKernelGGL(k_dft_x_inv<N>, dim3(nblocks(rows)), NTB, 0, s, t1, out, rows, M, c0, c1, tw);
+  hipLaunchKernelGGL(k_dft_x_inv<N>, dim3(nblocks(rows, kRows)), NTB, 0, s, t1, out, rows, M, c0, c1, tw);
   return hipGetLastError();
 }
 
