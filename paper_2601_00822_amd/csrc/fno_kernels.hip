@@ -194,22 +194,35 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   for (long long c = (long long)blockIdx.x * 4 + wave; c < chunks; c += (long long)gridDim.x * 4) {
     const int b = int(c / (V / 16));
     const long long v0 = (c % (V / 16)) * 16 + half * 8;
+    // eight consecutive voxels per lane: two 16-byte loads per operand row
+    auto load8 = [&](const float* src, bool ok, float (&x)[8]) {
+      float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+      if (ok) {
+        lo = reinterpret_cast<const float4*>(src)[0];
+        hi = reinterpret_cast<const float4*>(src)[1];
+      }
+      x[0] = lo.x; x[1] = lo.y; x[2] = lo.z; x[3] = lo.w;
+      x[4] = hi.x; x[5] = hi.y; x[6] = hi.z; x[7] = hi.w;
+    };
     bf16x8 bop[TI];
 #pragma unroll
     for (int q = 0; q < TI; ++q) {
       const int i = q * 32 + row;
+      float x[8];
+      load8(a.h + ((long long)b * a.I + (i < a.I ? i : 0)) * V + v0, i < a.I, x);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) bop[q][j] = (__bf16)((i < a.I) ? a.h[((long long)b * a.I + i) * V + v0 + j] : 0.0f);
+      for (int j = 0; j < 8; ++j) bop[q][j] = (__bf16)x[j];
     }
 #pragma unroll
     for (int p = 0; p < TO; ++p) {
       const int o = p * 32 + row;
+      float x[8];
+      load8(a.g + ((long long)b * a.O + (o < a.O ? o : 0)) * V + v0, o < a.O, x);
       bf16x8 aop;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const float gv = (o < a.O) ? a.g[((long long)b * a.O + o) * V + v0 + j] : 0.0f;
-        bsum[p] += gv;
-        aop[j] = (__bf16)gv;
+        bsum[p] += x[j];
+        aop[j] = (__bf16)x[j];
       }
 #pragma unroll
       for (int q = 0; q < TI; ++q) acc[p][q] = mfma(aop, bop[q], acc[p][q]);
