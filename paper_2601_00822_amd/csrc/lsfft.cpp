@@ -702,7 +702,7 @@ lsfft_status read_states(Batch& b, std::vector<int>& running) {
 // Iterate every solve on the dynamic lists until none is running.  With
 // `max_rounds` > 0 at most that many single-iteration rounds are run, without
 // a graph (the mixed-precision outer step).
-lsfft_status iterate(Batch& b, int max_rounds = 0) {
+lsfft_status iterate(Batch& b, int max_rounds = 0, std::vector<int>* running_out = nullptr) {
   lsfft_plan_s* p = b.p;
   const bool cg = p->scheme == LSFFT_CG;
   hipStream_t st = p->stream;
@@ -776,6 +776,7 @@ lsfft_status iterate(Batch& b, int max_rounds = 0) {
   }
   if (timing) timed_collect(p);
   p->timing_active = false;
+  if (running_out) *running_out = running;
   return LSFFT_OK;
 }
 
@@ -877,20 +878,26 @@ lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
   for (int i = 0; i < n; ++i) in.specs[i].leader = i;
   if ((ls = prepare(in)) != LSFFT_OK) return ls;
   std::vector<long long> inner_iters(n, 0);
-  std::vector<int> running;
+  std::vector<int> running, in_listed(n);
+  for (int i = 0; i < n; ++i) in_listed[i] = i;   // what prepare() listed for the inner batch
   for (;;) {
     // outer step 1: FP64 residual and stopping test at the current state
-    if ((ls = iterate(c, 1)) != LSFFT_OK) return ls;
-    if ((ls = read_states(c, running)) != LSFFT_OK) return ls;
+    // (iterate reads the states back and shrinks the lists to the running
+    // solves)
+    if ((ls = iterate(c, 1, &running)) != LSFFT_OK) return ls;
     if (running.empty()) break;
-    if ((ls = upload_lists(c, running, false)) != LSFFT_OK) return ls;
-    if ((ls = upload_lists(in, running, false)) != LSFFT_OK) return ls;
+    // the inner lists keep their last contents when every inner solve ends;
+    // rebuild them only when the set of solves changed
+    if (running != in_listed || in.n_running != (int)running.size()) {
+      if ((ls = upload_lists(in, running, false)) != LSFFT_OK) return ls;
+      in_listed = running;
+    }
     // step 2: defect as FP32 force, inner solve
     LSFFT_TRY(launch_defect(c.d_desc, c.d_state, in.d_desc, c.d_inst, c.n_running, max_pc(c, running), st));
     if ((ls = setup(in, true)) != LSFFT_OK) return ls;
-    if ((ls = iterate(in)) != LSFFT_OK) return ls;
-    std::vector<int> none;
-    if ((ls = read_states(in, none)) != LSFFT_OK) return ls;
+    std::vector<int> still;
+    if ((ls = iterate(in, 0, &still)) != LSFFT_OK) return ls;
+    if (in.n_running != (int)in_listed.size()) in_listed.clear();   // compacted on the way
     for (int i : running) inner_iters[i] += in.state[i].iter;
     // step 3: u += d in FP64
     LSFFT_TRY(launch_correct(c.d_desc, c.d_state, in.d_desc, in.d_state, c.d_inst, c.n_running, cg,
