@@ -401,8 +401,8 @@ def main() -> int:
         del src, dst
     # timed region: iterations replayed as captured HIP graphs
     plan = Plan([wl["shape"]], prec=args.prec, scheme=args.scheme, refine=args.refine)
-    # kernel-duration region: the same solves with a HIP event pair around
-    # every launch on the plan's work stream (graphs off)
+    # kernel-duration region: the same solves with graphs off and a HIP
+    # event pair stamped by every launch at its kernel's start and end
     plan_t = Plan([wl["shape"]], prec=args.prec, scheme=args.scheme, timing=True, refine=args.refine)
     nvox = int(np.prod(wl["shape"]))
 
@@ -468,8 +468,9 @@ def main() -> int:
         "status": reps[-1].status,
         "kernel_ms_per_iteration": {k: v[0] / max(iters_t, 1) for k, v in ktimes.items()},
         "timing_region": {"value": nvox * iters_t / elapsed_t,
-                          "note": "same solves with a HIP event pair around every launch and graphs off; "
-                                  "kernel durations and the roofline come from this region"},
+                          "note": "same solves with graphs off and a HIP event pair stamped at every kernel's "
+                                  "start and end (hipExtLaunchKernelGGL); kernel durations and the roofline come "
+                                  "from this region"},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch,

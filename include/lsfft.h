@@ -63,7 +63,7 @@ typedef enum { LSFFT_BASIC = 0, LSFFT_CG = 1 } lsfft_scheme;
 
 /* plan flags */
 #define LSFFT_STRICT_EQUIL 0x1u  /* reject forces whose voxel sum is not ~0 (Eq. 2.5) instead of projecting */
-#define LSFFT_TIMING       0x2u  /* record HIP events around every kernel launch (see lsfft_kernel_times) */
+#define LSFFT_TIMING       0x2u  /* time every kernel launch with a HIP event pair stamped at the kernel's start and end (see lsfft_kernel_times) */
 /* LSFFT_REFINE64 (LSFFT_F32 plans only): mixed-precision defect correction.
  * The displacement state is kept in FP64; each outer step evaluates the FP64
  * residual P f + div(L sym grad u) of that state (the stopping rule below is

@@ -9,58 +9,58 @@ hipError_t launch_green_f64_3d_s(const LaunchArgs& a, int mode, int len) {
   switch (len) {
     case 4:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_green<double, 4, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_INIT: hipLaunchKernelGGL((k_green<double, 4, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_green<double, 4, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_green<double, 4, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_INIT: hipLaunchKernelGGL((k_green<double, 4, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_AP: hipLaunchKernelGGL((k_green<double, 4, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_DIR: hipLaunchKernelGGL((k_green<double, 4, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_green<double, 4, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_INIT: LSFFT_LAUNCH((k_green<double, 4, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_green<double, 4, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_green<double, 4, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_INIT: LSFFT_LAUNCH((k_green<double, 4, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_AP: LSFFT_LAUNCH((k_green<double, 4, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_DIR: LSFFT_LAUNCH((k_green<double, 4, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 6:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_green<double, 6, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_INIT: hipLaunchKernelGGL((k_green<double, 6, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_green<double, 6, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_green<double, 6, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_INIT: hipLaunchKernelGGL((k_green<double, 6, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_AP: hipLaunchKernelGGL((k_green<double, 6, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_DIR: hipLaunchKernelGGL((k_green<double, 6, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_green<double, 6, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_INIT: LSFFT_LAUNCH((k_green<double, 6, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_green<double, 6, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_green<double, 6, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_INIT: LSFFT_LAUNCH((k_green<double, 6, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_AP: LSFFT_LAUNCH((k_green<double, 6, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_DIR: LSFFT_LAUNCH((k_green<double, 6, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 8:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_green<double, 8, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_INIT: hipLaunchKernelGGL((k_green<double, 8, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_green<double, 8, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_green<double, 8, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_INIT: hipLaunchKernelGGL((k_green<double, 8, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_AP: hipLaunchKernelGGL((k_green<double, 8, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_DIR: hipLaunchKernelGGL((k_green<double, 8, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_green<double, 8, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_INIT: LSFFT_LAUNCH((k_green<double, 8, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_green<double, 8, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_green<double, 8, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_INIT: LSFFT_LAUNCH((k_green<double, 8, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_AP: LSFFT_LAUNCH((k_green<double, 8, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_DIR: LSFFT_LAUNCH((k_green<double, 8, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 12:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_green<double, 12, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_INIT: hipLaunchKernelGGL((k_green<double, 12, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_green<double, 12, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_green<double, 12, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_INIT: hipLaunchKernelGGL((k_green<double, 12, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_AP: hipLaunchKernelGGL((k_green<double, 12, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_DIR: hipLaunchKernelGGL((k_green<double, 12, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_green<double, 12, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_INIT: LSFFT_LAUNCH((k_green<double, 12, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_green<double, 12, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_green<double, 12, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_INIT: LSFFT_LAUNCH((k_green<double, 12, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_AP: LSFFT_LAUNCH((k_green<double, 12, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_DIR: LSFFT_LAUNCH((k_green<double, 12, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 16:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_green<double, 16, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_INIT: hipLaunchKernelGGL((k_green<double, 16, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_green<double, 16, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_green<double, 16, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_INIT: hipLaunchKernelGGL((k_green<double, 16, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_AP: hipLaunchKernelGGL((k_green<double, 16, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_DIR: hipLaunchKernelGGL((k_green<double, 16, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_green<double, 16, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_INIT: LSFFT_LAUNCH((k_green<double, 16, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_green<double, 16, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_green<double, 16, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_INIT: LSFFT_LAUNCH((k_green<double, 16, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_AP: LSFFT_LAUNCH((k_green<double, 16, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_DIR: LSFFT_LAUNCH((k_green<double, 16, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 24:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_green<double, 24, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_INIT: hipLaunchKernelGGL((k_green<double, 24, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_green<double, 24, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_green<double, 24, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_INIT: hipLaunchKernelGGL((k_green<double, 24, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_AP: hipLaunchKernelGGL((k_green<double, 24, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
-        case M_CG_DIR: hipLaunchKernelGGL((k_green<double, 24, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_green<double, 24, 3, M_FT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_INIT: LSFFT_LAUNCH((k_green<double, 24, 3, M_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_green<double, 24, 3, M_ITER>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_green<double, 24, 3, M_MAT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_INIT: LSFFT_LAUNCH((k_green<double, 24, 3, M_CG_INIT>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_AP: LSFFT_LAUNCH((k_green<double, 24, 3, M_CG_AP>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError();
+        case M_CG_DIR: LSFFT_LAUNCH((k_green<double, 24, 3, M_CG_DIR>), a.grid, Cfg<double>::NTH_G, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     default: return hipErrorInvalidValue;
   }
 }

@@ -53,17 +53,17 @@ hipError_t launch_green(bool f64, const LaunchArgs& a, int mode, int dim, int le
 
 hipError_t launch_cg_update(bool f64, const LaunchArgs& a) {
   if (f64)
-    hipLaunchKernelGGL((k_cg_update<double>), a.grid, Cfg<double>::NTH, sizeof(double) * 16, a.stream, a.desc, a.state,
-                       a.items, a.count);
+    LSFFT_LAUNCH((k_cg_update<double>), a.grid, Cfg<double>::NTH, sizeof(double) * 16, a.stream, a.desc, a.state,
+                 a.items, a.count);
   else
-    hipLaunchKernelGGL((k_cg_update<float>), a.grid, Cfg<float>::NTH, sizeof(double) * 16, a.stream, a.desc, a.state,
-                       a.items, a.count);
+    LSFFT_LAUNCH((k_cg_update<float>), a.grid, Cfg<float>::NTH, sizeof(double) * 16, a.stream, a.desc, a.state,
+                 a.items, a.count);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const LaunchArgs& a, const int* inst_list, const int* d_ninst, int ninst, int mode) {
   if (ninst <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(ninst), NTR, 0, a.stream, a.desc, a.state, inst_list, d_ninst, mode);
+  LSFFT_LAUNCH(k_reduce, dim3(ninst), NTR, 0, a.stream, a.desc, a.state, inst_list, d_ninst, mode);
   return hipGetLastError();
 }
 

@@ -9,64 +9,64 @@ hipError_t launch_xpass_f32_2d(const LaunchArgs& a, int mode, int len) {
   switch (len) {
     case 4:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 4, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 4, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 4, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 4, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 4, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 4, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 6:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 6, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 6, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 6, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 6, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 6, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 6, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 8:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 8, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 8, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 8, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 8, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 8, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 8, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 12:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 12, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 12, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 12, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 12, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 12, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 12, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 16:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 16, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 16, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 16, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 16, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 16, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 16, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 24:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 24, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 24, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 24, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 24, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 24, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 24, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 32:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 32, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 32, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 32, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 32, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 32, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 32, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 48:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 48, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 48, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 48, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 48, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 48, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 48, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 64:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 64, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 64, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 64, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 64, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 64, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 64, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 96:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 96, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 96, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 96, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 96, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 96, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 96, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 128:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 128, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 128, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 128, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 128, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 128, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 128, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     case 256:
       switch (mode) {
-        case M_FT: hipLaunchKernelGGL((k_xpass<float, 256, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_ITER: hipLaunchKernelGGL((k_xpass<float, 256, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
-        case M_MAT: hipLaunchKernelGGL((k_xpass<float, 256, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
+        case M_FT: LSFFT_LAUNCH((k_xpass<float, 256, 2, M_FT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_ITER: LSFFT_LAUNCH((k_xpass<float, 256, 2, M_ITER>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError();
+        case M_MAT: LSFFT_LAUNCH((k_xpass<float, 256, 2, M_MAT>), a.grid, Cfg<float>::NTH_X, a.lds, a.stream, a.desc, a.state, a.items, a.count, a.lame, tw); return hipGetLastError(); default: return hipErrorInvalidValue; }
     default: return hipErrorInvalidValue;
   }
 }

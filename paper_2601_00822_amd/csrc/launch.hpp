@@ -1,5 +1,6 @@
 // Host-side launch interface of the solver kernels.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "lsfft_internal.hpp"
@@ -17,7 +18,16 @@ struct LaunchArgs {
   const int* count;       // device pointer to the number of items
   const double* lame;     // device Lame table, pairs (lambda, mu)
   const void* tw;         // device twiddle table in the plan precision
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;   // if set: timestamps of the kernel's own start and end
 };
+
+// Launch through LaunchArgs `a`: with timing events the runtime stamps them
+// at the kernel's start and end (not around the dispatch packets).
+#define LSFFT_LAUNCH(K, GRID, BLOCK, LDS, STREAM, ...)                                                 \
+  do {                                                                                                 \
+    if (a.ev0) hipExtLaunchKernelGGL(K, GRID, dim3(BLOCK), LDS, STREAM, a.ev0, a.ev1, 0, __VA_ARGS__);  \
+    else hipLaunchKernelGGL(K, GRID, BLOCK, LDS, STREAM, __VA_ARGS__);                                 \
+  } while (0)
 
 // kind 0: x pass (len = nx); kind 1: y pass (len = ny); kind 2: outer pass
 // (len = nz in 3D, ny in 2D).  Returns the LDS bytes of one work item (0 if

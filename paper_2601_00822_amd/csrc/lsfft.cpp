@@ -233,24 +233,30 @@ bool geometry(bool f64, const lsfft_grid& g, Geometry* o) {
 // -------------------------------------------------------------------------
 // timing helpers
 // -------------------------------------------------------------------------
+// Reserve an event pair for one timed launch of class `cls`; the launch
+// itself stamps the pair at the kernel's start and end.  Returns -1 when
+// timing is off.
 int timed_begin(lsfft_plan_s* p, int cls) {
   if (!p->timing_active) return -1;
   if (p->ev_next + 2 > p->ev_pool.size()) {
     for (int k = 0; k < 256; ++k) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return -1;
+      // device-scope release: no system-scope cache flush after every timed kernel
+      if (hipEventCreateWithFlags(&e, hipEventReleaseToDevice) != hipSuccess) return -1;
       p->ev_pool.push_back(e);
     }
   }
   const int idx = (int)p->ev_next;
   p->ev_next += 2;
-  (void)hipEventRecord(p->ev_pool[idx], p->stream);
   p->ev_pending.push_back({cls, idx});
   return idx;
 }
-void timed_end(lsfft_plan_s* p, int idx) {
-  if (idx < 0) return;
-  (void)hipEventRecord(p->ev_pool[idx + 1], p->stream);
+LaunchArgs timed(lsfft_plan_s* p, LaunchArgs a, int idx) {
+  if (idx >= 0) {
+    a.ev0 = p->ev_pool[idx];
+    a.ev1 = p->ev_pool[idx + 1];
+  }
+  return a;
 }
 void timed_collect(lsfft_plan_s* p) {
   for (auto& pr : p->ev_pending) {
@@ -613,8 +619,7 @@ hipError_t pass_x(Batch& b, int list, int mode, int cls) {
   for (const Seg& sg : b.segs[list]) {
     if (sg.count == 0) continue;
     const int t = timed_begin(b.p, cls);
-    hipError_t e = launch_xpass(b.p->f64, largs(b, list, sg), mode, sg.dim, sg.len);
-    timed_end(b.p, t);
+    hipError_t e = launch_xpass(b.p->f64, timed(b.p, largs(b, list, sg), t), mode, sg.dim, sg.len);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -623,8 +628,7 @@ hipError_t pass_y(Batch& b, int list, int dir, int which, int ncomp, int gate, i
   for (const Seg& sg : b.segs[list]) {
     if (sg.count == 0) continue;
     const int t = timed_begin(b.p, cls);
-    hipError_t e = launch_ypass(b.p->f64, largs(b, list, sg, ncomp), dir, which, ncomp, gate, sg.len);
-    timed_end(b.p, t);
+    hipError_t e = launch_ypass(b.p->f64, timed(b.p, largs(b, list, sg, ncomp), t), dir, which, ncomp, gate, sg.len);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -633,24 +637,21 @@ hipError_t pass_g(Batch& b, int list, int mode, int cls) {
   for (const Seg& sg : b.segs[list]) {
     if (sg.count == 0) continue;
     const int t = timed_begin(b.p, cls);
-    hipError_t e = launch_green(b.p->f64, largs(b, list, sg), mode, sg.dim, sg.len);
-    timed_end(b.p, t);
+    hipError_t e = launch_green(b.p->f64, timed(b.p, largs(b, list, sg), t), mode, sg.dim, sg.len);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 hipError_t pass_reduce(Batch& b, int mode) {
   const int t = timed_begin(b.p, LSFFT_K_REDUCE);
-  hipError_t e = launch_reduce(base_args(b), b.d_inst, b.d_counts + kMaxSegs - 1, b.n_running, mode);
-  timed_end(b.p, t);
+  hipError_t e = launch_reduce(timed(b.p, base_args(b), t), b.d_inst, b.d_counts + kMaxSegs - 1, b.n_running, mode);
   return e;
 }
 hipError_t pass_cg_update(Batch& b) {
   for (const Seg& sg : b.segs[L_CG]) {
     if (sg.count == 0) continue;
     const int t = timed_begin(b.p, LSFFT_K_CGUPD);
-    hipError_t e = launch_cg_update(b.p->f64, largs(b, L_CG, sg));
-    timed_end(b.p, t);
+    hipError_t e = launch_cg_update(b.p->f64, timed(b.p, largs(b, L_CG, sg), t));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
