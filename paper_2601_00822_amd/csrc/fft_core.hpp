@@ -184,14 +184,28 @@ __device__ __forceinline__ void bfly(T* vr, T* vi) {
   else if constexpr (R == 8) bfly8<T, DIR>(vr, vi);
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// waits for every direct global->LDS load of the wave still in flight (its
+// fence covers LDS, which those loads write); this one lets such loads run on
+// across the barrier, for kernels that prefetch a tile into a buffer nobody
+// touches until an explicit wait.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+template <bool LB> __device__ __forceinline__ void tile_sync() {
+  if constexpr (LB) lds_barrier();
+  else __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // tile transform with register input and register output
 // ---------------------------------------------------------------------------
 // T: float/double; N: length; DIR: -1/+1; REV: reversed radix order;
 // MP: pencils; SM, SN: LDS strides of pencil and index; TWS: twiddle stride;
-// JF: index-fastest butterfly mapping; NTH: threads; PL: radix plan family.
+// JF: index-fastest butterfly mapping; NTH: threads; PL: radix plan family;
+// LB: barriers between passes order LDS only (see lds_barrier).
 template <typename T, int N, int DIR, bool REV, int MP, int SM, int SN, int TWS, bool JF, int NTH,
-          template <int> class PL = Plan, bool SKEW = false>
+          template <int> class PL = Plan, bool SKEW = false, bool LB = false>
 struct TileFft {
   // LDS word of element (pencil m, index n); with SKEW one padding word is
   // inserted every 32 indices, which breaks the power-of-two strides of the
@@ -313,20 +327,20 @@ struct TileFft {
         for (int r = 0; r < RL; ++r) { out_r[q][r] = in_r[q][r]; out_i[q][r] = in_i[q][r]; }
     } else if constexpr (np == 2) {
       scatter_pass<0>(in_r, in_i, re, im, twr, twi, tid);
-      __syncthreads();
+      tile_sync<LB>();
       gather_pass<1>(out_r, out_i, re, im, tid);
       compute_pass<1>(out_r, out_i, twr, twi, tid);
     } else {
       scatter_pass<0>(in_r, in_i, re, im, twr, twi, tid);
-      __syncthreads();
+      tile_sync<LB>();
       {
         constexpr int R1 = S::r(1), BP1 = (MP * (N / R1) + NTH - 1) / NTH;
         T mr[BP1][R1], mi[BP1][R1];
         gather_pass<1>(mr, mi, re, im, tid);
-        __syncthreads();
+        tile_sync<LB>();
         scatter_pass<1>(mr, mi, re, im, twr, twi, tid);
       }
-      __syncthreads();
+      tile_sync<LB>();
       gather_pass<2>(out_r, out_i, re, im, tid);
       compute_pass<2>(out_r, out_i, twr, twi, tid);
     }

@@ -14,6 +14,7 @@ static size_t geom_query(int kind, int len, int* per_tile) {
 #define X(L)                                                                    \
   case L:                                                                       \
     if (kind == 0) { bytes = lds_x<T, L>(); q = XGeom<T, L / 2>::MR; }          \
+    else if (kind == 3) { bytes = lds_xi<T, L>(); q = XGeom<T, L / 2>::MR; }    \
     else if (kind == 1) { bytes = lds_y<T, L>(); q = SGeom<T, L>::MP; }         \
     else { bytes = lds_g<T, L>(); q = SGeom<T, L>::MPG; }                        \
     break;

@@ -295,8 +295,8 @@ __device__ inline void finalize(const InstDesc& D, InstState& St, int mode, doub
 //   X[k] = E + exp(-2 pi i k / NX) O, E = (Z[k] + conj Z[H-k]) / 2,
 //   O = -i (Z[k] - conj Z[H-k]) / 2.
 template <typename T, int NX, int DIM, int MODE>
-__device__ void xpass_item(const InstDesc& D, int local, const double* __restrict__ lame,
-                           const T* __restrict__ twtab, unsigned char* smem) {
+__device__ void xpass_item_std(const InstDesc& D, int local, const double* __restrict__ lame,
+                               const T* __restrict__ twtab, unsigned char* smem) {
   constexpr int NTH = Cfg<T>::NTH_X;
   constexpr int H = NX / 2;
   using G = XGeom<T, H>;
@@ -574,6 +574,281 @@ __device__ void xpass_item(const InstDesc& D, int local, const double* __restric
       for (int c = 0; c < DIM; ++c) forward_store(n_r[c], n_i[c], D.S, c);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// x pass of the iteration with row tiles staged by direct global->LDS loads
+// ---------------------------------------------------------------------------
+// FP32 tiles of 2048 complex entries (nx = 64, 128, 256).  The main block of
+// a row tile (MR rows x H entries) is contiguous in HBM; it lands in LDS in
+// 1 KB pieces, one per wave-wide 16-byte-per-lane load, each piece followed
+// by 64 bytes of padding so that row pairs of consecutive pieces fall on
+// different LDS banks.  The Nyquist entries of the rows go into those
+// paddings, eight rows per padding.  Loads bypass the registers, so the
+// normal group fetches the next component into the second buffer while the
+// current one is transformed.  The buffers double as transform staging and
+// fold tiles once their data has been read.
+constexpr int kXDmaPhases = kMaxPhases;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+template <typename T, int H> struct XDma {
+  using G = XGeom<T, H>;
+  static constexpr int MR = G::MR;
+  static constexpr bool ok = sizeof(T) == 4 && MR * H == 2048 && Cfg<T>::NTH_X == 256;
+  static constexpr int KB = 1024, PAD = 64, PITCH = KB + PAD;
+  static constexpr int NCH = MR * H * 8 / KB;                 // 1 KB pieces per tile
+  static constexpr int BUF = (cmax(cmax(NCH * PITCH, 2 * MR * G::SM2 * 4), 2 * MR * G::SM * 4) + 15) / 16 * 16;
+  // dynamic LDS: twiddles (2 x 2H), Lame table, phase ids of the tile
+  static constexpr int DYN = 4 * (2 * 2 * H + 2 * kXDmaPhases) + MR * 2 * H;
+  static_assert(!ok || (NCH % 4 == 0 && MR / 8 <= NCH && MR * 2 * H == 4096), "x tile geometry");
+  // rows never straddle a piece (a row is 256, 512 or 1024 bytes)
+  __device__ static __forceinline__ int row_off(int m) {
+    const int p = m * H * 8;
+    return p + (p >> 10) * PAD;
+  }
+  __device__ static __forceinline__ int nyq_off(int m) { return (m >> 3) * PITCH + KB + (m & 7) * 8; }
+};
+
+typedef __attribute__((address_space(3))) void* lds_vptr;
+
+// Issue the loads of component `comp` (global base of the component) of row
+// tile row0 into LDS buffer `buf`.  Lanes past the last row load nothing.
+// Every supported axis length is even, so the component stride (ny nz (H+1)
+// entries of 8 bytes) keeps every component base 16-byte aligned.
+template <typename T, int H>
+__device__ __forceinline__ void xdma_issue(const char* comp, long long Pm, int row0, int nrows, unsigned char* buf,
+                                           int tid) {
+  using X = XDma<T, H>;
+  constexpr int MR = X::MR;
+  const int wave = tid >> 6, lane = tid & 63;
+  const char* mainp = comp + (long long)row0 * H * 8;
+#pragma unroll
+  for (int i = 0; i < X::NCH / 4; ++i) {
+    const int g = i * 4 + wave;
+    const int b = g * X::KB + lane * 16;
+    if (row0 + b / (H * 8) < nrows)
+      __builtin_amdgcn_global_load_lds((const void*)(mainp + b), (lds_vptr)(buf + g * X::PITCH), 16, 0, 0);
+  }
+  if (wave == 0) {
+    const char* nyq = comp + (Pm + row0) * 8;
+#pragma unroll
+    for (int i = 0; i < MR / 8; ++i) {
+      if (lane < 16 && row0 + 8 * i + (lane >> 1) < nrows)
+        __builtin_amdgcn_global_load_lds((const void*)(nyq + i * 64 + lane * 4),
+                                         (lds_vptr)(buf + i * X::PITCH + X::KB), 4, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+template <typename T, int NX, int DIM>
+__device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __restrict__ lame,
+                               const T* __restrict__ twtab, unsigned char* smem) {
+  constexpr int NTH = 256;
+  constexpr int H = NX / 2;
+  using G = XGeom<T, H>;
+  using X = XDma<T, H>;
+  constexpr int MR = G::MR, SM = G::SM, SM2 = G::SM2;
+  constexpr int S = (DIM == 3) ? 6 : 3;
+  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true, true>;
+  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true, true>;
+  static_assert(FI::RL == FF::R0 && FI::BL == FF::B0, "x transforms must chain in registers");
+  constexpr int BP = FI::BL, RP = FI::RL;
+  constexpr int TOTP = FI::TOTL;
+  constexpr int PB = MR * NX / NTH;                // phase bytes per thread
+
+  __shared__ __align__(16) unsigned char xb0[X::BUF];
+  __shared__ __align__(16) unsigned char xb1[X::BUF];
+  T* twr = reinterpret_cast<T*>(smem);
+  T* twi = twr + NX;
+  T* lam_s = twi + NX;
+  T* mu_s = lam_s + kXDmaPhases;
+  unsigned char* ptile = reinterpret_cast<unsigned char*>(mu_s + kXDmaPhases);
+  const int tid = threadIdx.x;
+  const int nrows = D.ny * D.nz;
+  const int part = local / D.xtiles;
+  const int row0 = (local - part * D.xtiles) * MR;
+  const long long Pm = D.Pm, Pc = D.Pc;
+  const int cfirst = (part == 0) ? 0 : DIM + part - 1;
+
+  xdma_issue<T, H>(cptr<T>(D.S, Pc, cfirst), Pm, row0, nrows, xb0, tid);
+  // phase ids of the tile, 16 consecutive x of one row per thread, read at
+  // the shifted positions
+  static_assert(PB == 16, "x tile phase map");
+  uint4 phv = make_uint4(0u, 0u, 0u, 0u);
+  {
+    const int m = (tid * 16) / NX, x0 = (tid * 16) - m * NX;
+    const int row = row0 + m;
+    if (row < nrows) {
+      const int z = row / D.ny, y = row - (row / D.ny) * D.ny;
+      const long long rbase = (long long)(wrap(z - D.sz, D.nz) * D.ny + wrap(y - D.sy, D.ny)) * NX;
+      if (((reinterpret_cast<unsigned long long>(D.phase) | (unsigned)D.sx) & 15ull) == 0) {
+        phv = gld<uint4>(D.phase + rbase + wrap(x0 - D.sx, NX), 0);
+      } else {
+        unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          w[i >> 2] |= (unsigned)gld<uint8_t>(D.phase, rbase + wrap(x0 + i - D.sx, NX)) << (8 * (i & 3));
+        phv = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+  }
+  load_tw<T, NX, NTH>(twr, twi, twtab, tid);
+  for (int p = tid; p < D.nphase; p += NTH) {
+    lam_s[p] = T(gld<double>(lame, 2 * (D.lame_off + p)));
+    mu_s[p] = T(gld<double>(lame, 2 * (D.lame_off + p) + 1));
+  }
+  reinterpret_cast<uint4*>(ptile)[tid] = phv;
+  wait_vm_all();
+  __syncthreads();
+
+  // fold of the tile in `buf` and the length-H inverse core; the buffer then
+  // serves as the core's staging
+  auto c2r = [&](unsigned char* buf, T (&o_r)[BP][RP], T (&o_i)[BP][RP]) {
+    T in_r[FI::B0][FI::R0], in_i[FI::B0][FI::R0];
+#pragma unroll
+    for (int q = 0; q < FI::B0; ++q) {
+      const int b = tid + q * NTH;
+      int m, j;
+      FI::template bj<FI::R0>(b, m, j);
+      if (FI::TOT0 % NTH != 0 && b >= FI::TOT0) m = 0;
+      const unsigned char* rowp = buf + X::row_off(m);
+#pragma unroll
+      for (int r = 0; r < FI::R0; ++r) {
+        const int k = j + r * (H / FI::R0);
+        const float2 xv = *reinterpret_cast<const float2*>(rowp + 8 * k);
+        const float2 yv = *reinterpret_cast<const float2*>((r == 0 && j == 0) ? buf + X::nyq_off(m) : rowp + 8 * (H - k));
+        const T xr = xv.x, xi = xv.y;
+        const T yr = yv.x, yi = -yv.y;
+        const T dr = xr - yr, di = xi - yi;
+        const T cr = twr[k], ci = -twi[k];
+        const T tr = cr * dr - ci * di, ti = cr * di + ci * dr;
+        in_r[q][r] = xr + yr - ti;
+        in_i[q][r] = xi + yi + tr;
+      }
+    }
+    lds_barrier();   // every wave has read the tile
+    T* br = reinterpret_cast<T*>(buf);
+    FI::run(in_r, in_i, o_r, o_i, br, br + MR * SM2, twr, twi, tid);
+  };
+  // forward core and unfold (staging in xb1, fold tile in xb0), then the
+  // stores of component c of S
+  auto forward_store = [&](T (&in_r)[FF::B0][FF::R0], T (&in_i)[FF::B0][FF::R0], int c) {
+    T* br = reinterpret_cast<T*>(xb1);
+    T* bi = br + MR * SM2;
+    T* ar = reinterpret_cast<T*>(xb0);
+    T* ai = ar + MR * SM;
+    T o_r[FF::BL][FF::RL], o_i[FF::BL][FF::RL];
+    lds_barrier();   // staging buffer free
+    FF::run(in_r, in_i, o_r, o_i, br, bi, twr, twi, tid);
+    lds_barrier();   // previous users of the fold tile are done
+#pragma unroll
+    for (int q = 0; q < FF::BL; ++q) {
+      const int b = tid + q * NTH;
+      if (FF::TOTL % NTH == 0 || b < FF::TOTL) {
+        int m, j;
+        FF::template bj<FF::RL>(b, m, j);
+#pragma unroll
+        for (int r = 0; r < FF::RL; ++r) {
+          const int n = j + r * (H / FF::RL);
+          ar[m * SM + n] = o_r[q][r];
+          ai[m * SM + n] = o_i[q][r];
+        }
+      }
+    }
+    lds_barrier();
+    char* base = mptr<T>(D.S, Pc, c);
+    for (int e = tid; e < MR * (H + 1); e += NTH) {
+      const int m = e / (H + 1);
+      const int k = e - m * (H + 1);
+      const int row = row0 + m;
+      if (row >= nrows) continue;
+      const int k1 = (k == H) ? 0 : k;
+      const int k2 = (k == 0) ? 0 : H - k;
+      const T zr = ar[m * SM + k1], zi = ai[m * SM + k1];
+      const T wr = ar[m * SM + k2], wi = ai[m * SM + k2];
+      const T er = T(0.5) * (zr + wr), ei = T(0.5) * (zi - wi);
+      const T dr = T(0.5) * (zr - wr), di = T(0.5) * (zi + wi);
+      const T orr = di, oi = -dr;
+      const T cr = twr[k], ci = twi[k];
+      const T xr = er + cr * orr - ci * oi, xi = ei + cr * oi + ci * orr;
+      if (k < H) stc<T>(base, row * H + k, xr, xi);
+      else stc<T>(base, (int)Pm + row, xr, xi);
+    }
+  };
+  // fn(q, r, half, lam, mu) at every point of this thread
+  auto each_point = [&](auto&& fn) {
+#pragma unroll
+    for (int q = 0; q < BP; ++q) {
+      const int b = tid + q * NTH;
+      int m, j;
+      FI::template bj<RP>(b, m, j);
+      if ((TOTP % NTH == 0 || b < TOTP) && row0 + m < nrows) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          const int n = j + r * (H / RP);
+#pragma unroll
+          for (int half = 0; half < 2; ++half) {
+            const int ph = ptile[m * NX + 2 * n + half];
+            fn(q, r, half, lam_s[ph], mu_s[ph]);
+          }
+        }
+      }
+    }
+  };
+
+  if (part >= 1) {
+    // shear component: sigma_ab = 2 mu eps_ab
+    T e_r[BP][RP], e_i[BP][RP];
+    c2r(xb0, e_r, e_i);
+    each_point([&](int q, int r, int half, T lam, T mu) {
+      if (half) e_i[q][r] *= T(2) * mu; else e_r[q][r] *= T(2) * mu;
+    });
+    forward_store(e_r, e_i, cfirst);
+    return;
+  }
+  // normal components, coupled through the trace; component c + 1 is in
+  // flight while component c is transformed
+  T n_r[DIM][BP][RP], n_i[DIM][BP][RP];
+  xdma_issue<T, H>(cptr<T>(D.S, Pc, 1), Pm, row0, nrows, xb1, tid);
+  c2r(xb0, n_r[0], n_i[0]);
+  wait_vm_all();
+  __syncthreads();   // component 1 landed; the staging of component 0 is free
+  if constexpr (DIM == 3) xdma_issue<T, H>(cptr<T>(D.S, Pc, 2), Pm, row0, nrows, xb0, tid);
+  c2r(xb1, n_r[1], n_i[1]);
+  if constexpr (DIM == 3) {
+    wait_vm_all();
+    __syncthreads();
+    c2r(xb0, n_r[2], n_i[2]);
+  }
+  each_point([&](int q, int r, int half, T lam, T mu) {
+    T ev[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) ev[c] = half ? n_i[c][q][r] : n_r[c][q][r];
+    T tr = T(0);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) tr += ev[c];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const T sv = T(2) * mu * ev[c] + lam * tr;
+      if (half) n_i[c][q][r] = sv; else n_r[c][q][r] = sv;
+    }
+  });
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) forward_store(n_r[c], n_i[c], c);
+  (void)S;
+}
+
+template <typename T, int NX, int DIM, int MODE>
+__device__ __forceinline__ void xpass_item(const InstDesc& D, int local, const double* __restrict__ lame,
+                                           const T* __restrict__ twtab, unsigned char* smem) {
+#ifndef LSFFT_NO_XDMA
+  if constexpr (MODE == M_ITER && XDma<T, NX / 2>::ok) {
+    xpass_iter_dma<T, NX, DIM>(D, local, lame, twtab, smem);
+    return;
+  }
+#endif
+  xpass_item_std<T, NX, DIM, MODE>(D, local, lame, twtab, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1515,6 +1790,14 @@ __global__ __launch_bounds__(NTR) void k_narrow(const InstDesc* __restrict__ d64
 template <typename T, int L> constexpr size_t lds_x() {
   using G = XGeom<T, L / 2>;
   return sizeof(T) * (2 * G::MR * G::SM + 2 * G::MR * G::SM2 + 2 * L + 2 * kMaxPhases);
+}
+// the iteration-mode x kernel (dynamic part only when its tiles are staged
+// in static LDS buffers)
+template <typename T, int L> constexpr size_t lds_xi() {
+#ifndef LSFFT_NO_XDMA
+  if (XDma<T, L / 2>::ok) return XDma<T, L / 2>::DYN;
+#endif
+  return lds_x<T, L>();
 }
 template <int MP> constexpr int padded(int mp) { return mp > 1 ? mp + 1 : 1; }
 template <typename T, int L> constexpr size_t lds_y() {

@@ -166,7 +166,7 @@ struct Geometry {
   int nx, ny, nz, H, dim, s;
   long long Pm, Pc, nvox;
   int xtiles, items_x, items_xall, items_xft, items_y, ymain, mpk_y, ntk_y, items_g, gmain, mpk_g, ntk_g, items_cg;
-  size_t lds_x, lds_y, lds_g;
+  size_t lds_x, lds_xi, lds_y, lds_g;   // lds_xi: x pass of the iteration
 };
 
 int ilog2(int v) {
@@ -194,10 +194,11 @@ bool geometry(bool f64, const lsfft_grid& g, Geometry* o) {
   o->nvox = (long long)o->nz * o->ny * o->nx;
   int mr = 0, mpy = 0, mpg = 0;
   o->lds_x = query_geometry(f64, 0, o->nx, &mr);
+  o->lds_xi = query_geometry(f64, 3, o->nx, nullptr);
   o->lds_y = (g.dim == 3) ? query_geometry(f64, 1, o->ny, &mpy) : 0;
   const int outer = (g.dim == 3) ? o->nz : o->ny;
   o->lds_g = query_geometry(f64, 2, outer, &mpg);
-  if (!o->lds_x || !o->lds_g || (g.dim == 3 && !o->lds_y)) return false;
+  if (!o->lds_x || !o->lds_xi || !o->lds_g || (g.dim == 3 && !o->lds_y)) return false;
   const int rows = o->ny * o->nz;
   o->xtiles = (rows + mr - 1) / mr;
   o->items_x = o->xtiles * (1 + o->s - o->dim);          // normal group + shear components
@@ -342,7 +343,7 @@ void list_key(const Batch& b, int l, int i, int* dim, int* len, int* items, size
   const Geometry& g = b.geo[i];
   *dim = g.dim;
   switch (l) {
-    case L_X: *len = g.nx; *items = g.items_x; *lds = g.lds_x; break;
+    case L_X: *len = g.nx; *items = g.items_x; *lds = g.lds_xi; break;
     case L_XALL: *len = g.nx; *items = g.items_xall; *lds = g.lds_x; break;
     case L_XLEAD: *len = g.nx; *items = g.items_xft; *lds = g.lds_x; break;
     case L_Y: case L_YALL: case L_YLEAD: *len = g.ny; *items = g.items_y; *lds = g.lds_y; break;
@@ -745,27 +746,38 @@ lsfft_status iterate(Batch& b, int max_rounds = 0, std::vector<int>* running_out
   hipGraphExec_t& gexec = b.graph.exec;
   const bool use_graph = p->graphs && !timing && max_rounds == 0;
   std::vector<int> running;
-  for (int r = 0; max_rounds == 0 || r < max_rounds; ++r) {
-    if (use_graph) {
-      if (!gexec) {
-        hipGraph_t graph = nullptr;
-        LSFFT_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        const hipError_t ce = round();
-        const hipError_t ee = hipStreamEndCapture(st, &graph);
-        if (ce != hipSuccess || ee != hipSuccess) {
-          if (graph) (void)hipGraphDestroy(graph);
-          return LSFFT_E_DEVICE;
+  // Rounds launched between two host polls: from each running solve's
+  // observed contraction since the previous poll, the iterations it still
+  // needs; the earliest finisher sets how many rounds run unpolled (at most
+  // kMaxReplays).  Rounds past a solve's end are gated on the device.
+  constexpr int kMaxReplays = 8;
+  const int n = (int)b.specs.size();
+  std::vector<double> last_res(n, -1.0);
+  std::vector<int> last_it(n, -1);
+  int reps = 1;
+  for (int r = 0; max_rounds == 0 || r < max_rounds; r += reps) {
+    for (int k = 0; k < reps; ++k) {
+      if (use_graph) {
+        if (!gexec) {
+          hipGraph_t graph = nullptr;
+          LSFFT_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          const hipError_t ce = round();
+          const hipError_t ee = hipStreamEndCapture(st, &graph);
+          if (ce != hipSuccess || ee != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return LSFFT_E_DEVICE;
+          }
+          const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(graph);
+          if (ie != hipSuccess) {
+            gexec = nullptr;
+            return LSFFT_E_DEVICE;
+          }
         }
-        const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ie != hipSuccess) {
-          gexec = nullptr;
-          return LSFFT_E_DEVICE;
-        }
+        LSFFT_TRY(hipGraphLaunch(gexec, st));
+      } else {
+        LSFFT_TRY(round());
       }
-      LSFFT_TRY(hipGraphLaunch(gexec, st));
-    } else {
-      LSFFT_TRY(round());
     }
     lsfft_status ls = read_states(b, running);
     if (ls != LSFFT_OK) return ls;
@@ -773,6 +785,23 @@ lsfft_status iterate(Batch& b, int max_rounds = 0, std::vector<int>* running_out
     if ((int)running.size() < b.n_running) {
       ls = upload_lists(b, running, false);
       if (ls != LSFFT_OK) return ls;
+    }
+    double rem_min = 1e300;
+    for (int i : running) {
+      const InstState& S = b.state[i];
+      double rem = (double)per_round;   // unknown rate: one round
+      if (last_it[i] >= 0 && S.iter > last_it[i] && S.residual > 0.0 && S.residual < last_res[i]) {
+        const double rho = std::pow(S.residual / last_res[i], 1.0 / (double)(S.iter - last_it[i]));
+        if (rho < 1.0 && rho > 0.0 && b.tol < S.residual) rem = std::log(b.tol / S.residual) / std::log(rho);
+        else if (b.tol >= S.residual) rem = 0.0;
+      }
+      rem_min = std::min(rem_min, rem);
+      last_res[i] = S.residual;
+      last_it[i] = S.iter;
+    }
+    if (max_rounds == 0) {
+      reps = (int)std::floor(rem_min / (double)per_round);
+      reps = std::max(1, std::min(kMaxReplays, reps));
     }
   }
   if (timing) timed_collect(p);

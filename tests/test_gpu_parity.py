@@ -202,6 +202,45 @@ def test_fp32_2d_config1(torch_dev):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("shape", [(4, 6, 128), (6, 12, 128), (6, 16, 64), (4, 6, 256), (24, 128), (48, 64)])
+def test_fp32_staged_x_tiles(torch_dev, shape):
+    """FP32 x pass with row tiles staged by direct global->LDS loads (nx = 64,
+    128, 256; 32, 64 or 16 rows per tile): single and ragged row tiles, 2D and
+    3D."""
+    say(f"FP32 staged x tiles {shape}")
+    phase = rand_phase(shape, 51)
+    f = rand_force(shape, 52)
+    ref = O.solve_basic(phase, LAME10, f, tol=1e-8)
+    res, rep = gpu_solve(torch_dev, shape, phase, LAME10, f, prec="f32", tol=1e-8)
+    err = O.relative_strain_error_voigt(res["eps"], O.to_voigt(ref.eps))
+    serr = O.relative_strain_error_voigt(res["sig"], O.to_voigt(ref.sig))
+    print(f"status={rep.status} iters={rep.iters}/{ref.iters} residual={rep.residual:.3e} err={err:.3e} serr={serr:.3e}")
+    assert rep.status in (0, 1)
+    assert err < 1e-5 and serr < 1e-5
+
+
+def test_fp32_staged_x_tiles_shifted(torch_dev):
+    """Shifted microstructures in the staged x pass: x shifts that are and are
+    not multiples of 16 (vector and byte reads of the phase map)."""
+    say("FP32 staged x tiles, translated average 4x8x128")
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import Plan
+    shape = (4, 8, 128)
+    phase = rand_phase(shape, 53)
+    f = gen.bump_force(shape, (1.7, 3.2, 40.5), 3.0, gen.random_direction(3, 54))
+    shifts = np.array([[0, 0, 0], [1, 2, 16], [3, 1, 5], [2, 5, 37]], dtype=np.int32)
+    ref, _ = O.translate_average(phase, LAME10, f, shifts, tol=1e-10)
+    plan = Plan([shape], prec="f32", max_batch=4)
+    avg, reps = plan.translate_average(torch.from_numpy(phase).to(dev), LAME10,
+                                       torch.from_numpy(f).to(dev).float(), shifts, tol=1e-8)
+    a = avg.cpu().numpy()
+    print("iters", [r.iters for r in reps])
+    s = 6
+    assert O.relative_strain_error_voigt(a[6:6 + s], ref[6:6 + s]) < 1e-5
+    np.testing.assert_array_equal(a[-1], ref[-1])
+    plan.close()
+
+
 # ---------------------------------------------------------------- batches
 
 def test_batch_mixed_grids(torch_dev):
@@ -332,3 +371,29 @@ def test_determinism(torch_dev):
         for k in a:
             assert torch.equal(a[k], b[k])
         plan.close()
+
+
+def test_timing_plan_matches_graph_plan(torch_dev):
+    """The timed plan (graphs off, event pairs stamped by every launch) computes
+    the same iterates bit for bit and accounts one launch of each pass class
+    per iteration."""
+    say("timing plan vs graph plan, 3D 16x24x32 FP32")
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import Plan, K_GREEN, K_XPASS, K_YPASS, K_REDUCE
+    shape = (16, 24, 32)
+    phase = rand_phase(shape, 41)
+    f = torch.from_numpy(rand_force(shape, 42)).to(dev).float()
+    ph = torch.from_numpy(phase).to(dev)
+    outs = []
+    for timing in (False, True):
+        plan = Plan([shape], prec="f32", timing=timing)
+        o, rep = plan.solve(ph, LAME10, f, tol=1e-6)
+        torch.cuda.synchronize()
+        outs.append((o["eps"].cpu(), rep.iters))
+        if timing:
+            for k in (K_GREEN, K_XPASS, K_YPASS, K_REDUCE):
+                ms, n = plan.kernel_times(k)
+                assert ms > 0.0 and n >= rep.iters, (k, ms, n, rep.iters)
+        plan.close()
+    assert outs[0][1] == outs[1][1]
+    assert torch.equal(outs[0][0], outs[1][0])
