@@ -51,6 +51,30 @@ struct DevBuf {
   }
 };
 
+// Page-locked host mirror of the plan's metadata buffer: descriptors, states,
+// tables, counts and work lists are staged here at the offsets they occupy
+// on the device, so an upload is one asynchronous copy per contiguous range.
+struct HostBuf {
+  char* p = nullptr;
+  size_t cap = 0;
+  bool ensure(size_t bytes) {
+    if (bytes <= cap) return true;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    void* q = nullptr;
+    if (hipHostMalloc(&q, bytes, hipHostMallocDefault) != hipSuccess) return false;
+    p = static_cast<char*>(q);
+    cap = bytes;
+    return true;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
 // One solve of a batch, as resolved on the host.
 struct Spec {
   int grid = 0;
@@ -102,6 +126,8 @@ struct lsfft_plan_s {
   int poll = 8;
   bool owns_stream = true;
   DevBuf tw, arena, meta, lists;
+  HostBuf hmeta;            // host mirror of `meta`
+  bool h2d_inflight = false;  // copies out of `hmeta` may still be queued
   // LSFFT_REFINE64: FP64 companion (same grids, shares the work stream) and
   // the FP64 copies of the forces
   lsfft_plan_s* sub = nullptr;
@@ -292,6 +318,7 @@ struct Batch {
   int* d_phasemax = nullptr;
   WorkItem* d_lists[L_NUM] = {nullptr};
   int list_cap[L_NUM] = {0};
+  size_t m_state = 0, m_counts = 0, m_inst = 0, m_pmax = 0, m_list[L_NUM] = {0};   // offsets in meta
   std::vector<Seg> segs[L_NUM];   // per list: one segment per (dim, transform length)
   int nseg_total = 0;
   int n_running = 0;
@@ -307,8 +334,42 @@ struct Batch {
     GraphHolder& operator=(const GraphHolder&) { return *this; }
     ~GraphHolder() { if (exec) (void)hipGraphExecDestroy(exec); }
   } graph;
-  std::vector<WorkItem> host_items[L_NUM];         // staging of the uploaded lists
 };
+
+// The host mirror may be rewritten only once the copies queued from it ran.
+lsfft_status host_fence(lsfft_plan_s* p) {
+  if (p->h2d_inflight) {
+    LSFFT_TRY(hipStreamSynchronize(p->stream));
+    p->h2d_inflight = false;
+  }
+  return LSFFT_OK;
+}
+template <typename V> V* hptr(Batch& b, size_t off) { return reinterpret_cast<V*>(b.p->hmeta.p + off); }
+// queue one host-mirror -> device copy of meta bytes [off, off + bytes)
+lsfft_status h2d(Batch& b, size_t off, size_t bytes) {
+  if (bytes == 0) return LSFFT_OK;
+  LSFFT_TRY(hipMemcpyAsync(static_cast<char*>(b.p->meta.p) + off, b.p->hmeta.p + off, bytes, hipMemcpyHostToDevice,
+                           b.p->stream));
+  b.p->h2d_inflight = true;
+  return LSFFT_OK;
+}
+// device -> host copy of the solve states, then into b.state (synchronizes)
+lsfft_status d2h_states(Batch& b) {
+  const int n = (int)b.specs.size();
+  LSFFT_TRY(hipMemcpyAsync(b.p->hmeta.p + b.m_state, b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost,
+                           b.p->stream));
+  LSFFT_TRY(hipStreamSynchronize(b.p->stream));
+  b.p->h2d_inflight = false;
+  std::memcpy(b.state.data(), hptr<InstState>(b, b.m_state), sizeof(InstState) * n);
+  return LSFFT_OK;
+}
+// b.state -> device (asynchronous)
+lsfft_status h2d_states(Batch& b) {
+  const int n = (int)b.specs.size();
+  if (host_fence(b.p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  std::memcpy(hptr<InstState>(b, b.m_state), b.state.data(), sizeof(InstState) * n);
+  return h2d(b, b.m_state, sizeof(InstState) * n);
+}
 
 LaunchArgs largs(Batch& b, int list, const Seg& sg, int units = 1) {
   LaunchArgs a;
@@ -392,14 +453,16 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
     if (cidx > kMaxSegs - 1) return LSFFT_E_ALLOC;
     b.nseg_total = cidx;
   }
-  std::vector<int> counts(kMaxSegs, 0);
+  if (host_fence(b.p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  int* counts = hptr<int>(b, b.m_counts);
+  std::fill(counts, counts + kMaxSegs, 0);
   for (int l = 0; l < L_NUM; ++l) {
     if (!all_too && !is_dynamic(l)) {
       for (auto& x : b.segs[l]) counts[x.cidx] = x.count;
       continue;
     }
-    std::vector<WorkItem>& items = b.host_items[l];
-    items.resize(b.list_cap[l] > 0 ? b.list_cap[l] : 1);
+    WorkItem* items = hptr<WorkItem>(b, b.m_list[l]);
+    int lo = b.list_cap[l], hi = 0;   // item range to upload
     for (auto& x : b.segs[l]) {
       int fill = 0;
       const std::vector<int>* src = &running;
@@ -420,20 +483,22 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
       }
       x.count = fill;
       counts[x.cidx] = fill;
-      if (fill > 0)
-        LSFFT_TRY(hipMemcpyAsync(b.d_lists[l] + x.off, items.data() + x.off, sizeof(WorkItem) * fill,
-                                 hipMemcpyHostToDevice, b.p->stream));
+      if (fill > 0) {
+        lo = std::min(lo, x.off);
+        hi = std::max(hi, x.off + fill);
+      }
+    }
+    if (hi > lo) {
+      const lsfft_status ls = h2d(b, b.m_list[l] + sizeof(WorkItem) * (size_t)lo, sizeof(WorkItem) * (size_t)(hi - lo));
+      if (ls != LSFFT_OK) return ls;
     }
   }
-  std::vector<int> inst(running.begin(), running.end());
-  counts[kMaxSegs - 1] = (int)inst.size();   // solves listed for the reduction
-  LSFFT_TRY(hipMemcpyAsync(b.d_counts, counts.data(), sizeof(int) * counts.size(), hipMemcpyHostToDevice,
-                           b.p->stream));
-  if (!inst.empty())
-    LSFFT_TRY(hipMemcpyAsync(b.d_inst, inst.data(), sizeof(int) * inst.size(), hipMemcpyHostToDevice, b.p->stream));
-  b.n_running = (int)inst.size();
-  LSFFT_TRY(hipStreamSynchronize(b.p->stream));
-  return LSFFT_OK;
+  int* inst = hptr<int>(b, b.m_inst);
+  for (size_t k = 0; k < running.size(); ++k) inst[k] = running[k];
+  counts[kMaxSegs - 1] = (int)running.size();   // solves listed for the reduction
+  b.n_running = (int)running.size();
+  // counts and the solve list are adjacent in the metadata buffer
+  return h2d(b, b.m_counts, (b.m_inst - b.m_counts) + sizeof(int) * running.size());
 }
 
 // Largest half-spectrum size among the listed solves (grid of the
@@ -458,6 +523,7 @@ lsfft_status prepare(Batch& b) {
   const int n = (int)b.specs.size();
   const bool cg = p->scheme == LSFFT_CG;
 
+  if (host_fence(p) != LSFFT_OK) return LSFFT_E_DEVICE;
   // geometry, Lame tables
   b.geo.resize(n);
   b.desc.assign(n, InstDesc{});
@@ -522,8 +588,13 @@ lsfft_status prepare(Batch& b) {
     m_list[l] = moff;
     moff = align_up(moff + sizeof(WorkItem) * std::max(1, list_need[l]));
   }
-  if (!p->meta.ensure(moff)) return LSFFT_E_ALLOC;
+  if (!p->meta.ensure(moff) || !p->hmeta.ensure(moff)) return LSFFT_E_ALLOC;
   char* M = static_cast<char*>(p->meta.p);
+  b.m_state = m_state;
+  b.m_counts = m_counts;
+  b.m_inst = m_inst;
+  b.m_pmax = m_pmax;
+  for (int l = 0; l < L_NUM; ++l) b.m_list[l] = m_list[l];
   b.d_desc = reinterpret_cast<InstDesc*>(M + m_desc);
   b.d_state = reinterpret_cast<InstState*>(M + m_state);
   b.d_lame = reinterpret_cast<double*>(M + m_lame);
@@ -585,13 +656,18 @@ lsfft_status prepare(Batch& b) {
     S.iter = 0;
   }
   hipStream_t st = p->stream;
-  LSFFT_TRY(hipMemcpyAsync(b.d_desc, b.desc.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice, st));
-  LSFFT_TRY(hipMemcpyAsync(b.d_state, b.state.data(), sizeof(InstState) * n, hipMemcpyHostToDevice, st));
-  LSFFT_TRY(hipMemcpyAsync(b.d_lame, b.lame.data(), sizeof(double) * b.lame.size(), hipMemcpyHostToDevice, st));
-  std::vector<GroupDesc> gd;
-  for (auto& g : b.groups) gd.push_back(GroupDesc{g.first, g.count, g.incl_phase, 0, g.avg});
-  if (!gd.empty())
-    LSFFT_TRY(hipMemcpyAsync(b.d_groups, gd.data(), sizeof(GroupDesc) * gd.size(), hipMemcpyHostToDevice, st));
+  // descriptors, states, Lame tables and groups: one copy of their range
+  char* H = p->hmeta.p;
+  std::memcpy(H + m_desc, b.desc.data(), sizeof(InstDesc) * n);
+  std::memcpy(H + m_state, b.state.data(), sizeof(InstState) * n);
+  if (!b.lame.empty()) std::memcpy(H + m_lame, b.lame.data(), sizeof(double) * b.lame.size());
+  GroupDesc* gd = hptr<GroupDesc>(b, m_groups);
+  for (size_t g = 0; g < b.groups.size(); ++g)
+    gd[g] = GroupDesc{b.groups[g].first, b.groups[g].count, b.groups[g].incl_phase, 0, b.groups[g].avg};
+  {
+    const lsfft_status ls = h2d(b, 0, m_counts);
+    if (ls != LSFFT_OK) return ls;
+  }
 
   // phase ids must index the tables: one device max per distinct map
   LSFFT_TRY(hipMemsetAsync(b.d_phasemax, 0, sizeof(int) * n, st));
@@ -600,9 +676,10 @@ lsfft_status prepare(Batch& b) {
     for (int j = 0; j < i && !seen; ++j) seen = (b.specs[j].phase == b.specs[i].phase && b.geo[j].nvox == b.geo[i].nvox);
     if (!seen) LSFFT_TRY(launch_phase_max(b.specs[i].phase, b.geo[i].nvox, b.d_phasemax + i, st));
   }
-  std::vector<int> pmax(n, 0);
-  LSFFT_TRY(hipMemcpyAsync(pmax.data(), b.d_phasemax, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  LSFFT_TRY(hipMemcpyAsync(H + m_pmax, b.d_phasemax, sizeof(int) * n, hipMemcpyDeviceToHost, st));
   LSFFT_TRY(hipStreamSynchronize(st));
+  p->h2d_inflight = false;
+  const int* pmax = hptr<int>(b, m_pmax);
   for (int i = 0; i < n; ++i) {
     int m = pmax[i];
     for (int j = 0; j < i; ++j)
@@ -676,8 +753,8 @@ lsfft_status setup(Batch& b, bool spectral_force) {
   LSFFT_TRY(pass_reduce(b, M_INIT));
 
   if (!spectral_force && (p->flags & LSFFT_STRICT_EQUIL)) {
-    LSFFT_TRY(hipMemcpyAsync(b.state.data(), b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost, p->stream));
-    LSFFT_TRY(hipStreamSynchronize(p->stream));
+    const lsfft_status ls = d2h_states(b);
+    if (ls != LSFFT_OK) return ls;
     for (int i = 0; i < n; ++i) {
       const InstState& L = b.state[b.specs[i].leader];
       const double fn = std::sqrt(b.state[i].fnorm2 / (double)b.geo[i].nvox);
@@ -693,8 +770,8 @@ lsfft_status setup(Batch& b, bool spectral_force) {
 // Copy the solve states to the host and list the running ones.
 lsfft_status read_states(Batch& b, std::vector<int>& running) {
   const int n = (int)b.specs.size();
-  LSFFT_TRY(hipMemcpyAsync(b.state.data(), b.d_state, sizeof(InstState) * n, hipMemcpyDeviceToHost, b.p->stream));
-  LSFFT_TRY(hipStreamSynchronize(b.p->stream));
+  const lsfft_status ls = d2h_states(b);
+  if (ls != LSFFT_OK) return ls;
   running.clear();
   for (int i = 0; i < n; ++i)
     if (b.state[i].status == ST_RUNNING) running.push_back(i);
@@ -861,8 +938,14 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
 //   3. sets u += d in FP64.
 // The FP32 floor of the inner solves bounds only the reduction per step, not
 // the final accuracy.  The returned fields are materialized in FP32 from the
-// FP64 state rounded once.
-constexpr double kInnerTol = 1e-3;
+// FP64 state rounded once.  An inner tolerance of 3e-5 reaches 1e-8 in two
+// outer steps with about as many FP32 iterations in all as three steps of
+// 1e-3 take, and saves one FP64 residual evaluation and one round of host
+// decisions; 3e-5 stays well above the FP32 floor of the inner solves.
+#ifndef LSFFT_INNER_TOL
+#define LSFFT_INNER_TOL 3e-5
+#endif
+constexpr double kInnerTol = LSFFT_INNER_TOL;
 constexpr int kMaxOuter = 40;
 
 lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
@@ -944,7 +1027,7 @@ lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
     in.state[i].iter = 0;
     in.state[i].status = c.state[i].status;
   }
-  LSFFT_TRY(hipMemcpyAsync(in.d_state, in.state.data(), sizeof(InstState) * n, hipMemcpyHostToDevice, st));
+  if ((ls = h2d_states(in)) != LSFFT_OK) return ls;
   if ((ls = materialize(in)) != LSFFT_OK) return ls;
   const double secs = now_s() - t0_wall;
   lsfft_status worst = LSFFT_OK;
@@ -1019,6 +1102,7 @@ void free_plan(lsfft_plan_s* p) {
   p->tw.release();
   p->arena.release();
   p->meta.release();
+  p->hmeta.release();
   p->lists.release();
   p->fwide.release();
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
