@@ -596,9 +596,17 @@ template <typename T, int H> struct XDma {
   static constexpr bool ok = sizeof(T) == 4 && MR * H == 2048 && Cfg<T>::NTH_X == 256;
   static constexpr int KB = 1024, PAD = 64, PITCH = KB + PAD;
   static constexpr int NCH = MR * H * 8 / KB;                 // 1 KB pieces per tile
-  static constexpr int BUF = (cmax(cmax(NCH * PITCH, 2 * MR * G::SM2 * 4), 2 * MR * G::SM * 4) + 15) / 16 * 16;
+  // fold-tile pitch for the unfold: the forward core leaves NB = H / RL
+  // consecutive entries of a row in consecutive lanes, so a pitch of NB
+  // (mod 32) puts the rows of a wave on disjoint LDS banks
+  static constexpr int NB = H / PlanSeq<LSFFT_XPLAN, H, false>::last();
+  static constexpr int SMF = (H + 1 + ((NB - (H + 1) % 32) % 32 + 32) % 32);
+  static constexpr int BUF = (cmax(cmax(NCH * PITCH, 2 * MR * G::SM2 * 4), 2 * MR * SMF * 4) + 15) / 16 * 16;
+  // phase ids of the tile: rows of 2H bytes at a pitch of 2H + 16 (the rows
+  // of a wave then fall on different LDS banks)
+  static constexpr int PP = 2 * H + 16;
   // dynamic LDS: twiddles (2 x 2H), Lame table, phase ids of the tile
-  static constexpr int DYN = 4 * (2 * 2 * H + 2 * kXDmaPhases) + MR * 2 * H;
+  static constexpr int DYN = 4 * (2 * 2 * H + 2 * kXDmaPhases) + MR * PP;
   static_assert(!ok || (NCH % 4 == 0 && MR / 8 <= NCH && MR * 2 * H == 4096), "x tile geometry");
   // rows never straddle a piece (a row is 256, 512 or 1024 bytes)
   __device__ static __forceinline__ int row_off(int m) {
@@ -648,11 +656,12 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   constexpr int H = NX / 2;
   using G = XGeom<T, H>;
   using X = XDma<T, H>;
-  constexpr int MR = G::MR, SM = G::SM, SM2 = G::SM2;
+  constexpr int MR = G::MR, SM = X::SMF, SM2 = G::SM2;
   constexpr int S = (DIM == 3) ? 6 : 3;
   using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true, true>;
   using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true, true>;
   static_assert(FI::RL == FF::R0 && FI::BL == FF::B0, "x transforms must chain in registers");
+  static_assert(X::NB == H / FF::RL && SM % 32 == X::NB % 32 && SM > H, "fold-tile pitch");
   constexpr int BP = FI::BL, RP = FI::RL;
   constexpr int TOTP = FI::TOTL;
   constexpr int PB = MR * NX / NTH;                // phase bytes per thread
@@ -698,7 +707,10 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
     lam_s[p] = T(gld<double>(lame, 2 * (D.lame_off + p)));
     mu_s[p] = T(gld<double>(lame, 2 * (D.lame_off + p) + 1));
   }
-  reinterpret_cast<uint4*>(ptile)[tid] = phv;
+  {
+    const int m = (tid * 16) / NX, x0 = (tid * 16) - m * NX;
+    *reinterpret_cast<uint4*>(ptile + m * X::PP + x0) = phv;
+  }
   wait_vm_all();
   __syncthreads();
 
@@ -787,9 +799,10 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
 #pragma unroll
         for (int r = 0; r < RP; ++r) {
           const int n = j + r * (H / RP);
+          const unsigned pp = *reinterpret_cast<const unsigned short*>(ptile + m * X::PP + 2 * n);
 #pragma unroll
           for (int half = 0; half < 2; ++half) {
-            const int ph = ptile[m * NX + 2 * n + half];
+            const int ph = half ? (int)(pp >> 8) : (int)(pp & 0xffu);
             fn(q, r, half, lam_s[ph], mu_s[ph]);
           }
         }
