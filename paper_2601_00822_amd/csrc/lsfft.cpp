@@ -869,8 +869,9 @@ lsfft_status iterate(Batch& b, int max_rounds = 0, std::vector<int>* running_out
       double rem = (double)per_round;   // unknown rate: one round
       if (last_it[i] >= 0 && S.iter > last_it[i] && S.residual > 0.0 && S.residual < last_res[i]) {
         const double rho = std::pow(S.residual / last_res[i], 1.0 / (double)(S.iter - last_it[i]));
-        if (rho < 1.0 && rho > 0.0 && b.tol < S.residual) rem = std::log(b.tol / S.residual) / std::log(rho);
-        else if (b.tol >= S.residual) rem = 0.0;
+        const double tol = b.desc[i].tol;
+        if (rho < 1.0 && rho > 0.0 && tol < S.residual) rem = std::log(tol / S.residual) / std::log(rho);
+        else if (tol >= S.residual) rem = 0.0;
       }
       rem_min = std::min(rem_min, rem);
       last_res[i] = S.residual;
@@ -999,6 +1000,13 @@ lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
     // solves)
     if ((ls = iterate(c, 1, &running)) != LSFFT_OK) return ls;
     if (running.empty()) break;
+    // inner tolerance per solve: a step leaves about the inner tolerance
+    // times the current residual, so aim at 0.3 tol, within [kInnerTol, 0.1]
+    if ((ls = host_fence(p)) != LSFFT_OK) return ls;
+    for (int i : running)
+      in.desc[i].tol = std::min(0.1, std::max(kInnerTol, 0.3 * c.tol / std::max(c.state[i].residual, 1e-300)));
+    std::memcpy(hptr<InstDesc>(in, 0), in.desc.data(), sizeof(InstDesc) * n);
+    if ((ls = h2d(in, 0, sizeof(InstDesc) * n)) != LSFFT_OK) return ls;
     // the inner lists keep their last contents when every inner solve ends;
     // rebuild them only when the set of solves changed
     if (running != in_listed || in.n_running != (int)running.size()) {
