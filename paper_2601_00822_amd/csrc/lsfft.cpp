@@ -992,6 +992,7 @@ lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
   for (int i = 0; i < n; ++i) in.specs[i].leader = i;
   if ((ls = prepare(in)) != LSFFT_OK) return ls;
   std::vector<long long> inner_iters(n, 0);
+  std::vector<double> inner_floor(n, 0.0);
   std::vector<int> running, in_listed(n);
   for (int i = 0; i < n; ++i) in_listed[i] = i;   // what prepare() listed for the inner batch
   for (;;) {
@@ -1001,10 +1002,14 @@ lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
     if ((ls = iterate(c, 1, &running)) != LSFFT_OK) return ls;
     if (running.empty()) break;
     // inner tolerance per solve: a step leaves about the inner tolerance
-    // times the current residual, so aim at 0.3 tol, within [kInnerTol, 0.1]
+    // times the current residual, so aim at 0.3 tol, within [kInnerTol, 0.1],
+    // and not below 1.5 times the level where an earlier inner solve of this
+    // solve stagnated (its FP32 floor)
     if ((ls = host_fence(p)) != LSFFT_OK) return ls;
-    for (int i : running)
-      in.desc[i].tol = std::min(0.1, std::max(kInnerTol, 0.3 * c.tol / std::max(c.state[i].residual, 1e-300)));
+    for (int i : running) {
+      const double aim = std::max(0.3 * c.tol / std::max(c.state[i].residual, 1e-300), 1.5 * inner_floor[i]);
+      in.desc[i].tol = std::min(0.1, std::max(kInnerTol, aim));
+    }
     std::memcpy(hptr<InstDesc>(in, 0), in.desc.data(), sizeof(InstDesc) * n);
     if ((ls = h2d(in, 0, sizeof(InstDesc) * n)) != LSFFT_OK) return ls;
     // the inner lists keep their last contents when every inner solve ends;
@@ -1019,7 +1024,10 @@ lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
     std::vector<int> still;
     if ((ls = iterate(in, 0, &still)) != LSFFT_OK) return ls;
     if (in.n_running != (int)in_listed.size()) in_listed.clear();   // compacted on the way
-    for (int i : running) inner_iters[i] += in.state[i].iter;
+    for (int i : running) {
+      inner_iters[i] += in.state[i].iter;
+      if (in.state[i].status == ST_STAGNATED) inner_floor[i] = std::max(inner_floor[i], in.state[i].residual);
+    }
     // step 3: u += d in FP64
     LSFFT_TRY(launch_correct(c.d_desc, c.d_state, in.d_desc, in.d_state, c.d_inst, c.n_running, cg,
                              max_pc(c, running), st));
