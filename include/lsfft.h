@@ -186,6 +186,28 @@ typedef struct {
 lsfft_status lsfft_translate_average_batch(lsfft_plan_t p, int ngroup, const lsfft_avg_group* groups,
                                            double tol, int max_iter, lsfft_report* rep);
 
+/*
+ * lsfft_realization_average -- the deterministic-structure dataset of Sec. 3
+ * (Eq. 3.8): the force stays fixed and the ensemble average runs over
+ * realisations X^j of the microstructure (separate phase maps of one grid,
+ * e.g. samples of a CT image), each solved unshifted:
+ *   avg = (1/nreal) sum_j [u, u V, eps, eps V, sigma, sigma V, V]
+ * with V the indicator of phase incl_phase in realisation j.  The
+ * realisations share the phase table (and with it the reference medium)
+ * and one force spectrum; they are solved in batches of up to max_batch.
+ *  phases  host array [nreal] of device phase maps [N]
+ *  f       device force [d][N] in the plan precision
+ *  avg     device FP64 [2d + 4s + 1][N] (overwritten), component order as
+ *          for lsfft_translate_average
+ *  rep     host [nreal], per realisation
+ * Errors: LSFFT_E_ARG for a null map or pointer, nreal < 1, a bad table,
+ * incl_phase outside the table, tol <= 0 or a phase id outside the table.
+ */
+lsfft_status lsfft_realization_average(lsfft_plan_t p, int grid_idx, int nreal, const uint8_t* const* phases,
+                                       const lsfft_phases* tab, const lsfft_ref* c0, const void* f,
+                                       int incl_phase, double tol, int max_iter, double* avg,
+                                       lsfft_report* rep);
+
 /* Release the plan and its workspace.  NULL is accepted. */
 lsfft_status lsfft_plan_destroy(lsfft_plan_t p);
 

@@ -561,6 +561,43 @@ def translate_average(phase, lame, f, shifts, incl_phase=1, lam0=None, mu0=None,
     return acc / float(len(iters)), iters
 
 
+def realization_average(phases, lame, f, incl_phase=1, lam0=None, mu0=None, tol=1e-8, max_iter=10000,
+                         solver=None):
+    """Ensemble average over deterministic realisations (Sec. 3, Eq. 3.8):
+    the force stays fixed and every microstructure ``X^j`` in ``phases`` (maps
+    of one grid sharing the phase table ``lame``) is solved unshifted; ``u``,
+    ``u V``, ``eps``, ``eps V``, ``sigma``, ``sigma V`` and ``V`` are summed
+    over the realisations and divided by their number, in the component
+    order of ``translate_average``.  The reference medium comes from the
+    shared table unless given.  Returns ``[2d + 4s + 1][grid]`` and the
+    per-realisation iteration counts."""
+    phases = [np.asarray(ph) for ph in phases]
+    shape = phases[0].shape
+    d = len(shape)
+    if lam0 is None or mu0 is None:
+        lam0, mu0 = reference_medium(lame)
+    solver = solver or solve_basic
+    s = len(VOIGT[d])
+    acc = np.zeros((2 * d + 4 * s + 1,) + shape)
+    iters = []
+    for ph in phases:
+        if ph.shape != shape:
+            raise ValueError("realisations must share one grid")
+        res = solver(ph, lame, f, lam0, mu0, tol=tol, max_iter=max_iter)
+        ind = (ph == incl_phase).astype(np.float64)
+        ev, sv = to_voigt(res.eps), to_voigt(res.sig)
+        k = 0
+        acc[k:k + d] += res.u; k += d
+        acc[k:k + d] += res.u * ind; k += d
+        acc[k:k + s] += ev; k += s
+        acc[k:k + s] += ev * ind; k += s
+        acc[k:k + s] += sv; k += s
+        acc[k:k + s] += sv * ind; k += s
+        acc[k] += ind
+        iters.append(res.iters)
+    return acc / float(len(iters)), iters
+
+
 def relative_strain_error(eps, eps_ref):
     """``||eps - eps_ref||_F / ||eps_ref||_F`` over all voxels for full tensor
     fields ``[d][d][grid]``."""

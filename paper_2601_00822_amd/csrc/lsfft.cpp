@@ -1130,6 +1130,75 @@ void free_plan(lsfft_plan_s* p) {
 // ===========================================================================
 // C ABI
 // ===========================================================================
+namespace {
+
+// Accumulation target of one averaging group: FP64 sums of its solves,
+// divided by their count at the end.
+struct AvgTarget {
+  int grid_idx;
+  int incl_phase;
+  int count;
+  double* avg;
+};
+
+// Solve `specs` (consecutive solves of one group share a force spectrum) in
+// batches of at most max_batch and accumulate every solve into its group's
+// target (Eqs. 3.5-3.6 and 3.8).
+lsfft_status run_averages(lsfft_plan_t p, const std::vector<Spec>& specs, const std::vector<int>& spec_group,
+                          const std::vector<AvgTarget>& groups, double tol, int max_iter, lsfft_report* rep) {
+  const int ngroup = (int)groups.size();
+  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  for (int g = 0; g < ngroup; ++g) {
+    const lsfft_grid& gr = p->grids[groups[g].grid_idx];
+    const int d = gr.dim, s = d == 3 ? 6 : 3;
+    const long long nvox = gr.n[0] * gr.n[1] * (d == 3 ? gr.n[2] : 1);
+    if (hipMemsetAsync(groups[g].avg, 0, sizeof(double) * (size_t)(2 * d + 4 * s + 1) * nvox, p->stream) != hipSuccess)
+      return LSFFT_E_DEVICE;
+  }
+  lsfft_status worst = LSFFT_OK;
+  const int total = (int)specs.size();
+  for (int start = 0; start < total; start += p->max_batch) {
+    const int cnt = std::min(p->max_batch, total - start);
+    Batch b;
+    b.p = p;
+    b.tol = tol;
+    b.max_iter = max_iter;
+    b.averaging = true;
+    b.specs.assign(specs.begin() + start, specs.begin() + start + cnt);
+    // sub-groups of this batch: consecutive solves of the same group share
+    // one force spectrum (the first of them transforms it)
+    for (int i = 0; i < cnt; ++i) {
+      const int g = spec_group[start + i];
+      if (i == 0 || spec_group[start + i - 1] != g) {
+        BatchGroup bg;
+        bg.avg = groups[g].avg;
+        bg.incl_phase = groups[g].incl_phase;
+        bg.first = i;
+        bg.count = 0;
+        b.groups.push_back(bg);
+      }
+      b.groups.back().count += 1;
+      b.specs[i].group = (int)b.groups.size() - 1;
+      b.specs[i].leader = b.groups.back().first;
+    }
+    const double t0 = now_s();
+    lsfft_status s = p->sub ? run_refined(b, rep, t0) : run_batch(b, rep, t0);
+    if (s == LSFFT_E_ARG || s == LSFFT_E_ALLOC || s == LSFFT_E_DEVICE || s == LSFFT_E_NONEQUIL) return s;
+    worst = worse(worst, s);
+  }
+  for (int g = 0; g < ngroup; ++g) {
+    const lsfft_grid& gr = p->grids[groups[g].grid_idx];
+    const int d = gr.dim, s = d == 3 ? 6 : 3;
+    const long long nvox = gr.n[0] * gr.n[1] * (d == 3 ? gr.n[2] : 1);
+    if (launch_scale(groups[g].avg, (long long)(2 * d + 4 * s + 1) * nvox, 1.0 / groups[g].count, p->stream) != hipSuccess)
+      return LSFFT_E_DEVICE;
+  }
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return LSFFT_E_DEVICE;
+  return worst;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* lsfft_status_string(lsfft_status s) {
@@ -1319,54 +1388,9 @@ lsfft_status lsfft_translate_average_batch(lsfft_plan_t p, int ngroup, const lsf
       spec_group.push_back(g);
     }
   }
-  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
-  for (int g = 0; g < ngroup; ++g) {
-    const lsfft_grid& gr = p->grids[groups[g].grid_idx];
-    const int d = gr.dim, s = d == 3 ? 6 : 3;
-    const long long nvox = gr.n[0] * gr.n[1] * (d == 3 ? gr.n[2] : 1);
-    if (hipMemsetAsync(groups[g].avg, 0, sizeof(double) * (size_t)(2 * d + 4 * s + 1) * nvox, p->stream) != hipSuccess)
-      return LSFFT_E_DEVICE;
-  }
-  lsfft_status worst = LSFFT_OK;
-  const int total = (int)specs.size();
-  for (int start = 0; start < total; start += p->max_batch) {
-    const int cnt = std::min(p->max_batch, total - start);
-    Batch b;
-    b.p = p;
-    b.tol = tol;
-    b.max_iter = max_iter;
-    b.averaging = true;
-    b.specs.assign(specs.begin() + start, specs.begin() + start + cnt);
-    // sub-groups of this batch: consecutive solves of the same group share
-    // one force spectrum (the first of them transforms it)
-    for (int i = 0; i < cnt; ++i) {
-      const int g = spec_group[start + i];
-      if (i == 0 || spec_group[start + i - 1] != g) {
-        BatchGroup bg;
-        bg.avg = groups[g].avg;
-        bg.incl_phase = groups[g].incl_phase;
-        bg.first = i;
-        bg.count = 0;
-        b.groups.push_back(bg);
-      }
-      b.groups.back().count += 1;
-      b.specs[i].group = (int)b.groups.size() - 1;
-      b.specs[i].leader = b.groups.back().first;
-    }
-    const double t0 = now_s();
-    lsfft_status s = p->sub ? run_refined(b, rep, t0) : run_batch(b, rep, t0);
-    if (s == LSFFT_E_ARG || s == LSFFT_E_ALLOC || s == LSFFT_E_DEVICE || s == LSFFT_E_NONEQUIL) return s;
-    worst = worse(worst, s);
-  }
-  for (int g = 0; g < ngroup; ++g) {
-    const lsfft_grid& gr = p->grids[groups[g].grid_idx];
-    const int d = gr.dim, s = d == 3 ? 6 : 3;
-    const long long nvox = gr.n[0] * gr.n[1] * (d == 3 ? gr.n[2] : 1);
-    if (launch_scale(groups[g].avg, (long long)(2 * d + 4 * s + 1) * nvox, 1.0 / groups[g].nshift, p->stream) != hipSuccess)
-      return LSFFT_E_DEVICE;
-  }
-  if (hipStreamSynchronize(p->stream) != hipSuccess) return LSFFT_E_DEVICE;
-  return worst;
+  std::vector<AvgTarget> tg(ngroup);
+  for (int g = 0; g < ngroup; ++g) tg[g] = AvgTarget{groups[g].grid_idx, groups[g].incl_phase, groups[g].nshift, groups[g].avg};
+  return run_averages(p, specs, spec_group, tg, tol, max_iter, rep);
 }
 
 lsfft_status lsfft_translate_average(lsfft_plan_t p, int grid_idx, const uint8_t* phase, const lsfft_phases* tab,
@@ -1383,6 +1407,35 @@ lsfft_status lsfft_translate_average(lsfft_plan_t p, int grid_idx, const uint8_t
   g.incl_phase = incl_phase;
   g.avg = avg;
   return lsfft_translate_average_batch(p, 1, &g, tol, max_iter, rep);
+}
+
+lsfft_status lsfft_realization_average(lsfft_plan_t p, int grid_idx, int nreal, const uint8_t* const* phases,
+                                       const lsfft_phases* tab, const lsfft_ref* c0, const void* f, int incl_phase,
+                                       double tol, int max_iter, double* avg, lsfft_report* rep) {
+  if (check_plan(p) != LSFFT_OK) return LSFFT_E_ARG;
+  if (nreal < 1 || !phases || !f || !avg || !rep) return LSFFT_E_ARG;
+  if (!is_fin(tol) || tol <= 0.0 || max_iter < 0) return LSFFT_E_ARG;
+  if (grid_idx < 0 || grid_idx >= (int)p->grids.size()) return LSFFT_E_ARG;
+  const lsfft_grid& gr = p->grids[grid_idx];
+  if (check_table(tab, gr.dim) != LSFFT_OK) return LSFFT_E_ARG;
+  if (incl_phase < 0 || incl_phase >= tab->nphase) return LSFFT_E_ARG;
+  double lam0, mu0;
+  if (resolve_ref(tab, c0, &lam0, &mu0) != LSFFT_OK) return LSFFT_E_ARG;
+  std::vector<Spec> specs(nreal);
+  std::vector<int> spec_group(nreal, 0);
+  for (int j = 0; j < nreal; ++j) {
+    if (!phases[j]) return LSFFT_E_ARG;
+    Spec& s = specs[j];
+    s.grid = grid_idx;
+    s.phase = phases[j];
+    s.tab = tab;
+    s.lam0 = lam0;
+    s.mu0 = mu0;
+    s.f = f;
+    s.out_index = j;
+  }
+  return run_averages(p, specs, spec_group, std::vector<AvgTarget>{AvgTarget{grid_idx, incl_phase, nreal, avg}}, tol,
+                      max_iter, rep);
 }
 
 lsfft_status lsfft_kernel_times(lsfft_plan_t p, int kernel_class, double* total_ms, int64_t* launches) {

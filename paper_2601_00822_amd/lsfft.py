@@ -27,6 +27,7 @@ K_XPASS, K_YPASS, K_GREEN, K_REDUCE, K_CGUPD, K_OTHER = range(6)
 
 EXPORTS = [
     "lsfft_plan", "lsfft_solve_bfcs", "lsfft_translate_average", "lsfft_translate_average_batch",
+    "lsfft_realization_average",
     "lsfft_plan_destroy", "lsfft_status_string", "lsfft_lame_from_young", "lsfft_kernel_times",
     "lsfft_kernel_times_reset", "lsfft_iteration_bytes",
 ]
@@ -79,6 +80,9 @@ def load_library(path: str = LIB_PATH):
     lib.lsfft_translate_average.restype = ip
     lib.lsfft_translate_average_batch.argtypes = [vp, ip, C.POINTER(AvgGroup), dp, ip, C.POINTER(Report)]
     lib.lsfft_translate_average_batch.restype = ip
+    lib.lsfft_realization_average.argtypes = [vp, ip, ip, C.POINTER(vp), C.POINTER(Phases), C.POINTER(Ref), vp,
+                                              ip, dp, ip, vp, C.POINTER(Report)]
+    lib.lsfft_realization_average.restype = ip
     lib.lsfft_plan_destroy.argtypes = [vp]
     lib.lsfft_plan_destroy.restype = ip
     lib.lsfft_status_string.argtypes = [ip]
@@ -310,6 +314,27 @@ class Plan:
             [dict(grid=grid, phase=phase, lame=lame, f=f, shifts=shifts, incl_phase=incl_phase, c0=c0)],
             tol=tol, max_iter=max_iter)
         return avgs[0], reps
+
+    def realization_average(self, phases, lame, f, incl_phase=1, tol=1e-8, max_iter=10000, c0=None, grid=0):
+        """Deterministic-structure average (Eq. 3.8) over the realisations
+        ``phases`` (list of uint8 maps of one grid) with the force fixed.
+        Returns (FP64 average ``[2d + 4s + 1][...]``, per-realisation reports)."""
+        torch = _torch()
+        shp = self.shapes[grid]
+        d = len(shp)
+        s = 6 if d == 3 else 3
+        tab, lame_arr = self._phases(lame)
+        ref = self._ref(c0)
+        n = len(phases)
+        ptrs = (C.c_void_p * n)(*[self._check(ph, shp, torch.uint8, "phase") for ph in phases])
+        fp = self._check(f, (d,) + shp, self.dtype, "f")
+        avg = torch.empty((2 * d + 4 * s + 1,) + shp, dtype=torch.float64, device=f.device)
+        reps = (Report * n)()
+        st = self.lib.lsfft_realization_average(self.handle, int(grid), n, ptrs, C.byref(tab), C.byref(ref), fp,
+                                                int(incl_phase), float(tol), int(max_iter), avg.data_ptr(), reps)
+        if st not in (OK, W_STAGNATED, E_NOCONV, E_DIVERGED):
+            raise LsfftError(st, "lsfft_realization_average")
+        return avg, [_report(reps[k], d) for k in range(n)]
 
     # ------------------------------------------------------------------ timing
     def kernel_times(self, kclass: int):

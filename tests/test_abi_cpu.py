@@ -101,6 +101,8 @@ def test_calls_on_null_plan(lib):
                                 None, None, None, None, C.byref(rep)) == -1
     assert lib.lsfft_translate_average(None, 0, None, None, None, None, None, 1, 1, 1e-8, 10,
                                        None, C.byref(rep)) == -1
+    assert lib.lsfft_realization_average(None, 0, 1, None, None, None, None, 1, 1e-8, 10,
+                                         None, C.byref(rep)) == -1
     assert lib.lsfft_plan_destroy(None) == 0
     ms = C.c_double()
     assert lib.lsfft_kernel_times(None, 0, C.byref(ms), None) == -1
