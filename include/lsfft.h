@@ -208,6 +208,39 @@ lsfft_status lsfft_realization_average(lsfft_plan_t p, int grid_idx, int nreal, 
                                        int incl_phase, double tol, int max_iter, double* avg,
                                        lsfft_report* rep);
 
+/* Result of lsfft_rve_identify. */
+typedef struct {
+  double radius;      /* B^RVE: both magnitudes stay below tol times their
+                         maxima at distances >= radius; HUGE_VAL if the
+                         outermost bin is still above */
+  double box_radius;  /* radius of the largest ball in the cell, min_a n_a h_a / 2 */
+  int fits;           /* 1 when radius + support_radius / 2 <= box_radius */
+  int nbins;          /* bins used; bin b holds distances [b dr, (b + 1) dr) */
+  double max_eps;     /* largest |eps| over the grid */
+  double max_sig;     /* largest |sigma| over the grid */
+} lsfft_rve;
+
+/*
+ * lsfft_rve_identify -- the RVE of Definition 2.2 (Sec. 3) from averaged
+ * fields: with the body force's support centred at `center`, the RVE is the
+ * ball about it outside which the averaged strain and stress vanish to the
+ * relative tolerance `tol`, and the body-force unit cell is large enough
+ * when the annulus of width support_radius / 2 around the RVE, where the
+ * fields must stay stabilized, still lies inside the periodic cell.
+ * Magnitudes are |t| = sqrt(sum_ab t_ab^2) (Voigt shear counted twice);
+ * distances are minimum-image distances in the periodic cell in the grid's
+ * spacing; the radial profile holds the largest magnitude per bin of width dr.
+ *  avg       device FP64 [2d + 4s + 1][N], the layout of lsfft_translate_average
+ *  center    host [dim] in (x, y[, z]) order, voxel units
+ *  profile   host [2][max_bins] (|eps| maxima, then |sigma| maxima) or NULL;
+ *            filled when max_bins >= out->nbins
+ * Errors: LSFFT_E_ARG for null pointers, tol outside (0, 1), dr <= 0 or
+ * more than 1024 bins.
+ */
+lsfft_status lsfft_rve_identify(lsfft_plan_t p, int grid_idx, const double* avg, const double* center,
+                                double support_radius, double tol, double dr, double* profile, int max_bins,
+                                lsfft_rve* out);
+
 /* Release the plan and its workspace.  NULL is accepted. */
 lsfft_status lsfft_plan_destroy(lsfft_plan_t p);
 

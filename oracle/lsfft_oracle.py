@@ -598,6 +598,76 @@ def realization_average(phases, lame, f, incl_phase=1, lam0=None, mu0=None, tol=
     return acc / float(len(iters)), iters
 
 
+def tensor_magnitude(tv):
+    """``sqrt(sum_ab t_ab^2)`` of a Voigt field ``[s][grid]`` (tensor shear
+    counted twice), summed component by component in Voigt order."""
+    tv = np.asarray(tv, dtype=np.float64)
+    d = 3 if tv.shape[0] == 6 else 2
+    a = np.zeros(tv.shape[1:])
+    for c in range(tv.shape[0]):
+        q = tv[c] * tv[c]
+        a = a + (q if c < d else 2.0 * q)
+    return np.sqrt(a)
+
+
+def radial_maxima(field, center, h=None, dr=1.0):
+    """Largest value of ``field`` (a scalar ``[grid]``) per distance bin of
+    width ``dr`` about ``center`` (array order, voxel units), distances
+    measured to the nearest periodic image of the centre in the spacing
+    ``h`` (array order).  Returns the maxima ``[nbins]``, nbins covering the
+    half-diagonal of the cell."""
+    field = np.asarray(field, dtype=np.float64)
+    shape = field.shape
+    d = len(shape)
+    h = [1.0] * d if h is None else list(h)
+    r2 = np.zeros(shape)
+    half2 = 0.0
+    # summed x first, then y, then z (the order of the GPU kernel)
+    for a in reversed(range(d)):
+        n = shape[a]
+        idx = np.arange(n, dtype=np.float64) - float(center[a])
+        img = idx - float(n) * np.rint(idx / float(n))
+        off = img * h[a]
+        shp = [1] * d
+        shp[a] = n
+        r2 = r2 + (off * off).reshape(shp)
+        half2 += (0.5 * n * h[a]) ** 2
+    nbins = int(np.floor(np.sqrt(half2) / dr)) + 1
+    b = np.minimum(np.floor(np.sqrt(r2) / dr).astype(np.int64), nbins - 1)
+    out = np.zeros(nbins)
+    np.maximum.at(out, b.ravel(), field.ravel())
+    return out
+
+
+def rve_radius(avg, center, support_radius, tol, h=None, dr=1.0):
+    """RVE of Definition 2.2 from averaged fields ``avg`` (the layout of
+    ``translate_average``): the smallest bin edge beyond which the averaged
+    strain and stress magnitudes both stay below ``tol`` times their maxima,
+    and whether the annulus of width ``support_radius / 2`` around that ball
+    (where the fields must stay stabilized) lies inside the periodic cell.
+    Returns ``(radius, fits, maxima of |eps|, maxima of |sigma|)``."""
+    avg = np.asarray(avg)
+    shape = avg.shape[1:]
+    d = len(shape)
+    s = len(VOIGT[d])
+    h = [1.0] * d if h is None else list(h)
+    pe = radial_maxima(tensor_magnitude(avg[2 * d:2 * d + s]), center, h, dr)
+    ps = radial_maxima(tensor_magnitude(avg[2 * d + 2 * s:2 * d + 3 * s]), center, h, dr)
+    ge, gs = pe.max(), ps.max()
+    first = len(pe)
+    for b in range(len(pe) - 1, -1, -1):
+        if pe[b] < tol * ge and ps[b] < tol * gs:
+            first = b
+        else:
+            break
+    if ge == 0.0 and gs == 0.0:
+        first = 0
+    radius = first * dr if first < len(pe) else np.inf
+    box = min(0.5 * shape[a] * h[a] for a in range(d))
+    fits = bool(np.isfinite(radius) and radius + 0.5 * support_radius <= box)
+    return radius, fits, pe, ps
+
+
 def relative_strain_error(eps, eps_ref):
     """``||eps - eps_ref||_F / ||eps_ref||_F`` over all voxels for full tensor
     fields ``[d][d][grid]``."""

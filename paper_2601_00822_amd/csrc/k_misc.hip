@@ -90,6 +90,22 @@ hipError_t launch_accumulate(bool f64, int dim, const LaunchArgs& a, const Group
   return hipGetLastError();
 }
 
+hipError_t launch_radial_max(int dim, const double* avg, const int n[3], const double h[3], const double c[3],
+                             double dr, int nbins, unsigned long long* bins, hipStream_t st) {
+  if (nbins < 1 || nbins > kRveMaxBins) return hipErrorInvalidValue;
+  const long long nvox = (long long)n[0] * n[1] * n[2];
+  long long blocks = (nvox + NTR - 1) / NTR;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  if (dim == 3)
+    hipLaunchKernelGGL((k_radial_max<3>), dim3((unsigned)blocks), NTR, 0, st, avg, n[0], n[1], n[2], h[0], h[1], h[2],
+                       c[0], c[1], c[2], dr, nbins, bins);
+  else
+    hipLaunchKernelGGL((k_radial_max<2>), dim3((unsigned)blocks), NTR, 0, st, avg, n[0], n[1], 1, h[0], h[1], 1.0,
+                       c[0], c[1], 0.0, dr, nbins, bins);
+  return hipGetLastError();
+}
+
 hipError_t launch_scale(double* a, long long n, double s, hipStream_t st) {
   long long blocks = (n + NTR - 1) / NTR;
   if (blocks > 4096) blocks = 4096;

@@ -1711,6 +1711,58 @@ __global__ __launch_bounds__(NTR) void k_scale(double* __restrict__ a, long long
   for (long long i = (long long)blockIdx.x * NTR + threadIdx.x; i < n; i += (long long)gridDim.x * NTR) a[i] *= s;
 }
 
+// RVE identification (Definition 2.2): radial maxima of the averaged strain
+// and stress magnitudes about a centre.  Per voxel: the minimum-image offset
+// to the centre (periodic cell, voxel units, then times the spacing), the
+// distance r, bin floor(r / dr), and |eps|, |sigma| = sqrt(sum_ab t_ab^2)
+// with Voigt shear counted twice.  The arithmetic is pinned to IEEE
+// round-to-nearest operations in a fixed order (no contraction).  Bin maxima
+// of non-negative doubles are integer maxima of their bit patterns: the
+// result does not depend on the order of the updates.
+constexpr int kRveMaxBins = 1024;
+template <int DIM>
+__global__ __launch_bounds__(NTR) void k_radial_max(const double* __restrict__ avg, int nx, int ny, int nz, double hx,
+                                                    double hy, double hz, double cx, double cy, double cz, double dr,
+                                                    int nbins, unsigned long long* __restrict__ bins) {
+#pragma clang fp contract(off)
+  constexpr int S = (DIM == 3) ? 6 : 3;
+  __shared__ unsigned long long lmax[2 * kRveMaxBins];
+  for (int b = threadIdx.x; b < 2 * nbins; b += NTR) lmax[b] = 0ull;
+  __syncthreads();
+  const long long nvox = (long long)nx * ny * nz;
+  const double* eps = avg + (long long)(2 * DIM) * nvox;
+  const double* sig = eps + (long long)(2 * S) * nvox;
+  for (long long v = (long long)blockIdx.x * NTR + threadIdx.x; v < nvox; v += (long long)gridDim.x * NTR) {
+    const int x = (int)(v % nx);
+    const int y = (int)((v / nx) % ny);
+    const int z = (int)(v / ((long long)nx * ny));
+    // minimum-image offsets (voxel units), then times the spacing
+    double ox = (double)x - cx, oy = (double)y - cy, oz = (double)z - cz;
+    ox = ox - (double)nx * rint(ox / (double)nx);
+    oy = oy - (double)ny * rint(oy / (double)ny);
+    oz = oz - (double)nz * rint(oz / (double)nz);
+    const double dx = ox * hx, dy = oy * hy, dz = oz * hz;
+    double r2 = dx * dx;
+    r2 = r2 + dy * dy;
+    if constexpr (DIM == 3) r2 = r2 + dz * dz;
+    int b = (int)floor(sqrt(r2) / dr);
+    if (b >= nbins) b = nbins - 1;
+    double ae = 0.0, as = 0.0;
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      const double e = eps[(long long)c * nvox + v], t = sig[(long long)c * nvox + v];
+      const double qe = e * e, qs = t * t;
+      ae = ae + ((c < DIM) ? qe : 2.0 * qe);
+      as = as + ((c < DIM) ? qs : 2.0 * qs);
+    }
+    atomicMax(&lmax[b], (unsigned long long)__double_as_longlong(sqrt(ae)));
+    atomicMax(&lmax[nbins + b], (unsigned long long)__double_as_longlong(sqrt(as)));
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < 2 * nbins; b += NTR)
+    if (lmax[b]) atomicMax(&bins[b], lmax[b]);
+}
+
 // ---- mixed-precision defect correction: FP64 state, FP32 inner solves ----
 // Wavevector of entry g of the split half spectrum (main block, then the
 // x-Nyquist plane).

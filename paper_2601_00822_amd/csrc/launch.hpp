@@ -61,6 +61,9 @@ hipError_t launch_reduce(const LaunchArgs& a, const int* inst_list, const int* d
 hipError_t launch_phase_max(const uint8_t* phase, long long n, int* out, hipStream_t s);
 hipError_t launch_accumulate(bool f64, int dim, const LaunchArgs& a, const GroupDesc* groups, int g, long long nvox);
 hipError_t launch_scale(double* a, long long n, double s, hipStream_t st);
+constexpr int kRveBinsMax = 1024;   // bins of launch_radial_max
+hipError_t launch_radial_max(int dim, const double* avg, const int n[3], const double h[3], const double c[3],
+                             double dr, int nbins, unsigned long long* bins, hipStream_t st);
 
 // mixed-precision defect correction; `inst` lists `count` solves, `max_pc`
 // is the largest half spectrum among them

@@ -127,6 +127,7 @@ struct lsfft_plan_s {
   bool owns_stream = true;
   DevBuf tw, arena, meta, lists;
   HostBuf hmeta;            // host mirror of `meta`
+  DevBuf rve;               // radial maxima of lsfft_rve_identify
   bool h2d_inflight = false;  // copies out of `hmeta` may still be queued
   // LSFFT_REFINE64: FP64 companion (same grids, shares the work stream) and
   // the FP64 copies of the forces
@@ -1119,6 +1120,7 @@ void free_plan(lsfft_plan_s* p) {
   p->arena.release();
   p->meta.release();
   p->hmeta.release();
+  p->rve.release();
   p->lists.release();
   p->fwide.release();
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
@@ -1436,6 +1438,69 @@ lsfft_status lsfft_realization_average(lsfft_plan_t p, int grid_idx, int nreal, 
   }
   return run_averages(p, specs, spec_group, std::vector<AvgTarget>{AvgTarget{grid_idx, incl_phase, nreal, avg}}, tol,
                       max_iter, rep);
+}
+
+lsfft_status lsfft_rve_identify(lsfft_plan_t p, int grid_idx, const double* avg, const double* center,
+                                double support_radius, double tol, double dr, double* profile, int max_bins,
+                                lsfft_rve* out) {
+  if (check_plan(p) != LSFFT_OK || !avg || !center || !out) return LSFFT_E_ARG;
+  if (grid_idx < 0 || grid_idx >= (int)p->grids.size()) return LSFFT_E_ARG;
+  if (!is_fin(tol) || tol <= 0.0 || tol >= 1.0 || !is_fin(dr) || dr <= 0.0) return LSFFT_E_ARG;
+  if (!is_fin(support_radius) || support_radius < 0.0) return LSFFT_E_ARG;
+  const lsfft_grid& g = p->grids[grid_idx];
+  const int d = g.dim;
+  int n[3] = {(int)g.n[0], (int)g.n[1], d == 3 ? (int)g.n[2] : 1};
+  double h[3] = {g.h[0], g.h[1], d == 3 ? g.h[2] : 1.0};
+  double c[3] = {0.0, 0.0, 0.0};
+  double rmax2 = 0.0, box = 1e300;
+  for (int a = 0; a < d; ++a) {
+    if (!is_fin(center[a])) return LSFFT_E_ARG;
+    c[a] = center[a];
+    const double half = 0.5 * n[a] * h[a];
+    rmax2 += half * half;
+    box = std::min(box, half);
+  }
+  const int nbins = (int)std::floor(std::sqrt(rmax2) / dr) + 1;
+  if (nbins > kRveBinsMax) return LSFFT_E_ARG;
+  if (!p->rve.ensure(sizeof(unsigned long long) * 2 * (size_t)nbins)) return LSFFT_E_ALLOC;
+  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  auto* bins = static_cast<unsigned long long*>(p->rve.p);
+  std::vector<unsigned long long> hb(2 * (size_t)nbins);
+  if (hipMemsetAsync(bins, 0, sizeof(unsigned long long) * hb.size(), p->stream) != hipSuccess) return LSFFT_E_DEVICE;
+  if (launch_radial_max(d, avg, n, h, c, dr, nbins, bins, p->stream) != hipSuccess) return LSFFT_E_DEVICE;
+  if (hipMemcpyAsync(hb.data(), bins, sizeof(unsigned long long) * hb.size(), hipMemcpyDeviceToHost, p->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess)
+    return LSFFT_E_DEVICE;
+  std::vector<double> me(nbins), ms(nbins);
+  double ge = 0.0, gs = 0.0;
+  for (int b = 0; b < nbins; ++b) {
+    std::memcpy(&me[b], &hb[b], sizeof(double));
+    std::memcpy(&ms[b], &hb[nbins + b], sizeof(double));
+    ge = std::max(ge, me[b]);
+    gs = std::max(gs, ms[b]);
+  }
+  // smallest bin edge beyond which both magnitudes stay below tol times
+  // their maxima (Definition 2.2)
+  int first = nbins;   // +inf when the outermost bin is still above tol
+  for (int b = nbins - 1; b >= 0; --b) {
+    if (me[b] < tol * ge && ms[b] < tol * gs) first = b;
+    else break;
+  }
+  if (ge == 0.0 && gs == 0.0) first = 0;
+  out->radius = (first < nbins) ? first * dr : HUGE_VAL;
+  out->box_radius = box;
+  out->fits = (first < nbins && out->radius + 0.5 * support_radius <= box) ? 1 : 0;
+  out->nbins = nbins;
+  out->max_eps = ge;
+  out->max_sig = gs;
+  if (profile && max_bins >= nbins) {
+    for (int b = 0; b < nbins; ++b) {
+      profile[b] = me[b];
+      profile[max_bins + b] = ms[b];
+    }
+  }
+  return LSFFT_OK;
 }
 
 lsfft_status lsfft_kernel_times(lsfft_plan_t p, int kernel_class, double* total_ms, int64_t* launches) {

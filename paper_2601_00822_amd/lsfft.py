@@ -27,10 +27,15 @@ K_XPASS, K_YPASS, K_GREEN, K_REDUCE, K_CGUPD, K_OTHER = range(6)
 
 EXPORTS = [
     "lsfft_plan", "lsfft_solve_bfcs", "lsfft_translate_average", "lsfft_translate_average_batch",
-    "lsfft_realization_average",
+    "lsfft_realization_average", "lsfft_rve_identify",
     "lsfft_plan_destroy", "lsfft_status_string", "lsfft_lame_from_young", "lsfft_kernel_times",
     "lsfft_kernel_times_reset", "lsfft_iteration_bytes",
 ]
+
+
+class Rve(C.Structure):
+    _fields_ = [("radius", C.c_double), ("box_radius", C.c_double), ("fits", C.c_int), ("nbins", C.c_int),
+                ("max_eps", C.c_double), ("max_sig", C.c_double)]
 
 
 class Grid(C.Structure):
@@ -83,6 +88,8 @@ def load_library(path: str = LIB_PATH):
     lib.lsfft_realization_average.argtypes = [vp, ip, ip, C.POINTER(vp), C.POINTER(Phases), C.POINTER(Ref), vp,
                                               ip, dp, ip, vp, C.POINTER(Report)]
     lib.lsfft_realization_average.restype = ip
+    lib.lsfft_rve_identify.argtypes = [vp, ip, vp, C.POINTER(dp), dp, dp, dp, C.POINTER(dp), ip, C.POINTER(Rve)]
+    lib.lsfft_rve_identify.restype = ip
     lib.lsfft_plan_destroy.argtypes = [vp]
     lib.lsfft_plan_destroy.restype = ip
     lib.lsfft_status_string.argtypes = [ip]
@@ -335,6 +342,30 @@ class Plan:
         if st not in (OK, W_STAGNATED, E_NOCONV, E_DIVERGED):
             raise LsfftError(st, "lsfft_realization_average")
         return avg, [_report(reps[k], d) for k in range(n)]
+
+    def rve_identify(self, avg, center, support_radius, tol=1e-3, dr=1.0, grid=0):
+        """RVE of Definition 2.2 from averaged fields ``avg`` (the layout of
+        ``translate_average``): ``center`` of the force support in array
+        order, voxel units.  Returns a dict with the RVE radius, the cell's
+        inscribed radius, whether the RVE plus half the support fits, and the
+        radial maxima of |eps| and |sigma| per bin of width ``dr``."""
+        torch = _torch()
+        shp = self.shapes[grid]
+        d = len(shp)
+        s = 6 if d == 3 else 3
+        a = self._check(avg, (2 * d + 4 * s + 1,) + shp, torch.float64, "avg")
+        c = (C.c_double * 3)(*([float(v) for v in reversed(list(center))] + [0.0] * (3 - d)))
+        nmax = 1024
+        prof = np.zeros(2 * nmax)
+        out = Rve()
+        st = self.lib.lsfft_rve_identify(self.handle, int(grid), a, c, float(support_radius), float(tol), float(dr),
+                                         prof.ctypes.data_as(C.POINTER(C.c_double)), nmax, C.byref(out))
+        if st != OK:
+            raise LsfftError(st, "lsfft_rve_identify")
+        nb = out.nbins
+        return dict(radius=out.radius, box_radius=out.box_radius, fits=bool(out.fits), nbins=nb,
+                    max_eps=out.max_eps, max_sig=out.max_sig, profile_eps=prof[:nb].copy(),
+                    profile_sig=prof[nmax:nmax + nb].copy())
 
     # ------------------------------------------------------------------ timing
     def kernel_times(self, kclass: int):

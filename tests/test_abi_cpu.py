@@ -106,3 +106,21 @@ def test_calls_on_null_plan(lib):
     assert lib.lsfft_plan_destroy(None) == 0
     ms = C.c_double()
     assert lib.lsfft_kernel_times(None, 0, C.byref(ms), None) == -1
+
+
+def test_enlargement_lengths_match_the_library(lib):
+    # every length the BFUC enlargement steps through passes the plan's
+    # argument checks (on a machine without a GPU the plan then fails with
+    # LSFFT_E_DEVICE, never LSFFT_E_ARG); lengths outside the set are refused
+    from paper_2601_00822_amd.rve import LENGTHS
+    for n in LENGTHS:
+        g = _grid(2, (n, n, 1))
+        out = C.c_void_p()
+        st = lib.lsfft_plan(C.byref(out), C.byref(g), 1, 1, 1, 0, 0, None)
+        assert st != -1, n
+        if st == 0:
+            lib.lsfft_plan_destroy(out)
+    for n in (10, 18, 20, 512):
+        g = _grid(2, (n, n, 1))
+        out = C.c_void_p()
+        assert lib.lsfft_plan(C.byref(out), C.byref(g), 1, 1, 1, 0, 0, None) == -1, n
