@@ -419,7 +419,10 @@ bool is_dynamic(int l) { return l == L_X || l == L_Y || l == L_G || l == L_CG; }
 // Lay out every list as segments (first call), then fill the dynamic lists
 // with the items of the running solves (every call) and upload lists and
 // counts.  Segment offsets and capacities never change within a batch.
-lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_too) {
+// With all_too the whole range from meta offset `from` (0: descriptors
+// onward) to the end of the last list goes up in one copy; otherwise the
+// counts with the solve list, and the span of the dynamic lists.
+lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_too, size_t from = SIZE_MAX) {
   const int n = (int)b.specs.size();
   if (all_too) {
     int cidx = 0;
@@ -457,13 +460,14 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
   if (host_fence(b.p) != LSFFT_OK) return LSFFT_E_DEVICE;
   int* counts = hptr<int>(b, b.m_counts);
   std::fill(counts, counts + kMaxSegs, 0);
+  size_t lo_b = SIZE_MAX, hi_b = 0;   // meta byte span of the lists written
   for (int l = 0; l < L_NUM; ++l) {
     if (!all_too && !is_dynamic(l)) {
       for (auto& x : b.segs[l]) counts[x.cidx] = x.count;
       continue;
     }
     WorkItem* items = hptr<WorkItem>(b, b.m_list[l]);
-    int lo = b.list_cap[l], hi = 0;   // item range to upload
+    int lo = b.list_cap[l], hi = 0;   // item range written
     for (auto& x : b.segs[l]) {
       int fill = 0;
       const std::vector<int>* src = &running;
@@ -490,16 +494,24 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
       }
     }
     if (hi > lo) {
-      const lsfft_status ls = h2d(b, b.m_list[l] + sizeof(WorkItem) * (size_t)lo, sizeof(WorkItem) * (size_t)(hi - lo));
-      if (ls != LSFFT_OK) return ls;
+      lo_b = std::min(lo_b, b.m_list[l] + sizeof(WorkItem) * (size_t)lo);
+      hi_b = std::max(hi_b, b.m_list[l] + sizeof(WorkItem) * (size_t)hi);
     }
   }
   int* inst = hptr<int>(b, b.m_inst);
   for (size_t k = 0; k < running.size(); ++k) inst[k] = running[k];
   counts[kMaxSegs - 1] = (int)running.size();   // solves listed for the reduction
   b.n_running = (int)running.size();
-  // counts and the solve list are adjacent in the metadata buffer
-  return h2d(b, b.m_counts, (b.m_inst - b.m_counts) + sizeof(int) * running.size());
+  // counts and the solve list are adjacent in the metadata buffer, and the
+  // lists follow them
+  const size_t end_inst = b.m_inst + sizeof(int) * running.size();
+  if (all_too) {
+    const size_t lo = std::min(from, b.m_counts);
+    return h2d(b, lo, std::max(hi_b, end_inst) - lo);
+  }
+  lsfft_status ls = h2d(b, b.m_counts, end_inst - b.m_counts);
+  if (ls == LSFFT_OK && hi_b > lo_b) ls = h2d(b, lo_b, hi_b - lo_b);
+  return ls;
 }
 
 // Largest half-spectrum size among the listed solves (grid of the
@@ -516,7 +528,7 @@ double now_s() {
 
 // Workspace layout, descriptors, Lame tables, phase validation and the
 // initial work lists of a batch.
-lsfft_status prepare(Batch& b) {
+lsfft_status prepare(Batch& b, bool validate = true) {
   lsfft_plan_s* p = b.p;
   const bool f64 = p->f64;
   const size_t rs = f64 ? 8 : 4;   // real scalar
@@ -665,12 +677,10 @@ lsfft_status prepare(Batch& b) {
   GroupDesc* gd = hptr<GroupDesc>(b, m_groups);
   for (size_t g = 0; g < b.groups.size(); ++g)
     gd[g] = GroupDesc{b.groups[g].first, b.groups[g].count, b.groups[g].incl_phase, 0, b.groups[g].avg};
-  {
-    const lsfft_status ls = h2d(b, 0, m_counts);
-    if (ls != LSFFT_OK) return ls;
-  }
 
-  // phase ids must index the tables: one device max per distinct map
+  // phase ids must index the tables: one device max per distinct map (the
+  // inner batch of the defect correction reuses the companion's maps)
+  if (validate) {
   LSFFT_TRY(hipMemsetAsync(b.d_phasemax, 0, sizeof(int) * n, st));
   for (int i = 0; i < n; ++i) {
     bool seen = false;
@@ -687,10 +697,12 @@ lsfft_status prepare(Batch& b) {
       if (b.specs[j].phase == b.specs[i].phase && b.geo[j].nvox == b.geo[i].nvox) m = std::max(m, pmax[j]);
     if (m >= b.specs[i].tab->nphase) return LSFFT_E_ARG;
   }
+  }
 
+  // descriptors, states, tables, groups, counts and lists: one copy
   std::vector<int> all(n);
   for (int i = 0; i < n; ++i) all[i] = i;
-  return upload_lists(b, all, true);
+  return upload_lists(b, all, true, 0);
 }
 
 // ---- launches of one pass kind over the segments of a work list ----------
@@ -991,7 +1003,7 @@ lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
   Batch in = b;
   in.tol = kInnerTol;
   for (int i = 0; i < n; ++i) in.specs[i].leader = i;
-  if ((ls = prepare(in)) != LSFFT_OK) return ls;
+  if ((ls = prepare(in, false)) != LSFFT_OK) return ls;
   std::vector<long long> inner_iters(n, 0);
   std::vector<double> inner_floor(n, 0.0);
   std::vector<int> running, in_listed(n);
