@@ -601,7 +601,13 @@ template <typename T, int H> struct XDma {
   // (mod 32) puts the rows of a wave on disjoint LDS banks
   static constexpr int NB = H / PlanSeq<LSFFT_XPLAN, H, false>::last();
   static constexpr int SMF = (H + 1 + ((NB - (H + 1) % 32) % 32 + 32) % 32);
-  static constexpr int BUF = (cmax(cmax(NCH * PITCH, 2 * MR * G::SM2 * 4), 2 * MR * SMF * 4) + 15) / 16 * 16;
+  // transform staging pitch and skew
+#ifndef LSFFT_XSTG
+#define LSFFT_XSTG 1
+#endif
+  static constexpr int SMS = (LSFFT_XSTG && H == 64) ? 71 : G::SM2;
+  static constexpr bool SKS = !(LSFFT_XSTG && H == 64);
+  static constexpr int BUF = (cmax(cmax(NCH * PITCH, 2 * MR * SMS * 4), 2 * MR * SMF * 4) + 15) / 16 * 16;
   // phase ids of the tile: rows of 2H bytes at a pitch of 2H + 16 (the rows
   // of a wave then fall on different LDS banks)
   static constexpr int PP = 2 * H + 16;
@@ -656,10 +662,10 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   constexpr int H = NX / 2;
   using G = XGeom<T, H>;
   using X = XDma<T, H>;
-  constexpr int MR = G::MR, SM = X::SMF, SM2 = G::SM2;
+  constexpr int MR = G::MR, SM = X::SMF, SM2 = X::SMS;
   constexpr int S = (DIM == 3) ? 6 : 3;
-  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true, true>;
-  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true, true>;
+  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, X::SKS, true>;
+  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, X::SKS, true>;
   static_assert(FI::RL == FF::R0 && FI::BL == FF::B0, "x transforms must chain in registers");
   static_assert(X::NB == H / FF::RL && SM % 32 == X::NB % 32 && SM > H, "fold-tile pitch");
   constexpr int BP = FI::BL, RP = FI::RL;
