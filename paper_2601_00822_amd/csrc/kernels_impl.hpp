@@ -1619,6 +1619,9 @@ __global__ __launch_bounds__(NTR) void k_reduce(const InstDesc* __restrict__ des
   if (mode != M_INIT && St.status != ST_RUNNING) return;
   const int nslot = (mode == M_CG_UPD) ? D.items_cg : D.items_g;
   const bool two = (mode == M_CG_INIT || mode == M_CG_UPD);
+  // the solve's state comes in with the partials (thread 0 applies the rule)
+  InstState loc;
+  if (threadIdx.x == 0) loc = St;
   // eight slots per thread and step, all loads issued before the adds
   constexpr int U = 8;
   double a = 0.0, b = 0.0;
@@ -1638,7 +1641,10 @@ __global__ __launch_bounds__(NTR) void k_reduce(const InstDesc* __restrict__ des
   }
   a = block_sum<NTR>(a, red);
   b = block_sum<NTR>(b, red);
-  if (threadIdx.x == 0) finalize(D, St, mode, a, b);
+  if (threadIdx.x == 0) {
+    finalize(D, loc, mode, a, b);
+    St = loc;
+  }
 }
 
 // Largest phase id of a phase map (argument validation on the device).

@@ -101,7 +101,7 @@ struct InstDesc {
 struct InstState {
   int iter;
   int status;
-  int done;            // work items of the current launch finished (last one reduces)
+  int done;            // reserved
   int pad_;
   int mark_iter;       // iteration of the last >= 1% improvement
   int grow;            // consecutive iterations with a growing residual
