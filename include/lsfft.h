@@ -68,8 +68,10 @@ typedef enum { LSFFT_BASIC = 0, LSFFT_CG = 1 } lsfft_scheme;
  * The displacement state is kept in FP64; each outer step evaluates the FP64
  * residual P f + div(L sym grad u) of that state (the stopping rule below is
  * applied to it), solves the correction equation with that residual as its
- * force in FP32 with the plan's scheme to a relative residual of 1e-3, and
- * adds the correction in FP64.  The FP32 rounding floor then limits only the
+ * force in FP32 with the plan's scheme to a relative residual of
+ * 0.3 tol / (current FP64 residual), kept within [3e-5, 0.1] and not below
+ * 1.5 times the level where an earlier inner solve of the same solve
+ * stagnated, and adds the correction in FP64.  The FP32 rounding floor then limits only the
  * progress per step, so tol = 1e-8 is reachable at any contrast.  Reports:
  * iters = FP32 iterations summed over the inner solves, residual = FP64
  * residual of the returned state, at most 40 outer steps (else

@@ -948,14 +948,14 @@ lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
 //   1. evaluates the FP64 residual r = P f + div(L sym grad u) and its norm
 //      (one FP64 basic iteration: the stopping test runs on this residual),
 //   2. solves A d = r in FP32 with the plan's scheme to a relative residual
-//      of kInnerTol (A = -div(L sym grad .), the same operator),
+//      aimed at 0.3 tol / |r| (A = -div(L sym grad .), the same operator),
+//      at least kInnerTol,
 //   3. sets u += d in FP64.
 // The FP32 floor of the inner solves bounds only the reduction per step, not
 // the final accuracy.  The returned fields are materialized in FP32 from the
-// FP64 state rounded once.  An inner tolerance of 3e-5 reaches 1e-8 in two
-// outer steps with about as many FP32 iterations in all as three steps of
-// 1e-3 take, and saves one FP64 residual evaluation and one round of host
-// decisions; 3e-5 stays well above the FP32 floor of the inner solves.
+// FP64 state rounded once.  A floor of 3e-5 reaches 1e-8 in two outer steps
+// with about as many FP32 iterations in all as three steps of 1e-3 take, and
+// saves one FP64 residual evaluation and one round of host decisions.
 #ifndef LSFFT_INNER_TOL
 #define LSFFT_INNER_TOL 3e-5
 #endif
