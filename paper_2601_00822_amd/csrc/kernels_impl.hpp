@@ -79,7 +79,9 @@ template <> struct Cfg<double> {
 // pencils per strided tile of length N (y pass, outer pass)
 template <typename T, int N> struct SGeom {
   static constexpr int MP = clampi(pow2floor(Cfg<T>::E / N), 1, 64);
-  static constexpr int MPG = clampi(pow2floor(Cfg<T>::E_G / N), 1, 64);
+  // outer pass: FP32 pencils of 256 or more points come 8 to a tile (64-byte
+  // runs per line instead of 32), at 2 waves per SIMD (see WavesG)
+  static constexpr int MPG = clampi(pow2floor((sizeof(T) == 4 && N >= 256 ? 2 * Cfg<T>::E_G : Cfg<T>::E_G) / N), 1, 64);
 };
 
 // rows per x tile (H = nx / 2 complex points per row); odd LDS pitches
@@ -1512,10 +1514,10 @@ __device__ __forceinline__ bool gated(int mode) {
 }
 
 // occupancy targets (waves per SIMD) that bound the register allocation
-template <typename T> struct WavesG { static constexpr int value = 3; };
-template <> struct WavesG<double> { static constexpr int value = 2; };
+template <typename T, int NG> struct WavesG { static constexpr int value = (NG >= 256) ? 2 : 3; };
+template <int NG> struct WavesG<double, NG> { static constexpr int value = 2; };
 #ifndef LSFFT_WAVES_G
-#define LSFFT_WAVES_G WavesG<T>::value
+#define LSFFT_WAVES_G WavesG<T, NG>::value
 #endif
 #ifndef LSFFT_WAVES_X
 #define LSFFT_WAVES_X 3
@@ -1556,7 +1558,11 @@ __global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSF
   extern __shared__ __align__(16) unsigned char smem[];
   const int n_items = *nitems;
   const int n_units = n_items * ncomp;
-  for (int w = blockIdx.x; w < n_units; w += gridDim.x) {
+  // XCD-aware order when a tile row is narrower than a 128-byte line
+  // (neighbouring tiles then share lines: 8 kx columns of FP32 at ny = 256);
+  // with full lines the launch order is kept
+  constexpr bool kXcd = SGeom<T, NY>::MP * 2 * (int)sizeof(T) < 128;
+  for (int w = kXcd ? xcd_slot(blockIdx.x, gridDim.x) : (int)blockIdx.x; w < n_units; w += gridDim.x) {
     const int c = w / n_items;
     const WorkItem it = items[w - c * n_items];
     const InstDesc& D = descs[it.inst];

@@ -219,6 +219,21 @@ def test_fp32_staged_x_tiles(torch_dev, shape):
     assert err < 1e-5 and serr < 1e-5
 
 
+@pytest.mark.parametrize("shape", [(256, 16), (256, 8, 8), (256, 4, 12)])
+def test_fp32_outer_axis_256(torch_dev, shape):
+    """FP32 outer pass on 256-point pencils: 8 kx columns per tile (fewer
+    when nx / 2 is smaller), ragged y lines."""
+    say(f"FP32 outer axis 256 {shape}")
+    phase = rand_phase(shape, 61)
+    f = rand_force(shape, 62)
+    ref = O.solve_basic(phase, LAME10, f, tol=1e-8)
+    res, rep = gpu_solve(torch_dev, shape, phase, LAME10, f, prec="f32", tol=1e-8)
+    err = O.relative_strain_error_voigt(res["eps"], O.to_voigt(ref.eps))
+    print(f"status={rep.status} iters={rep.iters}/{ref.iters} residual={rep.residual:.3e} err={err:.3e}")
+    assert rep.status in (0, 1)
+    assert err < 1e-5
+
+
 def test_fp32_staged_x_tiles_shifted(torch_dev):
     """Shifted microstructures in the staged x pass: x shifts that are and are
     not multiples of 16 (vector and byte reads of the phase map)."""
