@@ -140,7 +140,12 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
  *  eps, sig  host arrays [nsolve] of device pointers [s][N] (plan precision),
  *            or NULL; an individual entry may be NULL to skip that output
  *  u         host array [nsolve] of device pointers [d][N], or NULL
- *  u_init    must be NULL (the free term u^b starts every solve)
+ *  u_init    NULL (every solve starts from the free term u^b), or a host
+ *            array [nsolve] of device pointers, starting displacements
+ *            [d][N] in the plan precision, one for every solve: the
+ *            iteration starts from their spectra projected off the xi = 0
+ *            set (the mean displacement is not determined).  Warm starts
+ *            need the basic scheme without LSFFT_REFINE64 (else LSFFT_E_ARG)
  *  rep       host [nsolve], filled on every return except LSFFT_E_ARG
  * Returns the worst per-solve status (errors before warnings before OK).
  */

@@ -303,15 +303,21 @@ def solve_basic(phase, lame, f, lam0=None, mu0=None, tol=1e-8, max_iter=10000):
     return Result(eps, stress(eps, lam, mu), u, j, delta, hist, removed, status)
 
 
-def solve_displacement_update(phase, lame, f, lam0=None, mu0=None, tol=1e-8, max_iter=10000):
+def solve_displacement_update(phase, lame, f, lam0=None, mu0=None, tol=1e-8, max_iter=10000, u_init=None):
     """The same iteration written on the displacement spectrum:
     ``u^{j+1} = u^j + N0 (i xi . sigma^j + f^)``.  This is Algorithm 1 after
     the identity of Eq. 2.27 (``U0 (L0 eps) = -eps`` for compatible mean-free
-    ``eps``), i.e. the body-force analogue of the recurrence Eq. 2.28.  Kept
-    in the oracle only to pin that equivalence."""
+    ``eps``), i.e. the body-force analogue of the recurrence Eq. 2.28.  It
+    pins that equivalence, and with ``u_init`` (a real ``[d][grid]`` field)
+    it starts from that displacement instead of the free term: its spectrum,
+    zeroed where xi = 0 like the force (the mean displacement is free)."""
     shape, lam0, mu0, lam, mu, xi, w, f_hat, removed = _prepare(phase, lame, f, lam0, mu0)
     fnorm = _norm_w(f_hat, w)
-    u_hat = apply_N0(f_hat, xi, lam0, mu0)
+    if u_init is None:
+        u_hat = apply_N0(f_hat, xi, lam0, mu0)
+    else:
+        u_hat = fft_r(np.asarray(u_init, dtype=np.float64), shape)
+        u_hat[:, zero_set(shape)] = 0.0
     j = 0
     hist = []
     while True:

@@ -82,6 +82,7 @@ struct Spec {
   const lsfft_phases* tab = nullptr;
   double lam0 = 0, mu0 = 0;
   const void* f = nullptr;
+  const void* u_init = nullptr;   // optional starting displacement (real, [d][N])
   void* eps = nullptr;
   void* sig = nullptr;
   void* u = nullptr;
@@ -921,10 +922,51 @@ lsfft_status rank_worst(lsfft_status worst, int s) {
   return rank(s) > rank(worst) ? (lsfft_status)s : worst;
 }
 
+// Starting displacements given by the caller: their spectra (forward
+// transforms, projected off the xi = 0 set like the force) are taken into
+// U[1] through the force-transform passes, with the descriptors pointed at
+// them for the occasion.  Needs every solve to be its own leader (plain
+// solves) and the basic scheme (U[1] exists).
+lsfft_status transform_starts(Batch& b) {
+  const int n = (int)b.specs.size();
+  lsfft_plan_s* p = b.p;
+  std::vector<InstDesc> keep(b.desc.begin(), b.desc.end());
+  if (host_fence(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  for (int i = 0; i < n; ++i) {
+    b.desc[i].f_in = b.specs[i].u_init;
+    b.desc[i].F = b.desc[i].U[1];
+  }
+  std::memcpy(hptr<InstDesc>(b, 0), b.desc.data(), sizeof(InstDesc) * n);
+  lsfft_status ls = h2d(b, 0, sizeof(InstDesc) * n);
+  if (ls != LSFFT_OK) return ls;
+  LSFFT_TRY(pass_x(b, L_XLEAD, M_FT, LSFFT_K_OTHER));
+  LSFFT_TRY(pass_y(b, L_YLEAD, -1, 1, 3, 0, LSFFT_K_OTHER));
+  LSFFT_TRY(pass_g(b, L_GLEAD, M_FT, LSFFT_K_OTHER));
+  if (host_fence(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  for (int i = 0; i < n; ++i) b.desc[i] = keep[i];
+  std::memcpy(hptr<InstDesc>(b, 0), b.desc.data(), sizeof(InstDesc) * n);
+  return h2d(b, 0, sizeof(InstDesc) * n);
+}
+
+// After setup: the starting spectra replace the free term as state 0, and
+// the strain spectrum of that state is recomputed.
+lsfft_status install_starts(Batch& b) {
+  const int n = (int)b.specs.size();
+  const size_t cs = b.p->f64 ? 16 : 8;
+  for (int i = 0; i < n; ++i)
+    LSFFT_TRY(hipMemcpyAsync(b.desc[i].U[0], b.desc[i].U[1], cs * (size_t)b.geo[i].dim * (size_t)b.geo[i].Pc,
+                             hipMemcpyDeviceToDevice, b.p->stream));
+  LSFFT_TRY(pass_g(b, L_G, M_MAT, LSFFT_K_OTHER));
+  return LSFFT_OK;
+}
+
 lsfft_status run_batch(Batch& b, lsfft_report* rep, double t0_wall) {
   lsfft_status ls = prepare(b);
   if (ls != LSFFT_OK) return ls;
+  const bool warm = !b.specs.empty() && b.specs[0].u_init != nullptr;
+  if (warm && (ls = transform_starts(b)) != LSFFT_OK) return ls;
   if ((ls = setup(b, false)) != LSFFT_OK) return ls;
+  if (warm && (ls = install_starts(b)) != LSFFT_OK) return ls;
   if ((ls = iterate(b)) != LSFFT_OK) return ls;
   if ((ls = materialize(b)) != LSFFT_OK) return ls;
   const double secs = now_s() - t0_wall;
@@ -1330,7 +1372,12 @@ lsfft_status lsfft_solve_bfcs(lsfft_plan_t p, int nsolve, const int* grid_idx, c
   if (check_plan(p) != LSFFT_OK) return LSFFT_E_ARG;
   if (nsolve < 1 || !grid_idx || !phase || !tab || !f || !rep) return LSFFT_E_ARG;
   if (!is_fin(tol) || tol <= 0.0 || max_iter < 0) return LSFFT_E_ARG;
-  if (u_init) return LSFFT_E_ARG;
+  // warm starts: plain basic-scheme plans, every solve given one
+  if (u_init) {
+    if (p->sub || p->scheme != LSFFT_BASIC) return LSFFT_E_ARG;
+    for (int i = 0; i < nsolve; ++i)
+      if (!u_init[i]) return LSFFT_E_ARG;
+  }
   std::vector<Spec> specs(nsolve);
   for (int i = 0; i < nsolve; ++i) {
     const int g = grid_idx[i];
@@ -1343,6 +1390,7 @@ lsfft_status lsfft_solve_bfcs(lsfft_plan_t p, int nsolve, const int* grid_idx, c
     s.tab = &tab[i];
     if (resolve_ref(&tab[i], c0 ? &c0[i] : nullptr, &s.lam0, &s.mu0) != LSFFT_OK) return LSFFT_E_ARG;
     s.f = f[i];
+    s.u_init = u_init ? u_init[i] : nullptr;
     s.eps = eps ? eps[i] : nullptr;
     s.sig = sig ? sig[i] : nullptr;
     s.u = u ? u[i] : nullptr;

@@ -219,7 +219,9 @@ class Plan:
     # ------------------------------------------------------------------ solves
     def solve_batch(self, problems, tol=1e-8, max_iter=10000, outputs=("eps", "sig", "u")):
         """``problems``: list of dicts with keys grid (index), phase (uint8 GPU
-        tensor), lame ([nphase][2]), f ([d][...] GPU tensor), optional c0.
+        tensor), lame ([nphase][2]), f ([d][...] GPU tensor), optional c0 and
+        optional u0 (starting displacement ``[d][...]`` GPU tensor: given for
+        every problem or for none).
         Returns (list of {eps, sig, u} tensors, list of SolveReport, status)."""
         torch = _torch()
         n = len(problems)
@@ -231,6 +233,10 @@ class Plan:
         eps_p = (C.c_void_p * n)()
         sig_p = (C.c_void_p * n)()
         u_p = (C.c_void_p * n)()
+        warm = [pb.get("u0") is not None for pb in problems]
+        if any(warm) and not all(warm):
+            raise ValueError("u0 must be given for every problem or for none")
+        u0_p = (C.c_void_p * n)() if all(warm) else None
         keep = []
         outs = []
         for i, pb in enumerate(problems):
@@ -241,6 +247,8 @@ class Plan:
             gidx[i] = g
             ph_p[i] = self._check(pb["phase"], shp, torch.uint8, "phase")
             f_p[i] = self._check(pb["f"], (d,) + shp, self.dtype, "f")
+            if u0_p is not None:
+                u0_p[i] = self._check(pb["u0"], (d,) + shp, self.dtype, "u0")
             tabs[i], arr = self._phases(pb["lame"])
             keep.append(arr)
             refs[i] = self._ref(pb.get("c0"))
@@ -258,15 +266,16 @@ class Plan:
             outs.append(o)
         reps = (Report * n)()
         st = self.lib.lsfft_solve_bfcs(self.handle, n, gidx, ph_p, tabs, refs, f_p, float(tol), int(max_iter),
-                                       eps_p, sig_p, u_p, None, reps)
+                                       eps_p, sig_p, u_p, u0_p, reps)
         if st not in (OK, W_STAGNATED, E_NOCONV, E_DIVERGED):
             raise LsfftError(st, "lsfft_solve_bfcs")
         return outs, [_report(reps[i], len(self.shapes[gidx[i]])) for i in range(n)], st
 
     def solve(self, phase, lame, f, tol=1e-8, max_iter=10000, c0=None, grid=0,
-              outputs=("eps", "sig", "u")):
-        """One solve; returns ({eps, sig, u}, SolveReport)."""
-        outs, reps, _ = self.solve_batch([dict(grid=grid, phase=phase, lame=lame, f=f, c0=c0)],
+              outputs=("eps", "sig", "u"), u0=None):
+        """One solve (optionally warm-started from the displacement ``u0``);
+        returns ({eps, sig, u}, SolveReport)."""
+        outs, reps, _ = self.solve_batch([dict(grid=grid, phase=phase, lame=lame, f=f, c0=c0, u0=u0)],
                                          tol=tol, max_iter=max_iter, outputs=outputs)
         return outs[0], reps[0]
 

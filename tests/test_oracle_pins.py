@@ -468,3 +468,24 @@ def test_average_shift_direction_and_phase_hooke_invariants():
     ref = O.solve_basic(np.roll(phase, (1, 3), (0, 1)), LAME10, f, tol=1e-11)
     ind = np.roll(phase, (1, 3), (0, 1)) == 1
     np.testing.assert_allclose(one[2:4], ref.u * ind, atol=1e-15)
+
+
+def test_warm_start_from_the_solution_and_from_a_shifted_start():
+    # started at its own converged displacement the iteration stops at once
+    # with the same fields; from any other start it reaches the same
+    # solution (the fixed point does not depend on the start)
+    shape = (16, 12)
+    phase = (np.random.default_rng(71).random(shape) < 0.4).astype(np.uint8)
+    f = np.random.default_rng(72).normal(size=(2,) + shape)
+    cold = O.solve_displacement_update(phase, LAME10, f, tol=1e-12)
+    warm = O.solve_displacement_update(phase, LAME10, f, tol=1e-10, u_init=cold.u)
+    assert warm.iters == 0
+    np.testing.assert_allclose(warm.eps, cold.eps, rtol=0, atol=1e-11 * np.abs(cold.eps).max())
+    rnd = O.solve_displacement_update(phase, LAME10, f, tol=1e-12,
+                                      u_init=np.random.default_rng(73).normal(size=(2,) + shape) + 5.0)
+    np.testing.assert_allclose(rnd.eps, cold.eps, rtol=0, atol=1e-9 * np.abs(cold.eps).max())
+    # the mean of the start is dropped: a uniform shift of the start changes nothing
+    a = O.solve_displacement_update(phase, LAME10, f, tol=1e-10, max_iter=3, u_init=cold.u * 0.5)
+    b = O.solve_displacement_update(phase, LAME10, f, tol=1e-10, max_iter=3, u_init=cold.u * 0.5 + 3.0)
+    np.testing.assert_allclose(a.eps, b.eps, rtol=0, atol=1e-13 * np.abs(a.eps).max())
+    np.testing.assert_allclose(a.u, b.u, rtol=0, atol=1e-13 * np.abs(a.u).max())
