@@ -49,7 +49,7 @@ typedef enum {
   LSFFT_E_DEVICE = -3,     /* HIP runtime error */
   LSFFT_E_NOCONV = -4,     /* max_iter reached; outputs hold the last iterate */
   LSFFT_E_NONEQUIL = -5,   /* LSFFT_STRICT_EQUIL set and the force is not self-equilibrated */
-  LSFFT_E_DIVERGED = -6    /* residual became non-finite or grew for more than 20 iterations */
+  LSFFT_E_DIVERGED = -6    /* residual became non-finite or grew in 20 consecutive iterations */
 } lsfft_status;
 
 typedef enum { LSFFT_F32 = 0, LSFFT_F64 = 1 } lsfft_prec;

@@ -221,6 +221,11 @@ __device__ inline void judge(const InstDesc& D, InstState& St, double delta) {
   if (!(delta == delta) || delta > 1e300) { St.status = ST_DIVERGED; return; }
   if (delta <= D.tol) { St.status = ST_OK; return; }
   if (St.iter >= D.max_iter) { St.status = ST_NOCONV; return; }
+  // a residual that grew over 20 iterations in a row diverges; this is
+  // tested before stagnation, which the same 20 iterations would also meet
+  St.grow = (delta > St.prev) ? St.grow + 1 : 0;
+  St.prev = delta;
+  if (St.grow >= 20) { St.status = ST_DIVERGED; return; }
   if (delta < 0.99 * St.mark) {
     St.mark = delta;
     St.mark_iter = St.iter;
@@ -228,9 +233,6 @@ __device__ inline void judge(const InstDesc& D, InstState& St, double delta) {
     St.status = ST_STAGNATED;
     return;
   }
-  St.grow = (delta > St.prev) ? St.grow + 1 : 0;
-  St.prev = delta;
-  if (St.grow > 20) { St.status = ST_DIVERGED; return; }
   St.iter += 1;
 }
 

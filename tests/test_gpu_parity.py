@@ -412,3 +412,33 @@ def test_timing_plan_matches_graph_plan(torch_dev):
         plan.close()
     assert outs[0][1] == outs[1][1]
     assert torch.equal(outs[0][0], outs[1][0])
+
+
+def test_failure_injection_in_a_batch(torch_dev):
+    """A NaN in one force and a far too soft reference medium in another are
+    caught on the device (E_DIVERGED at the first residual, resp. when the
+    residual grows) and retire alone: the healthy solves of the same batch
+    equal their single solves bit for bit."""
+    say("failure injection: NaN force, too soft C0, healthy neighbours")
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import Plan, E_DIVERGED
+    shape = (16, 16)
+    phase = rand_phase(shape, 51)
+    f = rand_force(shape, 52)
+    fnan = f.copy()
+    fnan[0, 5, 7] = np.nan
+    lam0, mu0 = O.reference_medium(LAME10)
+    probs = [dict(phase=torch.from_numpy(phase).to(dev), lame=LAME10, f=torch.from_numpy(f).to(dev)),
+             dict(phase=torch.from_numpy(phase).to(dev), lame=LAME10, f=torch.from_numpy(fnan).to(dev)),
+             dict(phase=torch.from_numpy(phase).to(dev), lame=LAME10, f=torch.from_numpy(f).to(dev),
+                  c0=(0.01 * lam0, 0.01 * mu0)),
+             dict(phase=torch.from_numpy(phase).to(dev), lame=LAME10, f=torch.from_numpy(2.0 * f).to(dev))]
+    plan = Plan([shape], prec="f64", max_batch=4)
+    outs, reps, st = plan.solve_batch(probs, tol=1e-9, max_iter=2000)
+    print("statuses", [r.status for r in reps], "iters", [r.iters for r in reps])
+    assert st == E_DIVERGED
+    assert reps[0].status == 0 and reps[3].status == 0
+    assert reps[1].status == E_DIVERGED and reps[2].status == E_DIVERGED
+    single, _ = plan.solve(probs[0]["phase"], LAME10, probs[0]["f"], tol=1e-9, max_iter=2000)
+    assert torch.equal(outs[0]["eps"], single["eps"])
+    plan.close()
