@@ -114,13 +114,15 @@ typedef struct lsfft_plan_s* lsfft_plan_t;
  *  grids      host [ngrid]; every axis length must be supported
  *  max_batch  largest number of solves (or shifts) run concurrently; larger
  *             requests are processed in successive batches (>= 1)
+ *  prec       an lsfft_prec value, scheme an lsfft_scheme value (passed as
+ *             int so that any value a caller holds is checked, not assumed)
  *  hip_stream hipStream_t to enqueue on (NULL = the null stream)
  * Errors: LSFFT_E_ARG for an unsupported grid, ngrid < 1, max_batch < 1,
- * unknown flags, LSFFT_REFINE64 on an LSFFT_F64 plan or with max_batch >
+ * an unknown precision, scheme or flag, LSFFT_REFINE64 on an LSFFT_F64 plan or with max_batch >
  * 65535; LSFFT_E_DEVICE if no HIP device is usable.
  */
 lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, int max_batch,
-                        lsfft_prec prec, lsfft_scheme scheme, unsigned flags, void* hip_stream);
+                        int prec, int scheme, unsigned flags, void* hip_stream);
 
 /*
  * lsfft_solve_bfcs -- solve the modified Lippmann-Schwinger equation
@@ -251,8 +253,10 @@ lsfft_status lsfft_rve_identify(lsfft_plan_t p, int grid_idx, const double* avg,
 /* Release the plan and its workspace.  NULL is accepted. */
 lsfft_status lsfft_plan_destroy(lsfft_plan_t p);
 
-/* Static, human-readable text for a status code. */
-const char* lsfft_status_string(lsfft_status s);
+/* Static, human-readable text for a status code.  Takes a plain int so that
+   any value a caller holds is valid input; codes the library does not define
+   give "unknown status". */
+const char* lsfft_status_string(int status);
 
 /* Isotropic (E, nu) pairs to Lame pairs (lambda, mu); host [nphase][2] each.
  * Returns LSFFT_E_ARG for nu outside (-1, 0.5) or E <= 0. */

@@ -1257,8 +1257,8 @@ lsfft_status run_averages(lsfft_plan_t p, const std::vector<Spec>& specs, const 
 
 extern "C" {
 
-const char* lsfft_status_string(lsfft_status s) {
-  switch (s) {
+const char* lsfft_status_string(int status) {
+  switch (status) {
     case LSFFT_OK: return "ok";
     case LSFFT_W_STAGNATED: return "stagnated: residual stopped improving above tol";
     case LSFFT_E_ARG: return "invalid argument";
@@ -1286,7 +1286,7 @@ lsfft_status lsfft_lame_from_young(int nphase, const double* e_nu, double* lame_
 }
 
 lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, int max_batch,
-                        lsfft_prec prec, lsfft_scheme scheme, unsigned flags, void* hip_stream) {
+                        int prec, int scheme, unsigned flags, void* hip_stream) {
   if (!out) return LSFFT_E_ARG;
   *out = nullptr;
   if (!grids || ngrid < 1 || max_batch < 1) return LSFFT_E_ARG;
@@ -1319,7 +1319,7 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
   }
   if (std::getenv("LSFFT_NO_GRAPH")) p->graphs = false;
   p->f64 = (prec == LSFFT_F64);
-  p->scheme = scheme;
+  p->scheme = static_cast<lsfft_scheme>(scheme);
   p->flags = flags;
   p->grids.assign(grids, grids + ngrid);
   for (auto& G : p->grids)
