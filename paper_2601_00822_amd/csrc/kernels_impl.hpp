@@ -291,8 +291,8 @@ __device__ inline void finalize(const InstDesc& D, InstState& St, int mode, doub
 // x pass
 // ---------------------------------------------------------------------------
 // Row block of MR rows (row = z * ny + y).  Per component: the H + 1 half
-// spectrum entries of each row (H from the main block, the last from the
-// Nyquist plane) are staged in LDS; the fold
+// spectrum entries of each row (X[0] and X[H] unpacked from the row's first
+// entry, which holds X[0] + i X[H]) are staged in LDS; the fold
 //   Z'[k] = (X[k] + conj X[H-k]) + i exp(+2 pi i k / NX) (X[k] - conj X[H-k])
 // feeds a length-H inverse transform whose output is NX (a[2n] + i a[2n+1]);
 // the forward direction is the mirror image:
@@ -334,7 +334,7 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
   // independent components of one row block run in parallel workgroups
   const int part = local / D.xtiles;
   const int row0 = (local - part * D.xtiles) * MR;
-  const long long Pm = D.Pm, Pc = D.Pc;
+  const long long Pc = D.Pc;
 
   // forward core on registers `in` (positions j + r H/R0 of butterfly tid + q NTH),
   // then unfold through LDS and store component c of `dst`
@@ -359,22 +359,24 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
     }
     __syncthreads();
     char* base = mptr<T>(dst, Pc, c);
-    for (int e = tid; e < MR * (H + 1); e += NTH) {
-      const int m = e / (H + 1);
-      const int k = e - m * (H + 1);
+    for (int e = tid; e < MR * H; e += NTH) {
+      const int m = e / H;
+      const int k = e - m * H;
       const int row = row0 + m;
       if (row >= nrows) continue;
-      const int k1 = (k == H) ? 0 : k;
-      const int k2 = (k == 0) ? 0 : H - k;
-      const T zr = ar[m * SM + k1], zi = ai[m * SM + k1];
-      const T wr = ar[m * SM + k2], wi = ai[m * SM + k2];
+      const T zr = ar[m * SM + k], zi = ai[m * SM + k];
+      if (k == 0) {
+        // X[0] = zr + zi and X[H] = zr - zi are real: one packed entry
+        stc<T>(base, row * H, zr + zi, zr - zi);
+        continue;
+      }
+      const T wr = ar[m * SM + H - k], wi = ai[m * SM + H - k];
       const T er = T(0.5) * (zr + wr), ei = T(0.5) * (zi - wi);
       const T dr = T(0.5) * (zr - wr), di = T(0.5) * (zi + wi);
       const T orr = di, oi = -dr;
       const T cr = twr[k], ci = twi[k];
       const T xr = er + cr * orr - ci * oi, xi = ei + cr * oi + ci * orr;
-      if (k < H) stc<T>(base, row * H + k, xr, xi);
-      else stc<T>(base, (int)Pm + row, xr, xi);
+      stc<T>(base, row * H + k, xr, xi);
     }
   };
 
@@ -409,10 +411,11 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
     return;
   } else {
     // C2R of component c of S into registers (real pairs at x = 2n, 2n + 1).
-    // The H + 1 entries of each row of the block (element e = tid + u NTH)
-    // are loaded into registers with every load issued before the first use,
-    // then staged in LDS for the fold.
-    constexpr int XE = MR * (H + 1);
+    // The H entries of each row of the block (element e = tid + u NTH) are
+    // loaded into registers with every load issued before the first use,
+    // then staged in LDS for the fold as H + 1 entries: the packed entry
+    // Z = X[0] + i X[H] becomes X[0] = (Re Z, 0) and X[H] = (Im Z, 0).
+    constexpr int XE = MR * H;
     constexpr int XL = (XE + NTH - 1) / NTH;
     auto c2r = [&](int c, T (&o_r)[BP][RP], T (&o_i)[BP][RP]) {
       const char* src = cptr<T>(D.S, Pc, c);
@@ -422,11 +425,10 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
         const int e = tid + u * NTH;
         T re = T(0), im = T(0);
         if (XE % NTH == 0 || e < XE) {
-          const int m = e / (H + 1);
-          const int k = e - m * (H + 1);
+          const int m = e / H;
           const int row = row0 + m;
           if (row < nrows) {
-            const typename C2<T>::type v = (k < H) ? ldc<T>(src, row * H + k) : ldc<T>(src, (int)Pm + row);
+            const typename C2<T>::type v = ldc<T>(src, row * H + (e - m * H));
             re = v.x;
             im = v.y;
           }
@@ -439,10 +441,17 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
       for (int u = 0; u < XL; ++u) {
         const int e = tid + u * NTH;
         if (XE % NTH == 0 || e < XE) {
-          const int m = e / (H + 1);
-          const int k = e - m * (H + 1);
-          ar[m * SM + k] = pr[u];
-          ai[m * SM + k] = pi[u];
+          const int m = e / H;
+          const int k = e - m * H;
+          if (k == 0) {
+            ar[m * SM] = pr[u];
+            ai[m * SM] = T(0);
+            ar[m * SM + H] = pi[u];
+            ai[m * SM + H] = T(0);
+          } else {
+            ar[m * SM + k] = pr[u];
+            ai[m * SM + k] = pi[u];
+          }
         }
       }
       __syncthreads();
@@ -587,8 +596,7 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
 // a row tile (MR rows x H entries) is contiguous in HBM; it lands in LDS in
 // 1 KB pieces, one per wave-wide 16-byte-per-lane load, each piece followed
 // by 64 bytes of padding so that row pairs of consecutive pieces fall on
-// different LDS banks.  The Nyquist entries of the rows go into those
-// paddings, eight rows per padding.  Loads bypass the registers, so the
+// different LDS banks.  Loads bypass the registers, so the
 // normal group fetches the next component into the second buffer while the
 // current one is transformed.  The buffers double as transform staging and
 // fold tiles once their data has been read.
@@ -617,26 +625,23 @@ template <typename T, int H> struct XDma {
   static constexpr int PP = 2 * H + 16;
   // dynamic LDS: twiddles (2 x 2H), Lame table, phase ids of the tile
   static constexpr int DYN = 4 * (2 * 2 * H + 2 * kXDmaPhases) + MR * PP;
-  static_assert(!ok || (NCH % 4 == 0 && MR / 8 <= NCH && MR * 2 * H == 4096), "x tile geometry");
+  static_assert(!ok || (NCH % 4 == 0 && MR * 2 * H == 4096), "x tile geometry");
   // rows never straddle a piece (a row is 256, 512 or 1024 bytes)
   __device__ static __forceinline__ int row_off(int m) {
     const int p = m * H * 8;
     return p + (p >> 10) * PAD;
   }
-  __device__ static __forceinline__ int nyq_off(int m) { return (m >> 3) * PITCH + KB + (m & 7) * 8; }
 };
 
 typedef __attribute__((address_space(3))) void* lds_vptr;
 
 // Issue the loads of component `comp` (global base of the component) of row
 // tile row0 into LDS buffer `buf`.  Lanes past the last row load nothing.
-// Every supported axis length is even, so the component stride (ny nz (H+1)
+// Every supported axis length is even, so the component stride (ny nz H
 // entries of 8 bytes) keeps every component base 16-byte aligned.
 template <typename T, int H>
-__device__ __forceinline__ void xdma_issue(const char* comp, long long Pm, int row0, int nrows, unsigned char* buf,
-                                           int tid) {
+__device__ __forceinline__ void xdma_issue(const char* comp, int row0, int nrows, unsigned char* buf, int tid) {
   using X = XDma<T, H>;
-  constexpr int MR = X::MR;
   const int wave = tid >> 6, lane = tid & 63;
   const char* mainp = comp + (long long)row0 * H * 8;
 #pragma unroll
@@ -645,15 +650,6 @@ __device__ __forceinline__ void xdma_issue(const char* comp, long long Pm, int r
     const int b = g * X::KB + lane * 16;
     if (row0 + b / (H * 8) < nrows)
       __builtin_amdgcn_global_load_lds((const void*)(mainp + b), (lds_vptr)(buf + g * X::PITCH), 16, 0, 0);
-  }
-  if (wave == 0) {
-    const char* nyq = comp + (Pm + row0) * 8;
-#pragma unroll
-    for (int i = 0; i < MR / 8; ++i) {
-      if (lane < 16 && row0 + 8 * i + (lane >> 1) < nrows)
-        __builtin_amdgcn_global_load_lds((const void*)(nyq + i * 64 + lane * 4),
-                                         (lds_vptr)(buf + i * X::PITCH + X::KB), 4, 0, 0);
-    }
   }
 }
 
@@ -687,10 +683,10 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   const int nrows = D.ny * D.nz;
   const int part = local / D.xtiles;
   const int row0 = (local - part * D.xtiles) * MR;
-  const long long Pm = D.Pm, Pc = D.Pc;
+  const long long Pc = D.Pc;
   const int cfirst = (part == 0) ? 0 : DIM + part - 1;
 
-  xdma_issue<T, H>(cptr<T>(D.S, Pc, cfirst), Pm, row0, nrows, xb0, tid);
+  xdma_issue<T, H>(cptr<T>(D.S, Pc, cfirst), row0, nrows, xb0, tid);
   // phase ids of the tile, 16 consecutive x of one row per thread, read at
   // the shifted positions
   static_assert(PB == 16, "x tile phase map");
@@ -739,9 +735,16 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
       for (int r = 0; r < FI::R0; ++r) {
         const int k = j + r * (H / FI::R0);
         const float2 xv = *reinterpret_cast<const float2*>(rowp + 8 * k);
-        const float2 yv = *reinterpret_cast<const float2*>((r == 0 && j == 0) ? buf + X::nyq_off(m) : rowp + 8 * (H - k));
-        const T xr = xv.x, xi = xv.y;
-        const T yr = yv.x, yi = -yv.y;
+        // at k = 0 this read lands in the next row or the piece's padding
+        // (inside the buffer) and is replaced below
+        const float2 yv = *reinterpret_cast<const float2*>(rowp + 8 * (H - k));
+        T xr = xv.x, xi = xv.y, yr = yv.x, yi = -yv.y;
+        if (r == 0 && j == 0) {
+          // packed entry Z: X[0] = (Re Z, 0), conj X[H] = (Im Z, 0)
+          yr = xi;
+          yi = T(0);
+          xi = T(0);
+        }
         const T dr = xr - yr, di = xi - yi;
         const T cr = twr[k], ci = -twi[k];
         const T tr = cr * dr - ci * di, ti = cr * di + ci * dr;
@@ -780,22 +783,26 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
     }
     lds_barrier();
     char* base = mptr<T>(D.S, Pc, c);
-    for (int e = tid; e < MR * (H + 1); e += NTH) {
-      const int m = e / (H + 1);
-      const int k = e - m * (H + 1);
+#pragma unroll
+    for (int u = 0; u < MR * H / NTH; ++u) {
+      const int e = tid + u * NTH;
+      const int m = e / H;
+      const int k = e - m * H;
       const int row = row0 + m;
       if (row >= nrows) continue;
-      const int k1 = (k == H) ? 0 : k;
-      const int k2 = (k == 0) ? 0 : H - k;
-      const T zr = ar[m * SM + k1], zi = ai[m * SM + k1];
-      const T wr = ar[m * SM + k2], wi = ai[m * SM + k2];
+      const T zr = ar[m * SM + k], zi = ai[m * SM + k];
+      if (k == 0) {
+        // X[0] = zr + zi and X[H] = zr - zi are real: one packed entry
+        stc<T>(base, row * H, zr + zi, zr - zi);
+        continue;
+      }
+      const T wr = ar[m * SM + H - k], wi = ai[m * SM + H - k];
       const T er = T(0.5) * (zr + wr), ei = T(0.5) * (zi - wi);
       const T dr = T(0.5) * (zr - wr), di = T(0.5) * (zi + wi);
       const T orr = di, oi = -dr;
       const T cr = twr[k], ci = twi[k];
       const T xr = er + cr * orr - ci * oi, xi = ei + cr * oi + ci * orr;
-      if (k < H) stc<T>(base, row * H + k, xr, xi);
-      else stc<T>(base, (int)Pm + row, xr, xi);
+      stc<T>(base, row * H + k, xr, xi);
     }
   };
   // fn(q, r, half, lam, mu) at every point of this thread
@@ -833,11 +840,11 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   // normal components, coupled through the trace; component c + 1 is in
   // flight while component c is transformed
   T n_r[DIM][BP][RP], n_i[DIM][BP][RP];
-  xdma_issue<T, H>(cptr<T>(D.S, Pc, 1), Pm, row0, nrows, xb1, tid);
+  xdma_issue<T, H>(cptr<T>(D.S, Pc, 1), row0, nrows, xb1, tid);
   c2r(xb0, n_r[0], n_i[0]);
   wait_vm_all();
   __syncthreads();   // component 1 landed; the staging of component 0 is free
-  if constexpr (DIM == 3) xdma_issue<T, H>(cptr<T>(D.S, Pc, 2), Pm, row0, nrows, xb0, tid);
+  if constexpr (DIM == 3) xdma_issue<T, H>(cptr<T>(D.S, Pc, 2), row0, nrows, xb0, tid);
   c2r(xb1, n_r[1], n_i[1]);
   if constexpr (DIM == 3) {
     wait_vm_all();
@@ -877,58 +884,34 @@ __device__ __forceinline__ void xpass_item(const InstDesc& D, int local, const d
 // ---------------------------------------------------------------------------
 // strided tiles (y pass and outer pass)
 // ---------------------------------------------------------------------------
-// A tile is MP pencils of length N.  Main tiles take mpk consecutive kx
-// columns times MP / mpk consecutive lines of the other axis; Nyquist tiles
-// take MP consecutive lines of the Nyquist plane.  Element (m, n) of
-// component c lives at c Pc + off(m) + n sn.
+// A tile is MP pencils of length N: mpk consecutive kx columns times MP / mpk
+// consecutive lines of the other axis.  Element (m, n) of component c lives
+// at c Pc + off(m) + n sn.
 struct TileAddr {
   int sn;              // stride along the pencil (elements)
   int base;            // offset of pencil 0 within a component
   int so;              // stride between lines of the other axis
   int mpk, lg;         // kx pencils per line (power of 2), log2
   int kx0, o0, nother; // first kx, first line, lines in the grid
-  bool nyq;
-  int H;
-  __device__ __forceinline__ int off(int m) const {
-    if (nyq) return base + m * so;
-    return base + (m >> lg) * so + (m & (mpk - 1));
-  }
-  __device__ __forceinline__ bool valid(int m) const {
-    if (nyq) return o0 + m < nother;
-    return o0 + (m >> lg) < nother;
-  }
-  __device__ __forceinline__ int kx(int m) const { return nyq ? H : kx0 + (m & (mpk - 1)); }
-  __device__ __forceinline__ int other(int m) const { return nyq ? o0 + m : o0 + (m >> lg); }
+  __device__ __forceinline__ int off(int m) const { return base + (m >> lg) * so + (m & (mpk - 1)); }
+  __device__ __forceinline__ bool valid(int m) const { return o0 + (m >> lg) < nother; }
+  __device__ __forceinline__ int kx(int m) const { return kx0 + (m & (mpk - 1)); }
+  __device__ __forceinline__ int other(int m) const { return o0 + (m >> lg); }
 };
 
 // y pass (3D): pencils along y; other axis = z.
 __device__ __forceinline__ TileAddr ytile(const InstDesc& D, int local, int MP) {
   TileAddr t;
-  t.H = D.H;
-  if (local < D.ymain) {
-    const int per = MP >> D.lg_y;                    // z lines per tile
-    const int tz = local / D.ntk_y, tk = local - (local / D.ntk_y) * D.ntk_y;
-    t.nyq = false;
-    t.mpk = D.mpk_y;
-    t.lg = D.lg_y;
-    t.kx0 = tk * D.mpk_y;
-    t.o0 = tz * per;
-    t.nother = D.nz;
-    t.sn = D.H;
-    t.so = D.ny * D.H;
-    t.base = t.o0 * t.so + t.kx0;
-  } else {
-    const int tn = local - D.ymain;
-    t.nyq = true;
-    t.mpk = 1;
-    t.lg = 0;
-    t.kx0 = D.H;
-    t.o0 = tn * MP;
-    t.nother = D.nz;
-    t.sn = 1;
-    t.so = D.ny;
-    t.base = (int)D.Pm + t.o0 * D.ny;
-  }
+  const int per = MP >> D.lg_y;                    // z lines per tile
+  const int tz = local / D.ntk_y, tk = local - (local / D.ntk_y) * D.ntk_y;
+  t.mpk = D.mpk_y;
+  t.lg = D.lg_y;
+  t.kx0 = tk * D.mpk_y;
+  t.o0 = tz * per;
+  t.nother = D.nz;
+  t.sn = D.H;
+  t.so = D.ny * D.H;
+  t.base = t.o0 * t.so + t.kx0;
   return t;
 }
 
@@ -936,47 +919,24 @@ __device__ __forceinline__ TileAddr ytile(const InstDesc& D, int local, int MP) 
 template <int DIM>
 __device__ __forceinline__ TileAddr gtile(const InstDesc& D, int local, int MP) {
   TileAddr t;
-  t.H = D.H;
-  if (local < D.gmain) {
-    t.nyq = false;
-    t.mpk = D.mpk_g;
-    t.lg = D.lg_g;
-    if constexpr (DIM == 3) {
-      const int per = MP >> D.lg_g;
-      const int ty = local / D.ntk_g, tk = local - (local / D.ntk_g) * D.ntk_g;
-      t.kx0 = tk * D.mpk_g;
-      t.o0 = ty * per;
-      t.nother = D.ny;
-      t.sn = D.ny * D.H;
-      t.so = D.H;
-      t.base = t.o0 * D.H + t.kx0;
-    } else {
-      t.kx0 = local * D.mpk_g;
-      t.o0 = 0;
-      t.nother = 1;                                 // only m < mpk are valid
-      t.sn = D.H;
-      t.so = D.H;
-      t.base = t.kx0;
-    }
+  t.mpk = D.mpk_g;
+  t.lg = D.lg_g;
+  if constexpr (DIM == 3) {
+    const int per = MP >> D.lg_g;
+    const int ty = local / D.ntk_g, tk = local - (local / D.ntk_g) * D.ntk_g;
+    t.kx0 = tk * D.mpk_g;
+    t.o0 = ty * per;
+    t.nother = D.ny;
+    t.sn = D.ny * D.H;
+    t.so = D.H;
+    t.base = t.o0 * D.H + t.kx0;
   } else {
-    const int tn = local - D.gmain;
-    t.nyq = true;
-    t.mpk = 1;
-    t.lg = 0;
-    t.kx0 = D.H;
-    if constexpr (DIM == 3) {
-      t.o0 = tn * MP;
-      t.nother = D.ny;
-      t.sn = D.ny;
-      t.so = 1;
-      t.base = (int)D.Pm + t.o0;
-    } else {
-      t.o0 = 0;
-      t.nother = 1;                                 // a single pencil
-      t.sn = 1;
-      t.so = 1;
-      t.base = (int)D.Pm;
-    }
+    t.kx0 = local * D.mpk_g;
+    t.o0 = 0;
+    t.nother = 1;                                 // only m < mpk are valid
+    t.sn = D.H;
+    t.so = D.H;
+    t.base = t.kx0;
   }
   return t;
 }
@@ -1087,7 +1047,7 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
     const int kx = t.kx(m);
     pxi0[q] = T(wavenum(kx, D.nx, D.kx));
     pxi1[q] = (DIM == 3) ? T(wavenum(t.other(m) < D.ny ? t.other(m) : 0, D.ny, D.ky)) : T(0);
-    pw[q] = (kx == 0 || kx == D.H) ? T(1) : T(2);
+    pw[q] = (kx == 0) ? T(1) : T(2);   // kx = 0 column: the packed kx = 0 and kx = H planes
   }
   auto point_xi = [&](int q, int r, T* xi, T& xi2) {
     const int n = pj[q] + r * NSTEP;
@@ -1452,18 +1412,10 @@ __device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsi
     for (int qq = 0; qq < QB; ++qq) {
       const long long g = (long long)local * NTH * 4 + (q0 + qq) * NTH + tid;
       if (g >= Pc) continue;
-      int kx, ky, kz;
-      if (g < D.Pm) {
-        kx = int(g % D.H);
-        const long long rest = g / D.H;
-        ky = int(rest % D.ny);
-        kz = int(rest / D.ny);
-      } else {
-        kx = D.H;
-        const long long rest = g - D.Pm;
-        ky = int(rest % D.ny);
-        kz = int(rest / D.ny);
-      }
+      const int kx = int(g % D.H);
+      const long long rest = g / D.H;
+      const int ky = int(rest % D.ny);
+      const int kz = int(rest / D.ny);
       T xi[DIM];
       xi[0] = T(wavenum(kx, D.nx, D.kx));
       xi[1] = T(wavenum(ky, D.ny, D.ky));
@@ -1471,7 +1423,7 @@ __device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsi
       T xi2 = T(0);
 #pragma unroll
       for (int a = 0; a < DIM; ++a) xi2 += xi[a] * xi[a];
-      const double wgt = (kx == 0 || kx == D.H) ? 1.0 : 2.0;
+      const double wgt = (kx == 0) ? 1.0 : 2.0;
       T rr[DIM], ri[DIM];
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
@@ -1784,18 +1736,11 @@ __global__ __launch_bounds__(NTR) void k_radial_max(const double* __restrict__ a
 }
 
 // ---- mixed-precision defect correction: FP64 state, FP32 inner solves ----
-// Wavevector of entry g of the split half spectrum (main block, then the
-// x-Nyquist plane).
+// Wavevector of entry g of the packed half spectrum (xi_x = 0 on the kx = 0
+// column, which also carries the kx = H plane).
 __device__ inline void spectrum_xi(const InstDesc& D, long long g, double xi[3]) {
-  int kx;
-  long long rest;
-  if (g < D.Pm) {
-    kx = int(g % D.H);
-    rest = g / D.H;
-  } else {
-    kx = D.H;
-    rest = g - D.Pm;
-  }
+  const int kx = int(g % D.H);
+  const long long rest = g / D.H;
   xi[0] = wavenum(kx, D.nx, D.kx);
   xi[1] = wavenum(int(rest % D.ny), D.ny, D.ky);
   xi[2] = (D.dim == 3) ? wavenum(int(rest / D.ny), D.nz, D.kz) : 0.0;

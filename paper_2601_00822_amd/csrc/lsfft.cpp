@@ -193,7 +193,7 @@ lsfft_status resolve_ref(const lsfft_phases* t, const lsfft_ref* c0, double* lam
 struct Geometry {
   int nx, ny, nz, H, dim, s;
   long long Pm, Pc, nvox;
-  int xtiles, items_x, items_xall, items_xft, items_y, ymain, mpk_y, ntk_y, items_g, gmain, mpk_g, ntk_g, items_cg;
+  int xtiles, items_x, items_xall, items_xft, items_y, mpk_y, ntk_y, items_g, mpk_g, ntk_g, items_cg;
   size_t lds_x, lds_xi, lds_y, lds_g;   // lds_xi: x pass of the iteration
 };
 
@@ -217,8 +217,9 @@ bool geometry(bool f64, const lsfft_grid& g, Geometry* o) {
   o->nz = (int)gnz(g);
   o->H = o->nx / 2;
   o->s = g.dim == 3 ? 6 : 3;
+  // kx = 0 and kx = H share one column (packed half spectrum): no Nyquist plane
   o->Pm = (long long)o->nz * o->ny * o->H;
-  o->Pc = o->Pm + (long long)o->nz * o->ny;
+  o->Pc = o->Pm;
   o->nvox = (long long)o->nz * o->ny * o->nx;
   int mr = 0, mpy = 0, mpg = 0;
   o->lds_x = query_geometry(f64, 0, o->nx, &mr);
@@ -236,23 +237,19 @@ bool geometry(bool f64, const lsfft_grid& g, Geometry* o) {
     o->mpk_y = kx_pencils(mpy, o->H);
     const int per = mpy / o->mpk_y;
     o->ntk_y = o->H / o->mpk_y;
-    o->ymain = o->ntk_y * ((o->nz + per - 1) / per);
-    o->items_y = o->ymain + (o->nz + mpy - 1) / mpy;
+    o->items_y = o->ntk_y * ((o->nz + per - 1) / per);
   } else {
     o->mpk_y = 1;
     o->ntk_y = 0;
-    o->ymain = 0;
     o->items_y = 0;
   }
   o->mpk_g = kx_pencils(mpg, o->H);
   o->ntk_g = o->H / o->mpk_g;
   if (g.dim == 3) {
     const int per = mpg / o->mpk_g;
-    o->gmain = o->ntk_g * ((o->ny + per - 1) / per);
-    o->items_g = o->gmain + (o->ny + mpg - 1) / mpg;
+    o->items_g = o->ntk_g * ((o->ny + per - 1) / per);
   } else {
-    o->gmain = o->ntk_g;
-    o->items_g = o->gmain + 1;
+    o->items_g = o->ntk_g;
   }
   const int nth = threads_per_block(f64);
   o->items_cg = (int)((o->Pc + nth * 4 - 1) / (nth * 4));
@@ -628,9 +625,9 @@ lsfft_status prepare(Batch& b, bool validate = true) {
     const lsfft_grid& gr = p->grids[sp.grid];
     InstDesc& D = b.desc[i];
     D.dim = g.dim; D.nx = g.nx; D.ny = g.ny; D.nz = g.nz; D.H = g.H; D.ncomp_s = g.s;
-    D.xtiles = g.xtiles; D.items_y = g.items_y; D.ymain = g.ymain;
+    D.xtiles = g.xtiles; D.items_y = g.items_y;
     D.mpk_y = g.mpk_y; D.lg_y = ilog2(g.mpk_y); D.ntk_y = g.ntk_y;
-    D.items_g = g.items_g; D.gmain = g.gmain;
+    D.items_g = g.items_g;
     D.mpk_g = g.mpk_g; D.lg_g = ilog2(g.mpk_g); D.ntk_g = g.ntk_g;
     D.items_cg = g.items_cg;
     D.nphase = sp.tab->nphase;

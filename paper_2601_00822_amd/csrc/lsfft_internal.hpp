@@ -54,22 +54,24 @@ enum PassMode : int {
 // One solve.  All pointers are device pointers; real and complex buffers are
 // stored in the plan precision (float or double), complex interleaved.
 //
-// Spectral layout ("split half spectrum"): component c of a spectral buffer
+// Spectral layout ("packed half spectrum"): component c of a spectral buffer
 // starts at c * Pc and holds the modes kx = 0 .. H-1 (H = nx / 2) as a
-// [nz][ny][H] block of Pm complex entries, followed by the Nyquist plane
-// kx = H as a [nz][ny] block of Pn entries (Pc = Pm + Pn).  Rows of the main
-// block are H entries long, so every tile of the strided passes is full.
+// [nz][ny][H] block of Pc = Pm complex entries.  The planes kx = 0 and
+// kx = H of a real field are both real after the x transform and both have
+// xi_x = 0, so they share the kx = 0 column as Z = F_0 + i F_H: the y and
+// outer transforms, the Green operator and the strain map are complex-linear
+// and identical on the two planes, and over +k and -k the cross terms of
+// |Z|^2 cancel, so the column carries Parseval weight 1.  Rows are H entries
+// long, so every tile of the strided passes is full.
 struct InstDesc {
   int dim;             // 2 or 3
   int nx, ny, nz;      // nz = 1 in 2D
   int H;               // nx / 2
   int ncomp_s;         // strain components: 3 (2D) or 6 (3D)
   int xtiles;          // x-pass row tiles (work items = row tiles x component groups)
-  int items_y;         // y-pass tiles per component (main + Nyquist)
-  int ymain;           // y-pass main tiles per component
+  int items_y;         // y-pass tiles per component
   int mpk_y, lg_y, ntk_y;  // y tiles: kx pencils per tile, log2, kx tiles per plane
-  int items_g;         // outer-pass tiles (main + Nyquist)
-  int gmain;           // outer-pass main tiles
+  int items_g;         // outer-pass tiles
   int mpk_g, lg_g, ntk_g;  // outer tiles: kx pencils per tile, log2, kx tiles per line
   int items_cg;        // CG update items
   int nphase;
