@@ -783,7 +783,7 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
     }
     lds_barrier();
     char* base = mptr<T>(D.S, Pc, c);
-#pragma unroll
+#pragma unroll 1
     for (int u = 0; u < MR * H / NTH; ++u) {
       const int e = tid + u * NTH;
       const int m = e / H;
