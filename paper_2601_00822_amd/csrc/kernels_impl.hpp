@@ -122,16 +122,25 @@ __device__ __forceinline__ void gst(void* base, long long i, V v) {
   ((LSFFT_GLOBAL V*)base)[i] = v;
 }
 
+// Complex entry i of a spectral component.  The byte offset is formed in 32
+// bits (a component holds at most 256 x 256 x 128 entries of 16 bytes, and
+// no index passed here exceeds the nine components of a work buffer), so
+// the access is a uniform 64-bit base plus an unsigned 32-bit lane offset:
+// one VGPR per address instead of a 64-bit lane address.
 template <typename T>
-__device__ __forceinline__ typename C2<T>::type ldc(const void* base, long long i) {
-  return gld<typename C2<T>::type>(base, i);
+__device__ __forceinline__ typename C2<T>::type ldc(const void* base, unsigned i) {
+  using V = typename C2<T>::type;
+  const unsigned off = i * (unsigned)sizeof(V);
+  return *reinterpret_cast<const LSFFT_GLOBAL V*>((const LSFFT_GLOBAL char*)base + off);
 }
 template <typename T>
-__device__ __forceinline__ void stc(void* base, long long i, T re, T im) {
-  typename C2<T>::type v;
+__device__ __forceinline__ void stc(void* base, unsigned i, T re, T im) {
+  using V = typename C2<T>::type;
+  V v;
   v.x = re;
   v.y = im;
-  gst<typename C2<T>::type>(base, i, v);
+  const unsigned off = i * (unsigned)sizeof(V);
+  *reinterpret_cast<LSFFT_GLOBAL V*>((LSFFT_GLOBAL char*)base + off) = v;
 }
 template <typename T>
 __device__ __forceinline__ const char* cptr(const void* base, long long comp_stride, int c) {
