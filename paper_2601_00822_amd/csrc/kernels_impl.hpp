@@ -81,7 +81,10 @@ template <typename T, int N> struct SGeom {
   static constexpr int MP = clampi(pow2floor(Cfg<T>::E / N), 1, 64);
   // outer pass: FP32 pencils of 256 or more points come 8 to a tile (64-byte
   // runs per line instead of 32), at 2 waves per SIMD (see WavesG)
-  static constexpr int MPG = clampi(pow2floor((sizeof(T) == 4 && N >= 256 ? 2 * Cfg<T>::E_G : Cfg<T>::E_G) / N), 1, 64);
+#ifndef LSFFT_G2_MIN
+#define LSFFT_G2_MIN 256
+#endif
+  static constexpr int MPG = clampi(pow2floor((sizeof(T) == 4 && N >= LSFFT_G2_MIN ? 2 * Cfg<T>::E_G : Cfg<T>::E_G) / N), 1, 64);
 };
 
 // rows per x tile (H = nx / 2 complex points per row); odd LDS pitches
@@ -1477,7 +1480,7 @@ __device__ __forceinline__ bool gated(int mode) {
 }
 
 // occupancy targets (waves per SIMD) that bound the register allocation
-template <typename T, int NG> struct WavesG { static constexpr int value = (NG >= 256) ? 2 : 3; };
+template <typename T, int NG> struct WavesG { static constexpr int value = (NG >= LSFFT_G2_MIN) ? 2 : 3; };
 template <int NG> struct WavesG<double, NG> { static constexpr int value = 2; };
 #ifndef LSFFT_WAVES_G
 #define LSFFT_WAVES_G WavesG<T, NG>::value
