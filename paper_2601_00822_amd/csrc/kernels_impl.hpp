@@ -1516,12 +1516,63 @@ __global__ __launch_bounds__(Cfg<T>::NTH_X) __attribute__((amdgpu_waves_per_eu(L
   }
 }
 
-// one component per work unit: unit w covers item w % n_items, component w / n_items
+// Fixed-order FP64 sums of one solve's per-item partials, then the stopping
+// rule, by one block of NTH threads: thread k adds slots k, k + NTH, ...
+// (eight loads issued before their adds), then block_sum.  The order depends
+// on NTH only, so every caller with the same block size gets the same bits.
+template <int NTH>
+__device__ inline void reduce_solve(const InstDesc& D, InstState& St, int mode, double* red) {
+  if (mode != M_INIT && St.status != ST_RUNNING) return;
+  const int nslot = (mode == M_CG_UPD) ? D.items_cg : D.items_g;
+  const bool two = (mode == M_CG_INIT || mode == M_CG_UPD);
+  constexpr int U = 8;
+  double a = 0.0, b = 0.0;
+  for (int k0 = threadIdx.x; k0 < nslot; k0 += NTH * U) {
+    double va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * NTH;
+      va[u] = (k < nslot) ? D.partial[2 * k] : 0.0;
+      vb[u] = (two && k < nslot) ? D.partial[2 * k + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a += va[u];
+      b += vb[u];
+    }
+  }
+  a = block_sum<NTH>(a, red);
+  b = block_sum<NTH>(b, red);
+  // thread 0 applies the rule (the state is read here, not kept across the
+  // barriers above, where it would live in scratch)
+  if (threadIdx.x == 0) {
+    InstState loc = St;
+    finalize(D, loc, mode, a, b);
+    St = loc;
+  }
+}
+
+// one component per work unit: unit w covers item w % n_items, component w / n_items.
+// With red_n set, the blocks first apply the stopping rule of the outer pass
+// that ran before (basic iteration) to the red_inst[0 .. *red_n) solves; the
+// gate below may then see a solve stop while its tiles are being
+// transformed, which is harmless: its returned iterate sits in the other
+// displacement buffer, and its work spectrum is rewritten before any use.
 template <typename T, int NY, int DIR>
 __global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_Y))) void k_ypass(
     const InstDesc* __restrict__ descs, InstState* __restrict__ states, const WorkItem* __restrict__ items,
-    const int* __restrict__ nitems, const T* __restrict__ tw, int which, int ncomp, int gate) {
+    const int* __restrict__ nitems, const T* __restrict__ tw, int which, int ncomp, int gate,
+    const int* __restrict__ red_inst, const int* __restrict__ red_n) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (red_n) {
+    __shared__ double red[Cfg<T>::NTH / 64];
+    const int nr = *red_n;
+    for (int r = blockIdx.x; r < nr; r += gridDim.x) {
+      const int i = red_inst[r];
+      reduce_solve<Cfg<T>::NTH>(descs[i], states[i], M_ITER, red);
+      __syncthreads();
+    }
+  }
   const int n_items = *nitems;
   const int n_units = n_items * ncomp;
   // XCD-aware order when a tile row is narrower than a 128-byte line
@@ -1586,37 +1637,7 @@ __global__ __launch_bounds__(NTR) void k_reduce(const InstDesc* __restrict__ des
   // keeps its grid while solves retire
   if ((int)blockIdx.x >= *ninst) return;
   const int i = inst_list[blockIdx.x];
-  const InstDesc& D = descs[i];
-  InstState& St = states[i];
-  if (mode != M_INIT && St.status != ST_RUNNING) return;
-  const int nslot = (mode == M_CG_UPD) ? D.items_cg : D.items_g;
-  const bool two = (mode == M_CG_INIT || mode == M_CG_UPD);
-  // the solve's state comes in with the partials (thread 0 applies the rule)
-  InstState loc;
-  if (threadIdx.x == 0) loc = St;
-  // eight slots per thread and step, all loads issued before the adds
-  constexpr int U = 8;
-  double a = 0.0, b = 0.0;
-  for (int k0 = threadIdx.x; k0 < nslot; k0 += NTR * U) {
-    double va[U], vb[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = k0 + u * NTR;
-      va[u] = (k < nslot) ? D.partial[2 * k] : 0.0;
-      vb[u] = (two && k < nslot) ? D.partial[2 * k + 1] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      a += va[u];
-      b += vb[u];
-    }
-  }
-  a = block_sum<NTR>(a, red);
-  b = block_sum<NTR>(b, red);
-  if (threadIdx.x == 0) {
-    finalize(D, loc, mode, a, b);
-    St = loc;
-  }
+  reduce_solve<NTR>(descs[i], states[i], mode, red);
 }
 
 // Largest phase id of a phase map (argument validation on the device).

@@ -19,6 +19,10 @@ struct LaunchArgs {
   const double* lame;     // device Lame table, pairs (lambda, mu)
   const void* tw;         // device twiddle table in the plan precision
   hipEvent_t ev0 = nullptr, ev1 = nullptr;   // if set: timestamps of the kernel's own start and end
+  // y pass only: solves whose stopping rule the launch applies first (device
+  // list and device count), or null
+  const int* red_inst = nullptr;
+  const int* red_n = nullptr;
 };
 
 // Launch through LaunchArgs `a`: with timing events the runtime stamps them

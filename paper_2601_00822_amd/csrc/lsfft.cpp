@@ -713,13 +713,24 @@ hipError_t pass_x(Batch& b, int list, int mode, int cls) {
   }
   return hipSuccess;
 }
-hipError_t pass_y(Batch& b, int list, int dir, int which, int ncomp, int gate, int cls) {
+hipError_t pass_reduce(Batch& b, int mode);
+// With `reduce`, the first launch also applies the stopping rule of the
+// outer pass before it to every running solve (in place of k_reduce).
+hipError_t pass_y(Batch& b, int list, int dir, int which, int ncomp, int gate, int cls, bool reduce = false) {
   for (const Seg& sg : b.segs[list]) {
     if (sg.count == 0) continue;
     const int t = timed_begin(b.p, cls);
-    hipError_t e = launch_ypass(b.p->f64, timed(b.p, largs(b, list, sg, ncomp), t), dir, which, ncomp, gate, sg.len);
+    LaunchArgs a = largs(b, list, sg, ncomp);
+    if (reduce) {
+      a.red_inst = b.d_inst;
+      a.red_n = b.d_counts + kMaxSegs - 1;
+      reduce = false;
+    }
+    hipError_t e = launch_ypass(b.p->f64, timed(b.p, a, t), dir, which, ncomp, gate, sg.len);
     if (e != hipSuccess) return e;
   }
+  // no y launch (2D grids only): the rule runs on its own
+  if (reduce) return pass_reduce(b, M_ITER);
   return hipSuccess;
 }
 hipError_t pass_g(Batch& b, int list, int mode, int cls) {
@@ -807,16 +818,26 @@ lsfft_status iterate(Batch& b, int max_rounds = 0, std::vector<int>* running_out
     LSFFT_TRY(pass_reduce(b, M_CG_INIT));
   }
   const int per_round = max_rounds > 0 ? 1 : p->poll;
+  // Inside a round of the basic FP32 scheme the stopping rule of iteration k
+  // runs at the start of iteration k + 1's first y pass (same block size and
+  // summation order as k_reduce, so the same bits); the round's last
+  // iteration keeps k_reduce, since the host reads the states after it.
+  // Timed plans keep k_reduce throughout, so that each pass class is timed
+  // on its own.
+  const bool fuse = !cg && !p->f64 && !timing;
   // one polling round: `per_round` iterations of every running solve
   auto round = [&]() -> hipError_t {
+    bool pending = false;
     for (int k = 0; k < per_round; ++k) {
       hipError_t e;
-      if ((e = pass_y(b, L_Y, +1, 0, 6, 1, LSFFT_K_YPASS)) != hipSuccess) return e;
+      if ((e = pass_y(b, L_Y, +1, 0, 6, 1, LSFFT_K_YPASS, pending)) != hipSuccess) return e;
+      pending = false;
       if ((e = pass_x(b, L_X, M_ITER, LSFFT_K_XPASS)) != hipSuccess) return e;
       if ((e = pass_y(b, L_Y, -1, 0, 6, 1, LSFFT_K_YPASS)) != hipSuccess) return e;
       if (!cg) {
         if ((e = pass_g(b, L_G, M_ITER, LSFFT_K_GREEN)) != hipSuccess) return e;
-        if ((e = pass_reduce(b, M_ITER)) != hipSuccess) return e;
+        if (fuse && k + 1 < per_round) pending = true;
+        else if ((e = pass_reduce(b, M_ITER)) != hipSuccess) return e;
       } else {
         if ((e = pass_g(b, L_G, M_CG_AP, LSFFT_K_GREEN)) != hipSuccess) return e;
         if ((e = pass_reduce(b, M_CG_AP)) != hipSuccess) return e;
