@@ -288,6 +288,41 @@ def test_batch_mixed_grids(torch_dev):
     plan2.close()
 
 
+def test_fp32_batch_mixed_dims_rule_in_y_pass(torch_dev):
+    """FP32 batch of 3D and 2D solves with different iteration counts: inside
+    a captured round the stopping rule runs in the next y pass (the 2D solves
+    have no y tiles), in a timed plan it runs in its own kernel.  Both give
+    the same iterates bit for bit, and every solve stopped at residual 1e-6
+    is within 1e-4 of its converged oracle solution."""
+    say("FP32 batch 3D + 2D, stopping rule in the y pass vs on its own")
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import Plan
+    shapes = [(16, 16, 16), (32, 32), (8, 16, 12), (24, 24)]
+    probs, refs = [], []
+    for g, shp in enumerate(shapes):
+        for k in range(2):
+            ph = rand_phase(shp, 300 + 10 * g + k)
+            f = rand_force(shp, 400 + 10 * g + k)
+            lame = O.lame_from_young(gen.Material.two_phase(1.0, 2.0 + 20 * k + 3 * g).table())
+            probs.append(dict(grid=g, phase=torch.from_numpy(ph).to(dev), lame=lame,
+                              f=torch.from_numpy(f).to(dev).float()))
+            refs.append(O.solve_basic(ph, lame, f, tol=1e-9))
+    res = []
+    for timing in (False, True):
+        plan = Plan(shapes, prec="f32", max_batch=8, timing=timing)
+        outs, reps, _ = plan.solve_batch(probs, tol=1e-6)
+        torch.cuda.synchronize()
+        res.append(([o["eps"].cpu() for o in outs], [r.iters for r in reps]))
+        plan.close()
+    assert len(set(res[0][1])) > 1          # the solves stop at different iterations
+    assert res[0][1] == res[1][1]
+    for a, b in zip(res[0][0], res[1][0]):
+        assert torch.equal(a, b)
+    # residual 1e-6 against the converged oracle solution, contrast <= 31
+    for e, ref in zip(res[0][0], refs):
+        assert O.relative_strain_error_voigt(e.double().numpy(), O.to_voigt(ref.eps)) < 1e-4
+
+
 # ---------------------------------------------------------------- translated averaging
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
