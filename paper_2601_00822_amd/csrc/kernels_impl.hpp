@@ -130,9 +130,12 @@ __device__ __forceinline__ void gst(void* base, long long i, V v) {
 // no index passed here exceeds the nine components of a work buffer), so
 // the access is a uniform 64-bit base plus an unsigned 32-bit lane offset:
 // one VGPR per address instead of a 64-bit lane address.
+// FP64 keeps a sign-extended 64-bit index: with the 32-bit offset the FP64
+// register-staged x pass spills (92 bytes per lane instead of 16).
 template <typename T>
 __device__ __forceinline__ typename C2<T>::type ldc(const void* base, unsigned i) {
   using V = typename C2<T>::type;
+  if constexpr (sizeof(T) == 8) return gld<V>(base, (long long)(int)i);
   const unsigned off = i * (unsigned)sizeof(V);
   return *reinterpret_cast<const LSFFT_GLOBAL V*>((const LSFFT_GLOBAL char*)base + off);
 }
@@ -142,6 +145,10 @@ __device__ __forceinline__ void stc(void* base, unsigned i, T re, T im) {
   V v;
   v.x = re;
   v.y = im;
+  if constexpr (sizeof(T) == 8) {
+    gst<V>(base, (long long)(int)i, v);
+    return;
+  }
   const unsigned off = i * (unsigned)sizeof(V);
   *reinterpret_cast<LSFFT_GLOBAL V*>((LSFFT_GLOBAL char*)base + off) = v;
 }
