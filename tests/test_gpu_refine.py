@@ -89,6 +89,26 @@ def test_refined_high_contrast_3d(torch_dev, scheme, kappa):
     assert eu < 1e-6 and es < 1e-5
 
 
+@pytest.mark.parametrize("kappa", [100.0, 0.01])
+def test_fp32_cg_alone_reaches_tol(torch_dev, kappa):
+    """FP32 CG without the FP64 correction at high contrast: the packed half
+    spectrum keeps the kx = 0 and kx = nx/2 planes real, and the iteration
+    reaches 1e-8 with the strain within FP32 reach of the solution."""
+    say(f"FP32 CG alone 3D 32^3 RSA kappa={kappa}")
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import Plan
+    shape, phase, f, lame, ref = high_contrast_case(kappa)
+    plan = Plan([shape], prec="f32", scheme="cg")
+    o, r = plan.solve(torch.from_numpy(np.ascontiguousarray(phase)).to(dev), lame,
+                      torch.from_numpy(np.ascontiguousarray(f)).to(dev).float(), tol=1e-8, max_iter=5000)
+    eps = o["eps"].double().cpu().numpy()
+    plan.close()
+    err = O.relative_strain_error_voigt(eps, O.to_voigt(ref.eps))
+    print(f"iters={r.iters} residual={r.residual:.3e} status={r.status} strain error {err:.3e}")
+    assert r.status == 0 and r.residual <= 1e-8
+    assert err < 5e-6
+
+
 def test_refined_config1_2d(torch_dev):
     say("FP32+FP64 refinement, 64x64 plane strain, one disk per cell")
     shape = (64, 64)
