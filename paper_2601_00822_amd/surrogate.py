@@ -14,8 +14,8 @@ by block means.
 
 Training and inference run entirely in the surrogate kernels (bf16 MFMA,
 fp32 accumulation, Adam); this module only moves batches and schedules the
-learning rate.  The solver stays the judge (held-out targets) and the
-fallback (``averaged_strain``).
+learning rate.  The solver supplies the held-out targets the surrogate is
+measured against, and stays the fallback (``averaged_strain``).
 """
 from __future__ import annotations
 
