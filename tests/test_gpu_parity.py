@@ -151,6 +151,49 @@ def test_2d_fp64_shapes(torch_dev, shape):
     check_iterates(torch_dev, shape, phase, LAME10, f, js=[1, 3])
 
 
+def plane_force(shape, seed, nyquist_only=False):
+    """Force with content in the x planes kx = 0 and kx = nx/2 only, each with
+    its own random (y, z) profile: f = a(y, z) + (-1)^x b(y, z)."""
+    rng = np.random.default_rng(seed)
+    d = len(shape)
+    rest = shape[:-1]
+    nx = shape[-1]
+    sign = (-1.0) ** np.arange(nx)
+    a = rng.normal(size=(d,) + rest + (1,))
+    b = rng.normal(size=(d,) + rest + (1,))
+    f = b * sign
+    if not nyquist_only:
+        f = f + a
+    return np.broadcast_to(f, (d,) + tuple(shape)).copy()
+
+
+@pytest.mark.parametrize("shape,nyq", [((8, 12, 16), False), ((6, 8, 32), True), ((24, 32), False), ((12, 16), True)])
+def test_fp64_x_zero_and_nyquist_planes(torch_dev, shape, nyq):
+    """The x planes kx = 0 and kx = nx/2 share one packed column on the GPU;
+    a force living on those planes only (or on the Nyquist plane alone) is
+    solved iterate for iterate like the oracle, which keeps the planes apart."""
+    say(f"FP64 force on the kx = 0 / nx/2 planes {shape} nyquist_only={nyq}")
+    phase = rand_phase(shape, 21)
+    f = plane_force(shape, 22, nyq)
+    check_iterates(torch_dev, shape, phase, LAME10, f, js=[0, 1, 3])
+
+
+@pytest.mark.parametrize("shape", [(4, 8, 128), (8, 64), (4, 8, 256)])
+def test_fp32_staged_x_zero_and_nyquist_planes(torch_dev, shape):
+    """The staged FP32 x pass unpacks the kx = 0 / nx/2 entry by value (no
+    address select): a force on those planes converges to the oracle's
+    solution within the FP32 bar."""
+    say(f"FP32 staged x tiles, force on the kx = 0 / nx/2 planes {shape}")
+    phase = rand_phase(shape, 23)
+    f = plane_force(shape, 24)
+    ref = O.solve_basic(phase, LAME10, f, tol=1e-8)
+    res, rep = gpu_solve(torch_dev, shape, phase, LAME10, f, prec="f32", tol=1e-6)
+    err = O.relative_strain_error_voigt(res["eps"], O.to_voigt(ref.eps))
+    print(f"iters={rep.iters} residual={rep.residual:.3e} err={err:.3e}")
+    assert rep.status in (0, 1)
+    assert err < 1e-5
+
+
 def test_cg_iterates(torch_dev):
     say("CG 2D 32x32 and 3D 12x16x16 FP64")
     for shape in [(32, 32), (12, 16, 16)]:
