@@ -64,7 +64,14 @@ hipError_t launch_cg_update(bool f64, const LaunchArgs& a) {
 
 hipError_t launch_reduce(const LaunchArgs& a, const int* inst_list, const int* d_ninst, int ninst, int mode) {
   if (ninst <= 0) return hipSuccess;
-  LSFFT_LAUNCH(k_reduce, dim3(ninst), NTR, 0, a.stream, a.desc, a.state, inst_list, d_ninst, mode);
+  // the block size of the plan's y pass (a.block): the same summation order
+  // as the stopping rule run inside that pass
+  if (a.block == Cfg<double>::NTH)
+    LSFFT_LAUNCH(k_reduce<Cfg<double>::NTH>, dim3(ninst), Cfg<double>::NTH, 0, a.stream, a.desc, a.state, inst_list,
+                 d_ninst, mode);
+  else
+    LSFFT_LAUNCH(k_reduce<Cfg<float>::NTH>, dim3(ninst), Cfg<float>::NTH, 0, a.stream, a.desc, a.state, inst_list,
+                 d_ninst, mode);
   return hipGetLastError();
 }
 

@@ -1563,8 +1563,9 @@ __device__ inline void reduce_solve(const InstDesc& D, InstState& St, int mode, 
 // With red_n set, the blocks first apply the stopping rule of the outer pass
 // that ran before (basic iteration) to the red_inst[0 .. *red_n) solves; the
 // gate below may then see a solve stop while its tiles are being
-// transformed, which is harmless: its returned iterate sits in the other
-// displacement buffer, and its work spectrum is rewritten before any use.
+// transformed, which is harmless (its returned iterate sits in the other
+// displacement buffer, and its work spectrum is rewritten before any use)
+// as long as each block takes one decision per unit.
 template <typename T, int NY, int DIR>
 __global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_Y))) void k_ypass(
     const InstDesc* __restrict__ descs, InstState* __restrict__ states, const WorkItem* __restrict__ items,
@@ -1586,11 +1587,26 @@ __global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSF
   // (neighbouring tiles then share lines: 8 kx columns of FP32 at ny = 256);
   // with full lines the launch order is kept
   constexpr bool kXcd = SGeom<T, NY>::MP * 2 * (int)sizeof(T) < 128;
+  __shared__ int s_run;
   for (int w = kXcd ? xcd_slot(blockIdx.x, gridDim.x) : (int)blockIdx.x; w < n_units; w += gridDim.x) {
     const int c = w / n_items;
     const WorkItem it = items[w - c * n_items];
     const InstDesc& D = descs[it.inst];
-    if (gate && states[it.inst].status != ST_RUNNING) continue;
+    if (gate) {
+      if (red_n) {
+        // the prologue of another block may change this solve's status
+        // while the block reads it: one read, shared, so that the whole
+        // block transforms the unit or skips it (the transform's barriers
+        // need every wave)
+        if (threadIdx.x == 0) s_run = (states[it.inst].status == ST_RUNNING);
+        __syncthreads();
+        const bool go = s_run != 0;
+        __syncthreads();   // read by every wave before the next unit rewrites it
+        if (!go) continue;
+      } else if (states[it.inst].status != ST_RUNNING) {
+        continue;
+      }
+    }
     void* buf = (which == 0) ? D.S : D.F;
     ypass_item<T, NY, DIR>(D, it.local, c, buf, tw, smem);
     __syncthreads();
@@ -1635,16 +1651,18 @@ __global__ __launch_bounds__(Cfg<T>::NTH) void k_cg_update(const InstDesc* __res
 constexpr int NTR = 256;   // reduction, validation and averaging kernels
 
 // One block per solve: fixed-order FP64 sums of the per-item partials, then
-// the stopping rule.
-__global__ __launch_bounds__(NTR) void k_reduce(const InstDesc* __restrict__ descs, InstState* __restrict__ states,
+// the stopping rule.  NTH is the y-pass block size of the plan's precision,
+// so that the same sums run as that pass's prologue with the same bits.
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_reduce(const InstDesc* __restrict__ descs, InstState* __restrict__ states,
                                                 const int* __restrict__ inst_list, const int* __restrict__ ninst,
                                                 int mode) {
-  __shared__ double red[NTR / 64];
+  __shared__ double red[NTH / 64];
   // the number of listed solves is read on the device: a captured launch
   // keeps its grid while solves retire
   if ((int)blockIdx.x >= *ninst) return;
   const int i = inst_list[blockIdx.x];
-  reduce_solve<NTR>(descs[i], states[i], mode, red);
+  reduce_solve<NTH>(descs[i], states[i], mode, red);
 }
 
 // Largest phase id of a phase map (argument validation on the device).

@@ -818,13 +818,13 @@ lsfft_status iterate(Batch& b, int max_rounds = 0, std::vector<int>* running_out
     LSFFT_TRY(pass_reduce(b, M_CG_INIT));
   }
   const int per_round = max_rounds > 0 ? 1 : p->poll;
-  // Inside a round of the basic FP32 scheme the stopping rule of iteration k
-  // runs at the start of iteration k + 1's first y pass (same block size and
+  // Inside a round of the basic scheme the stopping rule of iteration k runs
+  // at the start of iteration k + 1's first y pass (same block size and
   // summation order as k_reduce, so the same bits); the round's last
   // iteration keeps k_reduce, since the host reads the states after it.
   // Timed plans keep k_reduce throughout, so that each pass class is timed
   // on its own.
-  const bool fuse = !cg && !p->f64 && !timing;
+  const bool fuse = !cg && !timing;
   // one polling round: `per_round` iterations of every running solve
   auto round = [&]() -> hipError_t {
     bool pending = false;

@@ -331,13 +331,14 @@ def test_batch_mixed_grids(torch_dev):
     plan2.close()
 
 
-def test_fp32_batch_mixed_dims_rule_in_y_pass(torch_dev):
-    """FP32 batch of 3D and 2D solves with different iteration counts: inside
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_mixed_dims_rule_in_y_pass(torch_dev, prec):
+    """Batch of 3D and 2D solves with different iteration counts: inside
     a captured round the stopping rule runs in the next y pass (the 2D solves
     have no y tiles), in a timed plan it runs in its own kernel.  Both give
     the same iterates bit for bit, and every solve stopped at residual 1e-6
     is within 1e-4 of its converged oracle solution."""
-    say("FP32 batch 3D + 2D, stopping rule in the y pass vs on its own")
+    say(f"{prec} batch 3D + 2D, stopping rule in the y pass vs on its own")
     torch, dev = torch_dev
     from paper_2601_00822_amd import Plan
     shapes = [(16, 16, 16), (32, 32), (8, 16, 12), (24, 24)]
@@ -347,12 +348,13 @@ def test_fp32_batch_mixed_dims_rule_in_y_pass(torch_dev):
             ph = rand_phase(shp, 300 + 10 * g + k)
             f = rand_force(shp, 400 + 10 * g + k)
             lame = O.lame_from_young(gen.Material.two_phase(1.0, 2.0 + 20 * k + 3 * g).table())
+            ft = torch.from_numpy(f).to(dev)
             probs.append(dict(grid=g, phase=torch.from_numpy(ph).to(dev), lame=lame,
-                              f=torch.from_numpy(f).to(dev).float()))
+                              f=ft if prec == "f64" else ft.float()))
             refs.append(O.solve_basic(ph, lame, f, tol=1e-9))
     res = []
     for timing in (False, True):
-        plan = Plan(shapes, prec="f32", max_batch=8, timing=timing)
+        plan = Plan(shapes, prec=prec, max_batch=8, timing=timing)
         outs, reps, _ = plan.solve_batch(probs, tol=1e-6)
         torch.cuda.synchronize()
         res.append(([o["eps"].cpu() for o in outs], [r.iters for r in reps]))
@@ -364,6 +366,34 @@ def test_fp32_batch_mixed_dims_rule_in_y_pass(torch_dev):
     # residual 1e-6 against the converged oracle solution, contrast <= 31
     for e, ref in zip(res[0][0], refs):
         assert O.relative_strain_error_voigt(e.double().numpy(), O.to_voigt(ref.eps)) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_many_solves_stopping_together(torch_dev, prec):
+    """256 shifted solves of a point force, most of them stopping within a few
+    iterations of each other inside one captured round: the stopping rule in
+    the y pass must leave every running solve intact (each workgroup takes one
+    gate decision per unit).  Captured and timed plans agree bit for bit."""
+    say(f"{prec}: 256 solves stopping together, captured vs timed plan")
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import Plan
+    n, cell = 32, 8
+    phase = torch.from_numpy(gen.tile_cell(gen.rsa_cell(cell, 3, 0.2, 1.5, 2.5, seed=4)[0], (n, n, n))).to(dev)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    tol = 1e-10 if prec == "f64" else 1e-4
+    f = torch.zeros((3, n, n, n), dtype=dt, device=dev)
+    f[0, 0, 0, 0] = 1.0
+    shifts = gen.sample_shifts(cell, 3, 256, 5)
+    res = []
+    for timing in (False, True):
+        plan = Plan([(n, n, n)], prec=prec, max_batch=256, timing=timing)
+        avg, reps = plan.translate_average(phase, LAME10, f, shifts, tol=tol)
+        torch.cuda.synchronize()
+        res.append((avg.cpu(), [(r.status, r.iters) for r in reps]))
+        plan.close()
+    assert all(st == 0 for st, _ in res[0][1]), [x for x in res[0][1] if x[0] != 0][:5]
+    assert res[0][1] == res[1][1]
+    assert torch.equal(res[0][0], res[1][0])
 
 
 # ---------------------------------------------------------------- translated averaging
