@@ -128,3 +128,46 @@ def test_adam_first_step_is_signed_lr():
     F.adam_step(p, g, st, lr=0.1, step=1, eps=0.0)
     np.testing.assert_allclose(p["w"], [0.9, -1.9, 2.9], atol=1e-15)
     np.testing.assert_allclose(p["r0"], [1.1 + 0.9j], atol=1e-15)
+
+
+def test_adam_steps_two_and_three_by_hand():
+    """Three Adam steps on one real and one complex parameter with
+    beta1 = 1/2, beta2 = 3/4, eps = 0, lr = 1 and gradients 2, 4, -1 (the
+    complex one carries -1, -2, 1/2 on its imaginary part), worked out by
+    hand from the bias-corrected moments:
+      step 1: m = 1,   v = 1,     m^ = 2,    v^ = 4       -> step 1
+      step 2: m = 5/2, v = 19/4,  m^ = 10/3, v^ = 76/7    -> step (10/3)/sqrt(76/7)
+      step 3: m = 3/4, v = 61/16, m^ = 6/7,  v^ = 244/37  -> step (6/7)/sqrt(244/37)
+    With the two betas swapped the moments differ from step 2 on, so the
+    test fails for a swap (as it does for a wrong bias correction)."""
+    g_real = [2.0, 4.0, -1.0]
+    p = {"w": np.array([10.0]), "r0": np.array([10.0 + 10.0j])}
+    st = {}
+    for k, g in enumerate(g_real, start=1):
+        grads = {"w": np.array([g]), "r0": np.array([g - 0.5j * g])}
+        F.adam_step(p, grads, st, lr=1.0, step=k, beta1=0.5, beta2=0.75, eps=0.0)
+    expect = 10.0 - 1.0 - (10.0 / 3.0) / np.sqrt(76.0 / 7.0) - (6.0 / 7.0) / np.sqrt(244.0 / 37.0)
+    # the imaginary part sees the gradients scaled by -1/2: m^ scales by -1/2
+    # and sqrt(v^) by 1/2, so every step has the opposite sign
+    expect_im = 10.0 + 1.0 + (10.0 / 3.0) / np.sqrt(76.0 / 7.0) + (6.0 / 7.0) / np.sqrt(244.0 / 37.0)
+    np.testing.assert_allclose(p["w"], [expect], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(p["r0"].real, [expect], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(p["r0"].imag, [expect_im], rtol=0, atol=1e-13)
+    # defaults (0.9, 0.999), step 2 of gradients 2, 4: m^ = 58/19, v^ = 19996/1999
+    p2 = {"w": np.array([0.0])}
+    st2 = {}
+    F.adam_step(p2, {"w": np.array([2.0])}, st2, lr=1.0, step=1, eps=0.0)
+    F.adam_step(p2, {"w": np.array([4.0])}, st2, lr=1.0, step=2, eps=0.0)
+    np.testing.assert_allclose(p2["w"], [-1.0 - (58.0 / 19.0) / np.sqrt(19996.0 / 1999.0)], rtol=0, atol=1e-13)
+
+
+def test_loss_value_by_hand():
+    """Mean relative L2 loss of a two-sample batch worked out by hand:
+    sample 1: target (1, 0, 0, 0), prediction (1, 0, 3, 4): |d| = 5, |t| = 1;
+    sample 2: target (0, 2, 0, 0), prediction (0, 2, 0, 1): |d| = 1, |t| = 2;
+    loss = (5 + 1/2) / 2 = 2.75, gradient d / (|d| |t|) / B."""
+    t = np.array([[1.0, 0.0, 0.0, 0.0], [0.0, 2.0, 0.0, 0.0]]).reshape(2, 1, 4)
+    y = np.array([[1.0, 0.0, 3.0, 4.0], [0.0, 2.0, 0.0, 1.0]]).reshape(2, 1, 4)
+    loss, g = F.loss_and_grad_y(y, t)
+    assert loss == 2.75
+    np.testing.assert_allclose(g.reshape(2, 4), [[0.0, 0.0, 0.3, 0.4], [0.0, 0.0, 0.0, 0.25]], rtol=0, atol=1e-15)
