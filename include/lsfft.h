@@ -250,6 +250,25 @@ lsfft_status lsfft_rve_identify(lsfft_plan_t p, int grid_idx, const double* avg,
                                 double support_radius, double tol, double dr, double* profile, int max_bins,
                                 lsfft_rve* out);
 
+/*
+ * lsfft_rve_identify_noalloc -- lsfft_rve_identify for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * lsfft_rve_identify; it allocates nothing: the radial maxima live in a fixed
+ * device array inside the library (one per GPU, 2 x 1024 64-bit words =
+ * 16 KiB, held until the process ends), cleared by a fill kernel at the start
+ * of every call and read back into a stack buffer.
+ * Limits: at most 1024 bins (LSFFT_E_ARG beyond, as for lsfft_rve_identify).
+ * Every call on one GPU shares that GPU's array, so calls that overlap on
+ * one GPU (from several threads or plans) race; serialise them.
+ * LSFFT_E_DEVICE if the array's address could not be looked up on the plan's
+ * device when the plan was made.  The call still synchronises the plan's
+ * stream to return its results.
+ */
+lsfft_status lsfft_rve_identify_noalloc(lsfft_plan_t p, int grid_idx, const double* avg, const double* center,
+                                        double support_radius, double tol, double dr, double* profile,
+                                        int max_bins, lsfft_rve* out);
+
 /* Release the plan and its workspace.  NULL is accepted. */
 lsfft_status lsfft_plan_destroy(lsfft_plan_t p);
 

@@ -4,6 +4,8 @@
 #include "kernels_impl.hpp"
 #include "launch.hpp"
 
+#include <mutex>
+
 namespace lsfft {
 
 template <typename T>
@@ -110,6 +112,56 @@ hipError_t launch_radial_max(int dim, const double* avg, const int n[3], const d
   else
     hipLaunchKernelGGL((k_radial_max<2>), dim3((unsigned)blocks), NTR, 0, st, avg, n[0], n[1], 1, h[0], h[1], 1.0,
                        c[0], c[1], 0.0, dr, nbins, bins);
+  return hipGetLastError();
+}
+
+// ---- fixed device scratch of the allocation-free RVE entry point ----------
+// The radial maxima of lsfft_rve_identify_noalloc live in this array (one
+// copy per GPU, held until the process ends).  Host code never passes the
+// array's name to a kernel: it stands for a host-side shadow, not a device
+// address.  Each device's address is looked up once, with that device
+// current, and kept in rve_scratch_dev.
+static_assert(kRveMaxBins == kRveBinsMax, "radial-maxima bin limits must agree");
+static __device__ __align__(256) unsigned long long rve_scratch[kRveScratchWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex rve_scratch_mu;
+int rve_scratch_state[kMaxDevices] = {0};                  // 0 untried, 1 ready, -1 failed
+unsigned long long* rve_scratch_dev[kMaxDevices] = {nullptr};
+}  // namespace
+
+hipError_t rve_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(rve_scratch_mu);
+  if (rve_scratch_state[device] == 1) return hipSuccess;
+  if (rve_scratch_state[device] == -1) return hipErrorInvalidDevice;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+  void* ptr = nullptr;
+  if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(rve_scratch));
+  if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess || ptr == nullptr) {
+    rve_scratch_state[device] = -1;
+    return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  }
+  rve_scratch_dev[device] = static_cast<unsigned long long*>(ptr);
+  rve_scratch_state[device] = 1;
+  return hipSuccess;
+}
+
+unsigned long long* rve_scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(rve_scratch_mu);
+  return rve_scratch_state[device] == 1 ? rve_scratch_dev[device] : nullptr;
+}
+
+hipError_t launch_zero_u64(unsigned long long* a, long long n, hipStream_t st) {
+  long long blocks = (n + NTR - 1) / NTR;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), NTR, 0, st, a, n);
   return hipGetLastError();
 }
 

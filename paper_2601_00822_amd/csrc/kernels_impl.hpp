@@ -1737,6 +1737,12 @@ __global__ __launch_bounds__(NTR) void k_accumulate(const InstDesc* __restrict__
   }
 }
 
+// a fill kernel instead of a memset: callers of the allocation-free entry
+// points may capture their work in a graph
+__global__ __launch_bounds__(NTR) void k_zero_u64(unsigned long long* __restrict__ a, long long n) {
+  for (long long i = (long long)blockIdx.x * NTR + threadIdx.x; i < n; i += (long long)gridDim.x * NTR) a[i] = 0ull;
+}
+
 __global__ __launch_bounds__(NTR) void k_scale(double* __restrict__ a, long long n, double s) {
   for (long long i = (long long)blockIdx.x * NTR + threadIdx.x; i < n; i += (long long)gridDim.x * NTR) a[i] *= s;
 }

@@ -68,6 +68,14 @@ hipError_t launch_scale(double* a, long long n, double s, hipStream_t st);
 constexpr int kRveBinsMax = 1024;   // bins of launch_radial_max
 hipError_t launch_radial_max(int dim, const double* avg, const int n[3], const double h[3], const double c[3],
                              double dr, int nbins, unsigned long long* bins, hipStream_t st);
+// Fixed device scratch of the allocation-free RVE entry point: two rows of
+// kRveBinsMax bin maxima.  rve_scratch_init looks up the calling process's
+// copy on `device` (once per device; the plan constructor calls it);
+// rve_scratch_ptr returns it, or null if the lookup failed or never ran.
+constexpr int kRveScratchWords = 2 * kRveBinsMax;
+hipError_t rve_scratch_init(int device);
+unsigned long long* rve_scratch_ptr(int device);
+hipError_t launch_zero_u64(unsigned long long* a, long long n, hipStream_t st);
 
 // mixed-precision defect correction; `inst` lists `count` solves, `max_pc`
 // is the largest half spectrum among them

@@ -1335,6 +1335,9 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
     delete p;
     return LSFFT_E_DEVICE;
   }
+  // address of this device's copy of the fixed RVE scratch (once per
+  // device); a failed lookup only disables lsfft_rve_identify_noalloc
+  (void)rve_scratch_init(dev);
   if (std::getenv("LSFFT_NO_GRAPH")) p->graphs = false;
   p->f64 = (prec == LSFFT_F64);
   p->scheme = static_cast<lsfft_scheme>(scheme);
@@ -1518,66 +1521,123 @@ lsfft_status lsfft_realization_average(lsfft_plan_t p, int grid_idx, int nreal, 
                       max_iter, rep);
 }
 
-lsfft_status lsfft_rve_identify(lsfft_plan_t p, int grid_idx, const double* avg, const double* center,
-                                double support_radius, double tol, double dr, double* profile, int max_bins,
-                                lsfft_rve* out) {
+}  // extern "C"
+
+namespace {
+
+// Arguments of an RVE identification, checked and resolved on the host.
+struct RveArgs {
+  int d = 0;
+  int n[3] = {1, 1, 1};
+  double h[3] = {1.0, 1.0, 1.0};
+  double c[3] = {0.0, 0.0, 0.0};
+  double box = 0.0;
+  int nbins = 0;
+};
+
+lsfft_status rve_args(lsfft_plan_t p, int grid_idx, const double* avg, const double* center, double support_radius,
+                      double tol, double dr, lsfft_rve* out, RveArgs* a) {
   if (check_plan(p) != LSFFT_OK || !avg || !center || !out) return LSFFT_E_ARG;
   if (grid_idx < 0 || grid_idx >= (int)p->grids.size()) return LSFFT_E_ARG;
   if (!is_fin(tol) || tol <= 0.0 || tol >= 1.0 || !is_fin(dr) || dr <= 0.0) return LSFFT_E_ARG;
   if (!is_fin(support_radius) || support_radius < 0.0) return LSFFT_E_ARG;
   const lsfft_grid& g = p->grids[grid_idx];
-  const int d = g.dim;
-  int n[3] = {(int)g.n[0], (int)g.n[1], d == 3 ? (int)g.n[2] : 1};
-  double h[3] = {g.h[0], g.h[1], d == 3 ? g.h[2] : 1.0};
-  double c[3] = {0.0, 0.0, 0.0};
+  a->d = g.dim;
   double rmax2 = 0.0, box = 1e300;
-  for (int a = 0; a < d; ++a) {
-    if (!is_fin(center[a])) return LSFFT_E_ARG;
-    c[a] = center[a];
-    const double half = 0.5 * n[a] * h[a];
+  for (int k = 0; k < a->d; ++k) {
+    if (!is_fin(center[k])) return LSFFT_E_ARG;
+    a->n[k] = (int)g.n[k];
+    a->h[k] = g.h[k];
+    a->c[k] = center[k];
+    const double half = 0.5 * a->n[k] * a->h[k];
     rmax2 += half * half;
     box = std::min(box, half);
   }
-  const int nbins = (int)std::floor(std::sqrt(rmax2) / dr) + 1;
-  if (nbins > kRveBinsMax) return LSFFT_E_ARG;
-  if (!p->rve.ensure(sizeof(unsigned long long) * 2 * (size_t)nbins)) return LSFFT_E_ALLOC;
-  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
-  auto* bins = static_cast<unsigned long long*>(p->rve.p);
-  std::vector<unsigned long long> hb(2 * (size_t)nbins);
-  if (hipMemsetAsync(bins, 0, sizeof(unsigned long long) * hb.size(), p->stream) != hipSuccess) return LSFFT_E_DEVICE;
-  if (launch_radial_max(d, avg, n, h, c, dr, nbins, bins, p->stream) != hipSuccess) return LSFFT_E_DEVICE;
-  if (hipMemcpyAsync(hb.data(), bins, sizeof(unsigned long long) * hb.size(), hipMemcpyDeviceToHost, p->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(p->stream) != hipSuccess)
-    return LSFFT_E_DEVICE;
-  std::vector<double> me(nbins), ms(nbins);
+  a->box = box;
+  // the bin count is checked in floating point before the conversion
+  const double nb = std::floor(std::sqrt(rmax2) / dr) + 1.0;
+  if (!(nb <= (double)kRveBinsMax)) return LSFFT_E_ARG;
+  a->nbins = (int)nb;
+  return LSFFT_OK;
+}
+
+// Radius, fit flag and profile from the bin maxima `hb` (two rows of nbins
+// bit patterns of non-negative doubles), Definition 2.2: the smallest bin
+// edge beyond which both magnitudes stay below tol times their maxima.
+void rve_finish(const unsigned long long* hb, const RveArgs& a, double support_radius, double tol, double dr,
+                double* profile, int max_bins, lsfft_rve* out) {
+  const int nbins = a.nbins;
+  auto me = [&](int b) { double v; std::memcpy(&v, &hb[b], sizeof(double)); return v; };
+  auto ms = [&](int b) { double v; std::memcpy(&v, &hb[nbins + b], sizeof(double)); return v; };
   double ge = 0.0, gs = 0.0;
   for (int b = 0; b < nbins; ++b) {
-    std::memcpy(&me[b], &hb[b], sizeof(double));
-    std::memcpy(&ms[b], &hb[nbins + b], sizeof(double));
-    ge = std::max(ge, me[b]);
-    gs = std::max(gs, ms[b]);
+    ge = std::max(ge, me(b));
+    gs = std::max(gs, ms(b));
   }
-  // smallest bin edge beyond which both magnitudes stay below tol times
-  // their maxima (Definition 2.2)
   int first = nbins;   // +inf when the outermost bin is still above tol
   for (int b = nbins - 1; b >= 0; --b) {
-    if (me[b] < tol * ge && ms[b] < tol * gs) first = b;
+    if (me(b) < tol * ge && ms(b) < tol * gs) first = b;
     else break;
   }
   if (ge == 0.0 && gs == 0.0) first = 0;
   out->radius = (first < nbins) ? first * dr : HUGE_VAL;
-  out->box_radius = box;
-  out->fits = (first < nbins && out->radius + 0.5 * support_radius <= box) ? 1 : 0;
+  out->box_radius = a.box;
+  out->fits = (first < nbins && out->radius + 0.5 * support_radius <= a.box) ? 1 : 0;
   out->nbins = nbins;
   out->max_eps = ge;
   out->max_sig = gs;
   if (profile && max_bins >= nbins) {
     for (int b = 0; b < nbins; ++b) {
-      profile[b] = me[b];
-      profile[max_bins + b] = ms[b];
+      profile[b] = me(b);
+      profile[max_bins + b] = ms(b);
     }
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+lsfft_status lsfft_rve_identify(lsfft_plan_t p, int grid_idx, const double* avg, const double* center,
+                                double support_radius, double tol, double dr, double* profile, int max_bins,
+                                lsfft_rve* out) {
+  RveArgs a;
+  lsfft_status ls = rve_args(p, grid_idx, avg, center, support_radius, tol, dr, out, &a);
+  if (ls != LSFFT_OK) return ls;
+  const int nbins = a.nbins;
+  if (!p->rve.ensure(sizeof(unsigned long long) * 2 * (size_t)nbins)) return LSFFT_E_ALLOC;
+  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  auto* bins = static_cast<unsigned long long*>(p->rve.p);
+  std::vector<unsigned long long> hb(2 * (size_t)nbins);
+  if (hipMemsetAsync(bins, 0, sizeof(unsigned long long) * hb.size(), p->stream) != hipSuccess) return LSFFT_E_DEVICE;
+  if (launch_radial_max(a.d, avg, a.n, a.h, a.c, dr, nbins, bins, p->stream) != hipSuccess) return LSFFT_E_DEVICE;
+  if (hipMemcpyAsync(hb.data(), bins, sizeof(unsigned long long) * hb.size(), hipMemcpyDeviceToHost, p->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess)
+    return LSFFT_E_DEVICE;
+  rve_finish(hb.data(), a, support_radius, tol, dr, profile, max_bins, out);
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_rve_identify_noalloc(lsfft_plan_t p, int grid_idx, const double* avg, const double* center,
+                                        double support_radius, double tol, double dr, double* profile, int max_bins,
+                                        lsfft_rve* out) {
+  RveArgs a;
+  lsfft_status ls = rve_args(p, grid_idx, avg, center, support_radius, tol, dr, out, &a);
+  if (ls != LSFFT_OK) return ls;
+  // the device's copy of the fixed scratch, looked up when the plan was made
+  unsigned long long* bins = rve_scratch_ptr(p->device);
+  if (!bins) return LSFFT_E_DEVICE;
+  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  const long long words = 2 * (long long)a.nbins;
+  unsigned long long hb[kRveScratchWords];   // host copy of the bins (stack, no allocation)
+  if (launch_zero_u64(bins, words, p->stream) != hipSuccess) return LSFFT_E_DEVICE;
+  if (launch_radial_max(a.d, avg, a.n, a.h, a.c, dr, a.nbins, bins, p->stream) != hipSuccess) return LSFFT_E_DEVICE;
+  if (hipMemcpyAsync(hb, bins, sizeof(unsigned long long) * (size_t)words, hipMemcpyDeviceToHost, p->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess)
+    return LSFFT_E_DEVICE;
+  rve_finish(hb, a, support_radius, tol, dr, profile, max_bins, out);
   return LSFFT_OK;
 }
 

@@ -27,7 +27,7 @@ K_XPASS, K_YPASS, K_GREEN, K_REDUCE, K_CGUPD, K_OTHER = range(6)
 
 EXPORTS = [
     "lsfft_plan", "lsfft_solve_bfcs", "lsfft_translate_average", "lsfft_translate_average_batch",
-    "lsfft_realization_average", "lsfft_rve_identify",
+    "lsfft_realization_average", "lsfft_rve_identify", "lsfft_rve_identify_noalloc",
     "lsfft_plan_destroy", "lsfft_status_string", "lsfft_lame_from_young", "lsfft_kernel_times",
     "lsfft_kernel_times_reset", "lsfft_iteration_bytes",
 ]
@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH):
     lib.lsfft_realization_average.restype = ip
     lib.lsfft_rve_identify.argtypes = [vp, ip, vp, C.POINTER(dp), dp, dp, dp, C.POINTER(dp), ip, C.POINTER(Rve)]
     lib.lsfft_rve_identify.restype = ip
+    lib.lsfft_rve_identify_noalloc.argtypes = lib.lsfft_rve_identify.argtypes
+    lib.lsfft_rve_identify_noalloc.restype = ip
     lib.lsfft_plan_destroy.argtypes = [vp]
     lib.lsfft_plan_destroy.restype = ip
     lib.lsfft_status_string.argtypes = [ip]
@@ -352,12 +354,13 @@ class Plan:
             raise LsfftError(st, "lsfft_realization_average")
         return avg, [_report(reps[k], d) for k in range(n)]
 
-    def rve_identify(self, avg, center, support_radius, tol=1e-3, dr=1.0, grid=0):
+    def rve_identify(self, avg, center, support_radius, tol=1e-3, dr=1.0, grid=0, noalloc=False):
         """RVE of Definition 2.2 from averaged fields ``avg`` (the layout of
         ``translate_average``): ``center`` of the force support in array
         order, voxel units.  Returns a dict with the RVE radius, the cell's
         inscribed radius, whether the RVE plus half the support fits, and the
-        radial maxima of |eps| and |sigma| per bin of width ``dr``."""
+        radial maxima of |eps| and |sigma| per bin of width ``dr``.  With
+        ``noalloc`` the library's allocation-free entry point runs instead."""
         torch = _torch()
         shp = self.shapes[grid]
         d = len(shp)
@@ -367,8 +370,9 @@ class Plan:
         nmax = 1024
         prof = np.zeros(2 * nmax)
         out = Rve()
-        st = self.lib.lsfft_rve_identify(self.handle, int(grid), a, c, float(support_radius), float(tol), float(dr),
-                                         prof.ctypes.data_as(C.POINTER(C.c_double)), nmax, C.byref(out))
+        fn = self.lib.lsfft_rve_identify_noalloc if noalloc else self.lib.lsfft_rve_identify
+        st = fn(self.handle, int(grid), a, c, float(support_radius), float(tol), float(dr),
+                prof.ctypes.data_as(C.POINTER(C.c_double)), nmax, C.byref(out))
         if st != OK:
             raise LsfftError(st, "lsfft_rve_identify")
         nb = out.nbins
