@@ -1,20 +1,22 @@
 """Throughput benchmark of the BFCS Lippmann-Schwinger solver on one MI355X.
 
-A step is one complete BFCS solve of the default workload (3D 128^3 voxels =
-8x8x8 unit cells of 16^3, one sphere per cell at volume fraction 0.25,
-inclusion/matrix Young's contrast 10, nu = 0.3, vector bump force of radius 12
-voxels with seeded centre and direction, reference medium = mean of the
-extreme Lame constants, basic scheme, tol 1e-8, FP32 transforms and updates
-under FP64 defect correction: the state, the residual and the stopping test
-are FP64): force transform and free term, the iterations until the FP64
-residual meets the tolerance, and materialization of u, eps and sigma.  Inputs are resident in HBM before the
-timed region starts.
+A step is one complete BFCS solve of the default workload, the largest
+single-GPU configuration: 3D 256^3 voxels = 16^3 unit cells of 16^3, random
+non-overlapping spheres (volume fraction 0.3, radii 3-6 voxels) in every
+cell, stiff inclusions at Young's contrast 100, nu = 0.3, vector bump force
+of radius 12 voxels with seeded centre and direction, reference medium = mean
+of the extreme Lame constants, basic scheme, tol 1e-8, FP32 transforms and
+updates under FP64 defect correction (the state, the residual and the
+stopping test are FP64): force transform and free term, the iterations
+until the FP64 residual meets the tolerance, and materialization of u, eps
+and sigma.  Inputs are resident in HBM before the timed region starts.
 
 Printed: one JSON line with voxel-iterations/s (sum of |N| x iterations over
 the timed solves divided by wall time), solves/s, the roofline of the
-dominant kernel (algorithmic bytes per launch over its mean HIP-event
-duration inside the timed region), and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+dominant kernel (algorithmic bytes of its launches over their HIP-event
+durations on a timed plan), the whole-solve bandwidth fraction, and the FP64
+CPU oracle timed on a bounded sample of the same workload (one core, and
+with its transforms on all cores).
 """
 from __future__ import annotations
 
@@ -121,7 +123,26 @@ def run_batch_workload(args, wl):
                 k += 1
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # whole job: algorithmic bytes of every solver kernel per iteration of
+    # each solve's grid times its iterations, over the wall time
+    from paper_2601_00822_amd import K_GREEN, K_XPASS, K_YPASS, K_REDUCE, K_CGUPD
+    classes = (K_GREEN, K_XPASS, K_YPASS, K_REDUCE, K_CGUPD)
+    grid_of = [dg["grid"] for dg in dgroups for _ in range(len(dg["shifts"]))]
+    bytes_iter = {g: sum(plan.iteration_bytes(k, g) for k in classes) for g in range(len(shapes))}
+    job_bytes = args.steps * sum(bytes_iter[g] * r.iters for g, r in zip(grid_of, reps))
     plan.close()
+    # kernel-duration region: one more batch on a timed plan (graphs off, a
+    # HIP event pair stamped by every launch)
+    plan_t = Plan(shapes, prec=args.prec, scheme=args.scheme, max_batch=nsolve, refine=args.refine, timing=True)
+    plan_t.translate_average_batch(dgroups, tol=1e-8)
+    plan_t.kernel_times_reset()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, reps_t, _ = plan_t.translate_average_batch(dgroups, tol=1e-8)
+    torch.cuda.synchronize()
+    elapsed_t = time.perf_counter() - t1
+    per, dom = class_rooflines(plan_t, [(g, r.iters) for g, r in zip(grid_of, reps_t)], args.scheme == "cg")
+    plan_t.close()
     statuses = sorted({r.status for r in reps})
     return {
         "metric": METRIC, "value": vox_iters / elapsed, "unit": "voxel-iters/s", "n_gpus": 1,
@@ -136,6 +157,14 @@ def run_batch_workload(args, wl):
         "iterations": {"min": int(min(iters_all)), "max": int(max(iters_all)),
                        "mean": float(np.mean(iters_all))},
         "statuses": statuses,
+        "whole_job": {"gbs": job_bytes / elapsed / 1e9, "frac": job_bytes / elapsed / 1e9 / HBM_PEAK_GBS,
+                      "note": "algorithmic bytes of all solver kernels per iteration of each solve's grid x its "
+                              "iterations / wall time"},
+        "kernel_gbs": {k: round(v["gbs"], 1) for k, v in per.items()},
+        "timing_region": {"seconds": elapsed_t,
+                          "note": "one batch with graphs off and a HIP event pair stamped at every kernel's start "
+                                  "and end; kernel bandwidths and the roofline come from this region"},
+        "roofline": roofline_field(per, dom, None),
     }
 
 
@@ -324,23 +353,135 @@ def make_inputs(wl: dict, seed: int = 0):
     return phase, f, table, np.asarray(table)
 
 
-def cpu_baseline(wl: dict, phase, f, table, budget_s: float = 20.0):
-    """The FP64 oracle as it stands, timed on the host on a bounded sample:
-    Algorithm 1 on the full grid for a fixed number of iterations."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads this process may use: the machine's CPU share if the environment
+    states it, else the affinity mask."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return min(int(env), aff)
+    return aff
+
+
+def _oracle_iteration_rate(phase, lame, f):
+    """Time Algorithm 1 of the oracle on the full grid twice: stopped after
+    the free term and the first residual (max_iter = 0), and after one more
+    iteration (max_iter = 1).  The difference is the cost of one iteration.
+    Returns (seconds per iteration, seconds of the longer run)."""
+    from oracle import lsfft_oracle as O
+    t0 = time.perf_counter()
+    O.solve_basic(phase, lame, f, tol=1e-30, max_iter=0)
+    ta = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.solve_basic(phase, lame, f, tol=1e-30, max_iter=1)
+    tb = time.perf_counter() - t0
+    return max(tb - ta, 1e-6), tb
+
+
+def cpu_baseline(wl: dict, phase, f, table):
+    """The FP64 oracle as it stands, timed on the host on a bounded sample of
+    the same workload: one iteration of Algorithm 1 on the full grid (the
+    time of a run stopped after one iteration minus that of a run stopped
+    before it).  First with its transforms as written (numpy.fft, one
+    thread); then the same code with its two transform helpers routed to
+    scipy.fft on all the host threads (the pointwise NumPy work stays
+    single-threaded)."""
     from oracle import lsfft_oracle as O
     lame = O.lame_from_young(table)
     nvox = int(phase.size)
-    t0 = time.perf_counter()
-    O.solve_basic(phase, lame, f, tol=1e-30, max_iter=1)            # free term + 1 iteration
-    t1 = time.perf_counter()
-    per_iter = max(t1 - t0, 1e-3) / 2.0
-    iters = max(1, min(20, int(budget_s / per_iter) - 1))
-    t0 = time.perf_counter()
-    res = O.solve_basic(phase, lame, f, tol=1e-30, max_iter=iters)
-    dt = time.perf_counter() - t0
-    return {"value": nvox * res.iters / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"full {phase.shape} grid, {res.iters} iterations of Algorithm 1 in FP64 NumPy "
-                      f"(pocketfft, single thread), {dt:.1f} s including the free term"}
+    per1, run1 = _oracle_iteration_rate(phase, lame, f)
+    out = {"value": nvox / per1, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
+           "sample": f"one iteration of Algorithm 1 on the full {phase.shape} grid in FP64 NumPy (numpy.fft, "
+                     f"single thread): {per1:.1f} s, the difference of runs stopped after and before it "
+                     f"(the longer {run1:.1f} s)",
+           "cpu_model": cpu_model(), "host_threads": host_threads()}
+    try:
+        import scipy.fft as sfft
+    except ImportError:
+        return out
+    workers = host_threads()
+    keep = (O.fft_r, O.ifft_r)
+
+    def fft_r(a, shape):
+        lead = a.ndim - len(shape)
+        return sfft.rfftn(a, axes=tuple(range(lead, a.ndim)), workers=workers)
+
+    def ifft_r(a, shape):
+        lead = a.ndim - len(shape)
+        return sfft.irfftn(a, s=shape, axes=tuple(range(lead, a.ndim)), workers=workers)
+
+    O.fft_r, O.ifft_r = fft_r, ifft_r
+    try:
+        pern, _ = _oracle_iteration_rate(phase, lame, f)
+    finally:
+        O.fft_r, O.ifft_r = keep
+    out["all_cores"] = {"value": nvox / pern, "unit": "voxel-iters/s", "cores": workers,
+                        "sample": f"the same oracle code with its transforms by scipy.fft(workers={workers}): "
+                                  f"{pern:.1f} s per iteration"}
+    return out
+
+
+CLASS_NAMES = ("green", "xpass", "ypass", "reduce", "cgupd")
+
+
+def class_rooflines(plan_t, solves, cg: bool):
+    """Per kernel class of a timed plan: total HIP-event time, launches,
+    algorithmic bytes and bandwidth.  ``solves`` lists (grid index,
+    iterations) of every solve the timed region ran; a class's algorithmic
+    bytes are the sum over those solves of its bytes per iteration
+    (lsfft_iteration_bytes) times the iterations.  Launches past a solve's
+    convergence inside a polling round are gated and nearly empty; their
+    time stays in the total.  Returns (per-class dict, dominant class): the
+    dominant class is the one kernel with the most time (the y-pass class
+    holds two kernels per iteration, the inverse and the forward sweep; the
+    CG outer-pass class two, A p and the new direction)."""
+    from paper_2601_00822_amd import K_GREEN, K_XPASS, K_YPASS, K_REDUCE, K_CGUPD
+    ids = {"green": K_GREEN, "xpass": K_XPASS, "ypass": K_YPASS, "reduce": K_REDUCE, "cgupd": K_CGUPD}
+    kernels_per_iter = {"green": 2.0 if cg else 1.0, "xpass": 1.0, "ypass": 2.0, "reduce": 1.0,
+                        "cgupd": 1.0}
+    out = {}
+    iters_total = sum(it for _, it in solves)
+    for name in CLASS_NAMES:
+        ms, launches = plan_t.kernel_times(ids[name])
+        if launches == 0:
+            continue
+        byts = sum(plan_t.iteration_bytes(ids[name], g) * it for g, it in solves)
+        out[name] = {"ms": ms, "launches": launches, "bytes": byts,
+                     "gbs": byts / (ms / 1e3) / 1e9 if ms > 0 else 0.0,
+                     "kernels_per_iter": kernels_per_iter[name], "iterations": iters_total}
+    cands = [k for k in ("green", "xpass", "ypass") if k in out]
+    dom = max(cands, key=lambda k: out[k]["ms"] / out[k]["kernels_per_iter"])
+    return out, dom
+
+
+def roofline_field(per, dom, traffic):
+    d = per[dom]
+    kpi = d["kernels_per_iter"]
+    working = d["iterations"] * kpi
+    # one launch of the dominant kernel per iteration of each solve in a
+    # single solve; in a batch one launch covers every running solve, so the
+    # per-launch figures there are per solve-iteration
+    bytes_per_launch = d["bytes"] / max(working, 1)
+    per_launch_s = d["ms"] / 1e3 / max(working, 1)
+    achieved = d["gbs"]
+    return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_per_launch, "mean_launch_us": per_launch_s * 1e6,
+            "launches": d["launches"], "working_launches": int(working)}
 
 
 def main() -> int:
@@ -348,7 +489,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="bfcs128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="bfcs256", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--scheme", default="basic", choices=["basic", "cg"])
     ap.add_argument("--no-refine", action="store_true",
@@ -360,7 +501,6 @@ def main() -> int:
     ap.add_argument("--fno-batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--direct-checks", type=int, default=2)
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the solves, run one plain device-to-device copy of this many MiB "
                          "(reference dispatch for HBM byte counters)")
@@ -372,7 +512,7 @@ def main() -> int:
         return 2
     import numpy as np
     import torch
-    from paper_2601_00822_amd import Plan, K_GREEN, K_XPASS, K_YPASS, K_REDUCE
+    from paper_2601_00822_amd import Plan, K_GREEN, K_XPASS, K_YPASS, K_REDUCE, K_CGUPD
 
     wl = WORKLOADS[args.workload]
     if wl.get("batch"):
@@ -408,7 +548,7 @@ def main() -> int:
 
     for _ in range(args.warmup):
         plan.solve(phase_d, lame, f_d, tol=1e-8)
-        plan_t.solve(phase_d, lame, f_d, tol=1e-8)
+    plan_t.solve(phase_d, lame, f_d, tol=1e-8)
     torch.cuda.synchronize()
     iters = 0
     reps = []
@@ -425,29 +565,22 @@ def main() -> int:
     iters_t = 0
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(args.steps):
+    # the kernel-duration region repeats at most three solves: each holds
+    # hundreds to thousands of launches of every kernel
+    steps_t = min(args.steps, 3)
+    for _ in range(steps_t):
         _, rep = plan_t.solve(phase_d, lame, f_d, tol=1e-8)
         iters_t += rep.iters
     torch.cuda.synchronize()
     elapsed_t = time.perf_counter() - t1
 
-    classes = {"green": K_GREEN, "xpass": K_XPASS, "ypass": K_YPASS, "reduce": K_REDUCE}
-    ktimes = {k: plan_t.kernel_times(c) for k, c in classes.items()}
-    # dominant kernel: the largest time per iteration of one kernel (the y
-    # pass class holds two kernels, the inverse and the forward sweep)
-    per_kernel = {"green": 1.0, "xpass": 1.0, "ypass": 2.0}
-    dom = max(per_kernel, key=lambda k: ktimes[k][0] / per_kernel[k])
-    ms, launches = ktimes[dom]
-    bytes_per_iter = plan_t.iteration_bytes(classes[dom])
-    launches_per_iter = 2.0 if dom == "ypass" else 1.0   # two y launches per iteration
-    bytes_per_launch = bytes_per_iter / launches_per_iter
-    # launches past a solve's convergence inside a polling round are gated
-    # and nearly empty: time per working launch = all launch time of the
-    # class over the launches that did an iteration's work
-    working = iters_t * launches_per_iter
-    per_launch_s = ms / 1e3 / max(working, 1)
-    achieved = bytes_per_launch / per_launch_s / 1e9
+    per, dom = class_rooflines(plan_t, [(0, iters_t)], args.scheme == "cg")
     traffic = measured_traffic(dom, args.workload, args.prec)
+    # whole solve: algorithmic bytes of every solver kernel per iteration
+    # times the iterations, over the wall time of the graph region (host
+    # polls, setup, FP64 correction and materialization included)
+    bytes_iter = sum(plan.iteration_bytes(k) for k in (K_GREEN, K_XPASS, K_YPASS, K_REDUCE, K_CGUPD))
+    solve_gbs = bytes_iter * iters / elapsed / 1e9
 
     out = {
         "metric": METRIC,
@@ -469,19 +602,20 @@ def main() -> int:
         "iterations_per_solve": iters / args.steps,
         "final_residual": reps[-1].residual,
         "status": reps[-1].status,
-        "kernel_ms_per_iteration": {k: v[0] / max(iters_t, 1) for k, v in ktimes.items()},
-        "timing_region": {"value": nvox * iters_t / elapsed_t,
+        "kernel_ms_per_iteration": {k: v["ms"] / max(iters_t, 1) for k, v in per.items()},
+        "kernel_gbs": {k: round(v["gbs"], 1) for k, v in per.items()},
+        "whole_solve": {"gbs": solve_gbs, "frac": solve_gbs / HBM_PEAK_GBS,
+                        "bytes_per_iteration": bytes_iter,
+                        "note": "algorithmic bytes of all solver kernels per iteration x iterations / wall time "
+                                "of the timed region"},
+        "timing_region": {"value": nvox * iters_t / elapsed_t, "solves": steps_t,
                           "note": "same solves with graphs off and a HIP event pair stamped at every kernel's "
                                   "start and end (hipExtLaunchKernelGGL); kernel durations and the roofline come "
                                   "from this region"},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "mean_launch_us": per_launch_s * 1e6, "launches": launches,
-                     "working_launches": int(working)},
+        "roofline": roofline_field(per, dom, traffic),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, phase, f, table, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(wl, phase, f, table)
     plan.close()
     plan_t.close()
     print(json.dumps(out))
