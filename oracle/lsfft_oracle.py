@@ -440,6 +440,122 @@ def solve_pcg_displacement(phase, lame, f, lam0=None, mu0=None, tol=1e-8, max_it
     return Result(eps, stress(eps, lam, mu), ifft_r(u_hat, shape), j, delta, hist, removed, status)
 
 
+def solve_cg_alg3(phase, lame, f, lam0=None, mu0=None, tol=1e-8, max_iter=20000, start="printed"):
+    """Algorithm 3 (Sec. 5, Eqs. 5.17-5.22): plain conjugate gradients, no
+    preconditioner, on the displacement-fluctuation system ``A(u1) = b^A``
+    of Eqs. 5.14-5.17, with ``A(v) = -div(L sym grad v)`` and
+    ``b^A = div(L1 eps^b)`` (the printed right-hand side of Eq. 5.14 drops
+    the force; with ``u = u^b + u1`` the residual ``b^A - A(u1)`` equals
+    ``P f + div(L sym grad u)``).  The start is ``u1 = b^A`` as printed
+    (``start="printed"``) or ``u1 = 0`` (``start="zero"``, the reading used
+    where the printed start mixes a force with a displacement); then
+    ``r = b^A - A(u1)``, ``p = r``, and per iteration
+    ``alpha = r.r / p.A(p)`` (Eq. 5.18, ``A`` symmetric), ``u1 += alpha p``
+    (5.19), ``r -= alpha A(p)`` (5.20), ``beta = r'.r' / r.r`` (5.21),
+    ``p = r' + beta p`` (5.22).  Inner products are Parseval-weighted
+    half-spectrum sums.  Stops when ``||r|| / ||P f|| <= tol``; the strain is
+    ``sym grad(u^b + u1)`` (the printed ``u1 + eps^b``)."""
+    shape, lam0, mu0, lam, mu, xi, w, f_hat, removed = _prepare(phase, lame, f, lam0, mu0)
+    fnorm = _norm_w(f_hat, w)
+
+    def a_op(v_hat):
+        e = ifft_r(sym_grad_hat(v_hat, xi), shape)
+        return -div_hat(fft_r(stress(e, lam, mu), shape), xi)
+
+    def dot(a, b):
+        return float(np.sum(w * (np.conj(a) * b).real))
+
+    ub_hat = apply_N0(f_hat, xi, lam0, mu0)
+    b_a = f_hat - a_op(ub_hat)                                   # b^A = r(u^b)
+    if start == "printed":
+        u1 = b_a.copy()
+    elif start == "zero":
+        u1 = np.zeros_like(b_a)
+    else:
+        raise ValueError("start is 'printed' or 'zero'")
+    r = b_a - a_op(u1)
+    p = r.copy()
+    rr = dot(r, r)
+    j = 0
+    hist = []
+    while True:
+        delta = np.sqrt(rr) / fnorm if fnorm > 0 else 0.0
+        hist.append(delta)
+        if delta <= tol or j >= max_iter:
+            break
+        q = a_op(p)
+        alpha = rr / dot(p, q)                                   # Eq. 5.18
+        u1 = u1 + alpha * p                                      # Eq. 5.19
+        r = r - alpha * q                                        # Eq. 5.20
+        rr_new = dot(r, r)
+        beta = rr_new / rr                                       # Eq. 5.21
+        p = r + beta * p                                         # Eq. 5.22
+        rr = rr_new
+        j += 1
+    u_hat = ub_hat + u1
+    eps = ifft_r(sym_grad_hat(u_hat, xi), shape)
+    status = STATUS_OK if delta <= tol else STATUS_NOCONV
+    return Result(eps, stress(eps, lam, mu), ifft_r(u_hat, shape), j, delta, hist, removed, status)
+
+
+# --------------------------------------------------------------------------
+# Anderson acceleration of the basic scheme (Sec. 5 names accelerated
+# schemes for high contrast; the method is Anderson's, in the form of
+# Walker & Ni, SIAM J. Numer. Anal. 49 (2011))
+# --------------------------------------------------------------------------
+
+def solve_anderson(phase, lame, f, lam0=None, mu0=None, tol=1e-8, max_iter=10000, m=5):
+    """Anderson acceleration with memory ``m`` and mixing 1 of the basic
+    scheme's fixed-point map in displacement form,
+    ``g(u) = u + N0 (i xi . sigma^(u) + f^)`` (Algorithm 1 after Eq. 2.27).
+    With ``F_k = g(u_k) - u_k`` and the differences ``dF_i = F_{i+1} - F_i``,
+    ``dU_i = u_{i+1} - u_i`` of the last ``m_k = min(m, k)`` steps:
+    ``gamma = argmin || F_k - sum_i gamma_i dF_i ||`` (Parseval-weighted
+    least squares) and ``u_{k+1} = u_k + F_k - sum_i gamma_i (dU_i + dF_i)``.
+    ``m = 0`` is the basic scheme.  Starts at ``u^b``; stops when the
+    equilibrium residual ``||i xi . sigma^ + P f^|| / ||P f^|| <= tol``;
+    iterations = updates applied."""
+    shape, lam0, mu0, lam, mu, xi, w, f_hat, removed = _prepare(phase, lame, f, lam0, mu0)
+    fnorm = _norm_w(f_hat, w)
+    sw = np.sqrt(w)
+
+    def realvec(v_hat):
+        # half-spectrum field as a real vector whose dot products are the
+        # Parseval-weighted ones
+        return np.concatenate([(sw * v_hat.real).ravel(), (sw * v_hat.imag).ravel()])
+
+    u_hat = apply_N0(f_hat, xi, lam0, mu0)
+    dU, dF = [], []
+    u_prev = F_prev = None
+    j = 0
+    hist = []
+    while True:
+        eps = ifft_r(sym_grad_hat(u_hat, xi), shape)
+        sig = stress(eps, lam, mu)
+        r_hat = div_hat(fft_r(sig, shape), xi) + f_hat
+        delta = _norm_w(r_hat, w) / fnorm if fnorm > 0 else 0.0
+        hist.append(delta)
+        if delta <= tol or j >= max_iter:
+            break
+        F = apply_N0(r_hat, xi, lam0, mu0)
+        if F_prev is not None and m > 0:
+            dU.append(u_hat - u_prev)
+            dF.append(F - F_prev)
+            if len(dF) > m:
+                dU.pop(0)
+                dF.pop(0)
+        u_prev, F_prev = u_hat, F
+        if dF:
+            A = np.stack([realvec(v) for v in dF], axis=1)
+            gamma = np.linalg.lstsq(A, realvec(F), rcond=None)[0]
+            u_hat = u_hat + F - sum(g * (a + b) for g, a, b in zip(gamma, dU, dF))
+        else:
+            u_hat = u_hat + F
+        j += 1
+    status = STATUS_OK if delta <= tol else STATUS_NOCONV
+    return Result(eps, sig, ifft_r(u_hat, shape), j, delta, hist, removed, status)
+
+
 # --------------------------------------------------------------------------
 # Classical Lippmann-Schwinger mode (Eqs. 2.24-2.26, 5.1-5.2, 5.11, 6.1-6.3)
 # --------------------------------------------------------------------------
