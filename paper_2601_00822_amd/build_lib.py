@@ -18,11 +18,25 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblsfft.so")
 
+# Translation units built from k_pass.hip: (object name, defines).  Outer
+# pass launchers first (the slowest to compile), then the x and y passes.
+PASS_UNITS = (
+    [(f"k_pass_g_{p}_{d}d_{'l' if lng else 's'}", {"LSFFT_PASS": 2, "LSFFT_F64": int(p == "f64"), "LSFFT_DIM": d,
+                                                    "LSFFT_LONG": int(lng)})
+     for lng in (True, False) for p in ("f32", "f64") for d in (3, 2)]
+    + [(f"k_pass_x_{p}_{d}d", {"LSFFT_PASS": 0, "LSFFT_F64": int(p == "f64"), "LSFFT_DIM": d})
+       for p in ("f32", "f64") for d in (3, 2)]
+    + [(f"k_pass_y_{p}", {"LSFFT_PASS": 1, "LSFFT_F64": int(p == "f64")}) for p in ("f32", "f64")]
+)
+
+
 def sources():
-    """Every HIP translation unit in csrc/ (largest first) plus the host code."""
-    hips = sorted((f for f in os.listdir(CSRC) if f.endswith(".hip")),
-                  key=lambda f: (not f.startswith("k_g_"), f))
-    return hips + ["lsfft.cpp", "fno.cpp"]
+    """Every translation unit: (source in csrc/, object name, defines)."""
+    units = [("k_pass.hip", name, defs) for name, defs in PASS_UNITS]
+    others = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip") and f != "k_pass.hip")
+    units += [(f, os.path.splitext(f)[0], {}) for f in others]
+    units += [("lsfft.cpp", "lsfft", {}), ("fno.cpp", "fno", {})]
+    return units
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -38,9 +52,10 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP toolchain is required to build liblsfft")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit) -> str:
+    src, name, defs = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [hipcc(), *COMMON, *[f"-D{k}={v}" for k, v in defs.items()], "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd.insert(1, "-xhip")
     r = subprocess.run(cmd, capture_output=True, text=True)

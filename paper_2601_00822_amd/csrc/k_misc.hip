@@ -36,22 +36,22 @@ int threads_per_block(bool f64) { return f64 ? Cfg<double>::NTH : Cfg<float>::NT
 int threads_per_block_green(bool f64) { return f64 ? Cfg<double>::NTH_G : Cfg<float>::NTH_G; }
 
 hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode, int dim, int len) {
-  if (f64) return dim == 3 ? launch_xpass_f64_3d(a, mode, len) : launch_xpass_f64_2d(a, mode, len);
-  return dim == 3 ? launch_xpass_f32_3d(a, mode, len) : launch_xpass_f32_2d(a, mode, len);
+  if (f64) return dim == 3 ? launch_x<double, 3>(a, mode, len) : launch_x<double, 2>(a, mode, len);
+  return dim == 3 ? launch_x<float, 3>(a, mode, len) : launch_x<float, 2>(a, mode, len);
 }
 
 hipError_t launch_ypass(bool f64, const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len) {
-  return f64 ? launch_ypass_f64(a, dir, which, ncomp, gate, len) : launch_ypass_f32(a, dir, which, ncomp, gate, len);
+  return f64 ? launch_y<double>(a, dir, which, ncomp, gate, len) : launch_y<float>(a, dir, which, ncomp, gate, len);
 }
 
 hipError_t launch_green(bool f64, const LaunchArgs& a, int mode, int dim, int len) {
-  const bool small = len < 32;
+  const bool lng = len >= 32;
   if (f64) {
-    if (dim == 3) return small ? launch_green_f64_3d_s(a, mode, len) : launch_green_f64_3d_l(a, mode, len);
-    return small ? launch_green_f64_2d_s(a, mode, len) : launch_green_f64_2d_l(a, mode, len);
+    if (dim == 3) return lng ? launch_g<double, 3, true>(a, mode, len) : launch_g<double, 3, false>(a, mode, len);
+    return lng ? launch_g<double, 2, true>(a, mode, len) : launch_g<double, 2, false>(a, mode, len);
   }
-  if (dim == 3) return small ? launch_green_f32_3d_s(a, mode, len) : launch_green_f32_3d_l(a, mode, len);
-  return small ? launch_green_f32_2d_s(a, mode, len) : launch_green_f32_2d_l(a, mode, len);
+  if (dim == 3) return lng ? launch_g<float, 3, true>(a, mode, len) : launch_g<float, 3, false>(a, mode, len);
+  return lng ? launch_g<float, 2, true>(a, mode, len) : launch_g<float, 2, false>(a, mode, len);
 }
 
 hipError_t launch_cg_update(bool f64, const LaunchArgs& a) {

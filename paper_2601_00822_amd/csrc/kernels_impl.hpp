@@ -1499,11 +1499,12 @@ template <int NG> struct WavesG<double, NG> { static constexpr int value = 2; };
 #define LSFFT_WAVES_Y 4
 #endif
 
-#ifdef LSFFT_ONLY_LEN
-#define LSFFT_LEN_CASES(X) X(LSFFT_ONLY_LEN)
-#else
-#define LSFFT_LEN_CASES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
-#endif
+// The supported axis lengths (the twiddle table's order), split into the
+// short ones and those of 32 points and more: the outer-pass launchers of the
+// two groups are built in separate translation units.
+#define LSFFT_LEN_CASES_SHORT(X) X(4) X(6) X(8) X(12) X(16) X(24)
+#define LSFFT_LEN_CASES_LONG(X) X(32) X(48) X(64) X(96) X(128) X(256)
+#define LSFFT_LEN_CASES(X) LSFFT_LEN_CASES_SHORT(X) LSFFT_LEN_CASES_LONG(X)
 
 // One kernel per (precision, length, dimension, mode): every work item of a
 // launch has the same transform length, so register allocation and LDS

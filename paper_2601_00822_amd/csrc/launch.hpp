@@ -40,21 +40,26 @@ size_t query_geometry(bool f64, int kind, int len, int* per_tile);
 int threads_per_block(bool f64);
 int threads_per_block_green(bool f64);
 
-// per precision / dimension / length group (one translation unit each)
-hipError_t launch_xpass_f32_2d(const LaunchArgs& a, int mode, int len);
-hipError_t launch_xpass_f32_3d(const LaunchArgs& a, int mode, int len);
-hipError_t launch_xpass_f64_2d(const LaunchArgs& a, int mode, int len);
-hipError_t launch_xpass_f64_3d(const LaunchArgs& a, int mode, int len);
-hipError_t launch_ypass_f32(const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len);
-hipError_t launch_ypass_f64(const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len);
-hipError_t launch_green_f32_2d_s(const LaunchArgs& a, int mode, int len);
-hipError_t launch_green_f32_2d_l(const LaunchArgs& a, int mode, int len);
-hipError_t launch_green_f32_3d_s(const LaunchArgs& a, int mode, int len);
-hipError_t launch_green_f32_3d_l(const LaunchArgs& a, int mode, int len);
-hipError_t launch_green_f64_2d_s(const LaunchArgs& a, int mode, int len);
-hipError_t launch_green_f64_2d_l(const LaunchArgs& a, int mode, int len);
-hipError_t launch_green_f64_3d_s(const LaunchArgs& a, int mode, int len);
-hipError_t launch_green_f64_3d_l(const LaunchArgs& a, int mode, int len);
+// Launchers of one pass family for one precision T, dimension DIM (x and
+// outer pass) and length group (outer pass: LONG = lengths from 32 on); each
+// specialization below is built in its own translation unit from k_pass.hip.
+template <typename T, int DIM> hipError_t launch_x(const LaunchArgs& a, int mode, int len);
+template <typename T> hipError_t launch_y(const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len);
+template <typename T, int DIM, bool LONG> hipError_t launch_g(const LaunchArgs& a, int mode, int len);
+template <> hipError_t launch_x<float, 2>(const LaunchArgs&, int, int);
+template <> hipError_t launch_x<float, 3>(const LaunchArgs&, int, int);
+template <> hipError_t launch_x<double, 2>(const LaunchArgs&, int, int);
+template <> hipError_t launch_x<double, 3>(const LaunchArgs&, int, int);
+template <> hipError_t launch_y<float>(const LaunchArgs&, int, int, int, int, int);
+template <> hipError_t launch_y<double>(const LaunchArgs&, int, int, int, int, int);
+template <> hipError_t launch_g<float, 2, false>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<float, 2, true>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<float, 3, false>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<float, 3, true>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<double, 2, false>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<double, 2, true>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<double, 3, false>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<double, 3, true>(const LaunchArgs&, int, int);
 
 // dispatch on (precision, dimension, transform length)
 hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode, int dim, int len);
