@@ -1,0 +1,101 @@
+"""Pins of the nonlocal kernel surrogate's oracle (Sec. 6, Eqs. 6.5-6.6):
+the Bernstein basis, the operator on constant fields and on Fourier modes
+(closed-form multiplier), recovery of a planted kernel from data generated
+by an independent FFT convolution, and Adam against the closed-form
+Tikhonov minimiser."""
+import numpy as np
+import pytest
+
+from oracle import nonlocal_oracle as N
+
+
+def test_bernstein_basis():
+    t = np.linspace(0.0, 1.0, 11)
+    for M in (0, 1, 3, 6):
+        B = N.bernstein(M, t)
+        np.testing.assert_allclose(B.sum(axis=0), 1.0, rtol=0, atol=1e-15)     # partition of unity
+        assert (B >= 0.0).all()
+        assert B[0, 0] == 1.0 and B[M, -1] == 1.0
+    # degree 2 by hand at t = 1/4: (9/16, 6/16, 1/16)
+    np.testing.assert_allclose(N.bernstein(2, 0.25), [9 / 16, 6 / 16, 1 / 16], rtol=0, atol=1e-16)
+
+
+def test_operator_vanishes_on_constants():
+    u = np.ones((3, 6, 8, 10)) * np.array([1.5, -2.0, 0.25])[:, None, None, None]
+    out = N.apply_operator([0.3, -1.0, 2.0, 0.7], u, 2.6)
+    assert np.abs(out).max() < 1e-13
+
+
+@pytest.mark.parametrize("shape,k", [((16, 12), (3, -2)), ((8, 10, 12), (1, 2, -3))])
+def test_operator_on_a_fourier_mode(shape, k):
+    """u = cos(xi . x): L[u] = m(xi) u with m = sum over offsets inside the
+    horizon of K(|r|) (cos(xi . r) - 1), the offsets enumerated here by a
+    brute-force scan of the periodic grid's minimum images."""
+    d = len(shape)
+    delta = 3.2
+    c = np.array([0.4, -0.3, 1.1, 0.2])
+    xi = np.array([2 * np.pi * k[a] / shape[a] for a in range(d)])
+    pos = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    phase = sum(xi[a] * pos[a] for a in range(d))
+    u = np.stack([np.cos(phase), 0.5 * np.cos(phase)])
+    mult = 0.0
+    for idx in np.ndindex(*shape):
+        r = np.array([v if v <= n // 2 else v - n for v, n in zip(idx, shape)], dtype=np.float64)
+        rho = np.sqrt(r @ r)
+        if 0.0 < rho < delta:
+            t = rho / delta
+            K = sum(c[m] * N.comb(3, m) * t ** m * (1 - t) ** (3 - m) for m in range(4))
+            mult += K * (np.cos(xi @ r) - 1.0)
+    np.testing.assert_allclose(N.apply_operator(c, u, delta), mult * u, rtol=0, atol=1e-12)
+
+
+def kernel_image(c, shape, delta):
+    """K_c(|r|) on the periodic grid at the minimum-image offsets (origin 0)."""
+    d = len(shape)
+    M = len(c) - 1
+    img = np.zeros(shape)
+    for idx in np.ndindex(*shape):
+        r = np.array([v if v <= n // 2 else v - n for v, n in zip(idx, shape)], dtype=np.float64)
+        rho = np.sqrt(r @ r)
+        if 0.0 < rho < delta:
+            img[idx] = float(np.dot(c, N.bernstein(M, rho / delta)))
+    return img
+
+
+def operator_by_fft(c, u, delta):
+    """L_c[u] = (K * u)(x) - (sum K) u(x), the convolution by FFT."""
+    shape = u.shape[1:]
+    img = kernel_image(c, shape, delta)
+    axes = tuple(range(1, u.ndim))
+    # sum_r K(r) u(x + r) = correlation; K is even, so it equals the convolution
+    conv = np.fft.ifftn(np.fft.fftn(u, axes=axes) * np.fft.fftn(img)[None], axes=axes).real
+    return conv - img.sum() * u
+
+
+def test_planted_kernel_is_recovered():
+    rng = np.random.default_rng(4)
+    shape, delta, c_true = (10, 12, 14), 3.5, np.array([0.8, -0.4, 0.25, 1.3, -0.6])
+    us = [rng.normal(size=(3,) + shape) for _ in range(3)]
+    gammas = [operator_by_fft(c_true, u, delta) for u in us]
+    G, g, gg = N.normal_equations(us, gammas, len(c_true) - 1, delta)
+    c = N.fit_closed(G, g, 0.0)
+    np.testing.assert_allclose(c, c_true, rtol=0, atol=1e-9)
+    assert N.loss(c, G, g, gg, 0.0) < 1e-12 * gg     # the expanded quadratic cancels to rounding
+    # the operator itself agrees with the FFT route
+    np.testing.assert_allclose(N.apply_operator(c_true, us[0], delta), gammas[0], rtol=0,
+                               atol=1e-12 * np.abs(gammas[0]).max())
+
+
+def test_adam_reaches_the_tikhonov_minimiser():
+    rng = np.random.default_rng(6)
+    shape, delta, M, lam = (8, 8, 8), 2.8, 3, 0.05
+    us = [rng.normal(size=(3,) + shape) for _ in range(2)]
+    gammas = [rng.normal(size=(3,) + shape) for _ in range(2)]
+    G, g, gg = N.normal_equations(us, gammas, M, delta)
+    scale = np.trace(G) / (M + 1)
+    Gs, gs, lams = G / scale, g / scale, lam / scale        # same minimiser, unit-scale curvature
+    c_star = N.fit_closed(Gs, gs, lams)
+    np.testing.assert_allclose(c_star, N.fit_closed(G, g, lam), rtol=1e-9)
+    c = N.fit_adam(Gs, gs, lams, steps=50000, lr=1e-3)
+    np.testing.assert_allclose(c, c_star, rtol=0, atol=1e-6 * np.abs(c_star).max())
+    assert N.loss(c, G, g, gg, lam) <= N.loss(c_star, G, g, gg, lam) * (1 + 1e-9)
