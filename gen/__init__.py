@@ -25,7 +25,7 @@ __all__ = [
     "Material", "inclusion_per_cell", "rsa_cell", "tile_cell", "laminate",
     "bump_force", "dipole_force", "multi_bump_force", "sample_shifts",
     "all_shifts", "random_direction", "random_center", "grid_positions",
-    "bump_set_params", "bump_set_torch", "point_force",
+    "bump_set_params", "point_force",
 ]
 
 
@@ -265,26 +265,3 @@ def bump_set_params(n: int, count: int, seed: int, nmin: int = 1, nmax: int = 3,
     return out
 
 
-def bump_set_torch(n: int, params: list, device, dtype=None):
-    """Evaluate forces from ``bump_set_params`` on the GPU: returns a tensor
-    ``[len(params)][3][n][n][n]`` with the same bump profile as
-    ``bump_force`` (periodic minimum image)."""
-    import torch
-    dtype = dtype or torch.float64
-    ax = torch.arange(n, device=device, dtype=torch.float64)
-    out = torch.zeros((len(params), 3, n, n, n), device=device, dtype=dtype)
-    for i, bumps in enumerate(params):
-        for c, r, v in bumps:
-            r2 = 0.0
-            for a in range(3):
-                t = torch.remainder(ax - float(c[a]), float(n))
-                t = torch.where(t > n / 2.0, t - n, t)
-                shp = [1, 1, 1]
-                shp[a] = n
-                r2 = r2 + (t * t).view(shp)
-            q = r2 / (r * r)
-            b = torch.where(q < 1.0, torch.exp(-1.0 / (1.0 - torch.clamp(q, max=1.0 - 1e-12))),
-                            torch.zeros_like(q))
-            for comp in range(3):
-                out[i, comp] += (b * float(v[comp])).to(dtype)
-    return out

@@ -58,8 +58,23 @@ typedef enum { LSFFT_F32 = 0, LSFFT_F64 = 1 } lsfft_prec;
  * LSFFT_CG: conjugate gradients on the displacement form of the same
  * discrete equilibrium system (Algorithm 2's operator in the displacement
  * unknown of Eqs. 5.14-5.22), preconditioned by the reference-medium Green
- * operator; same limit, fewer iterations at high contrast. */
-typedef enum { LSFFT_BASIC = 0, LSFFT_CG = 1 } lsfft_scheme;
+ * operator; same limit, fewer iterations at high contrast.
+ * LSFFT_CG_PLAIN: Algorithm 3 (Sec. 5, Eqs. 5.17-5.22) as printed: the same
+ * CG without a preconditioner, started at u1 = b^A (the residual of the free
+ * term); the start costs one operator application and is not counted as an
+ * iteration.  Same limit; far more iterations than LSFFT_CG (the operator's
+ * spectrum spans |xi|^2 times the contrast).  Its stagnation window is 1000
+ * iterations instead of 50.
+ * LSFFT_ANDERSON: Anderson acceleration (Anderson 1965, in the form of
+ * Walker and Ni 2011) of Algorithm 1's fixed-point map in displacement form,
+ * one of the accelerated schemes Sec. 5 names for high contrast: with
+ * F_k = N0 (i xi . sigma^(u_k) + P f^) the basic step and the differences
+ * dF, dU of the last m steps, u_{k+1} = u_k + F_k - sum_j gamma_j (dU_j + dF_j),
+ * gamma minimizing ||F_k - sum_j gamma_j dF_j|| (Parseval-weighted; FP64
+ * normal equations).  Memory m = 5 unless set by lsfft_anderson_memory;
+ * same stopping rule and limit as the basic scheme; two outer-axis launches
+ * per iteration and 2 m + 1 extra displacement-sized fields per solve. */
+typedef enum { LSFFT_BASIC = 0, LSFFT_CG = 1, LSFFT_CG_PLAIN = 2, LSFFT_ANDERSON = 3 } lsfft_scheme;
 
 /* plan flags */
 #define LSFFT_STRICT_EQUIL 0x1u  /* reject forces whose voxel sum is not ~0 (Eq. 2.5) instead of projecting */
@@ -269,6 +284,62 @@ lsfft_status lsfft_rve_identify_noalloc(lsfft_plan_t p, int grid_idx, const doub
                                         double support_radius, double tol, double dr, double* profile,
                                         int max_bins, lsfft_rve* out);
 
+/*
+ * lsfft_kernel_convolve -- periodic convolution of forces with a kernel of
+ * the plan's grid, through the plan's own transforms (Sec. 6 dataset: with
+ * every shift of a cell, the translated average of Eqs. 3.3-3.6 is linear
+ * and commutes with grid translations, so it is the convolution of the
+ * force with the averaged response to a point force at the origin):
+ *   out_c = sum_j K_cj * P f_j   (c < s, j < d; * the periodic convolution,
+ *                                 P the projection off the xi = 0 set)
+ *  kernel  device [s][d][N] in the plan precision: K_cj = strain component c
+ *          (Voigt order) of the response to a unit force along axis j at the
+ *          origin voxel
+ *  f       host array [nforce] of device pointers, forces [d][N]
+ *  out     host array [nforce] of device pointers, results [s][N]
+ * Runs in batches of up to max_batch forces; synchronous.  LSFFT_E_ARG for
+ * null pointers, nforce < 1 or a bad grid index.
+ */
+lsfft_status lsfft_kernel_convolve(lsfft_plan_t p, int grid_idx, const void* kernel, int nforce,
+                                   const void* const* f, void* const* out);
+
+/*
+ * lsfft_block_mean -- block means of `nfield` fields [nz][ny][nx]
+ * (n = (nx, ny, nz), nz = 1 for 2D): out[f][Z][Y][X] = scale x the mean of
+ * the factor^d fine voxels of block (X, Y, Z) (factor^2 when nz = 1), FP64
+ * sums, rounded once to the output type; with factor 1 a scaled copy (and a
+ * precision conversion).  prec / out_prec: LSFFT_F32 or LSFFT_F64, the types
+ * of the device arrays in and out.  Every n_a > 1 must be a multiple of
+ * factor.  Synchronises hip_stream.
+ */
+lsfft_status lsfft_block_mean(int prec, int out_prec, int nfield, const int64_t* n, int factor, double scale,
+                              const void* in, void* out, void* hip_stream);
+
+/*
+ * lsfft_sample_norms -- per-sample Euclidean norms of nsample device arrays
+ * of len values (sample s at offset s x len): norm_diff[s] = ||y_s - t_s||
+ * (||t_s|| when y is NULL) and norm_t[s] = ||t_s||, FP64 sums in a fixed
+ * order (host outputs, either may be NULL).  Allocates a small device buffer.
+ */
+lsfft_status lsfft_sample_norms(int prec, int nsample, int64_t len, const void* y, const void* t, double* norm_diff,
+                                double* norm_t, void* hip_stream);
+
+/*
+ * lsfft_bump_forces -- body forces with compact support (Eq. 2.5's loading)
+ * made of smooth bumps: force i = sum over its nbump[i] bumps of
+ * exp(-1 / (1 - r^2 / R^2)) dir for r < R (zero outside), r the
+ * minimum-image distance from the node to the bump's centre in the periodic
+ * cell (voxel units).  bumps: host, per bump (centre x, y[, z], R,
+ * dir x, y[, z]), forces in order; f: host array [nforce] of device
+ * pointers [d][N] (overwritten).  Allocates a small device buffer.
+ */
+lsfft_status lsfft_bump_forces(int prec, int dim, const int64_t* n, int nforce, const int* nbump,
+                               const double* bumps, void* const* f, void* hip_stream);
+
+/* Memory m (1..8) of LSFFT_ANDERSON plans for later solves (default 5);
+ * LSFFT_E_ARG outside that range. */
+lsfft_status lsfft_anderson_memory(lsfft_plan_t p, int m);
+
 /* Release the plan and its workspace.  NULL is accepted. */
 lsfft_status lsfft_plan_destroy(lsfft_plan_t p);
 
@@ -300,6 +371,60 @@ lsfft_status lsfft_kernel_times_reset(lsfft_plan_t p);
 /* Algorithmic HBM bytes that one iteration of one solve on grid grid_idx
  * moves in each kernel class (complex half-spectrum streams and phase map). */
 lsfft_status lsfft_iteration_bytes(lsfft_plan_t p, int grid_idx, int kernel_class, double* bytes);
+
+/*
+ * Schedules and autotuning of the batched FFT passes (the plan-level
+ * choice of tile and radix schedule per transform length).  A pass kind is
+ * 0 (x pass), 1 (y pass) or 2 (outer pass).  Each (precision, dimension,
+ * kind, length) has a number of compiled schedule variants; variant 0 is the
+ * hand-tuned default and FP32 3D plans have 3 variants per pass for lengths
+ * of 32 points and more (outer pass: default tile, half the pencils, twice
+ * the pencils; y pass: default, twice the pencils, the other radix order; x
+ * pass: default, row tiles of half the entries, the other radix order).
+ * Every variant computes the same transforms; results differ only by
+ * rounding order.
+ */
+typedef struct {
+  int kind;       /* 0 x pass, 1 y pass, 2 outer pass */
+  int len;        /* transform length */
+  int variant;
+  int chosen;     /* 1 for the variant the plan now uses */
+  double us;      /* mean kernel time per launch in microseconds, summed over the plan's grids sharing that length */
+} lsfft_tune_entry;
+
+/* Current variant and number of variants of one pass of the plan's 3D (or
+ * 2D) grids on an axis of `len` points.  LSFFT_E_ARG for a bad kind,
+ * dimension or unsupported length. */
+lsfft_status lsfft_schedule_get(lsfft_plan_t p, int dim, int kind, int len, int* variant, int* nvariants);
+
+/* Select a variant explicitly (0 <= variant < nvariants, else LSFFT_E_ARG);
+ * applies to the plan's later solves.  2D grids keep variant 0. */
+lsfft_status lsfft_schedule_set(lsfft_plan_t p, int dim, int kind, int len, int variant);
+
+/*
+ * lsfft_autotune -- time every schedule variant of the plan's 3D grids and
+ * keep the fastest per pass kind and length.  For each distinct 3D grid a
+ * synthetic solve (two phases of Young's contrast 10 in 8-voxel blocks, a
+ * deterministic pseudo-random force) runs `iters` iterations (1..10000) once
+ * per variant round with every launch timed by a HIP event pair; each pass
+ * kind is judged by its own mean kernel time per launch.  The plan's own
+ * precision and scheme are used (FP32 inner solves for LSFFT_REFINE64).
+ *  cache_path  NULL, or a file to merge the choices into: a flat JSON object
+ *              {"f32/3d/outer/256": 2, ...}; lsfft_plan reads the file named
+ *              by the environment variable LSFFT_TUNE_CACHE and applies the
+ *              entries matching its grids
+ *  out         host [max_out] or NULL: every variant timed (kind, length,
+ *              variant, chosen flag, microseconds), *nout entries in all
+ * Allocates device memory for the synthetic inputs; synchronises the plan's
+ * stream.  LSFFT_E_ARG for bad arguments or a cache file that cannot be
+ * written.  FP64 plans and 2D grids have nothing to tune (*nout = 0).
+ */
+lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, lsfft_tune_entry* out, int max_out,
+                            int* nout);
+
+/* The cached variant for (precision, dimension, kind, length) in the text of
+ * a schedule cache, or -1 if there is no valid entry (host only, no GPU). */
+int lsfft_tune_cache_lookup(const char* json_text, int prec, int dim, int kind, int len);
 
 #ifdef __cplusplus
 }

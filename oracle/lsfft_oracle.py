@@ -720,6 +720,22 @@ def realization_average(phases, lame, f, incl_phase=1, lam0=None, mu0=None, tol=
     return acc / float(len(iters)), iters
 
 
+def kernel_convolve(kernel, f):
+    """Periodic convolution of a force with a kernel of the same grid
+    (Sec. 6 dataset: the full-shift translated average of Eqs. 3.3-3.6 is
+    the convolution of the force with the averaged point-force response):
+    ``out_c = sum_j K_cj * P f_j`` with ``P`` the projection off the
+    ``xi = 0`` set, written as the product of the transforms (Eqs. 4.3-4.5).
+    ``kernel`` is ``[s][d][grid]``, ``f`` is ``[d][grid]``."""
+    f = np.asarray(f, dtype=np.float64)
+    shape = f.shape[1:]
+    f_hat = fft_r(f, shape)
+    f_hat[:, zero_set(shape)] = 0.0
+    k_hat = fft_r(np.asarray(kernel, dtype=np.float64), shape)
+    out_hat = np.stack([sum(k_hat[c, j] * f_hat[j] for j in range(f.shape[0])) for c in range(k_hat.shape[0])])
+    return ifft_r(out_hat, shape)
+
+
 def tensor_magnitude(tv):
     """``sqrt(sum_ab t_ab^2)`` of a Voigt field ``[s][grid]`` (tensor shear
     counted twice), summed component by component in Voigt order."""

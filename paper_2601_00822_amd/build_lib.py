@@ -19,14 +19,21 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblsfft.so")
 
 # Translation units built from k_pass.hip: (object name, defines).  Outer
-# pass launchers first (the slowest to compile), then the x and y passes.
+# pass launchers first (the slowest to compile), then the x and y passes; the
+# schedule variants other than 0 (FP32 3D, lengths from 32 on) each get a
+# unit of their own.
 PASS_UNITS = (
     [(f"k_pass_g_{p}_{d}d_{'l' if lng else 's'}", {"LSFFT_PASS": 2, "LSFFT_F64": int(p == "f64"), "LSFFT_DIM": d,
                                                     "LSFFT_LONG": int(lng)})
      for lng in (True, False) for p in ("f32", "f64") for d in (3, 2)]
+    + [(f"k_pass_g_f32_3d_l_v{v}", {"LSFFT_PASS": 2, "LSFFT_F64": 0, "LSFFT_DIM": 3, "LSFFT_LONG": 1,
+                                    "LSFFT_VARIANT": v}) for v in (1, 2)]
     + [(f"k_pass_x_{p}_{d}d", {"LSFFT_PASS": 0, "LSFFT_F64": int(p == "f64"), "LSFFT_DIM": d})
        for p in ("f32", "f64") for d in (3, 2)]
+    + [(f"k_pass_x_f32_3d_v{v}", {"LSFFT_PASS": 0, "LSFFT_F64": 0, "LSFFT_DIM": 3, "LSFFT_VARIANT": v})
+       for v in (1, 2)]
     + [(f"k_pass_y_{p}", {"LSFFT_PASS": 1, "LSFFT_F64": int(p == "f64")}) for p in ("f32", "f64")]
+    + [(f"k_pass_y_f32_v{v}", {"LSFFT_PASS": 1, "LSFFT_F64": 0, "LSFFT_VARIANT": v}) for v in (1, 2)]
 )
 
 

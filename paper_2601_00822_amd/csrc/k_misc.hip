@@ -8,17 +8,17 @@
 
 namespace lsfft {
 
-template <typename T>
-static size_t geom_query(int kind, int len, int* per_tile) {
+template <typename T, int V>
+static size_t geom_query_v(int kind, int len, int* per_tile) {
   size_t bytes = 0;
   int q = 0;
   switch (len) {
-#define X(L)                                                                    \
-  case L:                                                                       \
-    if (kind == 0) { bytes = lds_x<T, L>(); q = XGeom<T, L / 2>::MR; }          \
-    else if (kind == 3) { bytes = lds_xi<T, L>(); q = XGeom<T, L / 2>::MR; }    \
-    else if (kind == 1) { bytes = lds_y<T, L>(); q = SGeom<T, L>::MP; }         \
-    else { bytes = lds_g<T, L>(); q = SGeom<T, L>::MPG; }                        \
+#define X(L)                                                                          \
+  case L:                                                                             \
+    if (kind == 0) { bytes = lds_x<T, L, V>(); q = XGeom<T, L / 2, XSched<V>::EX_DIV>::MR; } \
+    else if (kind == 3) { bytes = lds_xi<T, L, V>(); q = XGeom<T, L / 2, XSched<V>::EX_DIV>::MR; } \
+    else if (kind == 1) { bytes = lds_y<T, L, V>(); q = YSched<T, L, V>::MP; }         \
+    else { bytes = lds_g<T, L, V>(); q = GSched<T, L, V>::MP; }                        \
     break;
     LSFFT_LEN_CASES(X)
 #undef X
@@ -28,30 +28,65 @@ static size_t geom_query(int kind, int len, int* per_tile) {
   return bytes;
 }
 
-size_t query_geometry(bool f64, int kind, int len, int* per_tile) {
-  return f64 ? geom_query<double>(kind, len, per_tile) : geom_query<float>(kind, len, per_tile);
+int schedule_variants(bool f64, int dim, int kind, int len) {
+  if (f64 || dim != 3 || len < 32) return 1;
+  return kind == 2 ? kVarG : kind == 1 ? kVarY : kVarX;
+}
+
+size_t query_geometry(bool f64, int kind, int len, int var, int* per_tile) {
+  if (f64) return var == 0 ? geom_query_v<double, 0>(kind, len, per_tile) : 0;
+  switch (var) {
+    case 0: return geom_query_v<float, 0>(kind, len, per_tile);
+    case 1: return geom_query_v<float, 1>(kind, len, per_tile);
+    case 2: return geom_query_v<float, 2>(kind, len, per_tile);
+    default: return 0;
+  }
 }
 
 int threads_per_block(bool f64) { return f64 ? Cfg<double>::NTH : Cfg<float>::NTH; }
-int threads_per_block_green(bool f64) { return f64 ? Cfg<double>::NTH_G : Cfg<float>::NTH_G; }
 
-hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode, int dim, int len) {
-  if (f64) return dim == 3 ? launch_x<double, 3>(a, mode, len) : launch_x<double, 2>(a, mode, len);
-  return dim == 3 ? launch_x<float, 3>(a, mode, len) : launch_x<float, 2>(a, mode, len);
+hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode, int dim, int len, int var) {
+  if (f64) {
+    if (var != 0) return hipErrorInvalidValue;
+    return dim == 3 ? launch_x<double, 3, 0>(a, mode, len) : launch_x<double, 2, 0>(a, mode, len);
+  }
+  if (dim != 3) return var == 0 ? launch_x<float, 2, 0>(a, mode, len) : hipErrorInvalidValue;
+  switch (var) {
+    case 0: return launch_x<float, 3, 0>(a, mode, len);
+    case 1: return launch_x<float, 3, 1>(a, mode, len);
+    case 2: return launch_x<float, 3, 2>(a, mode, len);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_ypass(bool f64, const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len) {
-  return f64 ? launch_y<double>(a, dir, which, ncomp, gate, len) : launch_y<float>(a, dir, which, ncomp, gate, len);
+hipError_t launch_ypass(bool f64, const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len, int var) {
+  if (f64) return var == 0 ? launch_y<double, 0>(a, dir, which, ncomp, gate, len) : hipErrorInvalidValue;
+  switch (var) {
+    case 0: return launch_y<float, 0>(a, dir, which, ncomp, gate, len);
+    case 1: return launch_y<float, 1>(a, dir, which, ncomp, gate, len);
+    case 2: return launch_y<float, 2>(a, dir, which, ncomp, gate, len);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_green(bool f64, const LaunchArgs& a, int mode, int dim, int len) {
+hipError_t launch_green(bool f64, const LaunchArgs& a, int mode, int dim, int len, int var) {
   const bool lng = len >= 32;
   if (f64) {
-    if (dim == 3) return lng ? launch_g<double, 3, true>(a, mode, len) : launch_g<double, 3, false>(a, mode, len);
-    return lng ? launch_g<double, 2, true>(a, mode, len) : launch_g<double, 2, false>(a, mode, len);
+    if (var != 0) return hipErrorInvalidValue;
+    if (dim == 3) return lng ? launch_g<double, 3, true, 0>(a, mode, len) : launch_g<double, 3, false, 0>(a, mode, len);
+    return lng ? launch_g<double, 2, true, 0>(a, mode, len) : launch_g<double, 2, false, 0>(a, mode, len);
   }
-  if (dim == 3) return lng ? launch_g<float, 3, true>(a, mode, len) : launch_g<float, 3, false>(a, mode, len);
-  return lng ? launch_g<float, 2, true>(a, mode, len) : launch_g<float, 2, false>(a, mode, len);
+  if (dim != 3) {
+    if (var != 0) return hipErrorInvalidValue;
+    return lng ? launch_g<float, 2, true, 0>(a, mode, len) : launch_g<float, 2, false, 0>(a, mode, len);
+  }
+  if (!lng) return var == 0 ? launch_g<float, 3, false, 0>(a, mode, len) : hipErrorInvalidValue;
+  switch (var) {
+    case 0: return launch_g<float, 3, true, 0>(a, mode, len);
+    case 1: return launch_g<float, 3, true, 1>(a, mode, len);
+    case 2: return launch_g<float, 3, true, 2>(a, mode, len);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_cg_update(bool f64, const LaunchArgs& a) {
@@ -163,6 +198,81 @@ hipError_t launch_zero_u64(unsigned long long* a, long long n, hipStream_t st) {
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), NTR, 0, st, a, n);
   return hipGetLastError();
+}
+
+static unsigned grid_for(long long n, long long cap) {
+  long long b = (n + NTR - 1) / NTR;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t launch_block_mean(bool f64_in, bool f64_out, const void* in, void* out, long long nfield, int nx, int ny,
+                             int nz, int fct, double scale, hipStream_t st) {
+  const long long ncoarse = (long long)(nx / fct) * (ny / fct) * (nz > 1 ? nz / fct : 1);
+  const dim3 grid(grid_for(nfield * ncoarse, 8192));
+#define LSFFT_BM(TI, TO)                                                                                      \
+  hipLaunchKernelGGL((k_block_mean<TI, TO>), grid, NTR, 0, st, static_cast<const TI*>(in), static_cast<TO*>(out), \
+                     nfield, nx, ny, nz, fct, scale)
+  if (f64_in) {
+    if (f64_out) LSFFT_BM(double, double);
+    else LSFFT_BM(double, float);
+  } else {
+    if (f64_out) LSFFT_BM(float, double);
+    else LSFFT_BM(float, float);
+  }
+#undef LSFFT_BM
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_norms(bool f64, const void* y, const void* t, int nsample, long long len, double* res,
+                               hipStream_t st) {
+  if (nsample <= 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_sample_norms<double>, dim3((unsigned)nsample), NTR, 0, st, static_cast<const double*>(y),
+                       static_cast<const double*>(t), len, res);
+  else
+    hipLaunchKernelGGL(k_sample_norms<float>, dim3((unsigned)nsample), NTR, 0, st, static_cast<const float*>(y),
+                       static_cast<const float*>(t), len, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_bump_forces(bool f64, void* const* fs, const int* first, const double* bumps, int nforce, int nx,
+                              int ny, int nz, int dim, hipStream_t st) {
+  if (nforce <= 0) return hipSuccess;
+  const dim3 grid(grid_for((long long)nx * ny * nz, 2048), (unsigned)nforce);
+  if (f64)
+    hipLaunchKernelGGL(k_bump_forces<double>, grid, NTR, 0, st, reinterpret_cast<double* const*>(fs), first, bumps,
+                       nx, ny, nz, dim);
+  else
+    hipLaunchKernelGGL(k_bump_forces<float>, grid, NTR, 0, st, reinterpret_cast<float* const*>(fs), first, bumps, nx,
+                       ny, nz, dim);
+  return hipGetLastError();
+}
+
+hipError_t launch_nl_gram(bool f64, const void* u, const void* gam, int nsample, int nx, int ny, int nz, int dim,
+                          const int4* offs, int noffs, const double* W, int nshell, int deg, double* partial,
+                          double* out, hipStream_t st) {
+  if (nshell > kNlMaxShell || deg > kNlMaxDeg || deg < 0 || nsample < 1 || nsample > 65535) return hipErrorInvalidValue;
+  const long long nvox = (long long)nx * ny * nz;
+  const unsigned bx = (unsigned)((nvox + NTR - 1) / NTR);
+  const dim3 grid(bx, (unsigned)nsample);
+  if (f64)
+    hipLaunchKernelGGL(k_nl_gram<double>, grid, NTR, 0, st, static_cast<const double*>(u),
+                       static_cast<const double*>(gam), nx, ny, nz, dim, offs, noffs, W, nshell, deg, partial);
+  else
+    hipLaunchKernelGGL(k_nl_gram<float>, grid, NTR, 0, st, static_cast<const float*>(u), static_cast<const float*>(gam),
+                       nx, ny, nz, dim, offs, noffs, W, nshell, deg, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nf = deg + 1;
+  hipLaunchKernelGGL(k_nl_gram_sum, dim3(1), NTR, 0, st, partial, (long long)bx * nsample, nf * (nf + 1) / 2 + nf + 1,
+                     out);
+  return hipGetLastError();
+}
+
+size_t nl_partial_doubles(long long nvox, int nsample) {
+  return (size_t)((nvox + NTR - 1) / NTR) * (size_t)nsample * kNlAcc;
 }
 
 hipError_t launch_scale(double* a, long long n, double s, hipStream_t st) {

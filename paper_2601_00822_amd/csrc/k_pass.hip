@@ -5,6 +5,8 @@
 //   LSFFT_F64   0 float, 1 double
 //   LSFFT_DIM   2 or 3 (x and outer pass)
 //   LSFFT_LONG  outer pass: 0 lengths below 32, 1 lengths from 32 on
+//   LSFFT_VARIANT  schedule variant (0 when undefined); variants other than 0
+//               exist for FP32 3D only and cover the lengths from 32 on
 // so that every kernel specialization is compiled once and the translation
 // units build in parallel.
 #include "kernels_impl.hpp"
@@ -12,6 +14,9 @@
 
 #if !defined(LSFFT_PASS) || !defined(LSFFT_F64)
 #error "k_pass.hip is built once per pass family: define LSFFT_PASS and LSFFT_F64"
+#endif
+#ifndef LSFFT_VARIANT
+#define LSFFT_VARIANT 0
 #endif
 
 namespace lsfft {
@@ -32,8 +37,8 @@ hipError_t x_modes(const LaunchArgs& a, int mode) {
   switch (mode) {
 #define M(MODE)                                                                                                \
   case MODE:                                                                                                   \
-    LSFFT_LAUNCH((k_xpass<T, L, LSFFT_DIM, MODE>), a.grid, Cfg<T>::NTH_X, a.lds, a.stream, a.desc, a.state, \
-                 a.items, a.count, a.lame, tw);                                                                \
+    LSFFT_LAUNCH((k_xpass<T, L, LSFFT_DIM, MODE, LSFFT_VARIANT>), a.grid, Cfg<T>::NTH_X, a.lds, a.stream, a.desc, \
+                 a.state, a.items, a.count, a.lame, tw);                                                       \
     return hipGetLastError();
     M(M_FT) M(M_ITER) M(M_MAT)
 #undef M
@@ -43,10 +48,14 @@ hipError_t x_modes(const LaunchArgs& a, int mode) {
 }  // namespace
 
 template <>
-hipError_t launch_x<T, LSFFT_DIM>(const LaunchArgs& a, int mode, int len) {
+hipError_t launch_x<T, LSFFT_DIM, LSFFT_VARIANT>(const LaunchArgs& a, int mode, int len) {
   switch (len) {
 #define X(L) case L: return x_modes<L>(a, mode);
+#if LSFFT_VARIANT == 0
     LSFFT_LEN_CASES(X)
+#else
+    LSFFT_LEN_CASES_LONG(X)
+#endif
 #undef X
     default: return hipErrorInvalidValue;
   }
@@ -59,20 +68,26 @@ template <int L>
 hipError_t y_dirs(const LaunchArgs& a, int dir, int which, int ncomp, int gate) {
   const T* tw = static_cast<const T*>(a.tw);
   if (dir < 0)
-    LSFFT_LAUNCH((k_ypass<T, L, -1>), a.grid, Cfg<T>::NTH, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw,
+    LSFFT_LAUNCH((k_ypass<T, L, -1, LSFFT_VARIANT>), a.grid, Cfg<T>::NTH, a.lds, a.stream, a.desc, a.state, a.items,
+                 a.count, tw,
                  which, ncomp, gate, a.red_inst, a.red_n);
   else
-    LSFFT_LAUNCH((k_ypass<T, L, +1>), a.grid, Cfg<T>::NTH, a.lds, a.stream, a.desc, a.state, a.items, a.count, tw,
+    LSFFT_LAUNCH((k_ypass<T, L, +1, LSFFT_VARIANT>), a.grid, Cfg<T>::NTH, a.lds, a.stream, a.desc, a.state, a.items,
+                 a.count, tw,
                  which, ncomp, gate, a.red_inst, a.red_n);
   return hipGetLastError();
 }
 }  // namespace
 
 template <>
-hipError_t launch_y<T>(const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len) {
+hipError_t launch_y<T, LSFFT_VARIANT>(const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len) {
   switch (len) {
 #define X(L) case L: return y_dirs<L>(a, dir, which, ncomp, gate);
+#if LSFFT_VARIANT == 0
     LSFFT_LEN_CASES(X)
+#else
+    LSFFT_LEN_CASES_LONG(X)
+#endif
 #undef X
     default: return hipErrorInvalidValue;
   }
@@ -87,10 +102,10 @@ hipError_t g_modes(const LaunchArgs& a, int mode) {
   switch (mode) {
 #define M(MODE)                                                                                                 \
   case MODE:                                                                                                    \
-    LSFFT_LAUNCH((k_green<T, L, LSFFT_DIM, MODE>), a.grid, Cfg<T>::NTH_G, a.lds, a.stream, a.desc, a.state,  \
-                 a.items, a.count, tw);                                                                         \
+    LSFFT_LAUNCH((k_green<T, L, LSFFT_DIM, MODE, LSFFT_VARIANT>), a.grid, (GSched<T, L, LSFFT_VARIANT>::NTH),  \
+                 a.lds, a.stream, a.desc, a.state, a.items, a.count, tw);                                      \
     return hipGetLastError();
-    M(M_FT) M(M_INIT) M(M_ITER) M(M_MAT) M(M_CG_INIT) M(M_CG_AP) M(M_CG_DIR)
+    M(M_FT) M(M_INIT) M(M_ITER) M(M_MAT) M(M_CG_INIT) M(M_CG_AP) M(M_CG_DIR) M(M_AA_RES) M(M_AA_UPD) M(M_KCONV)
 #undef M
     default: return hipErrorInvalidValue;
   }
@@ -98,7 +113,7 @@ hipError_t g_modes(const LaunchArgs& a, int mode) {
 }  // namespace
 
 template <>
-hipError_t launch_g<T, LSFFT_DIM, (LSFFT_LONG != 0)>(const LaunchArgs& a, int mode, int len) {
+hipError_t launch_g<T, LSFFT_DIM, (LSFFT_LONG != 0), LSFFT_VARIANT>(const LaunchArgs& a, int mode, int len) {
   switch (len) {
 #define X(L) case L: return g_modes<L>(a, mode);
 #if LSFFT_LONG

@@ -50,9 +50,6 @@ constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi 
 // Threads per workgroup and tile elements per component, per kernel family:
 // x and y passes hold 8 (FP32) / 4 (FP64) points per thread, the outer pass 4.
 template <typename T> struct Cfg;
-#ifndef LSFFT_XPLAN
-#define LSFFT_XPLAN Plan
-#endif
 #ifndef LSFFT_XNTH_F32
 #define LSFFT_XNTH_F32 256
 #endif
@@ -87,13 +84,67 @@ template <typename T, int N> struct SGeom {
   static constexpr int MPG = clampi(pow2floor((sizeof(T) == 4 && N >= LSFFT_G2_MIN ? 2 * Cfg<T>::E_G : Cfg<T>::E_G) / N), 1, 64);
 };
 
-// rows per x tile (H = nx / 2 complex points per row); odd LDS pitches
-template <typename T, int H> struct XGeom {
-  static constexpr int MR = clampi(pow2floor(Cfg<T>::EX / H), 1, 64);
+// rows per x tile (H = nx / 2 complex points per row); odd LDS pitches.
+// DIV divides the tile's entries (schedule variant 1 of the x pass).
+template <typename T, int H, int DIV = 1> struct XGeom {
+  static constexpr int MR = clampi(pow2floor(Cfg<T>::EX / DIV / H), 1, 64);
   static constexpr int SM = ((H + 1) % 2 == 1) ? (H + 1) : (H + 2);  // fold tile, H + 1 entries
   static constexpr int SKW = H + (H >> 5) + 1;                        // skewed row length
   static constexpr int SM2 = (SKW % 2 == 1) ? SKW : (SKW + 1);         // transform staging
 };
+
+// occupancy targets (waves per SIMD) that bound the register allocation
+template <typename T, int NG> struct WavesG { static constexpr int value = (NG >= LSFFT_G2_MIN) ? 2 : 3; };
+template <int NG> struct WavesG<double, NG> { static constexpr int value = 2; };
+#ifndef LSFFT_WAVES_X
+#define LSFFT_WAVES_X 3
+#endif
+#ifndef LSFFT_WAVES_Y
+#define LSFFT_WAVES_Y 4
+#endif
+
+// ---------------------------------------------------------------------------
+// schedules: compiled variants of a pass kernel for one transform length.
+// Variant 0 is the hand-tuned default; FP32 3D plans also carry the others
+// for lengths of 32 points and more, and lsfft_autotune times them per
+// length and keeps the fastest.
+//   outer pass: 0 default tile; 1 half the pencils (finer work items, same
+//               occupancy target); 2 twice the pencils (512-thread
+//               workgroups on 256-point pencils, full 128-byte lines)
+//   y pass:     0 default; 1 twice the pencils at 2 waves per SIMD; 2 the
+//               other radix order (PlanG instead of Plan)
+//   x pass:     0 default; 1 row tiles of half the entries, register-staged
+//               (fewer registers per thread, finer items); 2 the other radix
+//               order of the core (PlanG instead of Plan)
+// The outer pass keeps PlanG (last radix at most 4): its tiles hold the
+// points of four pass kinds in registers at once, and the plans ending in
+// radix 8 spill there.
+// ---------------------------------------------------------------------------
+constexpr int kVarG = 3, kVarY = 3, kVarX = 3;
+template <typename T, int N, int V> struct GSched {
+  static constexpr int MP0 = SGeom<T, N>::MPG;
+#ifdef LSFFT_WAVES_G
+  static constexpr int W0 = LSFFT_WAVES_G;
+#else
+  static constexpr int W0 = WavesG<T, N>::value;
+#endif
+  static constexpr int MP = V == 1 ? (MP0 > 1 ? MP0 / 2 : 1) : V == 2 ? (MP0 < 64 ? 2 * MP0 : 64) : MP0;
+  static constexpr int NTH = (V == 2 && N >= 256) ? 2 * Cfg<T>::NTH_G : Cfg<T>::NTH_G;
+  static constexpr int WAVES = V == 2 ? 2 : W0;
+};
+template <typename T, int N, int V> struct YSched {
+  static constexpr int MP = V == 1 ? clampi(pow2floor(2 * Cfg<T>::E / N), 1, 64) : SGeom<T, N>::MP;
+  static constexpr int WAVES = V == 1 ? 2 : LSFFT_WAVES_Y;
+  static constexpr bool ALT = V == 2;
+};
+template <int V> struct XSched {
+  static constexpr int EX_DIV = V == 1 ? 2 : 1;   // row-tile entries: Cfg EX / EX_DIV
+  static constexpr bool ALT = V == 2;
+};
+// radix plan family: the default one or the other
+template <bool ALT_IS_G> struct PlanPick;
+template <> struct PlanPick<false> { template <int N> using P = Plan<N>; };
+template <> struct PlanPick<true> { template <int N> using P = PlanG<N>; };
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -260,6 +311,7 @@ __device__ inline void finalize(const InstDesc& D, InstState& St, int mode, doub
   if (mode == M_INIT) {
     St.fnorm2 = a;
     St.iter = 0;
+    St.start_step = 0;
     St.mark = 1e308;
     St.mark_iter = 0;
     St.prev = 1e308;
@@ -279,27 +331,44 @@ __device__ inline void finalize(const InstDesc& D, InstState& St, int mode, doub
     St.residual = delta;
     if (D.history) D.history[0] = delta;
     if (!(delta == delta)) St.status = ST_DIVERGED;
+    else if (D.cg_start) St.start_step = 1;      // Algorithm 3: u1 = b^A first
     else if (delta <= D.tol) St.status = ST_OK;
     else if (D.max_iter <= 0) St.status = ST_NOCONV;
   } else if (mode == M_CG_AP) {
     St.pq = a;
-    St.alpha = St.rz / a;
+    // the printed start u1 = b^A is the update u1 += 1 * p with p = r = b^A
+    St.alpha = St.start_step ? 1.0 : St.rz / a;
   } else if (mode == M_CG_UPD) {
     const double rz_new = a;
+    const double delta = sqrt(b / St.fnorm2);
+    if (St.start_step) {
+      // r = b^A - A(b^A) of the printed start; the next direction is r
+      // (beta = 0) and no iteration is counted
+      St.start_step = 0;
+      St.beta = 0.0;
+      St.rz = rz_new;
+      St.residual = delta;
+      if (D.history) D.history[0] = delta;
+      if (!(delta == delta) || delta > 1e300) St.status = ST_DIVERGED;
+      else if (delta <= D.tol) St.status = ST_OK;
+      else if (D.max_iter <= 0) St.status = ST_NOCONV;
+      return;
+    }
     St.beta = rz_new / St.rz;
     St.rz = rz_new;
     St.iter += 1;
-    const double delta = sqrt(b / St.fnorm2);
     St.residual = delta;
     if (D.history) D.history[St.iter] = delta;
     if (!(delta == delta) || delta > 1e300) St.status = ST_DIVERGED;
     else if (delta <= D.tol) St.status = ST_OK;
     else if (St.iter >= D.max_iter) St.status = ST_NOCONV;
     else {
+      // the plain CG's residual is far from monotone: a longer window
+      const int window = D.precond ? 50 : 1000;
       if (delta < 0.99 * St.mark) {
         St.mark = delta;
         St.mark_iter = St.iter;
-      } else if (St.iter - St.mark_iter >= 50) {
+      } else if (St.iter - St.mark_iter >= window) {
         St.status = ST_STAGNATED;
       }
     }
@@ -317,16 +386,17 @@ __device__ inline void finalize(const InstDesc& D, InstState& St, int mode, doub
 // the forward direction is the mirror image:
 //   X[k] = E + exp(-2 pi i k / NX) O, E = (Z[k] + conj Z[H-k]) / 2,
 //   O = -i (Z[k] - conj Z[H-k]) / 2.
-template <typename T, int NX, int DIM, int MODE>
+template <typename T, int NX, int DIM, int MODE, int V>
 __device__ void xpass_item_std(const InstDesc& D, int local, const double* __restrict__ lame,
                                const T* __restrict__ twtab, unsigned char* smem) {
   constexpr int NTH = Cfg<T>::NTH_X;
   constexpr int H = NX / 2;
-  using G = XGeom<T, H>;
+  using G = XGeom<T, H, XSched<V>::EX_DIV>;
   constexpr int MR = G::MR, SM = G::SM, SM2 = G::SM2;
   constexpr int S = (DIM == 3) ? 6 : 3;
-  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true>;   // C2R core
-  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, true>;  // R2C core
+  using PF = PlanPick<XSched<V>::ALT>;
+  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, PF::template P, true>;   // C2R core
+  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, PF::template P, true>;  // R2C core
   static_assert(FI::RL == FF::R0 && FI::BL == FF::B0, "x transforms must chain in registers");
   constexpr int BP = FI::BL, RP = FI::RL;          // points held per thread: BP x RP
   constexpr int TOTP = FI::TOTL;
@@ -621,7 +691,7 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
 // fold tiles once their data has been read.
 constexpr int kXDmaPhases = kMaxPhases;
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-template <typename T, int H> struct XDma {
+template <typename T, int H, bool ALT = false> struct XDma {
   using G = XGeom<T, H>;
   static constexpr int MR = G::MR;
   static constexpr bool ok = sizeof(T) == 4 && MR * H == 2048 && Cfg<T>::NTH_X == 256;
@@ -630,7 +700,7 @@ template <typename T, int H> struct XDma {
   // fold-tile pitch for the unfold: the forward core leaves NB = H / RL
   // consecutive entries of a row in consecutive lanes, so a pitch of NB
   // (mod 32) puts the rows of a wave on disjoint LDS banks
-  static constexpr int NB = H / PlanSeq<LSFFT_XPLAN, H, false>::last();
+  static constexpr int NB = H / PlanSeq<PlanPick<ALT>::template P, H, false>::last();
   static constexpr int SMF = (H + 1 + ((NB - (H + 1) % 32) % 32 + 32) % 32);
   // transform staging pitch and skew
 #ifndef LSFFT_XSTG
@@ -674,17 +744,18 @@ __device__ __forceinline__ void xdma_issue(const char* comp, int row0, int nrows
 
 __device__ __forceinline__ void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-template <typename T, int NX, int DIM>
+template <typename T, int NX, int DIM, int V>
 __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __restrict__ lame,
                                const T* __restrict__ twtab, unsigned char* smem) {
   constexpr int NTH = 256;
   constexpr int H = NX / 2;
   using G = XGeom<T, H>;
-  using X = XDma<T, H>;
+  using X = XDma<T, H, XSched<V>::ALT>;
   constexpr int MR = G::MR, SM = X::SMF, SM2 = X::SMS;
   constexpr int S = (DIM == 3) ? 6 : 3;
-  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, X::SKS, true>;
-  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, LSFFT_XPLAN, X::SKS, true>;
+  using PF = PlanPick<XSched<V>::ALT>;
+  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, PF::template P, X::SKS, true>;
+  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, PF::template P, X::SKS, true>;
   static_assert(FI::RL == FF::R0 && FI::BL == FF::B0, "x transforms must chain in registers");
   static_assert(X::NB == H / FF::RL && SM % 32 == X::NB % 32 && SM > H, "fold-tile pitch");
   constexpr int BP = FI::BL, RP = FI::RL;
@@ -888,16 +959,16 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   (void)S;
 }
 
-template <typename T, int NX, int DIM, int MODE>
+template <typename T, int NX, int DIM, int MODE, int V>
 __device__ __forceinline__ void xpass_item(const InstDesc& D, int local, const double* __restrict__ lame,
                                            const T* __restrict__ twtab, unsigned char* smem) {
 #ifndef LSFFT_NO_XDMA
-  if constexpr (MODE == M_ITER && XDma<T, NX / 2>::ok) {
-    xpass_iter_dma<T, NX, DIM>(D, local, lame, twtab, smem);
+  if constexpr (MODE == M_ITER && XSched<V>::EX_DIV == 1 && XDma<T, NX / 2, XSched<V>::ALT>::ok) {
+    xpass_iter_dma<T, NX, DIM, V>(D, local, lame, twtab, smem);
     return;
   }
 #endif
-  xpass_item_std<T, NX, DIM, MODE>(D, local, lame, twtab, smem);
+  xpass_item_std<T, NX, DIM, MODE, V>(D, local, lame, twtab, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -960,14 +1031,14 @@ __device__ __forceinline__ TileAddr gtile(const InstDesc& D, int local, int MP) 
   return t;
 }
 
-template <typename T, int NY, int DIR>
+template <typename T, int NY, int DIR, int V>
 __device__ void ypass_item(const InstDesc& D, int local, int c, void* buf, const T* __restrict__ twtab,
                            unsigned char* smem) {
   constexpr int NTH = Cfg<T>::NTH;
-  constexpr int MP = SGeom<T, NY>::MP;
+  constexpr int MP = YSched<T, NY, V>::MP;
   constexpr int LP = (MP > 1) ? MP + 1 : 1;     // padded LDS row (one index, all pencils)
   constexpr int E = LP * NY;
-  using F = TileFft<T, NY, DIR, (DIR > 0), MP, 1, LP, 1, false, NTH>;
+  using F = TileFft<T, NY, DIR, (DIR > 0), MP, 1, LP, 1, false, NTH, PlanPick<YSched<T, NY, V>::ALT>::template P>;
   T* re = reinterpret_cast<T*>(smem);
   T* im = re + E;
   T* twr = im + E;
@@ -1016,11 +1087,12 @@ __device__ void ypass_item(const InstDesc& D, int local, int c, void* buf, const
 // ---------------------------------------------------------------------------
 // Green / body-force pass along the outermost axis
 // ---------------------------------------------------------------------------
-template <typename T, int NG, int DIM, int MODE>
+template <typename T, int NG, int DIM, int MODE, int V>
 __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int local,
                            const T* __restrict__ twtab, unsigned char* smem) {
-  constexpr int NTH = Cfg<T>::NTH_G;
-  constexpr int MP = SGeom<T, NG>::MPG;
+  using GS = GSched<T, NG, V>;
+  constexpr int NTH = GS::NTH;
+  constexpr int MP = GS::MP;
   constexpr int LP = (MP > 1) ? MP + 1 : 1;     // padded LDS row
   constexpr int E = LP * NG;
   constexpr int S = (DIM == 3) ? 6 : 3;
@@ -1271,7 +1343,8 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
           ur[a] = vr[a][q][r];
           ui[a] = vi[a][q][r];
         }
-        apply_n0<T, DIM>(xi, xi2, c0, mu0, ur, ui);   // N0 r
+        // N0 r (the plain CG of Algorithm 3 keeps z = r; r vanishes where xi = 0)
+        if (MODE != M_CG_INIT || D.precond) apply_n0<T, DIM>(xi, xi2, c0, mu0, ur, ui);
         if constexpr (!early_u) LSFFT_FENCE();
         if constexpr (MODE == M_CG_INIT) {
 #pragma unroll
@@ -1366,7 +1439,7 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
           zr[a] = rv.x;
           zi[a] = rv.y;
         }
-        apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
+        if (D.precond) apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
           const typename C2<T>::type pd = ldc<T>(cptr<T>(D.Pd, Pc, a), g);
@@ -1378,6 +1451,203 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
       }
     }
     inverse_all(D.S, 0, std::integral_constant<int, S>{}, strain_gen);
+  } else if constexpr (MODE == M_KCONV) {
+    // periodic convolution with a kernel given by its half spectrum:
+    // eps^_c = sum_j Kh_cj f^_j / |N| from the (projected) force spectrum,
+    // then the inverse outer transforms of the s components
+#pragma unroll
+    for (int q = 0; q < BP; ++q)
+#pragma unroll
+      for (int r = 0; r < RP; ++r)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          T re = T(0), im = T(0);
+          if (pv[q]) {
+            const typename C2<T>::type fv = ldc<T>(cptr<T>(D.F, Pc, a), gidx(q, r));
+            re = fv.x;
+            im = fv.y;
+          }
+          vr[a][q][r] = re;
+          vi[a][q][r] = im;
+        }
+    // The kx = 0 column packs two planes, Z = P0 + i PH (P0, PH the planes'
+    // own spectra over (ky, kz)), and a product of two packed spectra is not
+    // the packed product: there P0 = (Z + conj Z') / 2 and PH = (Z - conj Z')
+    // / (2 i) with Z' the entry at (-ky, -kz), and A0 B0 + i AH BH =
+    // ((A + A*)(B + B*) - i (A - A*)(B - B*)) / 4 with X* = conj X'.
+    int pk0[BP], pth[BP];
+#pragma unroll
+    for (int q = 0; q < BP; ++q) {
+      int m, j;
+      FF::template bj<RP>(tid + q * NTH, m, j);
+      pk0[q] = t.kx(m) == 0;
+      pth[q] = t.other(m);
+    }
+    inverse_all(D.S, 0, std::integral_constant<int, S>{}, [&](int c, int q, int r, T& re, T& im) {
+      re = T(0);
+      im = T(0);
+      if (!pv[q]) return;
+      const int g = gidx(q, r);
+      if (pk0[q]) {
+        const int n = pj[q] + r * NSTEP;
+        const int gp = (DIM == 3) ? (((D.nz - n) % D.nz) * D.ny + (D.ny - pth[q]) % D.ny) * D.H
+                                  : ((D.ny - n) % D.ny) * D.H;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          const typename C2<T>::type a = ldc<T>(cptr<T>(D.Kh, Pc, c * DIM + j), g);
+          const typename C2<T>::type a2 = ldc<T>(cptr<T>(D.Kh, Pc, c * DIM + j), gp);
+          const typename C2<T>::type b2 = ldc<T>(cptr<T>(D.F, Pc, j), gp);
+          const T br = vr[j][q][r], bi = vi[j][q][r];
+          const T pr = a.x + a2.x, pi = a.y - a2.y;          // A + A*
+          const T qr = a.x - a2.x, qi = a.y + a2.y;          // A - A*
+          const T rr = br + b2.x, ri = bi - b2.y;            // B + B*
+          const T sr = br - b2.x, si = bi + b2.y;            // B - B*
+          const T ur = pr * rr - pi * ri, ui = pr * ri + pi * rr;   // (A + A*)(B + B*)
+          const T vr_ = qr * sr - qi * si, vi_ = qr * si + qi * sr; // (A - A*)(B - B*)
+          re += T(0.25) * (ur + vi_);
+          im += T(0.25) * (ui - vr_);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          const typename C2<T>::type kv = ldc<T>(cptr<T>(D.Kh, Pc, c * DIM + j), g);
+          re += kv.x * vr[j][q][r] - kv.y * vi[j][q][r];
+          im += kv.x * vi[j][q][r] + kv.y * vr[j][q][r];
+        }
+      }
+      re *= inv_n;
+      im *= inv_n;
+    });
+    return;
+  } else if constexpr (MODE == M_AA_RES) {
+    // Anderson acceleration, first half, at iteration k (state x_k in
+    // U[cur], x_{k-1} in the other buffer): the residual r = i xi . sigma^ +
+    // f^ with its FP64 norm, F = N0 r (the basic scheme's step), the newest
+    // differences dF = F - F_{k-1} and dU = x_k - x_{k-1} into ring slot
+    // (k - 1) mod m, F into Fp, and the inner products of the window's dF_j
+    // (newest first) with dF and with F.  No inverse transforms.
+    zero_v();
+    forward_all(D.S, std::integral_constant<int, S>{},
+                [&](int c, int q, int r, T re, T im) { div_acc(c, q, r, re, im, T(1)); });
+    const int k = St->iter;
+    const int m = D.aa_m;
+    const int nw = k < m ? k : m;
+    const int snew = k >= 1 ? (k - 1) % m : 0;
+    double pg[kAAMax], pb[kAAMax];
+#pragma unroll
+    for (int j = 0; j < kAAMax; ++j) {
+      pg[j] = 0.0;
+      pb[j] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < BP; ++q) {
+      if (!pv[q]) continue;
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        T xi[DIM], xi2;
+        point_xi(q, r, xi, xi2);
+        const int g = gidx(q, r);
+        T fr[DIM], fi[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const typename C2<T>::type fv = ldc<T>(cptr<T>(D.F, Pc, a), g);
+          const T rr = vr[a][q][r] + fv.x, ri = vi[a][q][r] + fv.y;
+          part += double(pw[q]) * (double(rr) * double(rr) + double(ri) * double(ri));
+          fr[a] = rr;
+          fi[a] = ri;
+        }
+        apply_n0<T, DIM>(xi, xi2, c0, mu0, fr, fi);   // F = N0 r
+        if (k >= 1) {
+          T dfr[DIM], dfi[DIM];
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            const typename C2<T>::type fo = ldc<T>(cptr<T>(D.Fp, Pc, a), g);
+            const typename C2<T>::type u0 = ldc<T>(cptr<T>(D.U[cur], Pc, a), g);
+            const typename C2<T>::type u1 = ldc<T>(cptr<T>(D.U[cur ^ 1], Pc, a), g);
+            dfr[a] = fr[a] - fo.x;
+            dfi[a] = fi[a] - fo.y;
+            stc<T>(mptr<T>(D.DF, Pc, snew * DIM + a), g, dfr[a], dfi[a]);
+            stc<T>(mptr<T>(D.DU, Pc, snew * DIM + a), g, u0.x - u1.x, u0.y - u1.y);
+          }
+#pragma unroll
+          for (int j = 0; j < kAAMax; ++j) {
+            if (j >= nw) break;
+            const int sj = (snew - j + m) % m;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+              T jr = dfr[a], ji = dfi[a];
+              if (j > 0) {
+                const typename C2<T>::type v = ldc<T>(cptr<T>(D.DF, Pc, sj * DIM + a), g);
+                jr = v.x;
+                ji = v.y;
+              }
+              pg[j] += double(pw[q]) * (double(jr) * double(dfr[a]) + double(ji) * double(dfi[a]));
+              pb[j] += double(pw[q]) * (double(jr) * double(fr[a]) + double(ji) * double(fi[a]));
+            }
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) stc<T>(mptr<T>(D.Fp, Pc, a), g, fr[a], fi[a]);
+      }
+    }
+    const double s0 = block_sum<NTH>(part, red);
+    if (tid == 0) gst<double>(D.partial, (long long)kAAPart * local, s0);
+#pragma unroll
+    for (int j = 0; j < kAAMax; ++j) {
+      if (j >= nw) break;
+      const double a1 = block_sum<NTH>(pg[j], red);
+      const double a2 = block_sum<NTH>(pb[j], red);
+      if (tid == 0) {
+        gst<double>(D.partial, (long long)kAAPart * local + 1 + j, a1);
+        gst<double>(D.partial, (long long)kAAPart * local + 1 + kAAMax + j, a2);
+      }
+    }
+    return;
+  } else if constexpr (MODE == M_AA_UPD) {
+    // second half, after the stopping rule advanced the iteration to k + 1:
+    // x_{k+1} = x_k + F_k - sum_j gamma_j (dU_j + dF_j) into the buffer of
+    // x_{k-1}, then its strain spectrum and the inverse outer transforms
+    const int k1 = St->iter;
+    const int cur2 = k1 & 1;
+    const int k = k1 - 1;
+    const int m = D.aa_m;
+    const int nw = k < m ? k : m;
+    const int snew = k >= 1 ? (k - 1) % m : 0;
+    T gam[kAAMax];
+#pragma unroll
+    for (int j = 0; j < kAAMax; ++j) gam[j] = (j < nw) ? T(D.aa[m * m + j]) : T(0);
+#pragma unroll
+    for (int q = 0; q < BP; ++q) {
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        if (!pv[q]) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) { vr[a][q][r] = T(0); vi[a][q][r] = T(0); }
+          continue;
+        }
+        const int g = gidx(q, r);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const typename C2<T>::type xk = ldc<T>(cptr<T>(D.U[cur2 ^ 1], Pc, a), g);
+          const typename C2<T>::type fk = ldc<T>(cptr<T>(D.Fp, Pc, a), g);
+          T nr = xk.x + fk.x, ni = xk.y + fk.y;
+#pragma unroll
+          for (int j = 0; j < kAAMax; ++j) {
+            if (j >= nw) break;
+            const int sj = (snew - j + m) % m;
+            const typename C2<T>::type du = ldc<T>(cptr<T>(D.DU, Pc, sj * DIM + a), g);
+            const typename C2<T>::type df = ldc<T>(cptr<T>(D.DF, Pc, sj * DIM + a), g);
+            nr -= gam[j] * (du.x + df.x);
+            ni -= gam[j] * (du.y + df.y);
+          }
+          stc<T>(mptr<T>(D.U[cur2], Pc, a), g, nr, ni);
+          vr[a][q][r] = nr;
+          vi[a][q][r] = ni;
+        }
+      }
+    }
+    inverse_all(D.S, 0, std::integral_constant<int, S>{}, strain_gen);
+    return;
   }
 
   // FP64 partial sums of this item, one slot per item; a separate one-block
@@ -1455,7 +1725,7 @@ __device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsi
       T zr[DIM], zi[DIM];
 #pragma unroll
       for (int a = 0; a < DIM; ++a) { zr[a] = rr[a]; zi[a] = ri[a]; }
-      apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
+      if (D.precond) apply_n0<T, DIM>(xi, xi2, c0, mu0, zr, zi);
 #pragma unroll
       for (int a = 0; a < DIM; ++a) prz += wgt * (double(rr[a]) * double(zr[a]) + double(ri[a]) * double(zi[a]));
     }
@@ -1483,21 +1753,10 @@ __device__ __forceinline__ int xcd_slot(int b, int G) {
 }
 
 __device__ __forceinline__ bool gated(int mode) {
-  return mode == M_ITER || mode == M_CG_AP || mode == M_CG_UPD || mode == M_CG_DIR || mode == M_CG_INIT;
+  return mode == M_ITER || mode == M_CG_AP || mode == M_CG_UPD || mode == M_CG_DIR || mode == M_CG_INIT ||
+         mode == M_AA_RES || mode == M_AA_UPD;
 }
 
-// occupancy targets (waves per SIMD) that bound the register allocation
-template <typename T, int NG> struct WavesG { static constexpr int value = (NG >= LSFFT_G2_MIN) ? 2 : 3; };
-template <int NG> struct WavesG<double, NG> { static constexpr int value = 2; };
-#ifndef LSFFT_WAVES_G
-#define LSFFT_WAVES_G WavesG<T, NG>::value
-#endif
-#ifndef LSFFT_WAVES_X
-#define LSFFT_WAVES_X 3
-#endif
-#ifndef LSFFT_WAVES_Y
-#define LSFFT_WAVES_Y 4
-#endif
 
 // The supported axis lengths (the twiddle table's order), split into the
 // short ones and those of 32 points and more: the outer-pass launchers of the
@@ -1509,7 +1768,7 @@ template <int NG> struct WavesG<double, NG> { static constexpr int value = 2; };
 // One kernel per (precision, length, dimension, mode): every work item of a
 // launch has the same transform length, so register allocation and LDS
 // layout are those of that length alone.
-template <typename T, int NX, int DIM, int MODE>
+template <typename T, int NX, int DIM, int MODE, int V>
 __global__ __launch_bounds__(Cfg<T>::NTH_X) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_X))) void k_xpass(
     const InstDesc* __restrict__ descs, InstState* __restrict__ states, const WorkItem* __restrict__ items,
     const int* __restrict__ nitems, const double* __restrict__ lame, const T* __restrict__ tw) {
@@ -1519,7 +1778,7 @@ __global__ __launch_bounds__(Cfg<T>::NTH_X) __attribute__((amdgpu_waves_per_eu(L
     const WorkItem it = items[w];
     const InstDesc& D = descs[it.inst];
     if (gated(MODE) && states[it.inst].status != ST_RUNNING) continue;
-    xpass_item<T, NX, DIM, MODE>(D, it.local, lame, tw, smem);
+    xpass_item<T, NX, DIM, MODE, V>(D, it.local, lame, tw, smem);
     __syncthreads();
   }
 }
@@ -1560,6 +1819,82 @@ __device__ inline void reduce_solve(const InstDesc& D, InstState& St, int mode, 
   }
 }
 
+// Anderson acceleration's stopping rule and mixing coefficients, by one
+// block per solve: fixed-order FP64 sums of the per-item partials of
+// M_AA_RES (residual, <dF_j, dF_new>, <dF_j, F>), the stopping rule of the
+// basic scheme, then the Gram matrix row and column of the newest ring slot
+// and the window's normal equations G gamma = b, solved by Gaussian
+// elimination with partial pivoting (a pivot below 1e-30 of the largest
+// diagonal entry drops its direction: gamma = 0 there).
+template <int NTH>
+__device__ inline void reduce_aa(const InstDesc& D, InstState& St, double* red) {
+  if (St.status != ST_RUNNING) return;
+  const int nslot = D.items_g;
+  const int m = D.aa_m;
+  const int k = St.iter;
+  const int nw = k < m ? k : m;
+  double tot[kAAPart];
+  for (int c = 0; c < kAAPart; ++c) {
+    tot[c] = 0.0;
+    if (c != 0 && (c - 1) % kAAMax >= nw) continue;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nslot; i += NTH) a += D.partial[(long long)kAAPart * i + c];
+    tot[c] = block_sum<NTH>(a, red);
+  }
+  if (threadIdx.x != 0) return;
+  InstState loc = St;
+  judge(D, loc, sqrt(tot[0] / loc.fnorm2));
+  if (loc.status == ST_RUNNING && nw > 0) {
+    double* G = D.aa;
+    const int snew = (k - 1) % m;
+    int slot[kAAMax];
+    for (int j = 0; j < nw; ++j) {
+      slot[j] = (snew - j + m) % m;
+      G[snew * m + slot[j]] = tot[1 + j];
+      G[slot[j] * m + snew] = tot[1 + j];
+    }
+    double A[kAAMax][kAAMax], b[kAAMax];
+    double dmax = 0.0;
+    for (int j = 0; j < nw; ++j) {
+      for (int l = 0; l < nw; ++l) A[j][l] = G[slot[j] * m + slot[l]];
+      b[j] = tot[1 + kAAMax + j];
+      dmax = fmax(dmax, fabs(A[j][j]));
+    }
+    bool live[kAAMax];
+    for (int c = 0; c < nw; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < nw; ++r)
+        if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+      live[c] = fabs(A[piv][c]) > 1e-30 * dmax;
+      if (!live[c]) continue;
+      if (piv != c) {
+        for (int l = 0; l < nw; ++l) {
+          const double t = A[c][l];
+          A[c][l] = A[piv][l];
+          A[piv][l] = t;
+        }
+        const double t = b[c];
+        b[c] = b[piv];
+        b[piv] = t;
+      }
+      for (int r = c + 1; r < nw; ++r) {
+        const double f = A[r][c] / A[c][c];
+        for (int l = c; l < nw; ++l) A[r][l] -= f * A[c][l];
+        b[r] -= f * b[c];
+      }
+    }
+    double gam[kAAMax];
+    for (int c = nw - 1; c >= 0; --c) {
+      if (!live[c]) { gam[c] = 0.0; continue; }
+      double v = b[c];
+      for (int l = c + 1; l < nw; ++l) v -= A[c][l] * gam[l];
+      gam[c] = v / A[c][c];
+    }
+    for (int j = 0; j < nw; ++j) G[m * m + j] = gam[j];
+  }
+  St = loc;
+}
+
 // one component per work unit: unit w covers item w % n_items, component w / n_items.
 // With red_n set, the blocks first apply the stopping rule of the outer pass
 // that ran before (basic iteration) to the red_inst[0 .. *red_n) solves; the
@@ -1567,8 +1902,8 @@ __device__ inline void reduce_solve(const InstDesc& D, InstState& St, int mode, 
 // transformed, which is harmless (its returned iterate sits in the other
 // displacement buffer, and its work spectrum is rewritten before any use)
 // as long as each block takes one decision per unit.
-template <typename T, int NY, int DIR>
-__global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_Y))) void k_ypass(
+template <typename T, int NY, int DIR, int V>
+__global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu((YSched<T, NY, V>::WAVES)))) void k_ypass(
     const InstDesc* __restrict__ descs, InstState* __restrict__ states, const WorkItem* __restrict__ items,
     const int* __restrict__ nitems, const T* __restrict__ tw, int which, int ncomp, int gate,
     const int* __restrict__ red_inst, const int* __restrict__ red_n) {
@@ -1587,7 +1922,7 @@ __global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSF
   // XCD-aware order when a tile row is narrower than a 128-byte line
   // (neighbouring tiles then share lines: 8 kx columns of FP32 at ny = 256);
   // with full lines the launch order is kept
-  constexpr bool kXcd = SGeom<T, NY>::MP * 2 * (int)sizeof(T) < 128;
+  constexpr bool kXcd = YSched<T, NY, V>::MP * 2 * (int)sizeof(T) < 128;
   __shared__ int s_run;
   for (int w = kXcd ? xcd_slot(blockIdx.x, gridDim.x) : (int)blockIdx.x; w < n_units; w += gridDim.x) {
     const int c = w / n_items;
@@ -1609,13 +1944,13 @@ __global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu(LSF
       }
     }
     void* buf = (which == 0) ? D.S : D.F;
-    ypass_item<T, NY, DIR>(D, it.local, c, buf, tw, smem);
+    ypass_item<T, NY, DIR, V>(D, it.local, c, buf, tw, smem);
     __syncthreads();
   }
 }
 
-template <typename T, int NG, int DIM, int MODE>
-__global__ __launch_bounds__(Cfg<T>::NTH_G) __attribute__((amdgpu_waves_per_eu(LSFFT_WAVES_G))) void k_green(
+template <typename T, int NG, int DIM, int MODE, int V>
+__global__ __launch_bounds__((GSched<T, NG, V>::NTH)) __attribute__((amdgpu_waves_per_eu((GSched<T, NG, V>::WAVES)))) void k_green(
     const InstDesc* __restrict__ descs, InstState* __restrict__ states, const WorkItem* __restrict__ items,
     const int* __restrict__ nitems, const T* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1625,7 +1960,7 @@ __global__ __launch_bounds__(Cfg<T>::NTH_G) __attribute__((amdgpu_waves_per_eu(L
     const InstDesc& D = descs[it.inst];
     InstState* St = states + it.inst;
     if (gated(MODE) && St->status != ST_RUNNING) continue;
-    green_item<T, NG, DIM, MODE>(D, St, it.local, tw, smem);
+    green_item<T, NG, DIM, MODE, V>(D, St, it.local, tw, smem);
     __syncthreads();
   }
 }
@@ -1663,7 +1998,8 @@ __global__ __launch_bounds__(NTH) void k_reduce(const InstDesc* __restrict__ des
   // keeps its grid while solves retire
   if ((int)blockIdx.x >= *ninst) return;
   const int i = inst_list[blockIdx.x];
-  reduce_solve<NTH>(descs[i], states[i], mode, red);
+  if (mode == M_AA_RES) reduce_aa<NTH>(descs[i], states[i], red);
+  else reduce_solve<NTH>(descs[i], states[i], mode, red);
 }
 
 // Largest phase id of a phase map (argument validation on the device).
@@ -1800,6 +2136,166 @@ __global__ __launch_bounds__(NTR) void k_radial_max(const double* __restrict__ a
     if (lmax[b]) atomicMax(&bins[b], lmax[b]);
 }
 
+// ---- data kernels of the surrogate's dataset --------------------------------
+// Block means: out[f][Z][Y][X] = scale * mean of the fct^d (fct^2 when nz = 1)
+// fine voxels of block (X, Y, Z) of field f; FP64 sums in a fixed order.
+template <typename T, typename TO>
+__global__ __launch_bounds__(NTR) void k_block_mean(const T* __restrict__ in, TO* __restrict__ out, long long nfield,
+                                                    int nx, int ny, int nz, int fct, double scale) {
+  const int fz = nz > 1 ? fct : 1;
+  const int cx = nx / fct, cy = ny / fct, cz = nz / fz;
+  const long long ncoarse = (long long)cx * cy * cz;
+  const long long total = nfield * ncoarse;
+  const double w = scale / double(fct * fct * fz);
+  for (long long o = (long long)blockIdx.x * NTR + threadIdx.x; o < total; o += (long long)gridDim.x * NTR) {
+    const long long fld = o / ncoarse;
+    long long rem = o - fld * ncoarse;
+    const int X = int(rem % cx);
+    rem /= cx;
+    const int Y = int(rem % cy);
+    const int Z = int(rem / cy);
+    const T* src = in + fld * ((long long)nx * ny * nz);
+    double acc = 0.0;
+    for (int dz = 0; dz < fz; ++dz)
+      for (int dy = 0; dy < fct; ++dy)
+        for (int dx = 0; dx < fct; ++dx)
+          acc += double(src[((long long)(Z * fz + dz) * ny + (Y * fct + dy)) * nx + (X * fct + dx)]);
+    out[o] = TO(acc * w);
+  }
+}
+
+// Per-sample Euclidean norms, one block per sample, fixed summation order:
+// res[2 s] = ||y_s - t_s|| (||t_s|| when y is null), res[2 s + 1] = ||t_s||.
+template <typename T>
+__global__ __launch_bounds__(NTR) void k_sample_norms(const T* __restrict__ y, const T* __restrict__ t, long long len,
+                                                      double* __restrict__ res) {
+  __shared__ double red[NTR / 64];
+  const long long base = (long long)blockIdx.x * len;
+  double dd = 0.0, tt = 0.0;
+  for (long long i = threadIdx.x; i < len; i += NTR) {
+    const double tv = double(t[base + i]);
+    const double dv = y ? double(y[base + i]) - tv : tv;
+    dd += dv * dv;
+    tt += tv * tv;
+  }
+  dd = block_sum<NTR>(dd, red);
+  tt = block_sum<NTR>(tt, red);
+  if (threadIdx.x == 0) {
+    res[2 * blockIdx.x] = sqrt(dd);
+    res[2 * blockIdx.x + 1] = sqrt(tt);
+  }
+}
+
+// Bump forces (Eq. 2.5's compact support): force f of a batch is the sum of
+// its bumps exp(-1/(1 - r^2/R^2)) d (r < R, minimum-image distance to the
+// bump's centre in the periodic cell, voxel units; zero outside).  bumps
+// holds per bump (cx, cy, cz, R, dx, dy, dz); first[f] .. first[f + 1] are
+// force f's bumps.  One thread per voxel and force.
+template <typename T>
+__global__ __launch_bounds__(NTR) void k_bump_forces(T* const* __restrict__ fs, const int* __restrict__ first,
+                                                     const double* __restrict__ bumps, int nx, int ny, int nz, int dim) {
+  const int fi = blockIdx.y;
+  const long long nvox = (long long)nx * ny * nz;
+  T* f = fs[fi];
+  for (long long v = (long long)blockIdx.x * NTR + threadIdx.x; v < nvox; v += (long long)gridDim.x * NTR) {
+    const double p[3] = {double(v % nx), double((v / nx) % ny), double(v / ((long long)nx * ny))};
+    const double nn[3] = {double(nx), double(ny), double(nz)};
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = first[fi]; b < first[fi + 1]; ++b) {
+      const double* B = bumps + 7 * b;
+      double r2 = 0.0;
+      for (int a = 0; a < dim; ++a) {
+        double t = fmod(p[a] - B[a], nn[a]);
+        if (t < 0.0) t += nn[a];
+        if (t > 0.5 * nn[a]) t -= nn[a];
+        r2 += t * t;
+      }
+      const double q = r2 / (B[3] * B[3]);
+      if (q < 1.0) {
+        const double e = exp(-1.0 / (1.0 - q));
+        for (int a = 0; a < dim; ++a) acc[a] += e * B[4 + a];
+      }
+    }
+    for (int a = 0; a < dim; ++a) f[a * nvox + v] = T(acc[a]);
+  }
+}
+
+// ---- nonlocal kernel regression (Eqs. 6.5-6.6): normal equations --------
+// Features of the Bernstein kernel basis, Phi_m[u](x) = sum over the
+// horizon's offsets r of B_m(|r| / delta) (u(x + r) - u(x)), grouped by shell
+// (offsets of equal |r|^2): Phi_m = sum_s W[m][s] S_s with the shell sums
+// S_s(x) = sum_{r in shell s} (u(x + r) - u(x)).  One thread per voxel and
+// sample accumulates, over the displacement components, the upper triangle
+// of Phi Phi^T, Phi . Gamma and Gamma . Gamma in FP64; each block writes the
+// fixed-order block sums of its threads to its partial slot.
+constexpr int kNlMaxDeg = 8;                                  // degree M
+constexpr int kNlMaxShell = 48;                               // shells in the horizon
+constexpr int kNlAcc = (kNlMaxDeg + 1) * (kNlMaxDeg + 2) / 2 + (kNlMaxDeg + 1) + 1;
+template <typename T>
+__global__ __launch_bounds__(NTR) void k_nl_gram(const T* __restrict__ u, const T* __restrict__ gam, int nx, int ny,
+                                                 int nz, int dim, const int4* __restrict__ offs, int noffs,
+                                                 const double* __restrict__ W, int nshell, int deg,
+                                                 double* __restrict__ partial) {
+  __shared__ double red[NTR / 64];
+  const long long nvox = (long long)nx * ny * nz;
+  const int k = blockIdx.y;                                   // sample
+  const T* uk = u + (long long)k * dim * nvox;
+  const T* gk = gam + (long long)k * dim * nvox;
+  const int nf = deg + 1;
+  const int ntri = nf * (nf + 1) / 2;
+  double acc[kNlAcc];
+#pragma unroll
+  for (int i = 0; i < kNlAcc; ++i) acc[i] = 0.0;
+  const long long v = (long long)blockIdx.x * NTR + threadIdx.x;
+  if (v < nvox) {
+    const int x = int(v % nx), y = int((v / nx) % ny), z = int(v / ((long long)nx * ny));
+    for (int a = 0; a < dim; ++a) {
+      const T* ua = uk + (long long)a * nvox;
+      const double u0 = double(ua[v]);
+      double sh[kNlMaxShell];
+      for (int q = 0; q < nshell; ++q) sh[q] = 0.0;
+      for (int o = 0; o < noffs; ++o) {
+        const int4 r = offs[o];
+        int xx = x + r.x, yy = y + r.y, zz = z + r.z;
+        xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+        yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+        zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+        sh[r.w] += double(ua[((long long)zz * ny + yy) * nx + xx]) - u0;
+      }
+      double phi[kNlMaxDeg + 1];
+      for (int m = 0; m < nf; ++m) {
+        double t = 0.0;
+        for (int q = 0; q < nshell; ++q) t += W[m * nshell + q] * sh[q];
+        phi[m] = t;
+      }
+      const double gv = double(gk[(long long)a * nvox + v]);
+      int i = 0;
+      for (int m = 0; m < nf; ++m)
+        for (int n2 = m; n2 < nf; ++n2) acc[i++] += phi[m] * phi[n2];
+      for (int m = 0; m < nf; ++m) acc[ntri + m] += phi[m] * gv;
+      acc[ntri + nf] += gv * gv;
+    }
+  }
+  const int nacc = ntri + nf + 1;
+  double* slot = partial + ((long long)k * gridDim.x + blockIdx.x) * kNlAcc;
+  for (int i = 0; i < nacc; ++i) {
+    const double sum = block_sum<NTR>(acc[i], red);
+    if (threadIdx.x == 0) slot[i] = sum;
+  }
+}
+
+// fixed-order sum of every block's partial slot (one block)
+__global__ __launch_bounds__(NTR) void k_nl_gram_sum(const double* __restrict__ partial, long long nslot, int nacc,
+                                                     double* __restrict__ out) {
+  __shared__ double red[NTR / 64];
+  for (int i = 0; i < nacc; ++i) {
+    double a = 0.0;
+    for (long long s = threadIdx.x; s < nslot; s += NTR) a += partial[s * kNlAcc + i];
+    const double sum = block_sum<NTR>(a, red);
+    if (threadIdx.x == 0) out[i] = sum;
+  }
+}
+
 // ---- mixed-precision defect correction: FP64 state, FP32 inner solves ----
 // Wavevector of entry g of the packed half spectrum (xi_x = 0 on the kx = 0
 // column, which also carries the kx = H plane).
@@ -1882,24 +2378,24 @@ __global__ __launch_bounds__(NTR) void k_narrow(const InstDesc* __restrict__ d64
 // ---------------------------------------------------------------------------
 // LDS requirements (bytes) of one work item, per precision and length
 // ---------------------------------------------------------------------------
-template <typename T, int L> constexpr size_t lds_x() {
-  using G = XGeom<T, L / 2>;
+template <typename T, int L, int V = 0> constexpr size_t lds_x() {
+  using G = XGeom<T, L / 2, XSched<V>::EX_DIV>;
   return sizeof(T) * (2 * G::MR * G::SM + 2 * G::MR * G::SM2 + 2 * L + 2 * kMaxPhases);
 }
 // the iteration-mode x kernel (dynamic part only when its tiles are staged
 // in static LDS buffers)
-template <typename T, int L> constexpr size_t lds_xi() {
+template <typename T, int L, int V = 0> constexpr size_t lds_xi() {
 #ifndef LSFFT_NO_XDMA
-  if (XDma<T, L / 2>::ok) return XDma<T, L / 2>::DYN;
+  if (XSched<V>::EX_DIV == 1 && XDma<T, L / 2, XSched<V>::ALT>::ok) return XDma<T, L / 2, XSched<V>::ALT>::DYN;
 #endif
-  return lds_x<T, L>();
+  return lds_x<T, L, V>();
 }
 template <int MP> constexpr int padded(int mp) { return mp > 1 ? mp + 1 : 1; }
-template <typename T, int L> constexpr size_t lds_y() {
-  return sizeof(T) * (2 * padded<0>(SGeom<T, L>::MP) * L + 2 * L);
+template <typename T, int L, int V = 0> constexpr size_t lds_y() {
+  return sizeof(T) * (2 * padded<0>(YSched<T, L, V>::MP) * L + 2 * L);
 }
-template <typename T, int L> constexpr size_t lds_g() {
-  return sizeof(T) * (4 * padded<0>(SGeom<T, L>::MPG) * L + 2 * L + 2) + sizeof(double) * 16;
+template <typename T, int L, int V = 0> constexpr size_t lds_g() {
+  return sizeof(T) * (4 * padded<0>(GSched<T, L, V>::MP) * L + 2 * L + 2) + sizeof(double) * 16;
 }
 
 }  // namespace lsfft

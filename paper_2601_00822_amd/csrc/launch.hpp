@@ -34,42 +34,70 @@ struct LaunchArgs {
   } while (0)
 
 // kind 0: x pass (len = nx); kind 1: y pass (len = ny); kind 2: outer pass
-// (len = nz in 3D, ny in 2D).  Returns the LDS bytes of one work item (0 if
+// (len = nz in 3D, ny in 2D); kind 3: the x pass of the iteration.  Returns
+// the LDS bytes of one work item of schedule variant `var` (0 if
 // unsupported) and the rows or pencils per tile.
-size_t query_geometry(bool f64, int kind, int len, int* per_tile);
+size_t query_geometry(bool f64, int kind, int len, int var, int* per_tile);
 int threads_per_block(bool f64);
-int threads_per_block_green(bool f64);
 
 // Launchers of one pass family for one precision T, dimension DIM (x and
-// outer pass) and length group (outer pass: LONG = lengths from 32 on); each
-// specialization below is built in its own translation unit from k_pass.hip.
-template <typename T, int DIM> hipError_t launch_x(const LaunchArgs& a, int mode, int len);
-template <typename T> hipError_t launch_y(const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len);
-template <typename T, int DIM, bool LONG> hipError_t launch_g(const LaunchArgs& a, int mode, int len);
-template <> hipError_t launch_x<float, 2>(const LaunchArgs&, int, int);
-template <> hipError_t launch_x<float, 3>(const LaunchArgs&, int, int);
-template <> hipError_t launch_x<double, 2>(const LaunchArgs&, int, int);
-template <> hipError_t launch_x<double, 3>(const LaunchArgs&, int, int);
-template <> hipError_t launch_y<float>(const LaunchArgs&, int, int, int, int, int);
-template <> hipError_t launch_y<double>(const LaunchArgs&, int, int, int, int, int);
-template <> hipError_t launch_g<float, 2, false>(const LaunchArgs&, int, int);
-template <> hipError_t launch_g<float, 2, true>(const LaunchArgs&, int, int);
-template <> hipError_t launch_g<float, 3, false>(const LaunchArgs&, int, int);
-template <> hipError_t launch_g<float, 3, true>(const LaunchArgs&, int, int);
-template <> hipError_t launch_g<double, 2, false>(const LaunchArgs&, int, int);
-template <> hipError_t launch_g<double, 2, true>(const LaunchArgs&, int, int);
-template <> hipError_t launch_g<double, 3, false>(const LaunchArgs&, int, int);
-template <> hipError_t launch_g<double, 3, true>(const LaunchArgs&, int, int);
+// outer pass), length group (outer pass: LONG = lengths from 32 on) and
+// schedule variant V (see GSched, YSched, XSched; variants other than 0 are
+// built for FP32 3D and lengths from 32 on only); each specialization below
+// is built in its own translation unit from k_pass.hip.
+template <typename T, int DIM, int V> hipError_t launch_x(const LaunchArgs& a, int mode, int len);
+template <typename T, int V> hipError_t launch_y(const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len);
+template <typename T, int DIM, bool LONG, int V> hipError_t launch_g(const LaunchArgs& a, int mode, int len);
+template <> hipError_t launch_x<float, 2, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_x<float, 3, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_x<float, 3, 1>(const LaunchArgs&, int, int);
+template <> hipError_t launch_x<float, 3, 2>(const LaunchArgs&, int, int);
+template <> hipError_t launch_x<double, 2, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_x<double, 3, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_y<float, 0>(const LaunchArgs&, int, int, int, int, int);
+template <> hipError_t launch_y<float, 1>(const LaunchArgs&, int, int, int, int, int);
+template <> hipError_t launch_y<float, 2>(const LaunchArgs&, int, int, int, int, int);
+template <> hipError_t launch_y<double, 0>(const LaunchArgs&, int, int, int, int, int);
+template <> hipError_t launch_g<float, 2, false, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<float, 2, true, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<float, 3, false, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<float, 3, true, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<float, 3, true, 1>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<float, 3, true, 2>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<double, 2, false, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<double, 2, true, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<double, 3, false, 0>(const LaunchArgs&, int, int);
+template <> hipError_t launch_g<double, 3, true, 0>(const LaunchArgs&, int, int);
 
-// dispatch on (precision, dimension, transform length)
-hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode, int dim, int len);
-hipError_t launch_ypass(bool f64, const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len);
-hipError_t launch_green(bool f64, const LaunchArgs& a, int mode, int dim, int len);
+// Schedule variants: kind 0 x pass, 1 y pass, 2 outer pass.  The number of
+// variants a (precision, dimension, kind, length) has (1 = the default only).
+int schedule_variants(bool f64, int dim, int kind, int len);
+
+// dispatch on (precision, dimension, transform length, schedule variant)
+hipError_t launch_xpass(bool f64, const LaunchArgs& a, int mode, int dim, int len, int var);
+hipError_t launch_ypass(bool f64, const LaunchArgs& a, int dir, int which, int ncomp, int gate, int len, int var);
+hipError_t launch_green(bool f64, const LaunchArgs& a, int mode, int dim, int len, int var);
 hipError_t launch_cg_update(bool f64, const LaunchArgs& a);
 hipError_t launch_reduce(const LaunchArgs& a, const int* inst_list, const int* d_ninst, int ninst, int mode);
 hipError_t launch_phase_max(const uint8_t* phase, long long n, int* out, hipStream_t s);
 hipError_t launch_accumulate(bool f64, int dim, const LaunchArgs& a, const GroupDesc* groups, int g, long long nvox);
 hipError_t launch_scale(double* a, long long n, double s, hipStream_t st);
+// data kernels of the surrogate's dataset (see k_block_mean, k_sample_norms,
+// k_bump_forces)
+hipError_t launch_block_mean(bool f64_in, bool f64_out, const void* in, void* out, long long nfield, int nx, int ny,
+                             int nz, int fct, double scale, hipStream_t st);
+hipError_t launch_sample_norms(bool f64, const void* y, const void* t, int nsample, long long len, double* res,
+                               hipStream_t st);
+hipError_t launch_bump_forces(bool f64, void* const* fs, const int* first, const double* bumps, int nforce, int nx,
+                              int ny, int nz, int dim, hipStream_t st);
+// normal equations of the nonlocal kernel regression: `out` receives the
+// upper triangle of G, then g, then Gamma . Gamma (see k_nl_gram); `partial`
+// holds nl_partial_doubles(nvox, nsample) doubles
+constexpr int kNlMaxDegree = 8, kNlMaxShells = 48;
+hipError_t launch_nl_gram(bool f64, const void* u, const void* gam, int nsample, int nx, int ny, int nz, int dim,
+                          const int4* offs, int noffs, const double* W, int nshell, int deg, double* partial,
+                          double* out, hipStream_t st);
+size_t nl_partial_doubles(long long nvox, int nsample);
 constexpr int kRveBinsMax = 1024;   // bins of launch_radial_max
 hipError_t launch_radial_max(int dim, const double* avg, const int n[3], const double h[3], const double c[3],
                              double dr, int nbins, unsigned long long* bins, hipStream_t st);

@@ -9,7 +9,11 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <cstdio>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "launch.hpp"
@@ -104,6 +108,7 @@ enum ListId { L_XLEAD, L_YLEAD, L_GLEAD, L_X, L_Y, L_G, L_CG, L_XALL, L_YALL, L_
 // specialization (dimension and transform length) and therefore one launch.
 struct Seg {
   int dim = 0, len = 0;
+  int var = 0;         // schedule variant of the pass kernel
   int off = 0, cap = 0, count = 0;
   size_t lds = 0;
   int cidx = 0;        // slot of its item count in the device count array
@@ -119,6 +124,8 @@ struct lsfft_plan_s {
   hipStream_t stream = nullptr;   // plan-owned work stream (capturable)
   hipEvent_t ev_in = nullptr;
   bool graphs = true;
+  bool force_timing = false;   // lsfft_autotune: time every launch
+  int aa_m = 5;                // Anderson memory (LSFFT_ANDERSON)
   bool f64 = false;
   lsfft_scheme scheme = LSFFT_BASIC;
   unsigned flags = 0;
@@ -129,6 +136,7 @@ struct lsfft_plan_s {
   DevBuf tw, arena, meta, lists;
   HostBuf hmeta;            // host mirror of `meta`
   DevBuf rve;               // radial maxima of lsfft_rve_identify
+  DevBuf kspec, zphase;     // lsfft_kernel_convolve: kernel spectrum, all-zero phase map
   bool h2d_inflight = false;  // copies out of `hmeta` may still be queued
   // LSFFT_REFINE64: FP64 companion (same grids, shares the work stream) and
   // the FP64 copies of the forces
@@ -141,6 +149,9 @@ struct lsfft_plan_s {
   double kt_ms[LSFFT_K_COUNT] = {0};
   int64_t kt_n[LSFFT_K_COUNT] = {0};
   bool timing_active = false;
+  // schedule variant per pass kind (0 x, 1 y, 2 outer) and length index,
+  // used by FP32 3D solves (lsfft_autotune, lsfft_schedule_set, the cache)
+  int sched[3][kNumLens] = {};
 };
 
 namespace {
@@ -192,6 +203,7 @@ lsfft_status resolve_ref(const lsfft_phases* t, const lsfft_ref* c0, double* lam
 
 struct Geometry {
   int nx, ny, nz, H, dim, s;
+  int var_x, var_y, var_g;   // schedule variants of the three passes
   long long Pm, Pc, nvox;
   int xtiles, items_x, items_xall, items_xft, items_y, mpk_y, ntk_y, items_g, mpk_g, ntk_g, items_cg;
   size_t lds_x, lds_xi, lds_y, lds_g;   // lds_xi: x pass of the iteration
@@ -210,7 +222,21 @@ int kx_pencils(int mp, int h) {
   return k;
 }
 
-bool geometry(bool f64, const lsfft_grid& g, Geometry* o) {
+int len_index(int L) {
+  for (int i = 0; i < kNumLens; ++i)
+    if (len_at(i) == L) return i;
+  return -1;
+}
+
+// schedule variant of pass `kind` on an axis of `len` points in a plan
+int plan_variant(const int sched[3][kNumLens], bool f64, int dim, int kind, int len) {
+  const int i = len_index(len);
+  if (i < 0) return 0;
+  const int v = sched[kind][i];
+  return (v > 0 && v < schedule_variants(f64, dim, kind, len)) ? v : 0;
+}
+
+bool geometry(bool f64, const lsfft_grid& g, const int sched[3][kNumLens], Geometry* o) {
   o->dim = g.dim;
   o->nx = (int)gnx(g);
   o->ny = (int)gny(g);
@@ -222,11 +248,14 @@ bool geometry(bool f64, const lsfft_grid& g, Geometry* o) {
   o->Pc = o->Pm;
   o->nvox = (long long)o->nz * o->ny * o->nx;
   int mr = 0, mpy = 0, mpg = 0;
-  o->lds_x = query_geometry(f64, 0, o->nx, &mr);
-  o->lds_xi = query_geometry(f64, 3, o->nx, nullptr);
-  o->lds_y = (g.dim == 3) ? query_geometry(f64, 1, o->ny, &mpy) : 0;
   const int outer = (g.dim == 3) ? o->nz : o->ny;
-  o->lds_g = query_geometry(f64, 2, outer, &mpg);
+  o->var_x = plan_variant(sched, f64, g.dim, 0, o->nx);
+  o->var_y = (g.dim == 3) ? plan_variant(sched, f64, g.dim, 1, o->ny) : 0;
+  o->var_g = plan_variant(sched, f64, g.dim, 2, outer);
+  o->lds_x = query_geometry(f64, 0, o->nx, o->var_x, &mr);
+  o->lds_xi = query_geometry(f64, 3, o->nx, o->var_x, nullptr);
+  o->lds_y = (g.dim == 3) ? query_geometry(f64, 1, o->ny, o->var_y, &mpy) : 0;
+  o->lds_g = query_geometry(f64, 2, outer, o->var_g, &mpg);
   if (!o->lds_x || !o->lds_xi || !o->lds_g || (g.dim == 3 && !o->lds_y)) return false;
   const int rows = o->ny * o->nz;
   o->xtiles = (rows + mr - 1) / mr;
@@ -399,16 +428,17 @@ LaunchArgs base_args(Batch& b) {
 }
 
 // Work-list key of solve i for list l: the kernel specialization it needs.
-void list_key(const Batch& b, int l, int i, int* dim, int* len, int* items, size_t* lds) {
+void list_key(const Batch& b, int l, int i, int* dim, int* len, int* items, size_t* lds, int* var) {
   const Geometry& g = b.geo[i];
   *dim = g.dim;
   switch (l) {
-    case L_X: *len = g.nx; *items = g.items_x; *lds = g.lds_xi; break;
-    case L_XALL: *len = g.nx; *items = g.items_xall; *lds = g.lds_x; break;
-    case L_XLEAD: *len = g.nx; *items = g.items_xft; *lds = g.lds_x; break;
-    case L_Y: case L_YALL: case L_YLEAD: *len = g.ny; *items = g.items_y; *lds = g.lds_y; break;
-    case L_G: case L_GALL: case L_GLEAD: *len = (g.dim == 3) ? g.nz : g.ny; *items = g.items_g; *lds = g.lds_g; break;
-    default: *len = 0; *items = g.items_cg; *lds = 0; break;   // L_CG
+    case L_X: *len = g.nx; *items = g.items_x; *lds = g.lds_xi; *var = g.var_x; break;
+    case L_XALL: *len = g.nx; *items = g.items_xall; *lds = g.lds_x; *var = g.var_x; break;
+    case L_XLEAD: *len = g.nx; *items = g.items_xft; *lds = g.lds_x; *var = g.var_x; break;
+    case L_Y: case L_YALL: case L_YLEAD: *len = g.ny; *items = g.items_y; *lds = g.lds_y; *var = g.var_y; break;
+    case L_G: case L_GALL: case L_GLEAD:
+      *len = (g.dim == 3) ? g.nz : g.ny; *items = g.items_g; *lds = g.lds_g; *var = g.var_g; break;
+    default: *len = 0; *items = g.items_cg; *lds = 0; *var = 0; break;   // L_CG
   }
 }
 
@@ -429,9 +459,9 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
       int off = 0;
       for (int i = 0; i < n; ++i) {
         if ((l == L_XLEAD || l == L_YLEAD || l == L_GLEAD) && b.specs[i].leader != i) continue;
-        int dim, len, items;
+        int dim, len, items, var;
         size_t lds;
-        list_key(b, l, i, &dim, &len, &items, &lds);
+        list_key(b, l, i, &dim, &len, &items, &lds, &var);
         if (items == 0) continue;
         Seg* sg = nullptr;
         for (auto& x : b.segs[l])
@@ -441,6 +471,7 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
           sg = &b.segs[l].back();
           sg->dim = dim;
           sg->len = len;
+          sg->var = var;
           sg->cidx = cidx++;
         }
         sg->cap += items;
@@ -477,9 +508,9 @@ lsfft_status upload_lists(Batch& b, const std::vector<int>& running, bool all_to
       }
       for (int i : *src) {
         if ((l == L_XLEAD || l == L_YLEAD || l == L_GLEAD) && b.specs[i].leader != i) continue;
-        int dim, len, cnt;
+        int dim, len, cnt, var;
         size_t lds;
-        list_key(b, l, i, &dim, &len, &cnt, &lds);
+        list_key(b, l, i, &dim, &len, &cnt, &lds, &var);
         if (cnt == 0 || dim != x.dim || len != x.len) continue;
         for (int k = 0; k < cnt; ++k) items[x.off + fill + k] = WorkItem{i, k};
         fill += cnt;
@@ -532,7 +563,7 @@ lsfft_status prepare(Batch& b, bool validate = true) {
   const size_t rs = f64 ? 8 : 4;   // real scalar
   const size_t cs = 2 * rs;        // complex scalar
   const int n = (int)b.specs.size();
-  const bool cg = p->scheme == LSFFT_CG;
+  const bool cg = p->scheme == LSFFT_CG || p->scheme == LSFFT_CG_PLAIN;
 
   if (host_fence(p) != LSFFT_OK) return LSFFT_E_DEVICE;
   // geometry, Lame tables
@@ -541,12 +572,15 @@ lsfft_status prepare(Batch& b, bool validate = true) {
   b.state.assign(n, InstState{});
   b.lame.clear();
   for (int i = 0; i < n; ++i) {
-    if (!geometry(f64, p->grids[b.specs[i].grid], &b.geo[i])) return LSFFT_E_ARG;
+    if (!geometry(f64, p->grids[b.specs[i].grid], p->sched, &b.geo[i])) return LSFFT_E_ARG;
   }
 
   // workspace layout
   size_t off = 0;
+  const bool aa = p->scheme == LSFFT_ANDERSON;
+  const int aam = aa ? p->aa_m : 0;
   std::vector<size_t> o_S(n), o_U0(n), o_U1(n), o_F(n), o_R(n), o_P(n), o_Q(n), o_oe(n), o_ou(n), o_part(n), o_hist(n);
+  std::vector<size_t> o_Fp(n), o_DF(n), o_DU(n), o_aa(n);
   for (int i = 0; i < n; ++i) {
     const Geometry& g = b.geo[i];
     const size_t comp = (size_t)g.Pc * cs;
@@ -563,7 +597,14 @@ lsfft_status prepare(Batch& b, bool validate = true) {
       o_oe[i] = off; off = align_up(off + (size_t)g.nvox * rs * g.s);
       o_ou[i] = off; off = align_up(off + (size_t)g.nvox * rs * g.dim);
     }
-    o_part[i] = off; off = align_up(off + sizeof(double) * 2 * (size_t)std::max(g.items_g, g.items_cg));
+    if (aa) {
+      o_Fp[i] = off; off = align_up(off + comp * g.dim);
+      o_DF[i] = off; off = align_up(off + comp * g.dim * aam);
+      o_DU[i] = off; off = align_up(off + comp * g.dim * aam);
+      o_aa[i] = off; off = align_up(off + sizeof(double) * (size_t)(aam * aam + aam));
+    }
+    const size_t per_item = aa ? kAAPart : 2;
+    o_part[i] = off; off = align_up(off + sizeof(double) * per_item * (size_t)std::max(g.items_g, g.items_cg));
     o_hist[i] = off; off = align_up(off + sizeof(double) * ((size_t)b.max_iter + 2));
   }
   if (!p->arena.ensure(off)) return LSFFT_E_ALLOC;
@@ -636,6 +677,13 @@ lsfft_status prepare(Batch& b, bool validate = true) {
     D.sx = sp.shift[0]; D.sy = sp.shift[1]; D.sz = sp.shift[2];
     D.max_iter = b.max_iter;
     D.group = sp.group;
+    D.precond = (p->scheme == LSFFT_CG_PLAIN) ? 0 : 1;
+    D.cg_start = (p->scheme == LSFFT_CG_PLAIN) ? 1 : 0;
+    D.aa_m = aam;
+    D.Fp = aa ? (void*)(A + o_Fp[i]) : nullptr;
+    D.DF = aa ? (void*)(A + o_DF[i]) : nullptr;
+    D.DU = aa ? (void*)(A + o_DU[i]) : nullptr;
+    D.aa = aa ? reinterpret_cast<double*>(A + o_aa[i]) : nullptr;
     D.Pm = g.Pm; D.Pc = g.Pc; D.nvox = g.nvox;
     const double two_pi = 6.283185307179586476925286766559;
     D.kx = two_pi / (g.nx * gr.h[0]);
@@ -708,7 +756,7 @@ hipError_t pass_x(Batch& b, int list, int mode, int cls) {
   for (const Seg& sg : b.segs[list]) {
     if (sg.count == 0) continue;
     const int t = timed_begin(b.p, cls);
-    hipError_t e = launch_xpass(b.p->f64, timed(b.p, largs(b, list, sg), t), mode, sg.dim, sg.len);
+    hipError_t e = launch_xpass(b.p->f64, timed(b.p, largs(b, list, sg), t), mode, sg.dim, sg.len, sg.var);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -726,7 +774,7 @@ hipError_t pass_y(Batch& b, int list, int dir, int which, int ncomp, int gate, i
       a.red_n = b.d_counts + kMaxSegs - 1;
       reduce = false;
     }
-    hipError_t e = launch_ypass(b.p->f64, timed(b.p, a, t), dir, which, ncomp, gate, sg.len);
+    hipError_t e = launch_ypass(b.p->f64, timed(b.p, a, t), dir, which, ncomp, gate, sg.len, sg.var);
     if (e != hipSuccess) return e;
   }
   // no y launch (2D grids only): the rule runs on its own
@@ -737,7 +785,7 @@ hipError_t pass_g(Batch& b, int list, int mode, int cls) {
   for (const Seg& sg : b.segs[list]) {
     if (sg.count == 0) continue;
     const int t = timed_begin(b.p, cls);
-    hipError_t e = launch_green(b.p->f64, timed(b.p, largs(b, list, sg), t), mode, sg.dim, sg.len);
+    hipError_t e = launch_green(b.p->f64, timed(b.p, largs(b, list, sg), t), mode, sg.dim, sg.len, sg.var);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -805,9 +853,9 @@ lsfft_status read_states(Batch& b, std::vector<int>& running) {
 // a graph (the mixed-precision outer step).
 lsfft_status iterate(Batch& b, int max_rounds = 0, std::vector<int>* running_out = nullptr) {
   lsfft_plan_s* p = b.p;
-  const bool cg = p->scheme == LSFFT_CG;
+  const bool cg = p->scheme == LSFFT_CG || p->scheme == LSFFT_CG_PLAIN;
   hipStream_t st = p->stream;
-  const bool timing = (p->flags & LSFFT_TIMING) != 0;
+  const bool timing = (p->flags & LSFFT_TIMING) != 0 || p->force_timing;
   p->timing_active = timing;
   if (cg) {
     // r0 = P f - A u^b from one operator application on u^b
@@ -824,7 +872,8 @@ lsfft_status iterate(Batch& b, int max_rounds = 0, std::vector<int>* running_out
   // iteration keeps k_reduce, since the host reads the states after it.
   // Timed plans keep k_reduce throughout, so that each pass class is timed
   // on its own.
-  const bool fuse = !cg && !timing;
+  const bool aa = p->scheme == LSFFT_ANDERSON;
+  const bool fuse = !cg && !aa && !timing;
   // one polling round: `per_round` iterations of every running solve
   auto round = [&]() -> hipError_t {
     bool pending = false;
@@ -834,7 +883,11 @@ lsfft_status iterate(Batch& b, int max_rounds = 0, std::vector<int>* running_out
       pending = false;
       if ((e = pass_x(b, L_X, M_ITER, LSFFT_K_XPASS)) != hipSuccess) return e;
       if ((e = pass_y(b, L_Y, -1, 0, 6, 1, LSFFT_K_YPASS)) != hipSuccess) return e;
-      if (!cg) {
+      if (aa) {
+        if ((e = pass_g(b, L_G, M_AA_RES, LSFFT_K_GREEN)) != hipSuccess) return e;
+        if ((e = pass_reduce(b, M_AA_RES)) != hipSuccess) return e;
+        if ((e = pass_g(b, L_G, M_AA_UPD, LSFFT_K_GREEN)) != hipSuccess) return e;
+      } else if (!cg) {
         if ((e = pass_g(b, L_G, M_ITER, LSFFT_K_GREEN)) != hipSuccess) return e;
         if (fuse && k + 1 < per_round) pending = true;
         else if ((e = pass_reduce(b, M_ITER)) != hipSuccess) return e;
@@ -1026,7 +1079,7 @@ lsfft_status run_refined(Batch& b, lsfft_report* rep, double t0_wall) {
   lsfft_plan_s* p = b.p;
   lsfft_plan_s* q = p->sub;
   const int n = (int)b.specs.size();
-  const bool cg = p->scheme == LSFFT_CG;
+  const bool cg = p->scheme == LSFFT_CG || p->scheme == LSFFT_CG_PLAIN;
   hipStream_t st = p->stream;
 
   // FP64 copies of the forces (exact widening), one per leader
@@ -1193,6 +1246,8 @@ void free_plan(lsfft_plan_s* p) {
   p->meta.release();
   p->hmeta.release();
   p->rve.release();
+  p->kspec.release();
+  p->zphase.release();
   p->lists.release();
   p->fwide.release();
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
@@ -1200,6 +1255,80 @@ void free_plan(lsfft_plan_s* p) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// schedule cache: a flat JSON object {"f32/3d/outer/256": 2, ...}
+// ---------------------------------------------------------------------------
+const char* kKindName[3] = {"x", "y", "outer"};
+
+std::string tune_key(bool f64, int dim, int kind, int len) {
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "%s/%dd/%s/%d", f64 ? "f64" : "f32", dim, kKindName[kind], len);
+  return buf;
+}
+
+// "key": integer pairs of a flat JSON object; anything else is skipped
+std::map<std::string, int> parse_tune_cache(const char* text) {
+  std::map<std::string, int> out;
+  if (!text) return out;
+  const char* c = text;
+  while (*c) {
+    if (*c != '"') { ++c; continue; }
+    const char* k0 = ++c;
+    while (*c && *c != '"') ++c;
+    if (!*c) break;
+    std::string key(k0, c - k0);
+    ++c;
+    while (*c == ' ' || *c == '\t' || *c == '\n' || *c == '\r') ++c;
+    if (*c != ':') continue;
+    ++c;
+    while (*c == ' ' || *c == '\t' || *c == '\n' || *c == '\r') ++c;
+    char* end = nullptr;
+    const long v = std::strtol(c, &end, 10);
+    if (end == c) continue;
+    if (v >= 0 && v < 64) out[key] = (int)v;
+    c = end;
+  }
+  return out;
+}
+
+bool read_file(const char* path, std::string* text) {
+  FILE* fh = std::fopen(path, "rb");
+  if (!fh) return false;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, fh)) > 0) text->append(buf, n);
+  std::fclose(fh);
+  return true;
+}
+
+bool write_tune_cache(const char* path, const std::map<std::string, int>& m) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* fh = std::fopen(tmp.c_str(), "wb");
+  if (!fh) return false;
+  std::fprintf(fh, "{\n");
+  size_t k = 0;
+  for (const auto& kv : m) std::fprintf(fh, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++k < m.size() ? "," : "");
+  std::fprintf(fh, "}\n");
+  const bool ok = std::fclose(fh) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+// apply every cache entry that matches one of the plan's grids
+void apply_tune_cache(lsfft_plan_s* p, const std::map<std::string, int>& m) {
+  for (const lsfft_grid& g : p->grids) {
+    const int lens[3] = {(int)gnx(g), (int)gny(g), (int)(g.dim == 3 ? gnz(g) : gny(g))};
+    for (int kind = 0; kind < 3; ++kind) {
+      if (kind == 1 && g.dim != 3) continue;
+      const auto it = m.find(tune_key(p->f64, g.dim, kind, lens[kind]));
+      if (it == m.end()) continue;
+      const int i = len_index(lens[kind]);
+      if (i >= 0 && it->second < schedule_variants(p->f64, g.dim, kind, lens[kind])) p->sched[kind][i] = it->second;
+    }
+  }
+}
+
+std::mutex tune_file_mu;
 
 // ===========================================================================
 // C ABI
@@ -1309,7 +1438,7 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
   *out = nullptr;
   if (!grids || ngrid < 1 || max_batch < 1) return LSFFT_E_ARG;
   if (prec != LSFFT_F32 && prec != LSFFT_F64) return LSFFT_E_ARG;
-  if (scheme != LSFFT_BASIC && scheme != LSFFT_CG) return LSFFT_E_ARG;
+  if (scheme < LSFFT_BASIC || scheme > LSFFT_ANDERSON) return LSFFT_E_ARG;
   if (flags & ~(LSFFT_STRICT_EQUIL | LSFFT_TIMING | LSFFT_REFINE64)) return LSFFT_E_ARG;
   if ((flags & LSFFT_REFINE64) && (prec != LSFFT_F32 || max_batch > 65535)) return LSFFT_E_ARG;
   for (int g = 0; g < ngrid; ++g) {
@@ -1346,6 +1475,12 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
   for (auto& G : p->grids)
     if (G.dim == 2) { G.n[2] = 1; G.h[2] = 1.0; }
   p->max_batch = max_batch;
+  // schedule variants chosen by an earlier lsfft_autotune, if a cache is named
+  if (const char* path = std::getenv("LSFFT_TUNE_CACHE")) {
+    std::string text;
+    std::lock_guard<std::mutex> lock(tune_file_mu);
+    if (read_file(path, &text)) apply_tune_cache(p, parse_tune_cache(text.c_str()));
+  }
   if (const char* e = std::getenv("LSFFT_POLL")) {
     const int v = std::atoi(e);
     if (v >= 1 && v <= 1024) p->poll = v;
@@ -1661,24 +1796,352 @@ lsfft_status lsfft_iteration_bytes(lsfft_plan_t p, int grid_idx, int kernel_clas
   if (!p || !bytes || grid_idx < 0 || grid_idx >= (int)p->grids.size()) return LSFFT_E_ARG;
   if (kernel_class < 0 || kernel_class >= LSFFT_K_COUNT) return LSFFT_E_ARG;
   Geometry g;
-  if (!geometry(p->f64, p->grids[grid_idx], &g)) return LSFFT_E_ARG;
+  if (!geometry(p->f64, p->grids[grid_idx], p->sched, &g)) return LSFFT_E_ARG;
   const double comp = (double)g.Pc * (p->f64 ? 16.0 : 8.0);  // one complex half-spectrum stream
   const double s = g.s, d = g.dim;
-  const bool cg = p->scheme == LSFFT_CG;
+  const bool cg = p->scheme == LSFFT_CG || p->scheme == LSFFT_CG_PLAIN;
   double b = 0.0;
   switch (kernel_class) {
     case LSFFT_K_XPASS: b = 2 * s * comp + (double)g.nvox; break;          // eps^ in, sigma^ out, phase
     case LSFFT_K_YPASS: b = (g.dim == 3) ? 4 * s * comp : 0.0; break;       // two sweeps, in and out
     case LSFFT_K_GREEN:
-      b = cg ? (s + 2 * d) * comp + (3 * d + s) * comp                      // A p pass + direction pass
-             : (2 * s + 3 * d) * comp;                                       // sigma^, u^, f^ in; u^, eps^ out
+      if (p->scheme == LSFFT_ANDERSON) {
+        // residual pass: sigma^, f^, x_k, x_{k-1}, F_{k-1}, m - 1 older dF in;
+        // F, dF, dU out; update pass: x_k, F, m dU and m dF in; x_{k+1}, eps^ out
+        const double m = p->aa_m;
+        b = ((s + 4 * d + (m - 1) * d) + 3 * d + (2 * d + 2 * m * d) + (d + s)) * comp;
+      } else {
+        b = cg ? (s + 2 * d) * comp + (3 * d + s) * comp                    // A p pass + direction pass
+               : (2 * s + 3 * d) * comp;                                     // sigma^, u^, f^ in; u^, eps^ out
+      }
       break;
-    case LSFFT_K_REDUCE: b = 8.0 * 2 * std::max(g.items_g, g.items_cg); break;
+    case LSFFT_K_REDUCE:
+      b = 8.0 * (p->scheme == LSFFT_ANDERSON ? kAAPart : 2) * std::max(g.items_g, g.items_cg);
+      break;
     case LSFFT_K_CGUPD: b = cg ? 6 * d * comp : 0.0; break;
     default: b = 0.0;
   }
   *bytes = b;
   return LSFFT_OK;
+}
+
+lsfft_status lsfft_schedule_get(lsfft_plan_t p, int dim, int kind, int len, int* variant, int* nvariants) {
+  if (!p || (dim != 2 && dim != 3) || kind < 0 || kind > 2 || len_index(len) < 0) return LSFFT_E_ARG;
+  if (variant) *variant = plan_variant(p->sched, p->f64, dim, kind, len);
+  if (nvariants) *nvariants = schedule_variants(p->f64, dim, kind, len);
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_schedule_set(lsfft_plan_t p, int dim, int kind, int len, int variant) {
+  if (!p || (dim != 2 && dim != 3) || kind < 0 || kind > 2 || len_index(len) < 0) return LSFFT_E_ARG;
+  if (variant < 0 || variant >= schedule_variants(p->f64, dim, kind, len)) return LSFFT_E_ARG;
+  if (dim == 3) p->sched[kind][len_index(len)] = variant;   // 2D grids have the default only
+  return LSFFT_OK;
+}
+
+int lsfft_tune_cache_lookup(const char* json_text, int prec, int dim, int kind, int len) {
+  if (!json_text || (prec != LSFFT_F32 && prec != LSFFT_F64) || (dim != 2 && dim != 3) || kind < 0 || kind > 2)
+    return -1;
+  const auto m = parse_tune_cache(json_text);
+  const auto it = m.find(tune_key(prec == LSFFT_F64, dim, kind, len));
+  if (it == m.end() || it->second >= schedule_variants(prec == LSFFT_F64, dim, kind, len)) return -1;
+  return it->second;
+}
+
+lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, lsfft_tune_entry* out, int max_out,
+                            int* nout) {
+  if (check_plan(p) != LSFFT_OK || iters < 1 || iters > 10000 || max_out < 0 || (max_out > 0 && !out)) return LSFFT_E_ARG;
+  if (nout) *nout = 0;
+  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  // kernel time per launch of every variant, keyed by (kind, length) and
+  // summed over the plan's grids that share that pass length
+  std::map<std::pair<int, int>, std::vector<double>> times;
+  const size_t rs = p->f64 ? 8 : 4;
+  // the tuning problem: two phases (E = 1 and 10, nu = 0.3) in a pattern of
+  // 8-voxel blocks, a deterministic pseudo-random force, `iters` iterations
+  double lame[4];
+  const double e_nu[4] = {1.0, 0.3, 10.0, 0.3};
+  if (lsfft_lame_from_young(2, e_nu, lame) != LSFFT_OK) return LSFFT_E_ARG;
+  lsfft_phases tab{2, lame};
+  for (size_t gi = 0; gi < p->grids.size(); ++gi) {
+    const lsfft_grid& g = p->grids[gi];
+    if (g.dim != 3) continue;
+    bool seen = false;
+    for (size_t gj = 0; gj < gi; ++gj)
+      seen = seen || (p->grids[gj].dim == 3 && p->grids[gj].n[0] == g.n[0] && p->grids[gj].n[1] == g.n[1] &&
+                      p->grids[gj].n[2] == g.n[2]);
+    if (seen) continue;
+    const int lens[3] = {(int)gnx(g), (int)gny(g), (int)gnz(g)};
+    int nv[3], rounds = 1;
+    for (int k = 0; k < 3; ++k) {
+      nv[k] = schedule_variants(p->f64, 3, k, lens[k]);
+      rounds = std::max(rounds, nv[k]);
+    }
+    if (rounds == 1) continue;
+    const long long nvox = (long long)lens[0] * lens[1] * lens[2];
+    std::vector<uint8_t> hph((size_t)nvox);
+    std::vector<double> hf(3 * (size_t)nvox);
+    unsigned long long st = 0x9e3779b97f4a7c15ull;
+    for (long long v = 0; v < nvox; ++v) {
+      const long long x = v % lens[0], y = (v / lens[0]) % lens[1], z = v / ((long long)lens[0] * lens[1]);
+      hph[(size_t)v] = (uint8_t)(((x / 8) + (y / 8) + (z / 8)) % 3 == 0);
+    }
+    for (double& q : hf) {
+      st = st * 6364136223846793005ull + 1442695040888963407ull;
+      q = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+    void *dph = nullptr, *df = nullptr;
+    if (hipMalloc(&dph, (size_t)nvox) != hipSuccess) return LSFFT_E_ALLOC;
+    if (hipMalloc(&df, 3 * (size_t)nvox * rs) != hipSuccess) {
+      (void)hipFree(dph);
+      return LSFFT_E_ALLOC;
+    }
+    hipError_t he = hipMemcpy(dph, hph.data(), (size_t)nvox, hipMemcpyHostToDevice);
+    if (he == hipSuccess) {
+      if (p->f64) {
+        he = hipMemcpy(df, hf.data(), 3 * (size_t)nvox * rs, hipMemcpyHostToDevice);
+      } else {
+        std::vector<float> ff(hf.begin(), hf.end());
+        he = hipMemcpy(df, ff.data(), 3 * (size_t)nvox * rs, hipMemcpyHostToDevice);
+      }
+    }
+    lsfft_status ls = he == hipSuccess ? LSFFT_OK : LSFFT_E_DEVICE;
+    int keep[3];
+    for (int k = 0; k < 3; ++k) keep[k] = p->sched[k][len_index(lens[k])];
+    for (int r = 0; r < rounds && ls == LSFFT_OK; ++r) {
+      for (int k = 0; k < 3; ++k) p->sched[k][len_index(lens[k])] = r < nv[k] ? r : 0;
+      Batch b;
+      b.p = p;
+      b.tol = 1e-300;
+      b.max_iter = iters;
+      Spec sp;
+      sp.grid = (int)gi;
+      sp.phase = static_cast<const uint8_t*>(dph);
+      sp.tab = &tab;
+      (void)resolve_ref(&tab, nullptr, &sp.lam0, &sp.mu0);
+      sp.f = df;
+      sp.leader = 0;
+      b.specs.push_back(sp);
+      lsfft_report rep;
+      lsfft_kernel_times_reset(p);
+      p->force_timing = true;
+      const lsfft_status rs_ = run_batch(b, &rep, now_s());
+      p->force_timing = false;
+      if (rs_ == LSFFT_E_ARG || rs_ == LSFFT_E_ALLOC || rs_ == LSFFT_E_DEVICE) {
+        ls = rs_;
+        break;
+      }
+      const int cls[3] = {LSFFT_K_XPASS, LSFFT_K_YPASS, LSFFT_K_GREEN};
+      const double per_iter[3] = {1.0, 2.0, p->scheme == LSFFT_BASIC ? 1.0 : 2.0};   // CG, Anderson: two outer launches
+      for (int k = 0; k < 3; ++k) {
+        if (r >= nv[k] || nv[k] == 1) continue;   // passes with the default only are not tuned
+        auto& v = times[{k, lens[k]}];
+        if ((int)v.size() < nv[k]) v.resize(nv[k], 0.0);
+        v[r] += 1e3 * p->kt_ms[cls[k]] / (per_iter[k] * iters);
+      }
+    }
+    for (int k = 0; k < 3; ++k) p->sched[k][len_index(lens[k])] = keep[k];
+    (void)hipFree(dph);
+    (void)hipFree(df);
+    lsfft_kernel_times_reset(p);
+    if (ls != LSFFT_OK) return ls;
+  }
+  // keep the fastest variant per (kind, length)
+  std::map<std::string, int> chosen;
+  int n = 0;
+  for (const auto& kv : times) {
+    const int kind = kv.first.first, len = kv.first.second;
+    const auto& v = kv.second;
+    int best = 0;
+    for (int r = 1; r < (int)v.size(); ++r)
+      if (v[r] < v[best]) best = r;
+    p->sched[kind][len_index(len)] = best;
+    chosen[tune_key(p->f64, 3, kind, len)] = best;
+    for (int r = 0; r < (int)v.size(); ++r, ++n)
+      if (n < max_out) out[n] = lsfft_tune_entry{kind, len, r, r == best ? 1 : 0, v[r]};
+  }
+  if (nout) *nout = n;
+  if (cache_path && !chosen.empty()) {
+    std::lock_guard<std::mutex> lock(tune_file_mu);
+    std::string text;
+    std::map<std::string, int> m;
+    if (read_file(cache_path, &text)) m = parse_tune_cache(text.c_str());
+    for (const auto& kv : chosen) m[kv.first] = kv.second;
+    if (!write_tune_cache(cache_path, m)) return LSFFT_E_ARG;
+  }
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_anderson_memory(lsfft_plan_t p, int m) {
+  if (!p || m < 1 || m > kAAMax) return LSFFT_E_ARG;
+  p->aa_m = m;
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_kernel_convolve(lsfft_plan_t p, int grid_idx, const void* kernel, int nforce,
+                                   const void* const* f, void* const* out) {
+  if (check_plan(p) != LSFFT_OK || !kernel || nforce < 1 || !f || !out) return LSFFT_E_ARG;
+  if (grid_idx < 0 || grid_idx >= (int)p->grids.size()) return LSFFT_E_ARG;
+  for (int i = 0; i < nforce; ++i)
+    if (!f[i] || !out[i]) return LSFFT_E_ARG;
+  const lsfft_grid& gr = p->grids[grid_idx];
+  Geometry geo;
+  if (!geometry(p->f64, gr, p->sched, &geo)) return LSFFT_E_ARG;
+  const int d = geo.dim, s = geo.s;
+  const size_t rs = p->f64 ? 8 : 4, cs = 2 * rs;
+  if (!p->kspec.ensure(cs * (size_t)(s * d) * (size_t)geo.Pc)) return LSFFT_E_ALLOC;
+  if (!p->zphase.ensure((size_t)geo.nvox)) return LSFFT_E_ALLOC;
+  if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+  // the pass kernels read a phase map (Hooke's law in the x pass runs
+  // whatever its output): one phase of unit moduli, unused here
+  LSFFT_TRY(hipMemsetAsync(p->zphase.p, 0, (size_t)geo.nvox, p->stream));
+  const double lame1[2] = {1.0, 1.0};
+  lsfft_phases tab{1, lame1};
+  auto spec_of = [&](const void* src, void* eps) {
+    Spec sp;
+    sp.grid = grid_idx;
+    sp.phase = static_cast<const uint8_t*>(p->zphase.p);
+    sp.tab = &tab;
+    sp.lam0 = 1.0;
+    sp.mu0 = 1.0;
+    sp.f = src;
+    sp.eps = eps;
+    return sp;
+  };
+  // kernel spectrum: the force transform of the s rows [d][N] of the kernel,
+  // each as one transform group, into consecutive rows of kspec
+  {
+    Batch kb;
+    kb.p = p;
+    kb.max_iter = 0;
+    for (int c = 0; c < s; ++c) {
+      kb.specs.push_back(spec_of(static_cast<const char*>(kernel) + (size_t)c * d * geo.nvox * rs, nullptr));
+      kb.specs.back().leader = c;
+    }
+    lsfft_status ls = prepare(kb, false);
+    if (ls != LSFFT_OK) return ls;
+    if (host_fence(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+    for (int c = 0; c < s; ++c) kb.desc[c].F = static_cast<char*>(p->kspec.p) + (size_t)c * d * geo.Pc * cs;
+    std::memcpy(hptr<InstDesc>(kb, 0), kb.desc.data(), sizeof(InstDesc) * s);
+    if ((ls = h2d(kb, 0, sizeof(InstDesc) * s)) != LSFFT_OK) return ls;
+    p->timing_active = false;
+    LSFFT_TRY(pass_x(kb, L_XLEAD, M_FT, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_y(kb, L_YLEAD, -1, 1, 3, 0, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_g(kb, L_GLEAD, M_FT, LSFFT_K_OTHER));
+    LSFFT_TRY(hipStreamSynchronize(p->stream));
+  }
+  // the forces, in batches of at most max_batch: force transform, product
+  // with the kernel spectrum, inverse transforms of the s strain components
+  for (int start = 0; start < nforce; start += p->max_batch) {
+    const int cnt = std::min(p->max_batch, nforce - start);
+    Batch b;
+    b.p = p;
+    b.max_iter = 0;
+    for (int i = 0; i < cnt; ++i) {
+      b.specs.push_back(spec_of(f[start + i], out[start + i]));
+      b.specs.back().leader = i;
+    }
+    lsfft_status ls = prepare(b, false);
+    if (ls != LSFFT_OK) return ls;
+    if (host_fence(p) != LSFFT_OK) return LSFFT_E_DEVICE;
+    for (int i = 0; i < cnt; ++i) b.desc[i].Kh = p->kspec.p;
+    std::memcpy(hptr<InstDesc>(b, 0), b.desc.data(), sizeof(InstDesc) * cnt);
+    if ((ls = h2d(b, 0, sizeof(InstDesc) * cnt)) != LSFFT_OK) return ls;
+    LSFFT_TRY(pass_x(b, L_XLEAD, M_FT, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_y(b, L_YLEAD, -1, 1, 3, 0, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_g(b, L_GLEAD, M_FT, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_g(b, L_GALL, M_KCONV, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_y(b, L_YALL, +1, 0, s, 0, LSFFT_K_OTHER));
+    LSFFT_TRY(pass_x(b, L_XALL, M_MAT, LSFFT_K_OTHER));
+    LSFFT_TRY(hipStreamSynchronize(p->stream));
+  }
+  return LSFFT_OK;
+}
+
+namespace {
+// the device a plan-free entry point runs on, and its stream
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+}  // namespace
+
+lsfft_status lsfft_block_mean(int prec, int out_prec, int nfield, const int64_t* n, int factor, double scale,
+                              const void* in, void* out, void* hip_stream) {
+  if ((prec != LSFFT_F32 && prec != LSFFT_F64) || (out_prec != LSFFT_F32 && out_prec != LSFFT_F64)) return LSFFT_E_ARG;
+  if (nfield < 1 || !n || !in || !out || factor < 1) return LSFFT_E_ARG;
+  if (!is_fin(scale)) return LSFFT_E_ARG;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1 || n[a] > (1 << 20)) return LSFFT_E_ARG;
+    if ((a < 2 || n[a] > 1) && n[a] % factor != 0) return LSFFT_E_ARG;
+  }
+  if (n[0] * n[1] * n[2] > (1ll << 40)) return LSFFT_E_ARG;
+  if (launch_block_mean(prec == LSFFT_F64, out_prec == LSFFT_F64, in, out, nfield, (int)n[0], (int)n[1], (int)n[2],
+                        factor, scale, as_stream(hip_stream)) != hipSuccess)
+    return LSFFT_E_DEVICE;
+  return hipStreamSynchronize(as_stream(hip_stream)) == hipSuccess ? LSFFT_OK : LSFFT_E_DEVICE;
+}
+
+lsfft_status lsfft_sample_norms(int prec, int nsample, int64_t len, const void* y, const void* t, double* norm_diff,
+                                double* norm_t, void* hip_stream) {
+  if ((prec != LSFFT_F32 && prec != LSFFT_F64) || nsample < 1 || nsample > (1 << 24) || len < 1 || !t)
+    return LSFFT_E_ARG;
+  double* dres = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&dres), sizeof(double) * 2 * (size_t)nsample) != hipSuccess)
+    return LSFFT_E_ALLOC;
+  std::vector<double> h(2 * (size_t)nsample);
+  hipStream_t st = as_stream(hip_stream);
+  hipError_t e = launch_sample_norms(prec == LSFFT_F64, y, t, nsample, len, dres, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), dres, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dres);
+  if (e != hipSuccess) return LSFFT_E_DEVICE;
+  for (int i = 0; i < nsample; ++i) {
+    if (norm_diff) norm_diff[i] = h[2 * (size_t)i];
+    if (norm_t) norm_t[i] = h[2 * (size_t)i + 1];
+  }
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_bump_forces(int prec, int dim, const int64_t* n, int nforce, const int* nbump,
+                               const double* bumps, void* const* f, void* hip_stream) {
+  if ((prec != LSFFT_F32 && prec != LSFFT_F64) || (dim != 2 && dim != 3) || !n || nforce < 1 || !nbump || !f)
+    return LSFFT_E_ARG;
+  if (nforce > 65535) return LSFFT_E_ARG;
+  int nz = dim == 3 ? (int)n[2] : 1;
+  for (int a = 0; a < dim; ++a)
+    if (n[a] < 1 || n[a] > (1 << 16)) return LSFFT_E_ARG;
+  std::vector<int> first(nforce + 1, 0);
+  for (int i = 0; i < nforce; ++i) {
+    if (nbump[i] < 0 || !f[i]) return LSFFT_E_ARG;
+    first[i + 1] = first[i] + nbump[i];
+  }
+  const int total = first[nforce];
+  if (total > 0 && !bumps) return LSFFT_E_ARG;
+  // per bump (centre x, y, z, radius, direction x, y, z); the caller gives dim + 1 + dim values
+  std::vector<double> packed(7 * (size_t)std::max(total, 1), 0.0);
+  for (int b = 0; b < total; ++b) {
+    const double* src = bumps + (size_t)b * (2 * dim + 1);
+    for (int a = 0; a < dim; ++a) packed[7 * (size_t)b + a] = src[a];
+    packed[7 * (size_t)b + 3] = src[dim];
+    for (int a = 0; a < dim; ++a) packed[7 * (size_t)b + 4 + a] = src[dim + 1 + a];
+    if (!is_fin(src[dim]) || src[dim] <= 0.0) return LSFFT_E_ARG;
+    for (int k = 0; k < 2 * dim + 1; ++k)
+      if (!is_fin(src[k])) return LSFFT_E_ARG;
+  }
+  hipStream_t st = as_stream(hip_stream);
+  char* dbuf = nullptr;
+  const size_t b_first = sizeof(int) * first.size(), b_bumps = sizeof(double) * packed.size(),
+               b_ptrs = sizeof(void*) * (size_t)nforce;
+  const size_t o_bumps = align_up(b_first, 16), o_ptrs = align_up(o_bumps + b_bumps, 16);
+  if (hipMalloc(reinterpret_cast<void**>(&dbuf), o_ptrs + b_ptrs) != hipSuccess) return LSFFT_E_ALLOC;
+  hipError_t e = hipMemcpy(dbuf, first.data(), b_first, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dbuf + o_bumps, packed.data(), b_bumps, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dbuf + o_ptrs, f, b_ptrs, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_bump_forces(prec == LSFFT_F64, reinterpret_cast<void* const*>(dbuf + o_ptrs),
+                           reinterpret_cast<const int*>(dbuf), reinterpret_cast<const double*>(dbuf + o_bumps), nforce,
+                           (int)n[0], (int)n[1], nz, dim, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dbuf);
+  return e == hipSuccess ? LSFFT_OK : LSFFT_E_DEVICE;
 }
 
 }  // extern "C"

@@ -49,7 +49,15 @@ enum PassMode : int {
   M_CG_DIR = 5,  // CG: p = z + beta p, eps^(p) and its inverse transform
   M_CG_INIT = 6, // CG: r0 = f^ - A u0 from the first operator pass, z0, p0 = z0
   M_FT = 7,      // force transform: R2C along x, y, then the outer axis and projection
+  M_AA_RES = 8,  // Anderson: residual, F = N0 r, newest differences, window inner products
+  M_AA_UPD = 9,  // Anderson: mixed update of the state and its strain spectrum
+  M_KCONV = 10,  // strain spectrum = kernel spectrum x force spectrum, inverse outer transforms
 };
+
+// Anderson acceleration: largest memory, and the per-item partial sums of
+// M_AA_RES (the residual, then <dF_j, dF_new> and <dF_j, F> for j < kAAMax)
+constexpr int kAAMax = 8;
+constexpr int kAAPart = 1 + 2 * kAAMax;
 
 // One solve.  All pointers are device pointers; real and complex buffers are
 // stored in the plan precision (float or double), complex interleaved.
@@ -79,6 +87,9 @@ struct InstDesc {
   int sx, sy, sz;      // microstructure shift: phase read at (x - s) mod n
   int max_iter;
   int group;           // averaging group, -1 if none
+  int precond;         // CG: 1 = preconditioned by N0, 0 = plain (Algorithm 3)
+  int cg_start;        // CG: 1 = Algorithm 3's printed start u1 = b^A
+  int aa_m;            // Anderson memory (1..kAAMax), 0 = not Anderson
   long long Pm, Pc;    // complex entries: main block, component stride
   long long nvox;      // nx * ny * nz
   double kx, ky, kz;   // 2 pi / (n h) per axis
@@ -93,6 +104,11 @@ struct InstDesc {
   void* R;             // CG residual [d][Pc]
   void* Pd;            // CG direction [d][Pc]
   void* Q;             // CG A p [d][Pc]
+  void* Fp;            // Anderson: F of the previous iteration [d][Pc]
+  void* DF;            // Anderson: ring of F differences [aa_m][d][Pc]
+  void* DU;            // Anderson: ring of state differences [aa_m][d][Pc]
+  double* aa;          // Anderson: Gram matrix [aa_m][aa_m] by ring slot, then the coefficients [aa_m]
+  const void* Kh;      // kernel convolution: half spectrum of the kernel [s][d][Pc]
   void* out_eps;       // real [s][nvox] or null
   void* out_sig;       // real [s][nvox] or null
   void* out_u;         // real [d][nvox] or null
@@ -104,7 +120,7 @@ struct InstState {
   int iter;
   int status;
   int done;            // reserved
-  int pad_;
+  int start_step;      // CG: 1 while the forced step of the printed start runs
   int mark_iter;       // iteration of the last >= 1% improvement
   int grow;            // consecutive iterations with a growing residual
   double residual;

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "liblsfft.so")
 OK, W_STAGNATED = 0, 1
 E_ARG, E_ALLOC, E_DEVICE, E_NOCONV, E_NONEQUIL, E_DIVERGED = -1, -2, -3, -4, -5, -6
 F32, F64 = 0, 1
-BASIC, CG = 0, 1
+BASIC, CG, CG_PLAIN, ANDERSON = 0, 1, 2, 3
+SCHEMES = {"basic": BASIC, "cg": CG, "cg_plain": CG_PLAIN, "anderson": ANDERSON}
 STRICT_EQUIL, TIMING, REFINE64 = 0x1, 0x2, 0x4
 K_XPASS, K_YPASS, K_GREEN, K_REDUCE, K_CGUPD, K_OTHER = range(6)
 
@@ -29,13 +30,20 @@ EXPORTS = [
     "lsfft_plan", "lsfft_solve_bfcs", "lsfft_translate_average", "lsfft_translate_average_batch",
     "lsfft_realization_average", "lsfft_rve_identify", "lsfft_rve_identify_noalloc",
     "lsfft_plan_destroy", "lsfft_status_string", "lsfft_lame_from_young", "lsfft_kernel_times",
-    "lsfft_kernel_times_reset", "lsfft_iteration_bytes",
+    "lsfft_kernel_times_reset", "lsfft_iteration_bytes", "lsfft_schedule_get", "lsfft_schedule_set",
+    "lsfft_autotune", "lsfft_tune_cache_lookup", "lsfft_anderson_memory", "lsfft_kernel_convolve",
+    "lsfft_block_mean", "lsfft_sample_norms", "lsfft_bump_forces",
 ]
+PASS_KINDS = {"x": 0, "y": 1, "outer": 2}
 
 
 class Rve(C.Structure):
     _fields_ = [("radius", C.c_double), ("box_radius", C.c_double), ("fits", C.c_int), ("nbins", C.c_int),
                 ("max_eps", C.c_double), ("max_sig", C.c_double)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("kind", C.c_int), ("len", C.c_int), ("variant", C.c_int), ("chosen", C.c_int), ("us", C.c_double)]
 
 
 class Grid(C.Structure):
@@ -104,8 +112,115 @@ def load_library(path: str = LIB_PATH):
     lib.lsfft_kernel_times_reset.restype = ip
     lib.lsfft_iteration_bytes.argtypes = [vp, ip, ip, C.POINTER(dp)]
     lib.lsfft_iteration_bytes.restype = ip
+    lib.lsfft_schedule_get.argtypes = [vp, ip, ip, ip, C.POINTER(ip), C.POINTER(ip)]
+    lib.lsfft_schedule_get.restype = ip
+    lib.lsfft_schedule_set.argtypes = [vp, ip, ip, ip, ip]
+    lib.lsfft_schedule_set.restype = ip
+    lib.lsfft_autotune.argtypes = [vp, ip, C.c_char_p, C.POINTER(TuneEntry), ip, C.POINTER(ip)]
+    lib.lsfft_autotune.restype = ip
+    lib.lsfft_tune_cache_lookup.argtypes = [C.c_char_p, ip, ip, ip, ip]
+    lib.lsfft_tune_cache_lookup.restype = ip
+    lib.lsfft_anderson_memory.argtypes = [vp, ip]
+    lib.lsfft_anderson_memory.restype = ip
+    lib.lsfft_kernel_convolve.argtypes = [vp, ip, vp, ip, C.POINTER(vp), C.POINTER(vp)]
+    lib.lsfft_kernel_convolve.restype = ip
+    lib.lsfft_block_mean.argtypes = [ip, ip, ip, C.POINTER(C.c_int64), ip, dp, vp, vp, vp]
+    lib.lsfft_block_mean.restype = ip
+    lib.lsfft_sample_norms.argtypes = [ip, ip, C.c_int64, vp, vp, C.POINTER(dp), C.POINTER(dp), vp]
+    lib.lsfft_sample_norms.restype = ip
+    lib.lsfft_bump_forces.argtypes = [ip, ip, C.POINTER(C.c_int64), ip, C.POINTER(ip), C.POINTER(dp),
+                                      C.POINTER(vp), vp]
+    lib.lsfft_bump_forces.restype = ip
     _lib = lib
     return lib
+
+
+def _prec_of(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"FP32 or FP64 tensors only, got {t.dtype}")
+
+
+def _dev_check(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous GPU tensor")
+
+
+def block_mean(a, factor: int = 2, scale: float = 1.0, dtype=None, spatial: int = 3):
+    """Block means over the last ``spatial`` axes of ``a`` (FP32 or FP64 GPU
+    tensor), times ``scale``, as ``dtype`` (default: the input's); computed
+    by the library (factor 1: a scaled copy)."""
+    torch = _torch()
+    _dev_check(a, "a")
+    nd = spatial
+    sp = tuple(a.shape[-nd:])
+    nfield = int(np.prod(a.shape[:-nd])) if a.dim() > nd else 1
+    n = (C.c_int64 * 3)(*(list(reversed(sp)) + [1] * (3 - nd)))
+    dtype = dtype or a.dtype
+    out = torch.empty(tuple(a.shape[:-nd]) + tuple(v // factor for v in sp), dtype=dtype, device=a.device)
+    st = load_library().lsfft_block_mean(_prec_of(a), _prec_of(out), nfield, n, int(factor), float(scale),
+                                         C.c_void_p(a.data_ptr()), C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != OK:
+        raise LsfftError(st, "lsfft_block_mean")
+    return out
+
+
+def sample_norms(t, y=None):
+    """Per-sample norms over all but the first axis: (||y - t|| or ||t||,
+    ||t||) as FP64 numpy arrays; computed by the library."""
+    torch = _torch()
+    _dev_check(t, "t")
+    if y is not None:
+        _dev_check(y, "y")
+        if y.shape != t.shape or y.dtype != t.dtype:
+            raise ValueError("y and t must match")
+    ns = int(t.shape[0])
+    ln = int(t.numel() // ns)
+    nd = np.zeros(ns)
+    nt = np.zeros(ns)
+    st = load_library().lsfft_sample_norms(_prec_of(t), ns, ln, None if y is None else C.c_void_p(y.data_ptr()),
+                                           C.c_void_p(t.data_ptr()), nd.ctypes.data_as(C.POINTER(C.c_double)),
+                                           nt.ctypes.data_as(C.POINTER(C.c_double)),
+                                           C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != OK:
+        raise LsfftError(st, "lsfft_sample_norms")
+    return nd, nt
+
+
+def relative_l2(y, t):
+    """Per-sample ||y - t|| / ||t|| (FP64 numpy), computed by the library."""
+    nd, nt = sample_norms(t, y)
+    return nd / nt
+
+
+def bump_forces(shape, params, dtype=None, device=None):
+    """Forces ``[len(params)][d][...shape]`` made of smooth bumps, evaluated
+    by the library: ``params[i]`` lists (centre in array order, radius,
+    direction x first) of force i's bumps."""
+    torch = _torch()
+    dtype = dtype or torch.float64
+    device = device or torch.device("cuda:0")
+    d = len(shape)
+    out = torch.empty((len(params), d) + tuple(shape), dtype=dtype, device=device)
+    nb = (C.c_int * len(params))(*[len(b) for b in params])
+    flat = []
+    for bumps in params:
+        for c, r, v in bumps:
+            flat += [float(x) for x in reversed(list(c))] + [float(r)] + [float(x) for x in v]
+    arr = np.ascontiguousarray(np.asarray(flat if flat else [0.0], dtype=np.float64))
+    ptrs = (C.c_void_p * len(params))(*[out[i].data_ptr() for i in range(len(params))])
+    n = (C.c_int64 * 3)(*(list(reversed(shape)) + [1] * (3 - d)))
+    st = load_library().lsfft_bump_forces(F64 if dtype == torch.float64 else F32, d, n, len(params), nb,
+                                          arr.ctypes.data_as(C.POINTER(C.c_double)), ptrs,
+                                          C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != OK:
+        raise LsfftError(st, "lsfft_bump_forces")
+    return out
 
 
 class LsfftError(RuntimeError):
@@ -152,7 +267,8 @@ class Plan:
     """A solver plan for one or more grids (array-order shapes)."""
 
     def __init__(self, shapes, prec: str = "f64", scheme: str = "basic", max_batch: int = 1,
-                 strict_equil: bool = False, timing: bool = False, spacing=None, refine: bool = False):
+                 strict_equil: bool = False, timing: bool = False, spacing=None, refine: bool = False,
+                 anderson_memory: int = None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("liblsfft needs a HIP GPU; none is visible")
@@ -176,11 +292,15 @@ class Plan:
         self.stream = torch.cuda.current_stream()
         h = C.c_void_p()
         st = self.lib.lsfft_plan(C.byref(h), grids, len(self.shapes), int(max_batch),
-                                 F64 if prec == "f64" else F32, CG if scheme == "cg" else BASIC,
+                                 F64 if prec == "f64" else F32, SCHEMES[scheme],
                                  flags, C.c_void_p(self.stream.cuda_stream))
         if st != OK:
             raise LsfftError(st, "lsfft_plan")
         self.handle = h
+        if anderson_memory is not None:
+            st = self.lib.lsfft_anderson_memory(self.handle, int(anderson_memory))
+            if st != OK:
+                raise LsfftError(st, "lsfft_anderson_memory")
 
     # ------------------------------------------------------------------ utils
     def close(self):
@@ -379,6 +499,54 @@ class Plan:
         return dict(radius=out.radius, box_radius=out.box_radius, fits=bool(out.fits), nbins=nb,
                     max_eps=out.max_eps, max_sig=out.max_sig, profile_eps=prof[:nb].copy(),
                     profile_sig=prof[nmax:nmax + nb].copy())
+
+    # ------------------------------------------------------------------ kernel convolution
+    def kernel_convolve(self, kernel, forces, grid=0):
+        """Periodic convolution of ``forces`` [B][d][...] with ``kernel``
+        [s][d][...] (the averaged point-force response), through the plan's
+        transforms; returns [B][s][...] in the plan precision."""
+        torch = _torch()
+        shp = self.shapes[grid]
+        d = len(shp)
+        s = 6 if d == 3 else 3
+        kp = self._check(kernel, (s, d) + shp, self.dtype, "kernel")
+        B = int(forces.shape[0])
+        out = torch.empty((B, s) + shp, dtype=self.dtype, device=forces.device)
+        fp = (C.c_void_p * B)(*[self._check(forces[i], (d,) + shp, self.dtype, "force") for i in range(B)])
+        op = (C.c_void_p * B)(*[out[i].data_ptr() for i in range(B)])
+        st = self.lib.lsfft_kernel_convolve(self.handle, int(grid), kp, B, fp, op)
+        if st != OK:
+            raise LsfftError(st, "lsfft_kernel_convolve")
+        return out
+
+    # ------------------------------------------------------------------ schedules
+    def schedule(self, kind: str, length: int, dim: int = 3):
+        """(variant in use, number of variants) of pass ``kind`` ("x", "y" or
+        "outer") on an axis of ``length`` points."""
+        v, n = C.c_int(), C.c_int()
+        st = self.lib.lsfft_schedule_get(self.handle, int(dim), PASS_KINDS[kind], int(length), C.byref(v), C.byref(n))
+        if st != OK:
+            raise LsfftError(st, "lsfft_schedule_get")
+        return v.value, n.value
+
+    def set_schedule(self, kind: str, length: int, variant: int, dim: int = 3):
+        st = self.lib.lsfft_schedule_set(self.handle, int(dim), PASS_KINDS[kind], int(length), int(variant))
+        if st != OK:
+            raise LsfftError(st, "lsfft_schedule_set")
+
+    def autotune(self, iters: int = 20, cache_path=None):
+        """Time every schedule variant of the plan's 3D grids and keep the
+        fastest; returns the timings as a list of dicts."""
+        cap = 64
+        out = (TuneEntry * cap)()
+        n = C.c_int()
+        st = self.lib.lsfft_autotune(self.handle, int(iters), None if cache_path is None else str(cache_path).encode(),
+                                     out, cap, C.byref(n))
+        if st != OK:
+            raise LsfftError(st, "lsfft_autotune")
+        kinds = {v: k for k, v in PASS_KINDS.items()}
+        return [dict(kind=kinds[out[i].kind], len=out[i].len, variant=out[i].variant, chosen=bool(out[i].chosen),
+                     us=out[i].us) for i in range(min(n.value, cap))]
 
     # ------------------------------------------------------------------ timing
     def kernel_times(self, kclass: int):

@@ -7,15 +7,17 @@ linear map of the force that commutes with grid translations, i.e. a
 periodic convolution.  Its kernel, the averaged strain response to a unit
 point force at the origin along each axis, comes from three
 ``translate_average`` calls of the batched solver (3 x cell^3 solves).  The
-averaged strain of any force is then that kernel convolved with the force;
-the convolution (a Fourier-space product) is data preparation, done with
-torch's FFT in FP64.  Forces and targets are restricted to the coarse grid
-by block means.
+averaged strain of any force is then that kernel convolved with the force,
+computed by the library's own transforms (``lsfft_kernel_convolve``); forces
+and targets are restricted to the coarse grid by the library's block means.
 
 Training and inference run entirely in the surrogate kernels (bf16 MFMA,
 fp32 accumulation, Adam); this module only moves batches and schedules the
 learning rate.  The solver supplies the held-out targets the surrogate is
-measured against, and stays the fallback (``averaged_strain``).
+measured against and stays the fallback: ``averaged_strain`` serves a
+prediction only when its error, judged per input against the exact
+averaged kernel, is within the caller's bound.  Torch holds the device
+memory; every arithmetic step runs in the library.
 """
 from __future__ import annotations
 
@@ -26,7 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .fno import FnoArch, Surrogate, pack
-from .lsfft import Plan
+from .lsfft import Plan, block_mean, relative_l2 as _relative_l2
 
 
 def cell_shifts(cell: int, d: int = 3) -> np.ndarray:
@@ -58,24 +60,27 @@ def averaged_strain_kernel(phase, lame, cell: int, prec: str = "f64", max_batch:
     return torch.stack(cols, dim=1), reps
 
 
-def kernel_spectrum(K):
+def averaged_strain_from_kernel(K, f, plan: Plan | None = None, max_batch: int = 64):
+    """``f`` [B][3][n][n][n] -> averaged strain [B][6][n][n][n]: the
+    convolution with the averaged kernel ``K`` [6][3][n][n][n], by the
+    library in the kernel's precision (a plan of that grid may be passed in
+    to reuse its workspace)."""
     import torch
-    return torch.fft.rfftn(K, dim=(-3, -2, -1))
+    shape = tuple(K.shape[-3:])
+    own = plan is None
+    if own:
+        plan = Plan([shape], prec="f64" if K.dtype == torch.float64 else "f32", max_batch=max_batch)
+    try:
+        return plan.kernel_convolve(K.contiguous(), f.contiguous())
+    finally:
+        if own:
+            plan.close()
 
 
-def averaged_strain_from_kernel(Khat, f):
-    """``f`` [B][3][n][n][n] -> averaged strain [B][6][n][n][n] (FP64)."""
-    import torch
-    fh = torch.fft.rfftn(f.to(torch.float64), dim=(-3, -2, -1))
-    eh = torch.einsum("cjzyx,bjzyx->bczyx", Khat, fh)
-    return torch.fft.irfftn(eh, s=f.shape[-3:], dim=(-3, -2, -1))
-
-
-def restrict2(a):
-    """2 x 2 x 2 block means of the last three axes."""
-    s = a.shape
-    n = s[-1]
-    return a.reshape(s[:-3] + (n // 2, 2, n // 2, 2, n // 2, 2)).mean(dim=(-5, -3, -1))
+def restrict2(a, dtype=None, scale: float = 1.0):
+    """2 x 2 x 2 block means of the last three axes (times ``scale``, as
+    ``dtype``), by the library."""
+    return block_mean(a.contiguous(), 2, scale=scale, dtype=dtype)
 
 
 def init_params(arch: FnoArch, seed: int) -> np.ndarray:
@@ -143,40 +148,64 @@ def predict(model: Surrogate, X, batch: int):
 
 
 def relative_l2(Y, T):
-    """Per-sample ``||Y - T|| / ||T||`` (FP64), a CPU numpy array."""
-    import torch
-    B = Y.shape[0]
-    d = (Y.double() - T.double()).reshape(B, -1)
-    return (torch.linalg.norm(d, dim=1) / torch.linalg.norm(T.double().reshape(B, -1), dim=1)).cpu().numpy()
+    """Per-sample ``||Y - T|| / ||T||`` (FP64 sums, by the library), a numpy array."""
+    return _relative_l2(Y.contiguous(), T.contiguous())
 
 
 @dataclass
 class TrainedSurrogate:
-    """A trained surrogate with its normalisation and held-out error; the
-    solver is used instead whenever that error exceeds the caller's bound."""
+    """A trained surrogate with its normalisation and its held-out errors."""
     model: Surrogate
     x_scale: float
     t_scale: float
-    heldout_error: float
+    heldout_error: float          # mean relative L2 over the held-out set
+    heldout_max: float = 0.0      # largest held-out relative L2
 
     def predict(self, f_coarse, batch: int = 32):
-        return predict(self.model, (f_coarse / self.x_scale).float().contiguous(), batch) * self.t_scale
+        """Coarse averaged strain [B][6][...] (FP32) of coarse forces."""
+        import torch
+        x = block_mean(f_coarse.contiguous(), 1, scale=1.0 / self.x_scale, dtype=torch.float32)
+        y = predict(self.model, x, batch)
+        return block_mean(y, 1, scale=self.t_scale)
 
 
 def averaged_strain(f_fine, tol_rel: float, surrogate: TrainedSurrogate | None, phase, lame, cell: int,
-                    prec: str = "f32", max_batch: int = 512):
+                    kernel=None, prec: str = "f32", max_batch: int = 512):
     """Coarse translation-averaged strain of the forces ``f_fine``
-    [B][3][n][n][n]: from the surrogate when its held-out error is within
-    ``tol_rel``, else from the solver (every shift of one cell)."""
+    [B][3][n][n][n], with the source of each field.
+
+    * With the averaged kernel ``kernel`` [6][3][n][n][n] (FP64): the exact
+      averaged strain is the kernel convolution; the surrogate's prediction
+      of each input is served when its relative L2 error against that is
+      within ``tol_rel``, the exact field otherwise (per input).
+    * Without it: the surrogate serves every input when its largest held-out
+      error is within ``tol_rel``; otherwise every field comes from the
+      solver (translated average over every shift of one cell).
+    Returns (fields [B][6][n/2]^3 FP32, list of "surrogate" / "kernel" /
+    "solver" per input)."""
     import torch
-    if surrogate is not None and surrogate.heldout_error <= tol_rel:
-        return surrogate.predict(restrict2(f_fine.double())), "surrogate"
+    B = f_fine.shape[0]
+    if kernel is not None:
+        if f_fine.dtype != kernel.dtype:
+            raise TypeError("the forces must have the averaged kernel's dtype")
+        exact = restrict2(averaged_strain_from_kernel(kernel, f_fine), dtype=torch.float32)
+        if surrogate is None:
+            return exact, ["kernel"] * B
+        pred = surrogate.predict(restrict2(f_fine))
+        err = relative_l2(pred, exact)
+        keep = [bool(e <= tol_rel) for e in err]
+        idx = torch.tensor([i for i in range(B) if not keep[i]], dtype=torch.long, device=pred.device)
+        if idx.numel():
+            pred.index_copy_(0, idx, exact.index_select(0, idx))
+        return pred, ["surrogate" if k else "kernel" for k in keep]
+    if surrogate is not None and surrogate.heldout_max <= tol_rel:
+        return surrogate.predict(restrict2(f_fine)), ["surrogate"] * B
     shape = tuple(phase.shape)
     plan = Plan([shape], prec=prec, max_batch=max_batch, refine=(prec == "f32"))
     dt = torch.float64 if prec == "f64" else torch.float32
     out = []
-    for b in range(f_fine.shape[0]):
+    for b in range(B):
         avg, _ = plan.translate_average(phase, lame, f_fine[b].to(dt).contiguous(), cell_shifts(cell, 3))
-        out.append(restrict2(avg[6:12]))
+        out.append(restrict2(avg[6:12].contiguous(), dtype=torch.float32))
     plan.close()
-    return torch.stack(out), "solver"
+    return torch.stack(out), ["solver"] * B

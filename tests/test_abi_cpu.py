@@ -23,7 +23,7 @@ def lib():
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:lsfft_status|const char\*)\s+(lsfft_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:lsfft_status|const char\*|int)\s+(lsfft_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_entry_points():
@@ -124,3 +124,24 @@ def test_enlargement_lengths_match_the_library(lib):
         g = _grid(2, (n, n, 1))
         out = C.c_void_p()
         assert lib.lsfft_plan(C.byref(out), C.byref(g), 1, 1, 1, 0, 0, None) == -1, n
+
+
+def test_tune_cache_lookup(lib):
+    """The schedule cache is a flat JSON object of "prec/dimd/kind/len":
+    variant pairs; entries outside a length's variant count, malformed text
+    and other keys give -1 (the plan then keeps its default)."""
+    text = b'{\n  "f32/3d/outer/256": 2,\n  "f32/3d/x/48": 1, "f32/3d/y/128":0,\n  "f32/3d/y/64": 7,\n' \
+           b'  "f64/3d/outer/256": 1, "junk": [1, 2], "f32/2d/outer/256": 1\n}'
+    look = lib.lsfft_tune_cache_lookup
+    assert look(text, 0, 3, 2, 256) == 2
+    assert look(text, 0, 3, 0, 48) == 1
+    assert look(text, 0, 3, 1, 128) == 0
+    assert look(text, 0, 3, 1, 64) == -1        # no such variant
+    assert look(text, 1, 3, 2, 256) == -1       # FP64 has the default only
+    assert look(text, 0, 2, 2, 256) == -1       # 2D has the default only
+    assert look(text, 0, 3, 2, 128) == -1       # no entry
+    assert look(text, 0, 3, 0, 16) == -1        # short lengths have the default only
+    assert look(b"not json at all", 0, 3, 2, 256) == -1
+    assert look(b'{"f32/3d/outer/256": }', 0, 3, 2, 256) == -1
+    assert look(None, 0, 3, 2, 256) == -1
+    assert look(text, 0, 3, 3, 256) == -1       # kind out of range

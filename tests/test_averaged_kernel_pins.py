@@ -30,3 +30,28 @@ def test_full_shift_average_is_a_convolution():
         conv = sum(np.fft.irfftn(np.fft.rfftn(kern[j][comp]) * fh[j], s=shape, axes=(0, 1)) for j in range(d))
         ref = direct[comp]
         assert np.abs(conv - ref).max() <= 1e-9 * np.abs(ref).max(), comp
+
+
+def test_kernel_convolve_is_the_direct_periodic_sum():
+    """The oracle's Fourier-product convolution against the O(N^2) sum
+    out_c(x) = sum_y sum_j K_cj(x - y) (P f)_j(y) on a tiny grid, the
+    projection P applied in real space with the dense zero-mode projector
+    (no transform routine involved)."""
+    from oracle import dense
+    rng = np.random.default_rng(3)
+    shape = (6, 8)
+    d, s = 2, 3
+    K = rng.normal(size=(s, d) + shape)
+    f = rng.normal(size=(d,) + shape)
+    P = dense.zero_mode_projector(shape)
+    pf = np.stack([(P @ f[j].ravel()).reshape(shape) for j in range(d)])
+    want = np.zeros((s,) + shape)
+    for x0 in range(shape[0]):
+        for x1 in range(shape[1]):
+            for y0 in range(shape[0]):
+                for y1 in range(shape[1]):
+                    i0, i1 = (x0 - y0) % shape[0], (x1 - y1) % shape[1]
+                    for c in range(s):
+                        want[c, x0, x1] += sum(K[c, j, i0, i1] * pf[j, y0, y1] for j in range(d))
+    got = O.kernel_convolve(K, f)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())

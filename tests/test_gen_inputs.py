@@ -49,14 +49,6 @@ def test_inclusion_per_cell_fraction():
     assert abs(vf - 0.2) < 0.02 and abs(ph.mean() - vf) < 1e-12
 
 
-def test_bump_set_torch_matches_numpy_bumps():
-    import torch  # noqa: F401  (CPU evaluation)
-    p = gen.bump_set_params(16, 3, seed=0)
-    t = gen.bump_set_torch(16, p, "cpu").numpy()
-    ref = np.stack([sum(gen.bump_force((16, 16, 16), c, r, v) for c, r, v in b) for b in p])
-    assert np.abs(t - ref).max() < 1e-15
-
-
 def test_point_force():
     f = gen.point_force((4, 6, 8), 1)
     assert f.shape == (3, 4, 6, 8) and f.sum() == 1.0 and f[1, 0, 0, 0] == 1.0
