@@ -250,29 +250,79 @@ hipError_t launch_bump_forces(bool f64, void* const* fs, const int* first, const
   return hipGetLastError();
 }
 
-hipError_t launch_nl_gram(bool f64, const void* u, const void* gam, int nsample, int nx, int ny, int nz, int dim,
-                          const int4* offs, int noffs, const double* W, int nshell, int deg, double* partial,
-                          double* out, hipStream_t st) {
-  if (nshell > kNlMaxShell || deg > kNlMaxDeg || deg < 0 || nsample < 1 || nsample > 65535) return hipErrorInvalidValue;
-  const long long nvox = (long long)nx * ny * nz;
-  const unsigned bx = (unsigned)((nvox + NTR - 1) / NTR);
-  const dim3 grid(bx, (unsigned)nsample);
+static_assert(kNlMaxDegree == kNlMaxDeg && kNlMaxHalo == kNlMaxR && kNlAccWords == kNlAcc &&
+                  kNlGramSlots == kNlGramBlocks,
+              "nonlocal constants of the launcher and the kernels must agree");
+
+static NlGeom nl_geom(int dim, const int n[3], int R, int nshell, int deg) {
+  NlGeom G;
+  G.nx = n[0];
+  G.ny = n[1];
+  G.nz = (dim == 3) ? n[2] : 1;
+  G.dim = dim;
+  G.tx = (dim == 3) ? kNlTX : kNlTX2;
+  G.ty = (dim == 3) ? kNlTY : kNlTY2;
+  G.tz = (dim == 3) ? kNlTZ : 1;
+  G.ntx = (G.nx + G.tx - 1) / G.tx;
+  G.nty = (G.ny + G.ty - 1) / G.ty;
+  G.ntz = (G.nz + G.tz - 1) / G.tz;
+  G.R = R;
+  G.lx = G.tx + 2 * R;
+  G.ly = G.ty + 2 * R;
+  G.lz = (dim == 3) ? G.tz + 2 * R : 1;
+  G.nshell = nshell;
+  G.deg = deg;
+  return G;
+}
+
+void nl_box(int dim, int R, int box[3]) {
+  const int n[3] = {1, 1, 1};
+  const NlGeom G = nl_geom(dim, n, R, 0, 0);
+  box[0] = G.lx;
+  box[1] = G.ly;
+  box[2] = G.lz;
+}
+
+static size_t nl_lds_bytes(const NlGeom& G, bool f64) {
+  const size_t box = (size_t)G.lx * G.ly * G.lz * (f64 ? 8 : 4);
+  const size_t red = (size_t)kNlAcc * (NTR / 64) * sizeof(double);
+  return box > red ? box : red;
+}
+
+hipError_t launch_nl_gram(bool f64, int dim, const int n[3], int R, int deg, int nsample, const void* u,
+                          const void* gam, const int* offs, const int* first, int nshell, const double* W,
+                          double* partial, double* out, hipStream_t st) {
+  if (deg < 0 || deg > kNlMaxDeg || R < 0 || R > kNlMaxR || nsample < 1 || nshell < 0) return hipErrorInvalidValue;
+  const NlGeom G = nl_geom(dim, n, R, nshell, deg);
+  const long long items = (long long)nsample * G.ntx * G.nty * G.ntz;
+  const unsigned grid = (unsigned)(items < kNlGramBlocks ? items : kNlGramBlocks);
+  const size_t lds = nl_lds_bytes(G, f64);
   if (f64)
-    hipLaunchKernelGGL(k_nl_gram<double>, grid, NTR, 0, st, static_cast<const double*>(u),
-                       static_cast<const double*>(gam), nx, ny, nz, dim, offs, noffs, W, nshell, deg, partial);
+    hipLaunchKernelGGL(k_nl_gram<double>, dim3(grid), NTR, lds, st, G, static_cast<const double*>(u),
+                       static_cast<const double*>(gam), nsample, offs, first, W, partial);
   else
-    hipLaunchKernelGGL(k_nl_gram<float>, grid, NTR, 0, st, static_cast<const float*>(u), static_cast<const float*>(gam),
-                       nx, ny, nz, dim, offs, noffs, W, nshell, deg, partial);
+    hipLaunchKernelGGL(k_nl_gram<float>, dim3(grid), NTR, lds, st, G, static_cast<const float*>(u),
+                       static_cast<const float*>(gam), nsample, offs, first, W, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nf = deg + 1;
-  hipLaunchKernelGGL(k_nl_gram_sum, dim3(1), NTR, 0, st, partial, (long long)bx * nsample, nf * (nf + 1) / 2 + nf + 1,
-                     out);
+  hipLaunchKernelGGL(k_nl_gram_sum, dim3(1), NTR, 0, st, partial, (int)grid, out);
   return hipGetLastError();
 }
 
-size_t nl_partial_doubles(long long nvox, int nsample) {
-  return (size_t)((nvox + NTR - 1) / NTR) * (size_t)nsample * kNlAcc;
+hipError_t launch_nl_apply(bool f64, int dim, const int n[3], int R, int nsample, const void* u, const int* offs,
+                           const int* first, int nshell, const double* kw, void* out, hipStream_t st) {
+  if (R < 0 || R > kNlMaxR || nsample < 1 || nshell < 0) return hipErrorInvalidValue;
+  const NlGeom G = nl_geom(dim, n, R, nshell, 0);
+  const long long items = (long long)nsample * G.ntx * G.nty * G.ntz;
+  if (items > 0x7fffffffLL) return hipErrorInvalidValue;
+  const size_t lds = nl_lds_bytes(G, f64);
+  if (f64)
+    hipLaunchKernelGGL(k_nl_apply<double>, dim3((unsigned)items), NTR, lds, st, G, static_cast<const double*>(u),
+                       nsample, offs, first, kw, static_cast<double*>(out));
+  else
+    hipLaunchKernelGGL(k_nl_apply<float>, dim3((unsigned)items), NTR, lds, st, G, static_cast<const float*>(u),
+                       nsample, offs, first, kw, static_cast<float*>(out));
+  return hipGetLastError();
 }
 
 hipError_t launch_scale(double* a, long long n, double s, hipStream_t st) {

@@ -2220,79 +2220,224 @@ __global__ __launch_bounds__(NTR) void k_bump_forces(T* const* __restrict__ fs, 
   }
 }
 
-// ---- nonlocal kernel regression (Eqs. 6.5-6.6): normal equations --------
-// Features of the Bernstein kernel basis, Phi_m[u](x) = sum over the
-// horizon's offsets r of B_m(|r| / delta) (u(x + r) - u(x)), grouped by shell
-// (offsets of equal |r|^2): Phi_m = sum_s W[m][s] S_s with the shell sums
-// S_s(x) = sum_{r in shell s} (u(x + r) - u(x)).  One thread per voxel and
-// sample accumulates, over the displacement components, the upper triangle
-// of Phi Phi^T, Phi . Gamma and Gamma . Gamma in FP64; each block writes the
-// fixed-order block sums of its threads to its partial slot.
-constexpr int kNlMaxDeg = 8;                                  // degree M
-constexpr int kNlMaxShell = 48;                               // shells in the horizon
-constexpr int kNlAcc = (kNlMaxDeg + 1) * (kNlMaxDeg + 2) / 2 + (kNlMaxDeg + 1) + 1;
+// ---- nonlocal kernel regression (Eqs. 6.5-6.6) ---------------------------
+// The operator L_c[u](x) = sum over grid offsets 0 < |r| < delta of
+// K_c(|r|) (u(x + r) - u(x)), K_c = sum_m c_m B_m(|r| / delta) in the
+// Bernstein basis, and the features Phi_m[u] = sum_r B_m(|r| / delta)
+// (u(x + r) - u(x)) of its least-squares fit.  Offsets of equal |r|^2 form a
+// shell: Phi_m = sum_q W[m][q] (S_q - n_q u(x)) with S_q the sum of u over
+// shell q's offsets and n_q its size.
+//
+// A workgroup stages one tile of the periodic field and its halo of width R
+// (the largest offset component) in LDS, one displacement component at a
+// time; each thread owns two voxels of the tile (the second kNlTZ / 2 along z
+// in 3D, kNlTY2 / 2 along y in 2D).  Offsets arrive sorted by shell as LDS
+// index deltas, so the shell loop and the offset loop are uniform across the
+// workgroup.
+constexpr int kNlMaxDeg = 8;                                   // degree M
+constexpr int kNlMaxR = 6;                                     // horizon <= 7 voxels
+constexpr int kNlF = kNlMaxDeg + 1;
+constexpr int kNlTri = kNlF * (kNlF + 1) / 2;
+constexpr int kNlAcc = kNlTri + kNlF + 1;                      // G (upper), g, Gamma . Gamma
+constexpr int kNlTX = 8, kNlTY = 8, kNlTZ = 8;                 // 3D tile
+constexpr int kNlTX2 = 16, kNlTY2 = 32;                        // 2D tile
+constexpr int kNlGramBlocks = 2048;                            // fixed: the sum order never depends on the device
+
+struct NlGeom {
+  int nx, ny, nz, dim;
+  int tx, ty, tz;          // tile
+  int ntx, nty, ntz;       // tiles per axis
+  int R;                   // halo width
+  int lx, ly, lz;          // LDS box (tile + 2 R; lz = 1 in 2D)
+  int nshell;
+  int deg;
+};
+
 template <typename T>
-__global__ __launch_bounds__(NTR) void k_nl_gram(const T* __restrict__ u, const T* __restrict__ gam, int nx, int ny,
-                                                 int nz, int dim, const int4* __restrict__ offs, int noffs,
-                                                 const double* __restrict__ W, int nshell, int deg,
-                                                 double* __restrict__ partial) {
-  __shared__ double red[NTR / 64];
-  const long long nvox = (long long)nx * ny * nz;
-  const int k = blockIdx.y;                                   // sample
-  const T* uk = u + (long long)k * dim * nvox;
-  const T* gk = gam + (long long)k * dim * nvox;
-  const int nf = deg + 1;
-  const int ntri = nf * (nf + 1) / 2;
-  double acc[kNlAcc];
-#pragma unroll
-  for (int i = 0; i < kNlAcc; ++i) acc[i] = 0.0;
-  const long long v = (long long)blockIdx.x * NTR + threadIdx.x;
-  if (v < nvox) {
-    const int x = int(v % nx), y = int((v / nx) % ny), z = int(v / ((long long)nx * ny));
-    for (int a = 0; a < dim; ++a) {
-      const T* ua = uk + (long long)a * nvox;
-      const double u0 = double(ua[v]);
-      double sh[kNlMaxShell];
-      for (int q = 0; q < nshell; ++q) sh[q] = 0.0;
-      for (int o = 0; o < noffs; ++o) {
-        const int4 r = offs[o];
-        int xx = x + r.x, yy = y + r.y, zz = z + r.z;
-        xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-        yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
-        zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
-        sh[r.w] += double(ua[((long long)zz * ny + yy) * nx + xx]) - u0;
-      }
-      double phi[kNlMaxDeg + 1];
-      for (int m = 0; m < nf; ++m) {
-        double t = 0.0;
-        for (int q = 0; q < nshell; ++q) t += W[m * nshell + q] * sh[q];
-        phi[m] = t;
-      }
-      const double gv = double(gk[(long long)a * nvox + v]);
-      int i = 0;
-      for (int m = 0; m < nf; ++m)
-        for (int n2 = m; n2 < nf; ++n2) acc[i++] += phi[m] * phi[n2];
-      for (int m = 0; m < nf; ++m) acc[ntri + m] += phi[m] * gv;
-      acc[ntri + nf] += gv * gv;
+__device__ __forceinline__ void nl_stage(const NlGeom& G, const T* __restrict__ ua, int x0, int y0, int z0, T* lds) {
+  const int nl = G.lx * G.ly * G.lz;
+  for (int i = threadIdx.x; i < nl; i += NTR) {
+    const int ix = i % G.lx, rest = i / G.lx;
+    const int iy = rest % G.ly, iz = rest / G.ly;
+    int gx = (x0 - G.R + ix) % G.nx;
+    int gy = (y0 - G.R + iy) % G.ny;
+    gx += gx < 0 ? G.nx : 0;
+    gy += gy < 0 ? G.ny : 0;
+    int gz = 0;
+    if (G.dim == 3) {
+      gz = (z0 - G.R + iz) % G.nz;
+      gz += gz < 0 ? G.nz : 0;
     }
-  }
-  const int nacc = ntri + nf + 1;
-  double* slot = partial + ((long long)k * gridDim.x + blockIdx.x) * kNlAcc;
-  for (int i = 0; i < nacc; ++i) {
-    const double sum = block_sum<NTR>(acc[i], red);
-    if (threadIdx.x == 0) slot[i] = sum;
+    lds[i] = ua[((long long)gz * G.ny + gy) * G.nx + gx];
   }
 }
 
-// fixed-order sum of every block's partial slot (one block)
-__global__ __launch_bounds__(NTR) void k_nl_gram_sum(const double* __restrict__ partial, long long nslot, int nacc,
+// tile `tile` of a field: origin and this thread's two voxels (local
+// coordinates, LDS index of each voxel's centre, validity)
+__device__ __forceinline__ void nl_tile(const NlGeom& G, int tile, int& x0, int& y0, int& z0, int (&vx)[2],
+                                        int (&vy)[2], int (&vz)[2], int (&base)[2], bool (&ok)[2]) {
+  const int tx = tile % G.ntx, rest = tile / G.ntx;
+  const int ty = rest % G.nty, tz = rest / G.nty;
+  x0 = tx * G.tx;
+  y0 = ty * G.ty;
+  z0 = tz * G.tz;
+  const int t = threadIdx.x;
+  const int lxv = t % G.tx, r2 = t / G.tx;
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    int ly, lz;
+    if (G.dim == 3) {
+      ly = r2 % G.ty;
+      lz = r2 / G.ty + v * (G.tz / 2);
+    } else {
+      ly = r2 + v * (G.ty / 2);
+      lz = 0;
+    }
+    vx[v] = x0 + lxv;
+    vy[v] = y0 + ly;
+    vz[v] = z0 + lz;
+    ok[v] = vx[v] < G.nx && vy[v] < G.ny && vz[v] < G.nz;
+    const int R = G.R, Rz = (G.dim == 3) ? G.R : 0;
+    base[v] = ((lz + Rz) * G.ly + (ly + R)) * G.lx + (lxv + R);
+  }
+}
+
+// shell sums minus n_q u(x) of both voxels, handed to fn(q, s0, s1)
+template <typename T, typename Fn>
+__device__ __forceinline__ void nl_shells(const NlGeom& G, const T* lds, const int (&base)[2],
+                                          const int* __restrict__ offs, const int* __restrict__ first, Fn&& fn) {
+  const double u0 = double(lds[base[0]]), u1 = double(lds[base[1]]);
+  for (int q = 0; q < G.nshell; ++q) {
+    const int o0 = first[q], o1 = first[q + 1];
+    double s0 = 0.0, s1 = 0.0;
+    for (int o = o0; o < o1; ++o) {
+      const int d = offs[o];
+      s0 += double(lds[base[0] + d]);
+      s1 += double(lds[base[1] + d]);
+    }
+    const double cnt = double(o1 - o0);
+    fn(q, s0 - cnt * u0, s1 - cnt * u1);
+  }
+}
+
+// Normal equations: each workgroup walks items (sample, tile) b, b + grid,
+// ... in order, accumulating per thread in FP64 the upper triangle of
+// Phi Phi^T, Phi . Gamma and Gamma . Gamma over its voxels and the
+// displacement components; the workgroup's sums go to its partial slot
+// (kNlAcc doubles, laid out for degree kNlMaxDeg).
+template <typename T>
+__global__ __launch_bounds__(NTR) void k_nl_gram(NlGeom G, const T* __restrict__ u, const T* __restrict__ gam,
+                                                 int nsample, const int* __restrict__ offs,
+                                                 const int* __restrict__ first, const double* __restrict__ W,
+                                                 double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char nl_smem[];
+  T* lds = reinterpret_cast<T*>(nl_smem);
+  const long long nvox = (long long)G.nx * G.ny * G.nz;
+  const int ntile = G.ntx * G.nty * G.ntz;
+  const int nf = G.deg + 1;
+  double acc[kNlAcc];
+#pragma unroll
+  for (int i = 0; i < kNlAcc; ++i) acc[i] = 0.0;
+  for (long long item = blockIdx.x; item < (long long)nsample * ntile; item += gridDim.x) {
+    const int k = int(item / ntile), tile = int(item % ntile);
+    int x0, y0, z0, vx[2], vy[2], vz[2], base[2];
+    bool ok[2];
+    nl_tile(G, tile, x0, y0, z0, vx, vy, vz, base, ok);
+    for (int a = 0; a < G.dim; ++a) {
+      const long long comp = ((long long)k * G.dim + a) * nvox;
+      __syncthreads();
+      nl_stage(G, u + comp, x0, y0, z0, lds);
+      __syncthreads();
+      double phi[2][kNlF];
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int m = 0; m < kNlF; ++m) phi[v][m] = 0.0;
+      nl_shells(G, lds, base, offs, first, [&](int q, double s0, double s1) {
+#pragma unroll
+        for (int m = 0; m < kNlF; ++m) {
+          if (m < nf) {
+            const double w = W[m * G.nshell + q];
+            phi[0][m] += w * s0;
+            phi[1][m] += w * s1;
+          }
+        }
+      });
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        if (!ok[v]) continue;
+        const double gv = double(gam[comp + ((long long)vz[v] * G.ny + vy[v]) * G.nx + vx[v]]);
+        int i = 0;
+#pragma unroll
+        for (int m = 0; m < kNlF; ++m)
+#pragma unroll
+          for (int n2 = m; n2 < kNlF; ++n2, ++i) acc[i] += phi[v][m] * phi[v][n2];
+#pragma unroll
+        for (int m = 0; m < kNlF; ++m) acc[kNlTri + m] += phi[v][m] * gv;
+        acc[kNlTri + kNlF] += gv * gv;
+      }
+    }
+  }
+  // workgroup sum in a fixed order: waves by shuffles, then across waves
+  // (in the staging LDS, which holds at least kNlAcc NTR / 64 doubles)
+  double* red = reinterpret_cast<double*>(nl_smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kNlAcc; ++i) {
+    double v = acc[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wave * kNlAcc + i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNlAcc) {
+    double s = 0.0;
+    for (int w = 0; w < NTR / 64; ++w) s += red[w * kNlAcc + threadIdx.x];
+    partial[(long long)blockIdx.x * kNlAcc + threadIdx.x] = s;
+  }
+}
+
+// fixed-order sum of the partial slots (one workgroup)
+__global__ __launch_bounds__(NTR) void k_nl_gram_sum(const double* __restrict__ partial, int nslot,
                                                      double* __restrict__ out) {
   __shared__ double red[NTR / 64];
-  for (int i = 0; i < nacc; ++i) {
+  for (int i = 0; i < kNlAcc; ++i) {
     double a = 0.0;
-    for (long long s = threadIdx.x; s < nslot; s += NTR) a += partial[s * kNlAcc + i];
+    for (int s = threadIdx.x; s < nslot; s += NTR) a += partial[(long long)s * kNlAcc + i];
     const double sum = block_sum<NTR>(a, red);
     if (threadIdx.x == 0) out[i] = sum;
+  }
+}
+
+// The fitted operator: out = sum_q kw[q] (S_q - n_q u(x)) per component,
+// kw[q] = K_c at shell q's radius; one workgroup per (sample, tile).
+template <typename T>
+__global__ __launch_bounds__(NTR) void k_nl_apply(NlGeom G, const T* __restrict__ u, int nsample,
+                                                  const int* __restrict__ offs, const int* __restrict__ first,
+                                                  const double* __restrict__ kw, T* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char nl_smem[];
+  T* lds = reinterpret_cast<T*>(nl_smem);
+  const long long nvox = (long long)G.nx * G.ny * G.nz;
+  const int ntile = G.ntx * G.nty * G.ntz;
+  const long long item = blockIdx.x;
+  if (item >= (long long)nsample * ntile) return;
+  const int k = int(item / ntile), tile = int(item % ntile);
+  int x0, y0, z0, vx[2], vy[2], vz[2], base[2];
+  bool ok[2];
+  nl_tile(G, tile, x0, y0, z0, vx, vy, vz, base, ok);
+  for (int a = 0; a < G.dim; ++a) {
+    const long long comp = ((long long)k * G.dim + a) * nvox;
+    __syncthreads();
+    nl_stage(G, u + comp, x0, y0, z0, lds);
+    __syncthreads();
+    double r0 = 0.0, r1 = 0.0;
+    nl_shells(G, lds, base, offs, first, [&](int q, double s0, double s1) {
+      const double w = kw[q];
+      r0 += w * s0;
+      r1 += w * s1;
+    });
+    if (ok[0]) out[comp + ((long long)vz[0] * G.ny + vy[0]) * G.nx + vx[0]] = T(r0);
+    if (ok[1]) out[comp + ((long long)vz[1] * G.ny + vy[1]) * G.nx + vx[1]] = T(r1);
   }
 }
 

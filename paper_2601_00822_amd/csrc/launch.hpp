@@ -90,14 +90,21 @@ hipError_t launch_sample_norms(bool f64, const void* y, const void* t, int nsamp
                                hipStream_t st);
 hipError_t launch_bump_forces(bool f64, void* const* fs, const int* first, const double* bumps, int nforce, int nx,
                               int ny, int nz, int dim, hipStream_t st);
-// normal equations of the nonlocal kernel regression: `out` receives the
-// upper triangle of G, then g, then Gamma . Gamma (see k_nl_gram); `partial`
-// holds nl_partial_doubles(nvox, nsample) doubles
-constexpr int kNlMaxDegree = 8, kNlMaxShells = 48;
-hipError_t launch_nl_gram(bool f64, const void* u, const void* gam, int nsample, int nx, int ny, int nz, int dim,
-                          const int4* offs, int noffs, const double* W, int nshell, int deg, double* partial,
-                          double* out, hipStream_t st);
-size_t nl_partial_doubles(long long nvox, int nsample);
+// Nonlocal kernel regression (see k_nl_gram, k_nl_apply).  Offsets of the
+// horizon are given as index deltas in the LDS box of a tile (nl_box: its
+// extent (lx, ly, lz) for halo R), sorted by shell: shell q holds offsets
+// first[q] .. first[q + 1] - 1.  launch_nl_gram writes kNlAccWords doubles to
+// `out`: the upper triangle of G row by row for degree kNlMaxDegree (entries
+// beyond `deg` zero), then g (kNlMaxDegree + 1), then Gamma . Gamma; W is
+// [deg + 1][nshell] and `partial` holds kNlGramSlots x kNlAccWords doubles.
+// launch_nl_apply writes sum_q kw[q] (S_q - n_q u) per component.
+constexpr int kNlMaxDegree = 8, kNlMaxHalo = 6, kNlAccWords = 55, kNlGramSlots = 2048;
+void nl_box(int dim, int R, int box[3]);
+hipError_t launch_nl_gram(bool f64, int dim, const int n[3], int R, int deg, int nsample, const void* u,
+                          const void* gam, const int* offs, const int* first, int nshell, const double* W,
+                          double* partial, double* out, hipStream_t st);
+hipError_t launch_nl_apply(bool f64, int dim, const int n[3], int R, int nsample, const void* u, const int* offs,
+                           const int* first, int nshell, const double* kw, void* out, hipStream_t st);
 constexpr int kRveBinsMax = 1024;   // bins of launch_radial_max
 hipError_t launch_radial_max(int dim, const double* avg, const int n[3], const double h[3], const double c[3],
                              double dr, int nbins, unsigned long long* bins, hipStream_t st);

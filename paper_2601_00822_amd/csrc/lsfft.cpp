@@ -2145,3 +2145,225 @@ lsfft_status lsfft_bump_forces(int prec, int dim, const int64_t* n, int nforce, 
 }
 
 }  // extern "C"
+
+namespace {
+// The horizon of the nonlocal operator (Eq. 6.5 on the grid, h = 1): the
+// offsets r != 0 with |r| < delta (z = 0 in 2D), grouped in shells of equal
+// |r|^2 in ascending order, as index deltas of the kernels' LDS box of halo
+// R (the largest offset component), with the Bernstein values of degree
+// `deg` at each shell's radius.
+struct NlHorizon {
+  int R = 0;
+  std::vector<int> delta, first;   // offsets of shell q: delta[first[q] .. first[q + 1])
+  std::vector<double> rho;         // per shell
+  int nshell() const { return (int)rho.size(); }
+};
+
+bool nl_horizon(int dim, double delta, NlHorizon& h) {
+  if (!is_fin(delta) || delta <= 1.0 || delta > kNlMaxHalo + 1) return false;
+  const int R = (int)std::ceil(delta) - 1;
+  int box[3];
+  nl_box(dim, R, box);
+  std::map<int, std::vector<int>> shells;   // |r|^2 -> deltas
+  const int rz = dim == 3 ? R : 0;
+  for (int dz = -rz; dz <= rz; ++dz)
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        const int rr = dx * dx + dy * dy + dz * dz;
+        if (rr == 0 || !(std::sqrt(double(rr)) < delta)) continue;
+        shells[rr].push_back((dz * box[1] + dy) * box[0] + dx);
+      }
+  if (shells.empty()) return false;
+  h.R = R;
+  h.first.push_back(0);
+  for (const auto& kv : shells) {
+    h.delta.insert(h.delta.end(), kv.second.begin(), kv.second.end());
+    h.first.push_back((int)h.delta.size());
+    h.rho.push_back(std::sqrt(double(kv.first)));
+  }
+  return true;
+}
+
+// B_{m,M}(rho / delta) for m = 0..M per shell, [M + 1][nshell]
+std::vector<double> nl_bernstein(int M, double delta, const NlHorizon& h) {
+  std::vector<double> W((size_t)(M + 1) * h.nshell());
+  for (int q = 0; q < h.nshell(); ++q) {
+    const double t = h.rho[q] / delta;
+    double binom = 1.0;
+    for (int m = 0; m <= M; ++m) {
+      if (m > 0) binom = binom * (M - m + 1) / m;
+      W[(size_t)m * h.nshell() + q] = binom * std::pow(t, m) * std::pow(1.0 - t, M - m);
+    }
+  }
+  return W;
+}
+
+// device copy of the horizon tables (ints, then doubles), freed by the caller
+struct NlTables {
+  char* buf = nullptr;
+  const int* delta = nullptr;
+  const int* first = nullptr;
+  const double* vals = nullptr;
+  double* work = nullptr;
+};
+
+hipError_t nl_upload(const NlHorizon& h, const std::vector<double>& vals, size_t work_doubles, hipStream_t st,
+                     NlTables& t) {
+  const size_t b_delta = sizeof(int) * h.delta.size(), b_first = sizeof(int) * h.first.size();
+  const size_t o_first = align_up(b_delta, 16), o_vals = align_up(o_first + b_first, 16);
+  const size_t o_work = align_up(o_vals + sizeof(double) * vals.size(), 256);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&t.buf), o_work + sizeof(double) * std::max<size_t>(work_doubles, 1));
+  if (e != hipSuccess) {
+    t.buf = nullptr;
+    return e;
+  }
+  t.delta = reinterpret_cast<const int*>(t.buf);
+  t.first = reinterpret_cast<const int*>(t.buf + o_first);
+  t.vals = reinterpret_cast<const double*>(t.buf + o_vals);
+  t.work = reinterpret_cast<double*>(t.buf + o_work);
+  e = hipMemcpyAsync(t.buf, h.delta.data(), b_delta, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(t.buf + o_first, h.first.data(), b_first, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(t.buf + o_vals, vals.data(), sizeof(double) * vals.size(), hipMemcpyHostToDevice, st);
+  return e;
+}
+
+lsfft_status nl_check(int prec, int dim, const int64_t* n, int nsample, int n_out[3]) {
+  if ((prec != LSFFT_F32 && prec != LSFFT_F64) || (dim != 2 && dim != 3) || !n || nsample < 1) return LSFFT_E_ARG;
+  for (int a = 0; a < 3; ++a) n_out[a] = 1;
+  long long nvox = 1;
+  for (int a = 0; a < dim; ++a) {
+    if (n[a] < 1 || n[a] > (1 << 16)) return LSFFT_E_ARG;
+    n_out[a] = (int)n[a];
+    nvox *= n[a];
+  }
+  if (nvox * dim * nsample > (1ll << 40)) return LSFFT_E_ARG;
+  return LSFFT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lsfft_status lsfft_nonlocal_normal_equations(int prec, int dim, const int64_t* n, int nsample, const void* u,
+                                             const void* gamma, int degree, double delta, double* G, double* g,
+                                             double* gg, void* hip_stream) {
+  int nn[3];
+  if (nl_check(prec, dim, n, nsample, nn) != LSFFT_OK || !u || !gamma || !G || !g || !gg) return LSFFT_E_ARG;
+  if (degree < 0 || degree > kNlMaxDegree) return LSFFT_E_ARG;
+  NlHorizon h;
+  if (!nl_horizon(dim, delta, h)) return LSFFT_E_ARG;
+  const std::vector<double> W = nl_bernstein(degree, delta, h);
+  hipStream_t st = as_stream(hip_stream);
+  NlTables t;
+  const size_t work = (size_t)kNlGramSlots * kNlAccWords + kNlAccWords;
+  hipError_t e = nl_upload(h, W, work, st, t);
+  if (!t.buf) return LSFFT_E_ALLOC;
+  double* out = t.work + (size_t)kNlGramSlots * kNlAccWords;
+  std::vector<double> acc(kNlAccWords);
+  if (e == hipSuccess)
+    e = launch_nl_gram(prec == LSFFT_F64, dim, nn, h.R, degree, nsample, u, gamma, t.delta, t.first, h.nshell(), t.vals,
+                       t.work, out, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(acc.data(), out, sizeof(double) * kNlAccWords, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(t.buf);
+  if (e != hipSuccess) return LSFFT_E_DEVICE;
+  // unpack the upper triangle (laid out for degree kNlMaxDegree)
+  constexpr int F = kNlMaxDegree + 1;
+  const int nf = degree + 1;
+  for (int m = 0; m < nf; ++m)
+    for (int k = m; k < nf; ++k) {
+      const double v = acc[(size_t)(m * F - m * (m - 1) / 2 + (k - m))];
+      G[m * nf + k] = v;
+      G[k * nf + m] = v;
+    }
+  const int tri = F * (F + 1) / 2;
+  for (int m = 0; m < nf; ++m) g[m] = acc[(size_t)(tri + m)];
+  *gg = acc[(size_t)(tri + F)];
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_nonlocal_apply(int prec, int dim, const int64_t* n, int nsample, const void* u, int degree,
+                                  const double* c, double delta, void* out, void* hip_stream) {
+  int nn[3];
+  if (nl_check(prec, dim, n, nsample, nn) != LSFFT_OK || !u || !c || !out) return LSFFT_E_ARG;
+  if (degree < 0 || degree > kNlMaxDegree) return LSFFT_E_ARG;
+  for (int m = 0; m <= degree; ++m)
+    if (!is_fin(c[m])) return LSFFT_E_ARG;
+  NlHorizon h;
+  if (!nl_horizon(dim, delta, h)) return LSFFT_E_ARG;
+  const std::vector<double> W = nl_bernstein(degree, delta, h);
+  std::vector<double> kw(h.nshell(), 0.0);        // K_c at each shell's radius
+  for (int q = 0; q < h.nshell(); ++q)
+    for (int m = 0; m <= degree; ++m) kw[q] += c[m] * W[(size_t)m * h.nshell() + q];
+  hipStream_t st = as_stream(hip_stream);
+  NlTables t;
+  hipError_t e = nl_upload(h, kw, 0, st, t);
+  if (!t.buf) return LSFFT_E_ALLOC;
+  if (e == hipSuccess)
+    e = launch_nl_apply(prec == LSFFT_F64, dim, nn, h.R, nsample, u, t.delta, t.first, h.nshell(), t.vals, out, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(t.buf);
+  return e == hipSuccess ? LSFFT_OK : LSFFT_E_DEVICE;
+}
+
+lsfft_status lsfft_nonlocal_fit(int degree, const double* G, const double* g, double lam, int adam_steps, double lr,
+                                double* c) {
+  if (degree < 0 || degree > kNlMaxDegree || !G || !g || !c || !is_fin(lam) || lam < 0.0 || adam_steps < 0)
+    return LSFFT_E_ARG;
+  const int nf = degree + 1;
+  for (int i = 0; i < nf * nf; ++i)
+    if (!is_fin(G[i])) return LSFFT_E_ARG;
+  for (int i = 0; i < nf; ++i)
+    if (!is_fin(g[i])) return LSFFT_E_ARG;
+  if (adam_steps == 0) {
+    // (G + lam I) c = g by Cholesky; a pivot that is not positive means the
+    // system is singular (or G is not a Gram matrix)
+    std::vector<double> L((size_t)nf * nf, 0.0);
+    for (int j = 0; j < nf; ++j) {
+      double d = G[j * nf + j] + lam;
+      for (int k = 0; k < j; ++k) d -= L[j * nf + k] * L[j * nf + k];
+      if (!(d > 0.0)) return LSFFT_E_ARG;
+      L[j * nf + j] = std::sqrt(d);
+      for (int i = j + 1; i < nf; ++i) {
+        double v = G[i * nf + j];
+        for (int k = 0; k < j; ++k) v -= L[i * nf + k] * L[j * nf + k];
+        L[i * nf + j] = v / L[j * nf + j];
+      }
+    }
+    std::vector<double> y(nf);
+    for (int i = 0; i < nf; ++i) {
+      double v = g[i];
+      for (int k = 0; k < i; ++k) v -= L[i * nf + k] * y[k];
+      y[i] = v / L[i * nf + i];
+    }
+    for (int i = nf - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < nf; ++k) v -= L[k * nf + i] * c[k];
+      c[i] = v / L[i * nf + i];
+    }
+    return LSFFT_OK;
+  }
+  // Adam (Kingma and Ba) on the quadratic loss c^T G c - 2 g . c + lam |c|^2
+  // from c = 0: gradient 2 (G c - g + lam c), beta1 0.9, beta2 0.999,
+  // eps 1e-12, bias-corrected moments, step lr
+  if (!is_fin(lr) || lr <= 0.0) return LSFFT_E_ARG;
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-12;
+  std::vector<double> m(nf, 0.0), v(nf, 0.0), grad(nf);
+  for (int i = 0; i < nf; ++i) c[i] = 0.0;
+  for (int k = 1; k <= adam_steps; ++k) {
+    for (int i = 0; i < nf; ++i) {
+      double gc = 0.0;
+      for (int j = 0; j < nf; ++j) gc += G[i * nf + j] * c[j];
+      grad[i] = 2.0 * (gc - g[i]) + 2.0 * lam * c[i];
+    }
+    const double c1 = 1.0 - std::pow(b1, k), c2 = 1.0 - std::pow(b2, k);
+    for (int i = 0; i < nf; ++i) {
+      m[i] = b1 * m[i] + (1.0 - b1) * grad[i];
+      v[i] = b2 * v[i] + (1.0 - b2) * grad[i] * grad[i];
+      c[i] -= lr * (m[i] / c1) / (std::sqrt(v[i] / c2) + eps);
+    }
+  }
+  return LSFFT_OK;
+}
+
+}  // extern "C"

@@ -32,7 +32,8 @@ EXPORTS = [
     "lsfft_plan_destroy", "lsfft_status_string", "lsfft_lame_from_young", "lsfft_kernel_times",
     "lsfft_kernel_times_reset", "lsfft_iteration_bytes", "lsfft_schedule_get", "lsfft_schedule_set",
     "lsfft_autotune", "lsfft_tune_cache_lookup", "lsfft_anderson_memory", "lsfft_kernel_convolve",
-    "lsfft_block_mean", "lsfft_sample_norms", "lsfft_bump_forces",
+    "lsfft_block_mean", "lsfft_sample_norms", "lsfft_bump_forces", "lsfft_nonlocal_normal_equations",
+    "lsfft_nonlocal_apply", "lsfft_nonlocal_fit",
 ]
 PASS_KINDS = {"x": 0, "y": 1, "outer": 2}
 
@@ -131,6 +132,13 @@ def load_library(path: str = LIB_PATH):
     lib.lsfft_bump_forces.argtypes = [ip, ip, C.POINTER(C.c_int64), ip, C.POINTER(ip), C.POINTER(dp),
                                       C.POINTER(vp), vp]
     lib.lsfft_bump_forces.restype = ip
+    lib.lsfft_nonlocal_normal_equations.argtypes = [ip, ip, C.POINTER(C.c_int64), ip, vp, vp, ip, dp, C.POINTER(dp),
+                                                    C.POINTER(dp), C.POINTER(dp), vp]
+    lib.lsfft_nonlocal_normal_equations.restype = ip
+    lib.lsfft_nonlocal_apply.argtypes = [ip, ip, C.POINTER(C.c_int64), ip, vp, ip, C.POINTER(dp), dp, vp, vp]
+    lib.lsfft_nonlocal_apply.restype = ip
+    lib.lsfft_nonlocal_fit.argtypes = [ip, C.POINTER(dp), C.POINTER(dp), dp, ip, dp, C.POINTER(dp)]
+    lib.lsfft_nonlocal_fit.restype = ip
     _lib = lib
     return lib
 
@@ -221,6 +229,72 @@ def bump_forces(shape, params, dtype=None, device=None):
     if st != OK:
         raise LsfftError(st, "lsfft_bump_forces")
     return out
+
+
+def _nl_fields(u, name):
+    """(prec, d, n[3], nsample) of fields ``[nsample][d][...grid]``."""
+    _dev_check(u, name)
+    d = u.dim() - 2
+    if d not in (2, 3) or u.shape[1] != d:
+        raise ValueError(f"{name} must be [nsample][d][...grid] with d = 2 or 3")
+    n = (C.c_int64 * 3)(*(list(reversed(tuple(u.shape[2:]))) + [1] * (3 - d)))
+    return _prec_of(u), d, n, int(u.shape[0])
+
+
+def nonlocal_normal_equations(u, gamma, degree: int, delta: float):
+    """(G, g, Gamma . Gamma) of the least-squares fit of the nonlocal
+    operator with a degree-``degree`` Bernstein kernel of horizon ``delta``
+    to the pairs (u_k, Gamma_k), ``[nsample][d][...grid]`` GPU tensors;
+    FP64 numpy, computed by the library."""
+    torch = _torch()
+    prec, d, n, ns = _nl_fields(u, "u")
+    _dev_check(gamma, "gamma")
+    if gamma.shape != u.shape or gamma.dtype != u.dtype:
+        raise ValueError("u and gamma must match")
+    nf = degree + 1
+    G = np.zeros((nf, nf))
+    g = np.zeros(nf)
+    gg = C.c_double(0.0)
+    dp = C.POINTER(C.c_double)
+    st = load_library().lsfft_nonlocal_normal_equations(prec, d, n, ns, C.c_void_p(u.data_ptr()),
+                                                        C.c_void_p(gamma.data_ptr()), int(degree), float(delta),
+                                                        G.ctypes.data_as(dp), g.ctypes.data_as(dp), C.byref(gg),
+                                                        C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != OK:
+        raise LsfftError(st, "lsfft_nonlocal_normal_equations")
+    return G, g, gg.value
+
+
+def nonlocal_apply(u, c, delta: float):
+    """L_c[u] of fields ``[nsample][d][...grid]`` (GPU tensor), by the library."""
+    torch = _torch()
+    prec, d, n, ns = _nl_fields(u, "u")
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+    out = torch.empty_like(u)
+    st = load_library().lsfft_nonlocal_apply(prec, d, n, ns, C.c_void_p(u.data_ptr()), len(c) - 1,
+                                             c.ctypes.data_as(C.POINTER(C.c_double)), float(delta),
+                                             C.c_void_p(out.data_ptr()),
+                                             C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != OK:
+        raise LsfftError(st, "lsfft_nonlocal_apply")
+    return out
+
+
+def nonlocal_fit(G, g, lam: float, adam_steps: int = 0, lr: float = 1e-3):
+    """Bernstein coefficients from the normal equations: the closed form
+    (adam_steps = 0) or Adam from zero; host arithmetic in the library."""
+    G = np.ascontiguousarray(np.asarray(G, dtype=np.float64))
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    nf = len(g)
+    if G.shape != (nf, nf):
+        raise ValueError("G must be square with the size of g")
+    c = np.zeros(nf)
+    dp = C.POINTER(C.c_double)
+    st = load_library().lsfft_nonlocal_fit(nf - 1, G.ctypes.data_as(dp), g.ctypes.data_as(dp), float(lam),
+                                           int(adam_steps), float(lr), c.ctypes.data_as(dp))
+    if st != OK:
+        raise LsfftError(st, "lsfft_nonlocal_fit")
+    return c
 
 
 class LsfftError(RuntimeError):

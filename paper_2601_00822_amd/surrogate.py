@@ -37,10 +37,13 @@ def cell_shifts(cell: int, d: int = 3) -> np.ndarray:
     return g.reshape(-1, d).astype(np.int32)
 
 
-def averaged_strain_kernel(phase, lame, cell: int, prec: str = "f64", max_batch: int = 512, tol: float = 1e-8):
-    """``K[c][j]`` = the translation-averaged strain component ``c`` (Voigt)
-    for a unit point force along axis ``j`` (x first) at the origin; FP64
-    torch tensor ``[6][3][n][n][n]``.  Returns (K, per-shift reports)."""
+def averaged_kernels(phase, lame, cell: int, prec: str = "f64", max_batch: int = 512, tol: float = 1e-8):
+    """The averaged responses to a unit point force at the origin along each
+    axis j (x first): ``K[c][j]`` for the strain components c (Voigt) and
+    ``Ku[a][j]`` for the displacement components a, from three
+    ``translate_average`` calls over every shift of one cell.  FP64 (or
+    FP32) torch tensors ``[6][3][n][n][n]`` and ``[3][3][n][n][n]``, and the
+    per-shift reports."""
     import torch
     shape = tuple(phase.shape)
     d = len(shape)
@@ -49,15 +52,26 @@ def averaged_strain_kernel(phase, lame, cell: int, prec: str = "f64", max_batch:
     plan = Plan([shape], prec=prec, max_batch=max_batch, refine=(prec == "f32"))
     dt = torch.float64 if prec == "f64" else torch.float32
     shifts = cell_shifts(cell, d)
-    cols, reps = [], []
-    for j in range(d):
-        f = torch.zeros((d,) + shape, dtype=dt, device=phase.device)
-        f[(j,) + (0,) * d] = 1.0
-        avg, r = plan.translate_average(phase, lame, f, shifts, tol=tol)
-        cols.append(avg[2 * d:2 * d + 6].clone())
-        reps += r
-    plan.close()
-    return torch.stack(cols, dim=1), reps
+    cols, ucols, reps = [], [], []
+    try:
+        for j in range(d):
+            f = torch.zeros((d,) + shape, dtype=dt, device=phase.device)
+            f[(j,) + (0,) * d] = 1.0
+            avg, r = plan.translate_average(phase, lame, f, shifts, tol=tol)
+            cols.append(avg[2 * d:2 * d + 6].clone())
+            ucols.append(avg[0:d].clone())
+            reps += r
+    finally:
+        plan.close()
+    return torch.stack(cols, dim=1), torch.stack(ucols, dim=1), reps
+
+
+def averaged_strain_kernel(phase, lame, cell: int, prec: str = "f64", max_batch: int = 512, tol: float = 1e-8):
+    """``K[c][j]`` = the translation-averaged strain component ``c`` (Voigt)
+    for a unit point force along axis ``j`` (x first) at the origin; FP64
+    torch tensor ``[6][3][n][n][n]``.  Returns (K, per-shift reports)."""
+    K, _, reps = averaged_kernels(phase, lame, cell, prec=prec, max_batch=max_batch, tol=tol)
+    return K, reps
 
 
 def averaged_strain_from_kernel(K, f, plan: Plan | None = None, max_batch: int = 64):
@@ -65,16 +79,27 @@ def averaged_strain_from_kernel(K, f, plan: Plan | None = None, max_batch: int =
     convolution with the averaged kernel ``K`` [6][3][n][n][n], by the
     library in the kernel's precision (a plan of that grid may be passed in
     to reuse its workspace)."""
-    import torch
     shape = tuple(K.shape[-3:])
     own = plan is None
     if own:
+        import torch
         plan = Plan([shape], prec="f64" if K.dtype == torch.float64 else "f32", max_batch=max_batch)
     try:
         return plan.kernel_convolve(K.contiguous(), f.contiguous())
     finally:
         if own:
             plan.close()
+
+
+def averaged_displacement_from_kernel(Ku, f, plan: Plan | None = None, max_batch: int = 64):
+    """``f`` [B][3][n][n][n] -> averaged displacement [B][3][n][n][n]: the
+    convolution with the averaged displacement kernel ``Ku`` [3][3][...]
+    (given to the library as the first rows of a six-row kernel)."""
+    import torch
+    d = Ku.shape[0]
+    K6 = torch.zeros((6,) + tuple(Ku.shape[1:]), dtype=Ku.dtype, device=Ku.device)
+    K6[:d] = Ku
+    return averaged_strain_from_kernel(K6, f, plan=plan, max_batch=max_batch)[:, :d].contiguous()
 
 
 def restrict2(a, dtype=None, scale: float = 1.0):
