@@ -145,7 +145,7 @@ def run_batch_workload(args, wl):
     _, reps_t, _ = plan_t.translate_average_batch(dgroups, tol=1e-8)
     torch.cuda.synchronize()
     elapsed_t = time.perf_counter() - t1
-    per, dom = class_rooflines(plan_t, [(g, r.iters) for g, r in zip(grid_of, reps_t)], args.scheme == "cg")
+    per, dom = class_rooflines(plan_t, [(g, r.iters) for g, r in zip(grid_of, reps_t)], args.scheme != "basic")
     plan_t.close()
     statuses = sorted({r.status for r in reps})
     return {
@@ -525,7 +525,7 @@ def cpu_baseline(wl: dict, phase, f, table):
 CLASS_NAMES = ("green", "xpass", "ypass", "reduce", "cgupd")
 
 
-def class_rooflines(plan_t, solves, cg: bool):
+def class_rooflines(plan_t, solves, two_outer: bool):
     """Per kernel class of a timed plan: total HIP-event time, launches,
     algorithmic bytes and bandwidth.  ``solves`` lists (grid index,
     iterations) of every solve the timed region ran; a class's algorithmic
@@ -538,7 +538,7 @@ def class_rooflines(plan_t, solves, cg: bool):
     CG outer-pass class two, A p and the new direction)."""
     from paper_2601_00822_amd import K_GREEN, K_XPASS, K_YPASS, K_REDUCE, K_CGUPD
     ids = {"green": K_GREEN, "xpass": K_XPASS, "ypass": K_YPASS, "reduce": K_REDUCE, "cgupd": K_CGUPD}
-    kernels_per_iter = {"green": 2.0 if cg else 1.0, "xpass": 1.0, "ypass": 2.0, "reduce": 1.0,
+    kernels_per_iter = {"green": 2.0 if two_outer else 1.0, "xpass": 1.0, "ypass": 2.0, "reduce": 1.0,
                         "cgupd": 1.0}
     out = {}
     iters_total = sum(it for _, it in solves)
@@ -578,7 +578,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="bfcs256", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--scheme", default="basic", choices=["basic", "cg"])
+    ap.add_argument("--scheme", default="basic", choices=["basic", "cg", "cg_plain", "anderson"])
     ap.add_argument("--no-refine", action="store_true",
                     help="FP32 without the FP64 defect correction (stops at the FP32 stagnation floor)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -673,7 +673,7 @@ def main() -> int:
     torch.cuda.synchronize()
     elapsed_t = time.perf_counter() - t1
 
-    per, dom = class_rooflines(plan_t, [(0, iters_t)], args.scheme == "cg")
+    per, dom = class_rooflines(plan_t, [(0, iters_t)], args.scheme != "basic")
     # the counter summaries were taken on the default schedule of every pass
     tuned = any(e["chosen"] and e["variant"] != 0 for e in tune)
     traffic = None if tuned else measured_traffic(dom, args.workload, args.prec)

@@ -760,7 +760,9 @@ def radial_maxima(field, center, h=None, dr=1.0):
     h = [1.0] * d if h is None else list(h)
     r2 = np.zeros(shape)
     half2 = 0.0
-    # summed x first, then y, then z (the order of the GPU kernel)
+    # summed in the fixed order x, y, z: the rounding of the squared
+    # distance decides the bin of a node that sits on a bin edge, so the
+    # order is part of the definition (any fixed order is a valid reading)
     for a in reversed(range(d)):
         n = shape[a]
         idx = np.arange(n, dtype=np.float64) - float(center[a])
