@@ -12,7 +12,17 @@ degree M on [0, delta]:
     K_c(rho) = sum_m c_m B_{m,M}(rho / delta),
     B_{m,M}(t) = binom(M, m) t^m (1 - t)^(M - m),
 
-and K = 0 for rho >= delta.  It acts on every displacement component alike.
+and K = 0 for rho >= delta.  It acts on every displacement component alike
+(``form = 0``, the literal reading).  With ``form = 1`` the kernel is the
+isotropic matrix function of the bond r = y - x,
+
+    K(r) = K1(|r|) I + K2(|r|) e e^T,   e = r / |r| (components x first),
+
+each of K1, K2 expanded in the same basis: coefficients (c1_0..c1_M,
+c2_0..c2_M).  Eq. 6.7 pairs the stress-type kernel with the bond vector,
+so the paper's kernels are tensors of the bond; this is the general such
+kernel for the displacement type, and the term e e^T couples the components
+as the divergence term of an isotropic Navier operator does.
 Eq. 6.6 fits the coefficients to pairs (<u>_k, Gamma_k) with Gamma_k = -b_k
 (the operator type of the body force):
 
@@ -51,36 +61,48 @@ def ball_offsets(d: int, delta: float):
     return offs[keep], rho[keep]
 
 
-def features(u, M: int, delta: float):
+def features(u, M: int, delta: float, form: int = 0):
     """Phi_m[u] for m = 0..M, ``[M + 1][comp][grid]``: the sum over the
-    horizon's offsets of B_m(|r| / delta) (u(x + r) - u(x))."""
+    horizon's offsets of B_m(|r| / delta) (u(x + r) - u(x)).  With
+    ``form = 1`` also the features of the e e^T term,
+    sum_r B_m(|r| / delta) e (e . (u(x + r) - u(x))), after them:
+    ``[2 (M + 1)][comp][grid]``.  Offsets are in array order (z first in
+    3D); the direction e is taken in component order (x first)."""
     u = np.asarray(u, dtype=np.float64)
     d = u.ndim - 1
     offs, rho = ball_offsets(d, delta)
     w = bernstein(M, rho / delta)                 # [M + 1][noffsets]
-    out = np.zeros((M + 1,) + u.shape)
+    out = np.zeros(((2 if form == 1 else 1) * (M + 1),) + u.shape)
     axes = tuple(range(1, d + 1))
     for i, r in enumerate(offs):
         diff = np.roll(u, shift=tuple(-int(v) for v in r), axis=axes) - u      # u(x + r) - u(x)
         for m in range(M + 1):
             out[m] += w[m, i] * diff
+        if form == 1:
+            e = r[::-1].astype(np.float64) / rho[i]                           # x first
+            proj = np.tensordot(e, diff, axes=(0, 0))                           # e . (u(x + r) - u(x))
+            for m in range(M + 1):
+                out[M + 1 + m] += w[m, i] * e.reshape((d,) + (1,) * d) * proj
     return out
 
 
-def apply_operator(c, u, delta: float):
-    """L_c[u] of Eq. 6.5 for coefficients ``c`` (degree len(c) - 1)."""
+def apply_operator(c, u, delta: float, form: int = 0):
+    """L_c[u] of Eq. 6.5 for coefficients ``c`` (degree len(c) - 1, or
+    len(c) / 2 - 1 with ``form = 1``)."""
     c = np.asarray(c, dtype=np.float64)
-    return np.tensordot(c, features(u, len(c) - 1, delta), axes=(0, 0))
+    M = (len(c) // 2 if form == 1 else len(c)) - 1
+    return np.tensordot(c, features(u, M, delta, form), axes=(0, 0))
 
 
-def normal_equations(us, gammas, M: int, delta: float):
+def normal_equations(us, gammas, M: int, delta: float, form: int = 0):
     """G and g of the quadratic loss over the pairs (u_k, Gamma_k), and
     sum_k ||Gamma_k||^2."""
-    G = np.zeros((M + 1, M + 1))
-    g = np.zeros(M + 1)
+    nf = (2 if form == 1 else 1) * (M + 1)
+    G = np.zeros((nf, nf))
+    g = np.zeros(nf)
     gg = 0.0
     for u, gam in zip(us, gammas):
-        phi = features(u, M, delta).reshape(M + 1, -1)
+        phi = features(u, M, delta, form).reshape(nf, -1)
         gam = np.asarray(gam, dtype=np.float64).ravel()
         G += phi @ phi.T
         g += phi @ gam

@@ -99,3 +99,92 @@ def test_adam_reaches_the_tikhonov_minimiser():
     c = N.fit_adam(Gs, gs, lams, steps=50000, lr=1e-3)
     np.testing.assert_allclose(c, c_star, rtol=0, atol=1e-6 * np.abs(c_star).max())
     assert N.loss(c, G, g, gg, lam) <= N.loss(c_star, G, g, gg, lam) * (1 + 1e-9)
+
+
+# ------------------------------------------------- isotropic matrix kernel (form 1)
+def kernel_pair(c, rho, delta):
+    """(K1, K2) at distance rho for coefficients (c1_0..c1_M, c2_0..c2_M)."""
+    c = np.asarray(c, dtype=np.float64)
+    M = len(c) // 2 - 1
+    t = rho / delta
+    b = [N.comb(M, m) * t ** m * (1 - t) ** (M - m) for m in range(M + 1)]
+    return float(np.dot(c[:M + 1], b)), float(np.dot(c[M + 1:], b))
+
+
+def min_image_offsets(shape):
+    """Every grid offset as its minimum-image vector in component order (x
+    first), with its array index."""
+    for idx in np.ndindex(*shape):
+        r_arr = [v if v <= n // 2 else v - n for v, n in zip(idx, shape)]
+        yield idx, np.array(r_arr[::-1], dtype=np.float64)
+
+
+@pytest.mark.parametrize("shape,k", [((16, 12), (3, -2)), ((8, 10, 12), (1, 2, -3))])
+def test_matrix_kernel_on_a_fourier_mode(shape, k):
+    """u_a = v_a cos(xi . x): L[u] = M(xi) v cos(xi . x) with
+    M = sum_r (cos(xi . r) - 1)(K1 I + K2 e e^T), the offsets enumerated by
+    a scan of the grid's minimum images, directions in component order."""
+    d = len(shape)
+    delta = 3.2
+    c = np.array([0.4, -0.3, 1.1, 0.2, -0.7, 0.5, 0.9, -0.2])
+    v = np.array([1.0, 0.5, -0.3][:d])
+    xi_arr = np.array([2 * np.pi * k[a] / shape[a] for a in range(d)])     # array order
+    pos = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    phase = sum(xi_arr[a] * pos[a] for a in range(d))
+    u = v.reshape((d,) + (1,) * d) * np.cos(phase)
+    Mx = np.zeros((d, d))
+    for idx, r in min_image_offsets(shape):
+        rho = np.sqrt(r @ r)
+        if 0.0 < rho < delta:
+            K1, K2 = kernel_pair(c, rho, delta)
+            e = r / rho
+            xr = sum(xi_arr[a] * idx_r for a, idx_r in enumerate(r[::-1]))    # xi . r in array order
+            Mx += (np.cos(xr) - 1.0) * (K1 * np.eye(d) + K2 * np.outer(e, e))
+    want = (Mx @ v).reshape((d,) + (1,) * d) * np.cos(phase)
+    np.testing.assert_allclose(N.apply_operator(c, u, delta, form=1), want, rtol=0, atol=1e-12)
+
+
+def matrix_operator_by_fft(c, u, delta):
+    """out_a = sum_b (K_ab * u_b) - (sum_r K_ab(r)) u_b with the 3x3 kernel
+    image on the periodic grid, by FFT."""
+    shape = u.shape[1:]
+    d = len(shape)
+    img = np.zeros((d, d) + shape)
+    for idx, r in min_image_offsets(shape):
+        rho = np.sqrt(r @ r)
+        if 0.0 < rho < delta:
+            K1, K2 = kernel_pair(c, rho, delta)
+            e = r / rho
+            img[(slice(None), slice(None)) + idx] = K1 * np.eye(d) + K2 * np.outer(e, e)
+    axes = tuple(range(1, d + 1))
+    uh = np.fft.fftn(u, axes=axes)
+    kh = np.fft.fftn(img, axes=tuple(range(2, d + 2)))
+    conv = np.fft.ifftn(np.einsum("ab...,b...->a...", kh, uh), axes=axes).real
+    tot = img.sum(axis=tuple(range(2, d + 2)))
+    return conv - np.einsum("ab,b...->a...", tot, u)
+
+
+@pytest.mark.parametrize("shape", [(10, 12, 14), (20, 18)])
+def test_planted_matrix_kernel_is_recovered(shape):
+    rng = np.random.default_rng(8)
+    d = len(shape)
+    delta = 3.5
+    c_true = np.array([0.8, -0.4, 0.25, 1.3, 0.6, -0.9, 0.3, 0.45])
+    us = [rng.normal(size=(d,) + shape) for _ in range(3)]
+    gammas = [matrix_operator_by_fft(c_true, u, delta) for u in us]
+    np.testing.assert_allclose(N.apply_operator(c_true, us[0], delta, form=1), gammas[0], rtol=0,
+                               atol=1e-12 * np.abs(gammas[0]).max())
+    G, g, gg = N.normal_equations(us, gammas, 3, delta, form=1)
+    c = N.fit_closed(G, g, 0.0)
+    np.testing.assert_allclose(c, c_true, rtol=0, atol=1e-8)
+
+
+def test_matrix_operator_is_self_adjoint_and_kills_constants():
+    rng = np.random.default_rng(9)
+    shape, delta = (8, 9, 10), 2.9
+    c = rng.normal(size=6)
+    u, v = rng.normal(size=(3,) + shape), rng.normal(size=(3,) + shape)
+    lu, lv = N.apply_operator(c, u, delta, form=1), N.apply_operator(c, v, delta, form=1)
+    assert abs(np.sum(v * lu) - np.sum(u * lv)) < 1e-11 * np.abs(lu).max() * np.abs(v).sum()
+    const = np.ones((3,) + shape) * np.array([0.3, -1.2, 2.0])[:, None, None, None]
+    assert np.abs(N.apply_operator(c, const, delta, form=1)).max() < 1e-13
