@@ -319,50 +319,56 @@ def run_nonlocal_leg(Ku, n, conv_plan, args, log):
     """The nonlocal kernel surrogate (Eqs. 6.5-6.6, displacement type) on
     the same microstructure: pairs (<u>_k, -b_k) from the averaged
     displacement kernel, normal equations on the device, closed-form and
-    Adam fits per horizon, held-out relative residuals."""
+    Adam fits per kernel form and horizon, held-out relative residuals
+    against the force and against its equilibrated part."""
     import numpy as np
     import torch
     import gen
     from paper_2601_00822_amd import bump_forces
     from paper_2601_00822_amd import nonlocal_operator as NL
     dev = Ku.device
-    M, deltas = 6, (3.0, 5.0, 7.0)
+    M = 6
+    fits = [(0, 3.0), (0, 5.0), (0, 7.0), (1, 3.0), (1, 5.0)]     # (form, horizon); form 1 in 3D up to 5
     ntr, nte = min(args.train_samples, 1024), min(args.test_samples, 256)
-    nes = {dl: NL.NormalEquations(M, dl) for dl in deltas}
-    t_ne = 0.0
+    nes = {k: NL.NormalEquations(M, k[1], form=k[0]) for k in fits}
+    t_ne = {k: 0.0 for k in fits}
     ptr = gen.bump_set_params(n, ntr, 11)
-    for k in range(0, ntr, 64):
-        u, gam = NL.pairs(Ku, bump_forces((n, n, n), ptr[k:k + 64], device=dev), plan=conv_plan)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for dl in deltas:
-            nes[dl].add(u, gam)
-        t_ne += time.perf_counter() - t1
+    for k0 in range(0, ntr, 64):
+        u, gam = NL.pairs(Ku, bump_forces((n, n, n), ptr[k0:k0 + 64], device=dev), plan=conv_plan)
+        for k in fits:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            nes[k].add(u, gam)
+            t_ne[k] += time.perf_counter() - t1
     pte = gen.bump_set_params(n, nte, 12)
-    tests = [NL.pairs(Ku, bump_forces((n, n, n), pte[k:k + 64], device=dev), plan=conv_plan)
-             for k in range(0, nte, 64)]
-    out = {"degree": M, "train_pairs": ntr, "heldout_pairs": nte, "grid": [n, n, n],
-           "seconds_per_pair_normal_equations": t_ne / (ntr * len(deltas)), "horizons": {}}
-    for dl in deltas:
-        ne = nes[dl]
-        s = float(np.trace(ne.G)) / (M + 1)
+    tests = [NL.pairs(Ku, bump_forces((n, n, n), pte[k0:k0 + 64], device=dev), plan=conv_plan)
+             for k0 in range(0, nte, 64)]
+    out = {"degree": M, "train_pairs": ntr, "heldout_pairs": nte, "grid": [n, n, n], "fits": {}}
+    for k in fits:
+        form, dl = k
+        ne = nes[k]
+        s = float(np.trace(ne.G)) / len(ne.g)
         lam = 1e-10 * s
         ops = {"closed": NL.fit(ne, lam), "adam": NL.fit(ne, lam, adam_steps=20000, lr=1e-3)}
-        row = {}
+        row = {"seconds_per_pair_normal_equations": t_ne[k] / ntr}
         for name, op in ops.items():
             res = np.concatenate([op.relative_residual(u, g) for u, g in tests])
+            req = np.concatenate([op.relative_residual(u, g, equilibrated=True) for u, g in tests])
             row[name] = {"c": [float(v) for v in op.c], "train_loss_rel": ne.loss(op.c, lam) / ne.gg,
-                         "heldout_rel_residual": {"mean": float(res.mean()), "max": float(res.max())}}
+                         "heldout_rel_residual": {"mean": float(res.mean()), "max": float(res.max())},
+                         "heldout_rel_residual_equilibrated": {"mean": float(req.mean()), "max": float(req.max())}}
         u0 = tests[0][0]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ops["closed"].apply(u0)
         torch.cuda.synchronize()
         row["seconds_per_field_apply"] = (time.perf_counter() - t1) / u0.shape[0]
-        out["horizons"][str(dl)] = row
-        log(f"nonlocal delta {dl}: held-out relative residual closed "
-            f"{row['closed']['heldout_rel_residual']['mean']:.4f} (max {row['closed']['heldout_rel_residual']['max']:.4f}), "
-            f"adam {row['adam']['heldout_rel_residual']['mean']:.4f}")
+        key = f"{'matrix' if form else 'scalar'}/{dl}"
+        out["fits"][key] = row
+        log(f"nonlocal {key}: held-out relative residual closed {row['closed']['heldout_rel_residual']['mean']:.4f} "
+            f"(equilibrated {row['closed']['heldout_rel_residual_equilibrated']['mean']:.4f}, max "
+            f"{row['closed']['heldout_rel_residual_equilibrated']['max']:.4f}), adam "
+            f"{row['adam']['heldout_rel_residual_equilibrated']['mean']:.4f}")
     return out
 
 

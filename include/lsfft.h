@@ -339,40 +339,51 @@ lsfft_status lsfft_bump_forces(int prec, int dim, const int64_t* n, int nforce, 
 /*
  * Nonlocal kernel surrogate (Sec. 6, Eqs. 6.5-6.6).  The operator on the
  * periodic grid (h = 1):
- *   L_c[u](x) = sum over offsets r, 0 < |r| < delta, of K_c(|r|) (u(x + r) - u(x)),
- *   K_c(rho)  = sum_m c_m B_{m,M}(rho / delta),  B_{m,M}(t) = C(M, m) t^m (1 - t)^(M - m),
- * a radial scalar kernel acting on each displacement component alike.  The
- * fit of Eq. 6.6 to pairs (u_k, Gamma_k) minimises
+ *   L_c[u](x) = sum over offsets r, 0 < |r| < delta, of K(r) (u(x + r) - u(x)),
+ * with, by `form`:
+ *   0  K(r) = K1(|r|) I                       (a scalar radial kernel on
+ *                                              every component alike)
+ *   1  K(r) = K1(|r|) I + K2(|r|) e e^T,      e = r / |r| (components x
+ *                                              first): the isotropic matrix
+ *                                              kernel of the bond (Eq. 6.7
+ *                                              pairs the paper's kernels with
+ *                                              the bond vector)
+ *   Kj(rho) = sum_m cj_m B_{m,M}(rho / delta),  B_{m,M}(t) = C(M, m) t^m (1 - t)^(M - m);
+ * coefficients c = (c1_0..c1_M[, c2_0..c2_M]), nc = (form + 1)(M + 1).
+ * The fit of Eq. 6.6 to pairs (u_k, Gamma_k) minimises
  *   sum_k ||L_c[u_k] - Gamma_k||^2 + lam ||c||^2,
- * a quadratic in c: (G + lam I) c = g with G_mn = sum_k <Phi_m[u_k], Phi_n[u_k]>,
- * g_m = sum_k <Phi_m[u_k], Gamma_k>, Phi_m[u] = L_{e_m}[u] the features.
- * Horizon: 1 < delta <= 7 (voxels); degree M: 0..8.  Grids n = (nx, ny[, nz]),
- * any positive sizes; fields are [nsample][d][N] contiguous, in prec.
+ * a quadratic in c: (G + lam I) c = g with G_ij = sum_k <Phi_i[u_k], Phi_j[u_k]>,
+ * g_i = sum_k <Phi_i[u_k], Gamma_k>, Phi_i[u] = L_{e_i}[u] the features.
+ * Horizon: 1 < delta <= 7 (voxels; at most 5 for the 3D normal equations of
+ * form 1); degree M: 0..8.  Grids n = (nx, ny[, nz]), any positive sizes;
+ * fields are [nsample][d][N] contiguous, in prec.
  */
 
 /* The normal equations over nsample pairs, in FP64 (fixed summation order):
  *  u, gamma  device [nsample][d][N] (gamma: the operator type's response,
  *            -b_k for the displacement type)
- *  G         host [(M + 1)^2], row major, symmetric
- *  g         host [M + 1];  gg  host, sum_k ||Gamma_k||^2
+ *  G         host [nc^2], row major, symmetric
+ *  g         host [nc];  gg  host, sum_k ||Gamma_k||^2
  * Allocates a small device buffer; synchronises hip_stream.  LSFFT_E_ARG for
- * bad sizes, a horizon outside (1, 7] or null pointers. */
+ * bad sizes, a form other than 0 or 1, a horizon outside its range or null
+ * pointers. */
 lsfft_status lsfft_nonlocal_normal_equations(int prec, int dim, const int64_t* n, int nsample, const void* u,
-                                             const void* gamma, int degree, double delta, double* G, double* g,
-                                             double* gg, void* hip_stream);
+                                             const void* gamma, int degree, int form, double delta, double* G,
+                                             double* g, double* gg, void* hip_stream);
 
 /* out = L_c[u] for nsample fields (device [nsample][d][N] each, in prec; out
- * must not overlap u); c host [M + 1].  Allocates a small device buffer;
+ * must not overlap u); c host [nc].  Allocates a small device buffer;
  * synchronises hip_stream. */
 lsfft_status lsfft_nonlocal_apply(int prec, int dim, const int64_t* n, int nsample, const void* u, int degree,
-                                  const double* c, double delta, void* out, void* hip_stream);
+                                  int form, const double* c, double delta, void* out, void* hip_stream);
 
-/* Coefficients c (host [M + 1]) of Eq. 6.6 from the normal equations (host
- * arithmetic, no device use): adam_steps = 0 solves (G + lam I) c = g by
- * Cholesky (LSFFT_E_ARG if that matrix is not positive definite);
- * adam_steps > 0 runs that many Adam steps of size lr from c = 0 on the
- * quadratic loss (beta1 0.9, beta2 0.999, eps 1e-12, bias-corrected). */
-lsfft_status lsfft_nonlocal_fit(int degree, const double* G, const double* g, double lam, int adam_steps, double lr,
+/* Coefficients c (host [ncoef], 1 <= ncoef <= 18) of Eq. 6.6 from the normal
+ * equations G (host [ncoef^2]) and g (host [ncoef]), host arithmetic, no
+ * device use: adam_steps = 0 solves (G + lam I) c = g by Cholesky
+ * (LSFFT_E_ARG if that matrix is not positive definite); adam_steps > 0 runs
+ * that many Adam steps of size lr from c = 0 on the quadratic loss (beta1
+ * 0.9, beta2 0.999, eps 1e-12, bias-corrected). */
+lsfft_status lsfft_nonlocal_fit(int ncoef, const double* G, const double* g, double lam, int adam_steps, double lr,
                                 double* c);
 
 /* Memory m (1..8) of LSFFT_ANDERSON plans for later solves (default 5);

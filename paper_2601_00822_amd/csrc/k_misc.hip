@@ -251,18 +251,22 @@ hipError_t launch_bump_forces(bool f64, void* const* fs, const int* first, const
 }
 
 static_assert(kNlMaxDegree == kNlMaxDeg && kNlMaxHalo == kNlMaxR && kNlAccWords == kNlAcc &&
-                  kNlGramSlots == kNlGramBlocks,
+                  kNlGramSlots == kNlGramBlocks && kNlMaxHalo1 == kNlMaxR1 && kNlAccWords1 == kNlAcc1,
               "nonlocal constants of the launcher and the kernels must agree");
 
-static NlGeom nl_geom(int dim, const int n[3], int R, int nshell, int deg) {
+// tiles of the nonlocal kernels: two voxels per thread (8 x 8 x 8 in 3D,
+// 16 x 32 in 2D), or one (8 x 8 x 4, 16 x 16: the matrix-form normal
+// equations)
+static NlGeom nl_geom(int dim, const int n[3], int R, int nshell, int deg, bool one_voxel) {
   NlGeom G;
   G.nx = n[0];
   G.ny = n[1];
   G.nz = (dim == 3) ? n[2] : 1;
   G.dim = dim;
+  G.vpt = one_voxel ? 1 : 2;
   G.tx = (dim == 3) ? kNlTX : kNlTX2;
-  G.ty = (dim == 3) ? kNlTY : kNlTY2;
-  G.tz = (dim == 3) ? kNlTZ : 1;
+  G.ty = (dim == 3) ? kNlTY : (one_voxel ? kNlTY21 : kNlTY2);
+  G.tz = (dim == 3) ? (one_voxel ? kNlTZ1 : kNlTZ) : 1;
   G.ntx = (G.nx + G.tx - 1) / G.tx;
   G.nty = (G.ny + G.ty - 1) / G.ty;
   G.ntz = (G.nz + G.tz - 1) / G.tz;
@@ -275,53 +279,79 @@ static NlGeom nl_geom(int dim, const int n[3], int R, int nshell, int deg) {
   return G;
 }
 
-void nl_box(int dim, int R, int box[3]) {
+void nl_box(int dim, int R, bool one_voxel, int box[3]) {
   const int n[3] = {1, 1, 1};
-  const NlGeom G = nl_geom(dim, n, R, 0, 0);
+  const NlGeom G = nl_geom(dim, n, R, 0, 0, one_voxel);
   box[0] = G.lx;
   box[1] = G.ly;
   box[2] = G.lz;
 }
 
+static size_t nl_box_bytes(const NlGeom& G, bool f64) { return (size_t)G.lx * G.ly * G.lz * (f64 ? 8 : 4); }
+
 static size_t nl_lds_bytes(const NlGeom& G, bool f64) {
-  const size_t box = (size_t)G.lx * G.ly * G.lz * (f64 ? 8 : 4);
+  const size_t box = nl_box_bytes(G, f64);
   const size_t red = (size_t)kNlAcc * (NTR / 64) * sizeof(double);
   return box > red ? box : red;
 }
 
-hipError_t launch_nl_gram(bool f64, int dim, const int n[3], int R, int deg, int nsample, const void* u,
-                          const void* gam, const int* offs, const int* first, int nshell, const double* W,
-                          double* partial, double* out, hipStream_t st) {
-  if (deg < 0 || deg > kNlMaxDeg || R < 0 || R > kNlMaxR || nsample < 1 || nshell < 0) return hipErrorInvalidValue;
-  const NlGeom G = nl_geom(dim, n, R, nshell, deg);
+hipError_t launch_nl_gram(bool f64, int dim, const int n[3], int R, int deg, int form, int nsample, const void* u,
+                          const void* gam, const int* offs, const int* first, const double* ee, int nshell,
+                          const double* W, double* partial, double* out, hipStream_t st) {
+  if (deg < 0 || deg > kNlMaxDeg || R < 0 || nsample < 1 || nshell < 0 || (form != 0 && form != 1))
+    return hipErrorInvalidValue;
+  if (R > (form == 1 && dim == 3 ? kNlMaxR1 : kNlMaxR)) return hipErrorInvalidValue;
+  const NlGeom G = nl_geom(dim, n, R, nshell, deg, form == 1);
   const long long items = (long long)nsample * G.ntx * G.nty * G.ntz;
   const unsigned grid = (unsigned)(items < kNlGramBlocks ? items : kNlGramBlocks);
-  const size_t lds = nl_lds_bytes(G, f64);
-  if (f64)
-    hipLaunchKernelGGL(k_nl_gram<double>, dim3(grid), NTR, lds, st, G, static_cast<const double*>(u),
-                       static_cast<const double*>(gam), nsample, offs, first, W, partial);
-  else
-    hipLaunchKernelGGL(k_nl_gram<float>, dim3(grid), NTR, lds, st, G, static_cast<const float*>(u),
-                       static_cast<const float*>(gam), nsample, offs, first, W, partial);
+  if (form == 0) {
+    const size_t lds = nl_lds_bytes(G, f64);
+    if (f64)
+      hipLaunchKernelGGL(k_nl_gram<double>, dim3(grid), NTR, lds, st, G, static_cast<const double*>(u),
+                         static_cast<const double*>(gam), nsample, offs, first, W, partial);
+    else
+      hipLaunchKernelGGL(k_nl_gram<float>, dim3(grid), NTR, lds, st, G, static_cast<const float*>(u),
+                         static_cast<const float*>(gam), nsample, offs, first, W, partial);
+  } else {
+    const size_t lds = sizeof(double) * ((size_t)kNlF1 * kNlFeatPitch + NTR) + nl_box_bytes(G, f64);
+    if (lds > 65536) return hipErrorInvalidValue;
+    if (f64)
+      hipLaunchKernelGGL(k_nl_gram1<double>, dim3(grid), NTR, lds, st, G, static_cast<const double*>(u),
+                         static_cast<const double*>(gam), nsample, offs, first, ee, W, partial);
+    else
+      hipLaunchKernelGGL(k_nl_gram1<float>, dim3(grid), NTR, lds, st, G, static_cast<const float*>(u),
+                         static_cast<const float*>(gam), nsample, offs, first, ee, W, partial);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_nl_gram_sum, dim3(1), NTR, 0, st, partial, (int)grid, out);
+  const int stride = form == 0 ? kNlAcc : kNlAcc1;
+  hipLaunchKernelGGL(k_nl_gram_sum, dim3(1), NTR, 0, st, partial, (int)grid, stride, stride, out);
   return hipGetLastError();
 }
 
-hipError_t launch_nl_apply(bool f64, int dim, const int n[3], int R, int nsample, const void* u, const int* offs,
-                           const int* first, int nshell, const double* kw, void* out, hipStream_t st) {
-  if (R < 0 || R > kNlMaxR || nsample < 1 || nshell < 0) return hipErrorInvalidValue;
-  const NlGeom G = nl_geom(dim, n, R, nshell, 0);
+hipError_t launch_nl_apply(bool f64, int dim, const int n[3], int R, int form, int nsample, const void* u,
+                           const int* offs, const int* first, const double* ee, int nshell, const double* kw1,
+                           const double* kw2, void* out, hipStream_t st) {
+  if (R < 0 || R > kNlMaxR || nsample < 1 || nshell < 0 || (form != 0 && form != 1)) return hipErrorInvalidValue;
+  const NlGeom G = nl_geom(dim, n, R, nshell, 0, false);
   const long long items = (long long)nsample * G.ntx * G.nty * G.ntz;
   if (items > 0x7fffffffLL) return hipErrorInvalidValue;
   const size_t lds = nl_lds_bytes(G, f64);
-  if (f64)
-    hipLaunchKernelGGL(k_nl_apply<double>, dim3((unsigned)items), NTR, lds, st, G, static_cast<const double*>(u),
-                       nsample, offs, first, kw, static_cast<double*>(out));
-  else
-    hipLaunchKernelGGL(k_nl_apply<float>, dim3((unsigned)items), NTR, lds, st, G, static_cast<const float*>(u),
-                       nsample, offs, first, kw, static_cast<float*>(out));
+  if (form == 0) {
+    if (f64)
+      hipLaunchKernelGGL(k_nl_apply<double>, dim3((unsigned)items), NTR, lds, st, G, static_cast<const double*>(u),
+                         nsample, offs, first, kw1, static_cast<double*>(out));
+    else
+      hipLaunchKernelGGL(k_nl_apply<float>, dim3((unsigned)items), NTR, lds, st, G, static_cast<const float*>(u),
+                         nsample, offs, first, kw1, static_cast<float*>(out));
+  } else {
+    if (f64)
+      hipLaunchKernelGGL(k_nl_apply1<double>, dim3((unsigned)items), NTR, lds, st, G, static_cast<const double*>(u),
+                         nsample, offs, first, ee, kw1, kw2, static_cast<double*>(out));
+    else
+      hipLaunchKernelGGL(k_nl_apply1<float>, dim3((unsigned)items), NTR, lds, st, G, static_cast<const float*>(u),
+                         nsample, offs, first, ee, kw1, kw2, static_cast<float*>(out));
+  }
   return hipGetLastError();
 }
 

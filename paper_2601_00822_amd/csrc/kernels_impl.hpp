@@ -2251,7 +2251,20 @@ struct NlGeom {
   int lx, ly, lz;          // LDS box (tile + 2 R; lz = 1 in 2D)
   int nshell;
   int deg;
+  int vpt;                 // voxels per thread: 2, or 1 (tiles of half the voxels)
 };
+
+// Matrix form K1(|r|) I + K2(|r|) e e^T: 2 (M + 1) features per component,
+// one voxel per thread on tiles of 8 x 8 x 4 (3D) or 16 x 16 (2D), the
+// features of a tile in LDS rows of kNlFeatPitch doubles, and one Gram
+// entry per thread (the upper triangle row by row, then g, then
+// Gamma . Gamma).  The halo of its 3D normal equations is at most kNlMaxR1.
+constexpr int kNlF1 = 2 * kNlF;
+constexpr int kNlAcc1 = kNlF1 * (kNlF1 + 1) / 2 + kNlF1 + 1;
+constexpr int kNlMaxR1 = 4;
+constexpr int kNlTZ1 = 4, kNlTY21 = 16;
+constexpr int kNlFeatPitch = NTR + 1;
+static_assert(kNlAcc1 <= NTR, "one Gram entry per thread");
 
 template <typename T>
 __device__ __forceinline__ void nl_stage(const NlGeom& G, const T* __restrict__ ua, int x0, int y0, int z0, T* lds) {
@@ -2285,18 +2298,19 @@ __device__ __forceinline__ void nl_tile(const NlGeom& G, int tile, int& x0, int&
   const int lxv = t % G.tx, r2 = t / G.tx;
 #pragma unroll
   for (int v = 0; v < 2; ++v) {
+    const int vv = (G.vpt == 2) ? v : 0;      // one voxel per thread: both slots name it
     int ly, lz;
     if (G.dim == 3) {
       ly = r2 % G.ty;
-      lz = r2 / G.ty + v * (G.tz / 2);
+      lz = r2 / G.ty + vv * (G.tz / 2);
     } else {
-      ly = r2 + v * (G.ty / 2);
+      ly = r2 + vv * (G.ty / 2);
       lz = 0;
     }
     vx[v] = x0 + lxv;
     vy[v] = y0 + ly;
     vz[v] = z0 + lz;
-    ok[v] = vx[v] < G.nx && vy[v] < G.ny && vz[v] < G.nz;
+    ok[v] = vx[v] < G.nx && vy[v] < G.ny && vz[v] < G.nz && (G.vpt == 2 || v == 0);
     const int R = G.R, Rz = (G.dim == 3) ? G.R : 0;
     base[v] = ((lz + Rz) * G.ly + (ly + R)) * G.lx + (lxv + R);
   }
@@ -2397,13 +2411,14 @@ __global__ __launch_bounds__(NTR) void k_nl_gram(NlGeom G, const T* __restrict__
   }
 }
 
-// fixed-order sum of the partial slots (one workgroup)
-__global__ __launch_bounds__(NTR) void k_nl_gram_sum(const double* __restrict__ partial, int nslot,
-                                                     double* __restrict__ out) {
+// fixed-order sum of the partial slots (one workgroup): out[i] = sum over
+// slots of partial[slot stride + i], i < nacc
+__global__ __launch_bounds__(NTR) void k_nl_gram_sum(const double* __restrict__ partial, int nslot, int stride,
+                                                     int nacc, double* __restrict__ out) {
   __shared__ double red[NTR / 64];
-  for (int i = 0; i < kNlAcc; ++i) {
+  for (int i = 0; i < nacc; ++i) {
     double a = 0.0;
-    for (int s = threadIdx.x; s < nslot; s += NTR) a += partial[(long long)s * kNlAcc + i];
+    for (int s = threadIdx.x; s < nslot; s += NTR) a += partial[(long long)s * stride + i];
     const double sum = block_sum<NTR>(a, red);
     if (threadIdx.x == 0) out[i] = sum;
   }
@@ -2438,6 +2453,174 @@ __global__ __launch_bounds__(NTR) void k_nl_apply(NlGeom G, const T* __restrict_
     });
     if (ok[0]) out[comp + ((long long)vz[0] * G.ny + vy[0]) * G.nx + vx[0]] = T(r0);
     if (ok[1]) out[comp + ((long long)vz[1] * G.ny + vy[1]) * G.nx + vx[1]] = T(r1);
+  }
+}
+
+// Normal equations of the matrix form.  Per staged input component b and
+// shell q: S = sum of (u_b(x + r) - u_b(x)) and T_a = sum of e_a e_b
+// (u_b(x + r) - u_b(x)), then Phi1[b][m] += W[m][q] S and Phi2[a][m] +=
+// W[m][q] T_a.  ee holds e_a e_b per offset as ee[(o 3 + b) 3 + a] (x
+// first, zero beyond the dimension).
+template <typename T>
+__global__ __launch_bounds__(NTR) void k_nl_gram1(NlGeom G, const T* __restrict__ u, const T* __restrict__ gam,
+                                                  int nsample, const int* __restrict__ offs,
+                                                  const int* __restrict__ first, const double* __restrict__ ee,
+                                                  const double* __restrict__ W, double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char nl_smem[];
+  double* feat = reinterpret_cast<double*>(nl_smem);          // [kNlF1][kNlFeatPitch]
+  double* gt = feat + kNlF1 * kNlFeatPitch;                    // [NTR]
+  T* lds = reinterpret_cast<T*>(gt + NTR);                     // staged box
+  const long long nvox = (long long)G.nx * G.ny * G.nz;
+  const int ntile = G.ntx * G.nty * G.ntz;
+  const int nf1 = G.deg + 1, nf = 2 * nf1;
+  const int ntri = nf * (nf + 1) / 2;
+  const int t = threadIdx.x;
+  // the Gram entry this thread owns
+  int kind = -1, ei = 0, ej = 0;
+  if (t < ntri) {
+    int i = 0, rem = t;
+    while (rem >= nf - i) {
+      rem -= nf - i;
+      ++i;
+    }
+    kind = 0;
+    ei = i;
+    ej = i + rem;
+  } else if (t < ntri + nf) {
+    kind = 1;
+    ei = t - ntri;
+  } else if (t == ntri + nf) {
+    kind = 2;
+  }
+  double acc = 0.0;
+  for (long long item = blockIdx.x; item < (long long)nsample * ntile; item += gridDim.x) {
+    const int k = int(item / ntile), tile = int(item % ntile);
+    int x0, y0, z0, vx[2], vy[2], vz[2], base[2];
+    bool ok[2];
+    nl_tile(G, tile, x0, y0, z0, vx, vy, vz, base, ok);
+    double p1[3][kNlF], p2[3][kNlF];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int m = 0; m < kNlF; ++m) {
+        p1[a][m] = 0.0;
+        p2[a][m] = 0.0;
+      }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (b >= G.dim) break;
+      __syncthreads();
+      nl_stage(G, u + ((long long)k * G.dim + b) * nvox, x0, y0, z0, lds);
+      __syncthreads();
+      const double u0 = double(lds[base[0]]);
+      for (int q = 0; q < G.nshell; ++q) {
+        const int o0 = first[q], o1 = first[q + 1];
+        double S = 0.0, T0 = 0.0, T1 = 0.0, T2 = 0.0;
+        for (int o = o0; o < o1; ++o) {
+          const double dv = double(lds[base[0] + offs[o]]) - u0;
+          const double* e = ee + (o * 3 + b) * 3;
+          S += dv;
+          T0 += e[0] * dv;
+          T1 += e[1] * dv;
+          T2 += e[2] * dv;
+        }
+#pragma unroll
+        for (int m = 0; m < kNlF; ++m) {
+          if (m < nf1) {
+            const double w = W[m * G.nshell + q];
+            p1[b][m] += w * S;
+            p2[0][m] += w * T0;
+            p2[1][m] += w * T1;
+            p2[2][m] += w * T2;
+          }
+        }
+      }
+    }
+    // per output component: the tile's features into LDS, then every owner
+    // thread adds its entry's sum over the tile's voxels
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a >= G.dim) break;
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < kNlF; ++m) {
+        if (m < nf1) {
+          feat[m * kNlFeatPitch + t] = ok[0] ? p1[a][m] : 0.0;
+          feat[(nf1 + m) * kNlFeatPitch + t] = ok[0] ? p2[a][m] : 0.0;
+        }
+      }
+      gt[t] = ok[0] ? double(gam[((long long)k * G.dim + a) * nvox + ((long long)vz[0] * G.ny + vy[0]) * G.nx + vx[0]])
+                    : 0.0;
+      __syncthreads();
+      if (kind == 0) {
+        const double* fi = feat + ei * kNlFeatPitch;
+        const double* fj = feat + ej * kNlFeatPitch;
+        for (int v = 0; v < NTR; ++v) acc += fi[v] * fj[v];
+      } else if (kind == 1) {
+        const double* fi = feat + ei * kNlFeatPitch;
+        for (int v = 0; v < NTR; ++v) acc += fi[v] * gt[v];
+      } else if (kind == 2) {
+        for (int v = 0; v < NTR; ++v) acc += gt[v] * gt[v];
+      }
+    }
+  }
+  if (t < kNlAcc1) partial[(long long)blockIdx.x * kNlAcc1 + t] = (kind >= 0) ? acc : 0.0;
+}
+
+// The fitted matrix-form operator: out_a = sum over b and shells of
+// (K1_q delta_ab S_q + K2_q T_aq), kw1 / kw2 the two kernels at each
+// shell's radius; one workgroup per (sample, tile), two voxels per thread.
+template <typename T>
+__global__ __launch_bounds__(NTR) void k_nl_apply1(NlGeom G, const T* __restrict__ u, int nsample,
+                                                   const int* __restrict__ offs, const int* __restrict__ first,
+                                                   const double* __restrict__ ee, const double* __restrict__ kw1,
+                                                   const double* __restrict__ kw2, T* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char nl_smem[];
+  T* lds = reinterpret_cast<T*>(nl_smem);
+  const long long nvox = (long long)G.nx * G.ny * G.nz;
+  const int ntile = G.ntx * G.nty * G.ntz;
+  const long long item = blockIdx.x;
+  if (item >= (long long)nsample * ntile) return;
+  const int k = int(item / ntile), tile = int(item % ntile);
+  int x0, y0, z0, vx[2], vy[2], vz[2], base[2];
+  bool ok[2];
+  nl_tile(G, tile, x0, y0, z0, vx, vy, vz, base, ok);
+  double r[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if (b >= G.dim) break;
+    __syncthreads();
+    nl_stage(G, u + ((long long)k * G.dim + b) * nvox, x0, y0, z0, lds);
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const double u0 = double(lds[base[v]]);
+      for (int q = 0; q < G.nshell; ++q) {
+        const int o0 = first[q], o1 = first[q + 1];
+        double S = 0.0, T0 = 0.0, T1 = 0.0, T2 = 0.0;
+        for (int o = o0; o < o1; ++o) {
+          const double dv = double(lds[base[v] + offs[o]]) - u0;
+          const double* e = ee + (o * 3 + b) * 3;
+          S += dv;
+          T0 += e[0] * dv;
+          T1 += e[1] * dv;
+          T2 += e[2] * dv;
+        }
+        const double w1 = kw1[q], w2 = kw2[q];
+        r[v][b] += w1 * S;
+        r[v][0] += w2 * T0;
+        r[v][1] += w2 * T1;
+        r[v][2] += w2 * T2;
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    if (!ok[v]) continue;
+    const long long vox = ((long long)vz[v] * G.ny + vy[v]) * G.nx + vx[v];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (a < G.dim) out[((long long)k * G.dim + a) * nvox + vox] = T(r[v][a]);
   }
 }
 

@@ -90,21 +90,29 @@ hipError_t launch_sample_norms(bool f64, const void* y, const void* t, int nsamp
                                hipStream_t st);
 hipError_t launch_bump_forces(bool f64, void* const* fs, const int* first, const double* bumps, int nforce, int nx,
                               int ny, int nz, int dim, hipStream_t st);
-// Nonlocal kernel regression (see k_nl_gram, k_nl_apply).  Offsets of the
-// horizon are given as index deltas in the LDS box of a tile (nl_box: its
-// extent (lx, ly, lz) for halo R), sorted by shell: shell q holds offsets
-// first[q] .. first[q + 1] - 1.  launch_nl_gram writes kNlAccWords doubles to
-// `out`: the upper triangle of G row by row for degree kNlMaxDegree (entries
-// beyond `deg` zero), then g (kNlMaxDegree + 1), then Gamma . Gamma; W is
-// [deg + 1][nshell] and `partial` holds kNlGramSlots x kNlAccWords doubles.
-// launch_nl_apply writes sum_q kw[q] (S_q - n_q u) per component.
+// Nonlocal kernel regression (see k_nl_gram, k_nl_gram1, k_nl_apply,
+// k_nl_apply1).  Offsets of the horizon are given as index deltas in the
+// LDS box of a tile (nl_box: its extent (lx, ly, lz) for halo R; one_voxel
+// names the tiles of the matrix-form normal equations), sorted by shell:
+// shell q holds offsets first[q] .. first[q + 1] - 1; ee holds the direction
+// products e_a e_b of every offset at ee[(o 3 + b) 3 + a].  form 0 is the
+// scalar kernel, form 1 the matrix kernel K1 I + K2 e e^T.
+// launch_nl_gram writes to `out` for form 0 kNlAccWords doubles (the upper
+// triangle of G row by row for degree kNlMaxDegree, entries beyond `deg`
+// zero, then g, then Gamma . Gamma) and for form 1 kNlAccWords1 doubles (the
+// upper triangle for nf = 2 (deg + 1) features row by row, then g, then
+// Gamma . Gamma, then zeros); W is [deg + 1][nshell] and `partial` holds
+// kNlGramSlots x kNlAccWords1 doubles.  launch_nl_apply writes
+// sum_q kw1[q] (S_q - n_q u) per component, plus the kw2 terms for form 1.
 constexpr int kNlMaxDegree = 8, kNlMaxHalo = 6, kNlAccWords = 55, kNlGramSlots = 2048;
-void nl_box(int dim, int R, int box[3]);
-hipError_t launch_nl_gram(bool f64, int dim, const int n[3], int R, int deg, int nsample, const void* u,
-                          const void* gam, const int* offs, const int* first, int nshell, const double* W,
-                          double* partial, double* out, hipStream_t st);
-hipError_t launch_nl_apply(bool f64, int dim, const int n[3], int R, int nsample, const void* u, const int* offs,
-                           const int* first, int nshell, const double* kw, void* out, hipStream_t st);
+constexpr int kNlMaxHalo1 = 4, kNlAccWords1 = 190;
+void nl_box(int dim, int R, bool one_voxel, int box[3]);
+hipError_t launch_nl_gram(bool f64, int dim, const int n[3], int R, int deg, int form, int nsample, const void* u,
+                          const void* gam, const int* offs, const int* first, const double* ee, int nshell,
+                          const double* W, double* partial, double* out, hipStream_t st);
+hipError_t launch_nl_apply(bool f64, int dim, const int n[3], int R, int form, int nsample, const void* u,
+                           const int* offs, const int* first, const double* ee, int nshell, const double* kw1,
+                           const double* kw2, void* out, hipStream_t st);
 constexpr int kRveBinsMax = 1024;   // bins of launch_radial_max
 hipError_t launch_radial_max(int dim, const double* avg, const int n[3], const double h[3], const double c[3],
                              double dr, int nbins, unsigned long long* bins, hipStream_t st);

@@ -2156,28 +2156,39 @@ struct NlHorizon {
   int R = 0;
   std::vector<int> delta, first;   // offsets of shell q: delta[first[q] .. first[q + 1])
   std::vector<double> rho;         // per shell
+  std::vector<double> ee;          // per offset, e_a e_b at (o 3 + b) 3 + a (x first)
   int nshell() const { return (int)rho.size(); }
 };
 
-bool nl_horizon(int dim, double delta, NlHorizon& h) {
+// one_voxel: the deltas of the tiles of the matrix-form normal equations
+bool nl_horizon(int dim, double delta, bool one_voxel, NlHorizon& h) {
   if (!is_fin(delta) || delta <= 1.0 || delta > kNlMaxHalo + 1) return false;
   const int R = (int)std::ceil(delta) - 1;
   int box[3];
-  nl_box(dim, R, box);
-  std::map<int, std::vector<int>> shells;   // |r|^2 -> deltas
+  nl_box(dim, R, one_voxel, box);
+  struct Off {
+    int delta;
+    double e[3];
+  };
+  std::map<int, std::vector<Off>> shells;   // |r|^2 -> offsets
   const int rz = dim == 3 ? R : 0;
   for (int dz = -rz; dz <= rz; ++dz)
     for (int dy = -R; dy <= R; ++dy)
       for (int dx = -R; dx <= R; ++dx) {
         const int rr = dx * dx + dy * dy + dz * dz;
-        if (rr == 0 || !(std::sqrt(double(rr)) < delta)) continue;
-        shells[rr].push_back((dz * box[1] + dy) * box[0] + dx);
+        const double rho = std::sqrt(double(rr));
+        if (rr == 0 || !(rho < delta)) continue;
+        shells[rr].push_back({(dz * box[1] + dy) * box[0] + dx, {dx / rho, dy / rho, dz / rho}});
       }
   if (shells.empty()) return false;
   h.R = R;
   h.first.push_back(0);
   for (const auto& kv : shells) {
-    h.delta.insert(h.delta.end(), kv.second.begin(), kv.second.end());
+    for (const Off& o : kv.second) {
+      h.delta.push_back(o.delta);
+      for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) h.ee.push_back(o.e[a] * o.e[b]);
+    }
     h.first.push_back((int)h.delta.size());
     h.rho.push_back(std::sqrt(double(kv.first)));
   }
@@ -2198,11 +2209,13 @@ std::vector<double> nl_bernstein(int M, double delta, const NlHorizon& h) {
   return W;
 }
 
-// device copy of the horizon tables (ints, then doubles), freed by the caller
+// device copy of the horizon tables (ints, then the direction products and
+// the caller's doubles), freed by the caller
 struct NlTables {
   char* buf = nullptr;
   const int* delta = nullptr;
   const int* first = nullptr;
+  const double* ee = nullptr;
   const double* vals = nullptr;
   double* work = nullptr;
 };
@@ -2210,7 +2223,9 @@ struct NlTables {
 hipError_t nl_upload(const NlHorizon& h, const std::vector<double>& vals, size_t work_doubles, hipStream_t st,
                      NlTables& t) {
   const size_t b_delta = sizeof(int) * h.delta.size(), b_first = sizeof(int) * h.first.size();
-  const size_t o_first = align_up(b_delta, 16), o_vals = align_up(o_first + b_first, 16);
+  const size_t b_ee = sizeof(double) * h.ee.size();
+  const size_t o_first = align_up(b_delta, 16), o_ee = align_up(o_first + b_first, 16);
+  const size_t o_vals = align_up(o_ee + b_ee, 16);
   const size_t o_work = align_up(o_vals + sizeof(double) * vals.size(), 256);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&t.buf), o_work + sizeof(double) * std::max<size_t>(work_doubles, 1));
   if (e != hipSuccess) {
@@ -2219,10 +2234,12 @@ hipError_t nl_upload(const NlHorizon& h, const std::vector<double>& vals, size_t
   }
   t.delta = reinterpret_cast<const int*>(t.buf);
   t.first = reinterpret_cast<const int*>(t.buf + o_first);
+  t.ee = reinterpret_cast<const double*>(t.buf + o_ee);
   t.vals = reinterpret_cast<const double*>(t.buf + o_vals);
   t.work = reinterpret_cast<double*>(t.buf + o_work);
   e = hipMemcpyAsync(t.buf, h.delta.data(), b_delta, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(t.buf + o_first, h.first.data(), b_first, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(t.buf + o_ee, h.ee.data(), b_ee, hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(t.buf + o_vals, vals.data(), sizeof(double) * vals.size(), hipMemcpyHostToDevice, st);
   return e;
@@ -2245,31 +2262,35 @@ lsfft_status nl_check(int prec, int dim, const int64_t* n, int nsample, int n_ou
 extern "C" {
 
 lsfft_status lsfft_nonlocal_normal_equations(int prec, int dim, const int64_t* n, int nsample, const void* u,
-                                             const void* gamma, int degree, double delta, double* G, double* g,
-                                             double* gg, void* hip_stream) {
+                                             const void* gamma, int degree, int form, double delta, double* G,
+                                             double* g, double* gg, void* hip_stream) {
   int nn[3];
   if (nl_check(prec, dim, n, nsample, nn) != LSFFT_OK || !u || !gamma || !G || !g || !gg) return LSFFT_E_ARG;
-  if (degree < 0 || degree > kNlMaxDegree) return LSFFT_E_ARG;
+  if (degree < 0 || degree > kNlMaxDegree || (form != 0 && form != 1)) return LSFFT_E_ARG;
   NlHorizon h;
-  if (!nl_horizon(dim, delta, h)) return LSFFT_E_ARG;
+  if (!nl_horizon(dim, delta, form == 1, h)) return LSFFT_E_ARG;
+  if (form == 1 && dim == 3 && h.R > kNlMaxHalo1) return LSFFT_E_ARG;
   const std::vector<double> W = nl_bernstein(degree, delta, h);
   hipStream_t st = as_stream(hip_stream);
   NlTables t;
-  const size_t work = (size_t)kNlGramSlots * kNlAccWords + kNlAccWords;
+  const size_t work = (size_t)kNlGramSlots * kNlAccWords1 + kNlAccWords1;
   hipError_t e = nl_upload(h, W, work, st, t);
   if (!t.buf) return LSFFT_E_ALLOC;
-  double* out = t.work + (size_t)kNlGramSlots * kNlAccWords;
-  std::vector<double> acc(kNlAccWords);
+  double* out = t.work + (size_t)kNlGramSlots * kNlAccWords1;
+  std::vector<double> acc(kNlAccWords1);
   if (e == hipSuccess)
-    e = launch_nl_gram(prec == LSFFT_F64, dim, nn, h.R, degree, nsample, u, gamma, t.delta, t.first, h.nshell(), t.vals,
-                       t.work, out, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(acc.data(), out, sizeof(double) * kNlAccWords, hipMemcpyDeviceToHost, st);
+    e = launch_nl_gram(prec == LSFFT_F64, dim, nn, h.R, degree, form, nsample, u, gamma, t.delta, t.first, t.ee,
+                       h.nshell(), t.vals, t.work, out, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(acc.data(), out, sizeof(double) * (form == 0 ? kNlAccWords : kNlAccWords1),
+                       hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(t.buf);
   if (e != hipSuccess) return LSFFT_E_DEVICE;
-  // unpack the upper triangle (laid out for degree kNlMaxDegree)
-  constexpr int F = kNlMaxDegree + 1;
-  const int nf = degree + 1;
+  // unpack the upper triangle: form 0 laid out for degree kNlMaxDegree,
+  // form 1 for its own nf = 2 (degree + 1) features
+  const int nf = (form == 0 ? 1 : 2) * (degree + 1);
+  const int F = form == 0 ? kNlMaxDegree + 1 : nf;
   for (int m = 0; m < nf; ++m)
     for (int k = m; k < nf; ++k) {
       const double v = acc[(size_t)(m * F - m * (m - 1) / 2 + (k - m))];
@@ -2283,34 +2304,39 @@ lsfft_status lsfft_nonlocal_normal_equations(int prec, int dim, const int64_t* n
 }
 
 lsfft_status lsfft_nonlocal_apply(int prec, int dim, const int64_t* n, int nsample, const void* u, int degree,
-                                  const double* c, double delta, void* out, void* hip_stream) {
+                                  int form, const double* c, double delta, void* out, void* hip_stream) {
   int nn[3];
   if (nl_check(prec, dim, n, nsample, nn) != LSFFT_OK || !u || !c || !out) return LSFFT_E_ARG;
-  if (degree < 0 || degree > kNlMaxDegree) return LSFFT_E_ARG;
-  for (int m = 0; m <= degree; ++m)
+  if (degree < 0 || degree > kNlMaxDegree || (form != 0 && form != 1)) return LSFFT_E_ARG;
+  const int nf1 = degree + 1, nc = (form + 1) * nf1;
+  for (int m = 0; m < nc; ++m)
     if (!is_fin(c[m])) return LSFFT_E_ARG;
   NlHorizon h;
-  if (!nl_horizon(dim, delta, h)) return LSFFT_E_ARG;
+  if (!nl_horizon(dim, delta, false, h)) return LSFFT_E_ARG;
   const std::vector<double> W = nl_bernstein(degree, delta, h);
-  std::vector<double> kw(h.nshell(), 0.0);        // K_c at each shell's radius
-  for (int q = 0; q < h.nshell(); ++q)
-    for (int m = 0; m <= degree; ++m) kw[q] += c[m] * W[(size_t)m * h.nshell() + q];
+  // K1 (and K2) at each shell's radius, one table after the other
+  std::vector<double> kw((size_t)(form + 1) * h.nshell(), 0.0);
+  for (int f = 0; f <= form; ++f)
+    for (int q = 0; q < h.nshell(); ++q)
+      for (int m = 0; m <= degree; ++m)
+        kw[(size_t)f * h.nshell() + q] += c[f * nf1 + m] * W[(size_t)m * h.nshell() + q];
   hipStream_t st = as_stream(hip_stream);
   NlTables t;
   hipError_t e = nl_upload(h, kw, 0, st, t);
   if (!t.buf) return LSFFT_E_ALLOC;
   if (e == hipSuccess)
-    e = launch_nl_apply(prec == LSFFT_F64, dim, nn, h.R, nsample, u, t.delta, t.first, h.nshell(), t.vals, out, st);
+    e = launch_nl_apply(prec == LSFFT_F64, dim, nn, h.R, form, nsample, u, t.delta, t.first, t.ee, h.nshell(),
+                        t.vals, t.vals + (form == 1 ? h.nshell() : 0), out, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(t.buf);
   return e == hipSuccess ? LSFFT_OK : LSFFT_E_DEVICE;
 }
 
-lsfft_status lsfft_nonlocal_fit(int degree, const double* G, const double* g, double lam, int adam_steps, double lr,
+lsfft_status lsfft_nonlocal_fit(int ncoef, const double* G, const double* g, double lam, int adam_steps, double lr,
                                 double* c) {
-  if (degree < 0 || degree > kNlMaxDegree || !G || !g || !c || !is_fin(lam) || lam < 0.0 || adam_steps < 0)
+  if (ncoef < 1 || ncoef > 2 * (kNlMaxDegree + 1) || !G || !g || !c || !is_fin(lam) || lam < 0.0 || adam_steps < 0)
     return LSFFT_E_ARG;
-  const int nf = degree + 1;
+  const int nf = ncoef;
   for (int i = 0; i < nf * nf; ++i)
     if (!is_fin(G[i])) return LSFFT_E_ARG;
   for (int i = 0; i < nf; ++i)

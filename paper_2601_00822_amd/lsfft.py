@@ -132,10 +132,10 @@ def load_library(path: str = LIB_PATH):
     lib.lsfft_bump_forces.argtypes = [ip, ip, C.POINTER(C.c_int64), ip, C.POINTER(ip), C.POINTER(dp),
                                       C.POINTER(vp), vp]
     lib.lsfft_bump_forces.restype = ip
-    lib.lsfft_nonlocal_normal_equations.argtypes = [ip, ip, C.POINTER(C.c_int64), ip, vp, vp, ip, dp, C.POINTER(dp),
-                                                    C.POINTER(dp), C.POINTER(dp), vp]
+    lib.lsfft_nonlocal_normal_equations.argtypes = [ip, ip, C.POINTER(C.c_int64), ip, vp, vp, ip, ip, dp,
+                                                    C.POINTER(dp), C.POINTER(dp), C.POINTER(dp), vp]
     lib.lsfft_nonlocal_normal_equations.restype = ip
-    lib.lsfft_nonlocal_apply.argtypes = [ip, ip, C.POINTER(C.c_int64), ip, vp, ip, C.POINTER(dp), dp, vp, vp]
+    lib.lsfft_nonlocal_apply.argtypes = [ip, ip, C.POINTER(C.c_int64), ip, vp, ip, ip, C.POINTER(dp), dp, vp, vp]
     lib.lsfft_nonlocal_apply.restype = ip
     lib.lsfft_nonlocal_fit.argtypes = [ip, C.POINTER(dp), C.POINTER(dp), dp, ip, dp, C.POINTER(dp)]
     lib.lsfft_nonlocal_fit.restype = ip
@@ -241,38 +241,43 @@ def _nl_fields(u, name):
     return _prec_of(u), d, n, int(u.shape[0])
 
 
-def nonlocal_normal_equations(u, gamma, degree: int, delta: float):
+def nonlocal_normal_equations(u, gamma, degree: int, delta: float, form: int = 0):
     """(G, g, Gamma . Gamma) of the least-squares fit of the nonlocal
-    operator with a degree-``degree`` Bernstein kernel of horizon ``delta``
-    to the pairs (u_k, Gamma_k), ``[nsample][d][...grid]`` GPU tensors;
-    FP64 numpy, computed by the library."""
+    operator with degree-``degree`` Bernstein kernels of horizon ``delta``
+    (``form`` 0: scalar kernel, 1: K1 I + K2 e e^T) to the pairs
+    (u_k, Gamma_k), ``[nsample][d][...grid]`` GPU tensors; FP64 numpy,
+    computed by the library."""
     torch = _torch()
     prec, d, n, ns = _nl_fields(u, "u")
     _dev_check(gamma, "gamma")
     if gamma.shape != u.shape or gamma.dtype != u.dtype:
         raise ValueError("u and gamma must match")
-    nf = degree + 1
+    nf = (2 if form == 1 else 1) * (degree + 1)
     G = np.zeros((nf, nf))
     g = np.zeros(nf)
     gg = C.c_double(0.0)
     dp = C.POINTER(C.c_double)
     st = load_library().lsfft_nonlocal_normal_equations(prec, d, n, ns, C.c_void_p(u.data_ptr()),
-                                                        C.c_void_p(gamma.data_ptr()), int(degree), float(delta),
-                                                        G.ctypes.data_as(dp), g.ctypes.data_as(dp), C.byref(gg),
+                                                        C.c_void_p(gamma.data_ptr()), int(degree), int(form),
+                                                        float(delta), G.ctypes.data_as(dp), g.ctypes.data_as(dp),
+                                                        C.byref(gg),
                                                         C.c_void_p(torch.cuda.current_stream().cuda_stream))
     if st != OK:
         raise LsfftError(st, "lsfft_nonlocal_normal_equations")
     return G, g, gg.value
 
 
-def nonlocal_apply(u, c, delta: float):
-    """L_c[u] of fields ``[nsample][d][...grid]`` (GPU tensor), by the library."""
+def nonlocal_apply(u, c, delta: float, form: int = 0):
+    """L_c[u] of fields ``[nsample][d][...grid]`` (GPU tensor), by the
+    library; ``c`` holds (form + 1)(degree + 1) coefficients."""
     torch = _torch()
     prec, d, n, ns = _nl_fields(u, "u")
     c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+    if form not in (0, 1) or len(c) % (form + 1):
+        raise ValueError("form 0 or 1 with (form + 1)(degree + 1) coefficients")
     out = torch.empty_like(u)
-    st = load_library().lsfft_nonlocal_apply(prec, d, n, ns, C.c_void_p(u.data_ptr()), len(c) - 1,
-                                             c.ctypes.data_as(C.POINTER(C.c_double)), float(delta),
+    st = load_library().lsfft_nonlocal_apply(prec, d, n, ns, C.c_void_p(u.data_ptr()), len(c) // (form + 1) - 1,
+                                             int(form), c.ctypes.data_as(C.POINTER(C.c_double)), float(delta),
                                              C.c_void_p(out.data_ptr()),
                                              C.c_void_p(torch.cuda.current_stream().cuda_stream))
     if st != OK:
@@ -290,7 +295,7 @@ def nonlocal_fit(G, g, lam: float, adam_steps: int = 0, lr: float = 1e-3):
         raise ValueError("G must be square with the size of g")
     c = np.zeros(nf)
     dp = C.POINTER(C.c_double)
-    st = load_library().lsfft_nonlocal_fit(nf - 1, G.ctypes.data_as(dp), g.ctypes.data_as(dp), float(lam),
+    st = load_library().lsfft_nonlocal_fit(nf, G.ctypes.data_as(dp), g.ctypes.data_as(dp), float(lam),
                                            int(adam_steps), float(lr), c.ctypes.data_as(dp))
     if st != OK:
         raise LsfftError(st, "lsfft_nonlocal_fit")

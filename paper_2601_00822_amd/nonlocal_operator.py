@@ -2,12 +2,14 @@
 displacement, around the library's nonlocal kernels.
 
 The operator maps an averaged displacement field to
-``L_c[u](x) = sum over grid offsets 0 < |r| < delta of K_c(|r|) (u(x + r) - u(x))``
-with a radial scalar kernel in the Bernstein basis of degree M on
-[0, delta], acting on each component alike; for the displacement type the
-response it must reproduce is the negated body force, ``Gamma_k = -b_k``.
-The fit of Eq. 6.6 (least squares plus a Tikhonov term lam ||c||^2) is a
-quadratic in the M + 1 coefficients: the library assembles its normal
+``L_c[u](x) = sum over grid offsets 0 < |r| < delta of K(r) (u(x + r) - u(x))``
+with kernels in the Bernstein basis of degree M on [0, delta]: a radial
+scalar K1(|r|) acting on each component alike (form 0), or the isotropic
+matrix kernel K1(|r|) I + K2(|r|) e e^T of the bond direction e (form 1),
+which couples the components.  For the displacement type the response it
+must reproduce is the negated body force, ``Gamma_k = -b_k``.  The fit of
+Eq. 6.6 (least squares plus a Tikhonov term lam ||c||^2) is a quadratic in
+the (form + 1)(M + 1) coefficients: the library assembles its normal
 equations on the device in FP64 and solves them in closed form or runs the
 paper's optimiser, Adam, on the same loss.
 
@@ -36,17 +38,19 @@ def pairs(Ku, forces, plan: Plan | None = None):
 
 
 class NormalEquations:
-    """Running sums of the normal equations over batches of pairs."""
+    """Running sums of the normal equations over batches of pairs; ``form``
+    0 is the scalar kernel, 1 the matrix kernel K1 I + K2 e e^T."""
 
-    def __init__(self, degree: int, delta: float):
-        self.degree, self.delta = int(degree), float(delta)
-        self.G = np.zeros((degree + 1, degree + 1))
-        self.g = np.zeros(degree + 1)
+    def __init__(self, degree: int, delta: float, form: int = 0):
+        self.degree, self.delta, self.form = int(degree), float(delta), int(form)
+        nf = (self.form + 1) * (self.degree + 1)
+        self.G = np.zeros((nf, nf))
+        self.g = np.zeros(nf)
         self.gg = 0.0
         self.count = 0
 
     def add(self, u, gamma):
-        G, g, gg = nonlocal_normal_equations(u.contiguous(), gamma.contiguous(), self.degree, self.delta)
+        G, g, gg = nonlocal_normal_equations(u.contiguous(), gamma.contiguous(), self.degree, self.delta, self.form)
         self.G += G
         self.g += g
         self.gg += gg
@@ -60,42 +64,59 @@ class NormalEquations:
 
 @dataclass
 class NonlocalOperator:
-    """A fitted operator L_c with its horizon."""
+    """A fitted operator L_c with its horizon and kernel form."""
     c: np.ndarray
     delta: float
+    form: int = 0
 
     @property
     def degree(self) -> int:
-        return len(self.c) - 1
+        return len(self.c) // (self.form + 1) - 1
 
     def apply(self, u):
         """L_c[u] of fields ``[B][d][...grid]``."""
-        return nonlocal_apply(u.contiguous(), self.c, self.delta)
+        return nonlocal_apply(u.contiguous(), self.c, self.delta, self.form)
 
     def kernel(self, rho):
-        """K_c(rho) (zero from the horizon on), for inspection."""
+        """(K1(rho)[, K2(rho)]) (zero from the horizon on), for inspection."""
         from math import comb
         t = np.asarray(rho, dtype=np.float64) / self.delta
         M = self.degree
-        k = sum(self.c[m] * comb(M, m) * t ** m * (1.0 - t) ** (M - m) for m in range(M + 1))
-        return np.where((t > 0) & (t < 1), k, 0.0)
+        out = []
+        for f in range(self.form + 1):
+            c = self.c[f * (M + 1):(f + 1) * (M + 1)]
+            k = sum(c[m] * comb(M, m) * t ** m * (1.0 - t) ** (M - m) for m in range(M + 1))
+            out.append(np.where((t > 0) & (t < 1), k, 0.0))
+        return tuple(out)
 
-    def relative_residual(self, u, gamma):
-        """Per-sample ||L_c[u] - Gamma|| / ||Gamma|| (FP64 numpy)."""
+    def relative_residual(self, u, gamma, equilibrated: bool = False):
+        """Per-sample ||L_c[u] - Gamma|| / ||Gamma|| (FP64 numpy).  With
+        ``equilibrated`` both norms leave out Gamma's mean (its part on the
+        xi = 0 set, which no operator of this form produces: L_c[u] has zero
+        mean, so ||L_c[u] - Gamma||^2 = ||L_c[u] - P Gamma||^2 + N |mean|^2);
+        the means come from the library's block mean over the whole grid, so
+        every grid axis must share one length."""
         nd, nt = sample_norms(gamma.contiguous(), self.apply(u))
-        return nd / nt
+        if not equilibrated:
+            return nd / nt
+        sp = tuple(gamma.shape[2:])
+        if len(set(sp)) != 1:
+            raise ValueError("the equilibrated residual needs equal grid lengths")
+        mean = block_mean(gamma.contiguous(), sp[0], spatial=len(sp)).double().cpu().numpy()
+        rm2 = float(np.prod(sp)) * (mean.reshape(mean.shape[0], -1) ** 2).sum(axis=1)
+        return np.sqrt(np.maximum(nd ** 2 - rm2, 0.0) / np.maximum(nt ** 2 - rm2, 1e-300))
 
 
 def fit(ne: NormalEquations, lam: float, adam_steps: int = 0, lr: float = 1e-3) -> NonlocalOperator:
     """Eq. 6.6 from accumulated normal equations: the closed-form minimiser
     (``adam_steps = 0``) or Adam from zero.  Adam runs on the loss divided by
-    trace(G) / (M + 1), which has the same minimiser and unit-scale
-    curvature, so one step size serves any data scale."""
+    trace(G) / nc (nc coefficients), which has the same minimiser and
+    unit-scale curvature, so one step size serves any data scale."""
     if adam_steps == 0:
         c = nonlocal_fit(ne.G, ne.g, lam)
     else:
-        s = float(np.trace(ne.G)) / (ne.degree + 1)
+        s = float(np.trace(ne.G)) / len(ne.g)
         if not s > 0.0:
             raise ValueError("the normal equations are empty")
         c = nonlocal_fit(ne.G / s, ne.g / s, lam / s, adam_steps=adam_steps, lr=lr)
-    return NonlocalOperator(c, ne.delta)
+    return NonlocalOperator(c, ne.delta, ne.form)

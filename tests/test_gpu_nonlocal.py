@@ -178,3 +178,72 @@ def test_dataset_route_matches_the_oracle(torch_dev):
     np.testing.assert_allclose(ne.G, Gw, rtol=1e-7, atol=1e-9 * np.abs(Gw).max())
     np.testing.assert_allclose(ne.g, gw, rtol=1e-7, atol=1e-9 * np.abs(gw).max())
     np.testing.assert_allclose(op.c, N.fit_closed(Gw, gw, 1e-3), rtol=1e-5, atol=1e-6 * np.abs(op.c).max())
+
+
+CASES1 = [
+    # matrix kernel K1 I + K2 e e^T: (grid in array order, horizon, degree, nsample)
+    ((10, 12, 14), 3.5, 3, 2),     # ragged 8 x 8 x 4 tiles
+    ((9, 20, 13), 5.0, 8, 2),      # largest halo of the 3D normal equations (R = 4) and degree
+    ((5, 4, 6), 3.5, 2, 2),        # grid smaller than the halo
+    ((40, 36), 3.2, 3, 3),         # 2D, ragged 16 x 16 tiles
+    ((7, 5), 7.0, 4, 2),           # 2D, largest halo (R = 6), grid smaller than it
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape,delta,deg,ns", CASES1)
+def test_matrix_form_normal_equations_and_operator_match_the_oracle(torch_dev, shape, delta, deg, ns, prec):
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import nonlocal_normal_equations, nonlocal_apply
+    say(f"nonlocal matrix form {shape} delta {delta} degree {deg} x{ns} {prec}")
+    d = len(shape)
+    rng = np.random.default_rng(int(sum(shape) * 7 + delta * 3))
+    us = [rounded(rng.normal(size=(d,) + shape), prec) for _ in range(ns)]
+    gs = [rounded(rng.normal(size=(d,) + shape), prec) for _ in range(ns)]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    U = torch.from_numpy(np.stack(us)).to(dev).to(dt)
+    G, g, gg = nonlocal_normal_equations(U, torch.from_numpy(np.stack(gs)).to(dev).to(dt), deg, delta, form=1)
+    Gw, gw, ggw = N.normal_equations(us, gs, deg, delta, form=1)
+    assert G.shape == (2 * (deg + 1), 2 * (deg + 1))
+    np.testing.assert_allclose(G, Gw, rtol=0, atol=1e-12 * np.abs(Gw).max())
+    np.testing.assert_allclose(g, gw, rtol=0, atol=1e-12 * np.abs(Gw).max() ** 0.5 * ggw ** 0.5)
+    np.testing.assert_allclose(gg, ggw, rtol=1e-13)
+    c = rng.normal(size=2 * (deg + 1))
+    out = nonlocal_apply(U, c, delta, form=1).double().cpu().numpy()
+    tol = 1e-12 if prec == "f64" else 6e-8
+    for k in range(ns):
+        want = N.apply_operator(c, us[k], delta, form=1)
+        np.testing.assert_allclose(out[k], want, rtol=0, atol=tol * np.abs(want).max(), err_msg=f"sample {k}")
+
+
+def test_matrix_form_operator_at_the_largest_3d_halo(torch_dev):
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import nonlocal_apply
+    say("nonlocal matrix-form operator 9x20x13 delta 7 (R = 6)")
+    rng = np.random.default_rng(31)
+    u = rng.normal(size=(1, 3, 9, 20, 13))
+    c = rng.normal(size=10)
+    out = nonlocal_apply(torch.from_numpy(u).to(dev), c, 7.0, form=1).cpu().numpy()
+    want = N.apply_operator(c, u[0], 7.0, form=1)
+    np.testing.assert_allclose(out[0], want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_planted_matrix_kernel_is_recovered(torch_dev):
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import LsfftError, nonlocal_normal_equations
+    from paper_2601_00822_amd import nonlocal_operator as NL
+    say("nonlocal planted matrix kernel 12x10x14 delta 3.5 degree 3; matrix-form argument errors")
+    rng = np.random.default_rng(22)
+    shape, delta = (12, 10, 14), 3.5
+    c_true = np.array([0.8, -0.4, 0.25, 1.3, 0.6, -0.9, 0.3, 0.45])
+    us = [rng.normal(size=(3,) + shape) for _ in range(3)]
+    gam = [N.apply_operator(c_true, u, delta, form=1) for u in us]
+    U, Gm = torch.from_numpy(np.stack(us)).to(dev), torch.from_numpy(np.stack(gam)).to(dev)
+    ne = NL.NormalEquations(3, delta, form=1).add(U, Gm)
+    op = NL.fit(ne, 0.0)
+    np.testing.assert_allclose(op.c, c_true, rtol=0, atol=1e-8)
+    assert op.relative_residual(U, Gm).max() < 1e-9
+    with pytest.raises(LsfftError):
+        nonlocal_normal_equations(U, Gm, 3, 5.5, form=1)          # 3D halo above 4
+    with pytest.raises(LsfftError):
+        nonlocal_normal_equations(U, Gm, 3, 3.0, form=2)
