@@ -592,7 +592,7 @@ def main() -> int:
                     help="keep the default schedule of every pass instead of autotuning it")
     ap.add_argument("--train-samples", type=int, default=20000)
     ap.add_argument("--test-samples", type=int, default=512)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--fno-batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--direct-checks", type=int, default=2)
