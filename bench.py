@@ -283,7 +283,7 @@ def run_surrogate_workload(args, wl):
     served, src = S.averaged_strain(bump_forces((n, n, n), pte[:args.fno_batch], device=dev), 0.02, trained,
                                     phase, lame, cell, kernel=K)
     served_err = S.relative_l2(served, Tte[:args.fno_batch])
-    nonlocal_leg = run_nonlocal_leg(Ku, n, conv_plan, args, log)
+    nonlocal_leg = run_nonlocal_leg(Ku, n, conv_plan, args, log, lame=lame, vf=vf)
     conv_plan.close()
     speedup = t_solver / t_inf
     log(f"solver {t_solver:.2f} s, kernel convolution {1e6 * t_conv:.1f} us, surrogate {1e6 * t_inf:.1f} us "
@@ -315,7 +315,7 @@ def run_surrogate_workload(args, wl):
     }
 
 
-def run_nonlocal_leg(Ku, n, conv_plan, args, log):
+def run_nonlocal_leg(Ku, n, conv_plan, args, log, lame=None, vf=None):
     """The nonlocal kernel surrogate (Eqs. 6.5-6.6, displacement type) on
     the same microstructure: pairs (<u>_k, -b_k) from the averaged
     displacement kernel, normal equations on the device, closed-form and
@@ -363,12 +363,26 @@ def run_nonlocal_leg(Ku, n, conv_plan, args, log):
         ops["closed"].apply(u0)
         torch.cuda.synchronize()
         row["seconds_per_field_apply"] = (time.perf_counter() - t1) / u0.shape[0]
+        if form == 1:
+            C11, C12, C44 = ops["closed"].long_wave_stiffness()
+            row["long_wave_stiffness"] = {"C11": C11, "C12": C12, "C44": C44, "bulk": (C11 + 2.0 * C12) / 3.0,
+                                          "shear_44": C44, "shear_11_12": 0.5 * (C11 - C12)}
         key = f"{'matrix' if form else 'scalar'}/{dl}"
         out["fits"][key] = row
         log(f"nonlocal {key}: held-out relative residual closed {row['closed']['heldout_rel_residual']['mean']:.4f} "
             f"(equilibrated {row['closed']['heldout_rel_residual_equilibrated']['mean']:.4f}, max "
             f"{row['closed']['heldout_rel_residual_equilibrated']['max']:.4f}), adam "
             f"{row['adam']['heldout_rel_residual_equilibrated']['mean']:.4f}")
+    if lame is not None and vf is not None:
+        # Voigt and Reuss bounds of the two phases at the voxelized volume
+        # fraction (matrix phase 0, inclusions phase 1)
+        lam_p, mu_p = np.asarray(lame)[:, 0], np.asarray(lame)[:, 1]
+        kap_p = lam_p + 2.0 * mu_p / 3.0
+        fr = np.array([1.0 - vf, vf])
+        out["phase_bounds"] = {"volume_fraction": float(vf),
+                               "bulk": [float(1.0 / np.sum(fr / kap_p)), float(np.sum(fr * kap_p))],
+                               "shear": [float(1.0 / np.sum(fr / mu_p)), float(np.sum(fr * mu_p))],
+                               "note": "[Reuss, Voigt] of the phases' bulk and shear moduli"}
     return out
 
 

@@ -89,6 +89,37 @@ class NonlocalOperator:
             out.append(np.where((t > 0) & (t < 1), k, 0.0))
         return tuple(out)
 
+    def long_wave_stiffness(self):
+        """(C11, C12, C44): the cubic stiffness of the Navier operator the
+        fitted 3D operator reduces to at long wavelengths.  With
+        u(x + r) - u(x) expanded to second order, L_c[u]_a becomes
+        sum_{b,i,j} (alpha d_ab d_ij + B_abij) d_i d_j u_b, alpha = 1/2
+        sum_r K1 |r|^2 e_1^2 and B_abij = 1/2 sum_r K2 |r|^2 e_a e_b e_i e_j
+        over the grid offsets inside the horizon (cubic symmetry of the
+        lattice); matched to div(C grad u): C11 = alpha + B_1111,
+        C44 = alpha + B_1122, C12 = 2 B_1212 - C44.  The analogue, for the
+        displacement type, of the stiffness the paper takes from the
+        stress-type kernel (Eq. 6.7).  Host arithmetic over the offsets."""
+        from math import comb
+        R = int(np.ceil(self.delta)) - 1
+        g = np.arange(-R, R + 1)
+        r = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
+        rho = np.sqrt((r * r).sum(axis=1))
+        keep = (rho > 0.0) & (rho < self.delta)
+        r, rho = r[keep], rho[keep]
+        e = r / rho[:, None]
+        M = self.degree
+        t = rho / self.delta
+        basis = np.stack([comb(M, m) * t ** m * (1.0 - t) ** (M - m) for m in range(M + 1)])
+        k1 = self.c[:M + 1] @ basis
+        k2 = self.c[M + 1:] @ basis if self.form == 1 else np.zeros_like(k1)
+        w1, w2 = 0.5 * k1 * rho ** 2, 0.5 * k2 * rho ** 2
+        alpha = float(np.sum(w1 * e[:, 0] ** 2))
+        b1111 = float(np.sum(w2 * e[:, 0] ** 4))
+        b1122 = float(np.sum(w2 * e[:, 0] ** 2 * e[:, 1] ** 2))
+        c44 = alpha + b1122
+        return alpha + b1111, 2.0 * b1122 - c44, c44
+
     def relative_residual(self, u, gamma, equilibrated: bool = False):
         """Per-sample ||L_c[u] - Gamma|| / ||Gamma|| (FP64 numpy).  With
         ``equilibrated`` both norms leave out Gamma's mean (its part on the

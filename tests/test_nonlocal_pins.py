@@ -188,3 +188,35 @@ def test_matrix_operator_is_self_adjoint_and_kills_constants():
     assert abs(np.sum(v * lu) - np.sum(u * lv)) < 1e-11 * np.abs(lu).max() * np.abs(v).sum()
     const = np.ones((3,) + shape) * np.array([0.3, -1.2, 2.0])[:, None, None, None]
     assert np.abs(N.apply_operator(c, const, delta, form=1)).max() < 1e-13
+
+
+def test_long_wave_stiffness_matches_the_small_wavenumber_multiplier():
+    """The product's long-wavelength stiffness of a matrix-kernel operator
+    against the exact Fourier multiplier sum_r (K1 I + K2 e e^T)(cos xi.r - 1)
+    at a small wavevector: M(xi) v = -(C grad grad) v, i.e.
+    M_ab = -(C11 - C44 or C44 ... ) assembled from (C11, C12, C44), to the
+    fourth-order truncation error."""
+    from paper_2601_00822_amd.nonlocal_operator import NonlocalOperator
+    rng = np.random.default_rng(17)
+    delta, M = 4.5, 5
+    c = rng.normal(size=2 * (M + 1))
+    C11, C12, C44 = NonlocalOperator(c, delta, form=1).long_wave_stiffness()
+    xi = np.array([0.7, -1.1, 0.4]) * 1e-3
+    Mx = np.zeros((3, 3))
+    R = int(np.ceil(delta))
+    for idx in np.ndindex(2 * R + 1, 2 * R + 1, 2 * R + 1):
+        r = np.array(idx, dtype=np.float64) - R                 # component order (x first)
+        rho = np.sqrt(r @ r)
+        if 0.0 < rho < delta:
+            K1, K2 = kernel_pair(c, rho, delta)
+            e = r / rho
+            Mx += (np.cos(xi @ r) - 1.0) * (K1 * np.eye(3) + K2 * np.outer(e, e))
+    # div(C grad) of a plane wave: -(C_aibj xi_i xi_j) for a cubic C
+    want = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            if a == b:
+                want[a, a] = -(C11 * xi[a] ** 2 + C44 * (xi @ xi - xi[a] ** 2))
+            else:
+                want[a, b] = -(C12 + C44) * xi[a] * xi[b]
+    np.testing.assert_allclose(Mx, want, rtol=0, atol=1e-5 * np.abs(want).max())
