@@ -10,6 +10,7 @@
 //       row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32.
 #include <hip/hip_runtime.h>
 
+#include "fft_core.hpp"
 #include "fno_launch.hpp"
 
 namespace lsfft_fno {
@@ -406,227 +407,350 @@ hipError_t launch_modemix(int mode, const float2* x, const __hip_bfloat16* r, co
 }
 
 // ---------------------------------------------------------------------------
-// truncated transforms: direct sums along one axis at a time, fp32
+// truncated transforms: length-N FFTs along one axis at a time, fp32
 // ---------------------------------------------------------------------------
-// Every kernel stages a contiguous block of its input in LDS with coalesced
-// loads, sums from LDS (odd pitches keep the strided reads conflict free),
-// and writes a contiguous block of output.  Layouts (BC = batch x channels,
-// P = 2M M):
+// Every kernel transforms a tile of MP pencils with the solver's Stockham
+// tile transform (fft_core.hpp): full pencils are loaded (the truncated
+// inputs of an inverse as zeros), transformed in registers and LDS, and only
+// the kept outputs are stored.  Layouts (BC = batch x channels, P = 2M M):
 //   h   [BC][z][y][x]           real
 //   t1  [BC][z][y][kx]          kx < M
 //   t2  [BC][z][iy][kx]         iy < 2M (signed ky)
 //   md  [iz P + iy M + kx][BC]  the kept modes, mode-major
 // Kept array index of the signed wavenumber slot s in [0, 2M): s for s < M,
-// n - 2M + s for the negative ones.
+// n - 2M + s for the negative ones; the slot of FFT index k is k for k < M,
+// k - n + 2M for k >= n - M, none otherwise.
 template <int N> __device__ __forceinline__ int kidx(int s, int M) { return s < M ? s : N - 2 * M + s; }
-
-template <int N>
-__device__ __forceinline__ void load_tw(float2* tw, const float2* twg) {
-  if (threadIdx.x < N) tw[threadIdx.x] = twg[threadIdx.x];
+template <int N> __device__ __forceinline__ int kslot(int k, int M) {
+  return k < M ? k : (k >= N - M ? k - N + 2 * M : -1);
 }
 
-constexpr int kRows = 64;    // rows of N per x-transform block
-constexpr int kSlabs = 8;    // (bc, z) slabs per y-transform block
-constexpr int kZbc = 16;     // bc per z-transform block
-constexpr int kZyx = 8;      // (iy, kx) pairs per z-transform block
+// twiddles exp(-2 pi i k / N) split into LDS as the tile transform reads
+// them, from the (cos, sin) table of the surrogate
+template <int N>
+__device__ __forceinline__ void load_tw_split(float* twr, float* twi, const float2* twg) {
+  for (int k = threadIdx.x; k < N; k += NTB) {
+    const float2 w = twg[k];
+    twr[k] = w.x;
+    twi[k] = -w.y;
+  }
+}
 
-// x forward: kRows real rows -> M complex each (e^{-i})
+// x axis: MX rows of N reals per tile, index-fastest butterflies (each
+// row's points come from consecutive lanes)
+template <int N> struct XT {
+  static constexpr int MP = 2048 / N;
+  static constexpr int SM = N + 1;
+  template <int DIR> using F = lsfft::TileFft<float, N, DIR, false, MP, SM, 1, 1, true, NTB>;
+};
+// y and z axes: 64 pencils per tile, pencil-fastest butterflies
+constexpr int kPen = 64;
+template <int N> struct ST {
+  static constexpr int SN = kPen + 1;
+  template <int DIR> using F = lsfft::TileFft<float, N, DIR, false, kPen, 1, SN, 1, false, NTB>;
+};
+
+// x forward: rows of reals -> kx < M
 template <int N>
 __global__ __launch_bounds__(NTB) void k_dft_x_fwd(const float* __restrict__ h, float2* __restrict__ t1, long long rows,
                                                    int M, const float2* __restrict__ twg) {
-  __shared__ float2 tw[N];
-  __shared__ float tile[kRows * (N + 1)];
-  __shared__ float2 res[kRows * (N / 2 + 1)];
-  load_tw<N>(tw, twg);
-  const long long row0 = (long long)blockIdx.x * kRows;
-  const int nr = (int)((rows - row0) < kRows ? (rows - row0) : kRows);
-  for (int e = threadIdx.x; e < kRows * N / 4; e += NTB) {
-    const int r = (4 * e) / N, x = (4 * e) % N;
+  using F = typename XT<N>::template F<-1>;
+  constexpr int MP = XT<N>::MP;
+  __shared__ float re[MP * XT<N>::SM], im[MP * XT<N>::SM], twr[N], twi[N];
+  load_tw_split<N>(twr, twi, twg);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const long long row0 = (long long)blockIdx.x * MP;
+  const int nr = (int)((rows - row0) < MP ? (rows - row0) : MP);
+  // the tile's rows arrive as coalesced 16-byte loads into LDS
+  for (int e = tid; e < MP * N / 4; e += NTB) {
+    const int m = (4 * e) / N, x = (4 * e) - m * N;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (r < nr) v = reinterpret_cast<const float4*>(h + row0 * N)[e];
-    float* d = tile + r * (N + 1) + x;
-    d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+    if (m < nr) v = reinterpret_cast<const float4*>(h + row0 * N)[e];
+    float* d = re + m * XT<N>::SM + x;
+    d[0] = v.x;
+    d[1] = v.y;
+    d[2] = v.z;
+    d[3] = v.w;
   }
   __syncthreads();
-  const int r = threadIdx.x % kRows;
-  for (int kx = threadIdx.x / kRows; kx < M; kx += NTB / kRows) {
-    float re = 0.f, im = 0.f;
+  float in_r[F::B0][F::R0], in_i[F::B0][F::R0];
 #pragma unroll
-    for (int x = 0; x < N; ++x) {
-      const float a = tile[r * (N + 1) + x];
-      const float2 w = tw[(kx * x) & (N - 1)];
-      re += a * w.x;
-      im -= a * w.y;
+  for (int q = 0; q < F::B0; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::R0>(b, m, j);
+    const bool ok = F::TOT0 % NTB == 0 || b < F::TOT0;
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      in_r[q][r] = ok ? re[m * XT<N>::SM + j + r * (N / F::R0)] : 0.0f;
+      in_i[q][r] = 0.0f;
     }
-    res[r * (N / 2 + 1) + kx] = make_float2(re, im);
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < nr * M; e += NTB) t1[row0 * M + e] = res[(e / M) * (N / 2 + 1) + e % M];
+  __syncthreads();   // the transform's first pass rewrites the tile
+  float o_r[F::BL][F::RL], o_i[F::BL][F::RL];
+  F::run(in_r, in_i, o_r, o_i, re, im, twr, twi, tid);
+#pragma unroll
+  for (int q = 0; q < F::BL; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::RL>(b, m, j);
+    if ((F::TOTL % NTB == 0 || b < F::TOTL) && row0 + m < rows) {
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r) {
+        const int k = j + r * (N / F::RL);
+        if (k < M) t1[(row0 + m) * M + k] = make_float2(o_r[q][r], o_i[q][r]);
+      }
+    }
+  }
 }
 
-// x inverse: out[row][x] = sum_kx c(kx) Re(t1[row][kx] e^{+i kx x})
+// x inverse: out[row][x] = sum_kx c(kx) Re(t1[row][kx] e^{+i kx x}),
+// c(0) = c0, c(kx > 0) = c1
 template <int N>
 __global__ __launch_bounds__(NTB) void k_dft_x_inv(const float2* __restrict__ t1, float* __restrict__ out, long long rows,
                                                    int M, float c0, float c1, const float2* __restrict__ twg) {
-  __shared__ float2 tw[N];
-  __shared__ float2 tin[kRows * (N / 2 + 1)];
-  __shared__ float tile[kRows * (N + 1)];
-  load_tw<N>(tw, twg);
-  const long long row0 = (long long)blockIdx.x * kRows;
-  const int nr = (int)((rows - row0) < kRows ? (rows - row0) : kRows);
-  for (int e = threadIdx.x; e < nr * M; e += NTB) {
-    const int kx = e % M;
-    const float c = (kx == 0) ? c0 : c1;
-    const float2 v = t1[row0 * M + e];
-    tin[(e / M) * (N / 2 + 1) + kx] = make_float2(c * v.x, c * v.y);
-  }
+  using F = typename XT<N>::template F<+1>;
+  constexpr int MP = XT<N>::MP;
+  __shared__ float re[MP * XT<N>::SM], im[MP * XT<N>::SM], twr[N], twi[N];
+  load_tw_split<N>(twr, twi, twg);
   __syncthreads();
-  const int r = threadIdx.x % kRows;
-  for (int x = threadIdx.x / kRows; x < N; x += NTB / kRows) {
-    float acc = 0.f;
-    for (int kx = 0; kx < M; ++kx) {
-      const float2 a = tin[r * (N / 2 + 1) + kx];
-      const float2 w = tw[(kx * x) & (N - 1)];
-      acc += a.x * w.x - a.y * w.y;
+  const int tid = threadIdx.x;
+  const long long row0 = (long long)blockIdx.x * MP;
+  float in_r[F::B0][F::R0], in_i[F::B0][F::R0];
+#pragma unroll
+  for (int q = 0; q < F::B0; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::R0>(b, m, j);
+    const bool ok = (F::TOT0 % NTB == 0 || b < F::TOT0) && row0 + m < rows;
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      const int k = j + r * (N / F::R0);
+      float2 v = make_float2(0.0f, 0.0f);
+      if (ok && k < M) {
+        v = t1[(row0 + m) * M + k];
+        const float c = (k == 0) ? c0 : c1;
+        v.x *= c;
+        v.y *= c;
+      }
+      in_r[q][r] = v.x;
+      in_i[q][r] = v.y;
     }
-    tile[r * (N + 1) + x] = acc;
+  }
+  float o_r[F::BL][F::RL], o_i[F::BL][F::RL];
+  F::run(in_r, in_i, o_r, o_i, re, im, twr, twi, tid);
+  // real parts through the LDS tile, then coalesced 16-byte stores
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < F::BL; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::RL>(b, m, j);
+    if (F::TOTL % NTB == 0 || b < F::TOTL) {
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r) re[m * XT<N>::SM + j + r * (N / F::RL)] = o_r[q][r];
+    }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < nr * N / 4; e += NTB) {
-    const int rr = (4 * e) / N, x = (4 * e) % N;
-    const float* sft = tile + rr * (N + 1) + x;
-    reinterpret_cast<float4*>(out + row0 * N)[e] = make_float4(sft[0], sft[1], sft[2], sft[3]);
+  const int nr = (int)((rows - row0) < MP ? (rows - row0) : MP);
+  for (int e = tid; e < nr * N / 4; e += NTB) {
+    const int m = (4 * e) / N, x = (4 * e) - m * N;
+    const float* sp = re + m * XT<N>::SM + x;
+    reinterpret_cast<float4*>(out + row0 * N)[e] = make_float4(sp[0], sp[1], sp[2], sp[3]);
   }
 }
 
-// y forward: slabs t1[bz][y][kx] -> t2[bz][iy][kx] (e^{-i})
+// y forward: t1[bz][y][kx] -> t2[bz][iy][kx]; pencil g = bz M + kx
 template <int N>
 __global__ __launch_bounds__(NTB) void k_dft_y_fwd(const float2* __restrict__ t1, float2* __restrict__ t2, long long nbz,
                                                    int M, const float2* __restrict__ twg) {
-  __shared__ float2 tw[N];
-  __shared__ float2 slab[kSlabs * N * (N / 2 + 1)];
-  load_tw<N>(tw, twg);
-  const long long bz0 = (long long)blockIdx.x * kSlabs;
-  const int ns = (int)((nbz - bz0) < kSlabs ? (nbz - bz0) : kSlabs);
-  const int per_in = N * M;
-  for (int e = threadIdx.x; e < ns * per_in; e += NTB) {
-    const int sl = e / per_in, rem = e % per_in;
-    slab[sl * N * (N / 2 + 1) + (rem / M) * (N / 2 + 1) + rem % M] = t1[bz0 * per_in + e];
-  }
+  using F = typename ST<N>::template F<-1>;
+  __shared__ float re[N * ST<N>::SN], im[N * ST<N>::SN], twr[N], twi[N];
+  load_tw_split<N>(twr, twi, twg);
   __syncthreads();
-  const int per_out = 2 * M * M;
-  for (int o = threadIdx.x; o < ns * per_out; o += NTB) {
-    const int sl = o / per_out, rem = o % per_out;
-    const int iy = rem / M, kx = rem % M;
-    const int k = kidx<N>(iy, M);
-    const float2* src = slab + sl * N * (N / 2 + 1) + kx;
-    float re = 0.f, im = 0.f;
+  const int tid = threadIdx.x;
+  const long long g0 = (long long)blockIdx.x * kPen, npen = nbz * M;
+  float in_r[F::B0][F::R0], in_i[F::B0][F::R0];
 #pragma unroll
-    for (int y = 0; y < N; ++y) {
-      const float2 a = src[y * (N / 2 + 1)];
-      const float2 w = tw[(k * y) & (N - 1)];
-      re += a.x * w.x + a.y * w.y;
-      im += a.y * w.x - a.x * w.y;
+  for (int q = 0; q < F::B0; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::R0>(b, m, j);
+    const long long g = g0 + m;
+    const bool ok = (F::TOT0 % NTB == 0 || b < F::TOT0) && g < npen;
+    const long long bz = ok ? g / M : 0;
+    const int kx = ok ? int(g - bz * M) : 0;
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      float2 v = make_float2(0.0f, 0.0f);
+      if (ok) v = t1[(bz * N + j + r * (N / F::R0)) * M + kx];
+      in_r[q][r] = v.x;
+      in_i[q][r] = v.y;
     }
-    t2[bz0 * per_out + o] = make_float2(re, im);
+  }
+  float o_r[F::BL][F::RL], o_i[F::BL][F::RL];
+  F::run(in_r, in_i, o_r, o_i, re, im, twr, twi, tid);
+#pragma unroll
+  for (int q = 0; q < F::BL; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::RL>(b, m, j);
+    const long long g = g0 + m;
+    if ((F::TOTL % NTB == 0 || b < F::TOTL) && g < npen) {
+      const long long bz = g / M;
+      const int kx = int(g - bz * M);
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r) {
+        const int iy = kslot<N>(j + r * (N / F::RL), M);
+        if (iy >= 0) t2[(bz * 2 * M + iy) * M + kx] = make_float2(o_r[q][r], o_i[q][r]);
+      }
+    }
   }
 }
 
-// y inverse: t2[bz][iy][kx] -> t1[bz][y][kx] (e^{+i}); one thread per
-// (bz, kx) holding the N outputs in registers, so every input is read once
-// and the twiddle index is the same across the wave
+// y inverse: t2[bz][iy][kx] -> t1[bz][y][kx]
 template <int N>
 __global__ __launch_bounds__(NTB) void k_dft_y_inv(const float2* __restrict__ t2, float2* __restrict__ t1, long long nbz,
                                                    int M, const float2* __restrict__ twg) {
-  __shared__ float2 tw[N];
-  load_tw<N>(tw, twg);
+  using F = typename ST<N>::template F<+1>;
+  __shared__ float re[N * ST<N>::SN], im[N * ST<N>::SN], twr[N], twi[N];
+  load_tw_split<N>(twr, twi, twg);
   __syncthreads();
-  const long long t = (long long)blockIdx.x * NTB + threadIdx.x;
-  if (t >= nbz * M) return;
-  const int kx = int(t % M);
-  const long long bz = t / M;
-  float2 acc[N];
+  const int tid = threadIdx.x;
+  const long long g0 = (long long)blockIdx.x * kPen, npen = nbz * M;
+  float in_r[F::B0][F::R0], in_i[F::B0][F::R0];
 #pragma unroll
-  for (int y = 0; y < N; ++y) acc[y] = make_float2(0.f, 0.f);
-  for (int s2 = 0; s2 < 2 * M; ++s2) {
-    const float2 a = t2[(bz * 2 * M + s2) * M + kx];
-    const int k = kidx<N>(s2, M);
+  for (int q = 0; q < F::B0; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::R0>(b, m, j);
+    const long long g = g0 + m;
+    const bool ok = (F::TOT0 % NTB == 0 || b < F::TOT0) && g < npen;
+    const long long bz = ok ? g / M : 0;
+    const int kx = ok ? int(g - bz * M) : 0;
 #pragma unroll
-    for (int y = 0; y < N; ++y) {
-      const float2 w = tw[(k * y) & (N - 1)];
-      acc[y].x += a.x * w.x - a.y * w.y;
-      acc[y].y += a.y * w.x + a.x * w.y;
+    for (int r = 0; r < F::R0; ++r) {
+      const int iy = kslot<N>(j + r * (N / F::R0), M);
+      float2 v = make_float2(0.0f, 0.0f);
+      if (ok && iy >= 0) v = t2[(bz * 2 * M + iy) * M + kx];
+      in_r[q][r] = v.x;
+      in_i[q][r] = v.y;
     }
   }
+  float o_r[F::BL][F::RL], o_i[F::BL][F::RL];
+  F::run(in_r, in_i, o_r, o_i, re, im, twr, twi, tid);
 #pragma unroll
-  for (int y = 0; y < N; ++y) t1[(bz * N + y) * M + kx] = acc[y];
+  for (int q = 0; q < F::BL; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::RL>(b, m, j);
+    const long long g = g0 + m;
+    if ((F::TOTL % NTB == 0 || b < F::TOTL) && g < npen) {
+      const long long bz = g / M;
+      const int kx = int(g - bz * M);
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r)
+        t1[(bz * N + j + r * (N / F::RL)) * M + kx] = make_float2(o_r[q][r], o_i[q][r]);
+    }
+  }
 }
 
-// z forward: t2[bc][z][yx] -> md[(iz P + yx) BC + bc] * scale(kx) (e^{-i}),
-// one block per kZbc x kZyx tile of (bc, yx)
+// z axis: tiles of kZyx (iy, kx) pairs x kZbc batch-channels, pencil
+// m = yx_local + kZyx bc_local: consecutive lanes read runs of kZyx entries
+// of t2 and write runs of kZbc entries of md
+constexpr int kZyx = 8, kZbc = 8;
+static_assert(kZyx * kZbc == kPen, "z tile");
+
+// z forward: t2[bc][z][yx] -> md[(iz P + yx) BC + bc] * scale(kx)
 template <int N>
 __global__ __launch_bounds__(NTB) void k_dft_z_fwd(const float2* __restrict__ t2, float2* __restrict__ md, int BC, int M,
                                                    float sc0, float sc1, const float2* __restrict__ twg) {
-  __shared__ float2 tw[N];
-  constexpr int BP = N * (kZyx + 1) + 1;   // odd pitch between bc: the sums read one bc per lane
-  __shared__ float2 tile[kZbc * BP];
-  load_tw<N>(tw, twg);
+  using F = typename ST<N>::template F<-1>;
+  __shared__ float re[N * ST<N>::SN], im[N * ST<N>::SN], twr[N], twi[N];
+  load_tw_split<N>(twr, twi, twg);
+  __syncthreads();
+  const int tid = threadIdx.x;
   const int P = 2 * M * M;
   const int nyx = (P + kZyx - 1) / kZyx;
   const int bc0 = (blockIdx.x / nyx) * kZbc, yx0 = (blockIdx.x % nyx) * kZyx;
-  for (int e = threadIdx.x; e < kZbc * N * kZyx; e += NTB) {
-    const int j = e % kZyx, z = (e / kZyx) % N, b = e / (kZyx * N);
-    float2 v = make_float2(0.f, 0.f);
-    if (bc0 + b < BC && yx0 + j < P) v = t2[((long long)(bc0 + b) * N + z) * P + yx0 + j];
-    tile[b * BP + z * (kZyx + 1) + j] = v;
-  }
-  __syncthreads();
-  for (int o = threadIdx.x; o < 2 * M * kZyx * kZbc; o += NTB) {
-    const int b = o % kZbc, j = (o / kZbc) % kZyx, iz = o / (kZbc * kZyx);
-    if (bc0 + b >= BC || yx0 + j >= P) continue;
-    const int k = kidx<N>(iz, M);
-    const float2* src = tile + b * BP + j;
-    float re = 0.f, im = 0.f;
+  float in_r[F::B0][F::R0], in_i[F::B0][F::R0];
 #pragma unroll
-    for (int z = 0; z < N; ++z) {
-      const float2 a = src[z * (kZyx + 1)];
-      const float2 w = tw[(k * z) & (N - 1)];
-      re += a.x * w.x + a.y * w.y;
-      im += a.y * w.x - a.x * w.y;
+  for (int q = 0; q < F::B0; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::R0>(b, m, j);
+    const int yx = yx0 + m % kZyx, bc = bc0 + m / kZyx;
+    const bool ok = (F::TOT0 % NTB == 0 || b < F::TOT0) && yx < P && bc < BC;
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      float2 v = make_float2(0.0f, 0.0f);
+      if (ok) v = t2[((long long)bc * N + j + r * (N / F::R0)) * P + yx];
+      in_r[q][r] = v.x;
+      in_i[q][r] = v.y;
     }
-    const float sc = ((yx0 + j) % M == 0) ? sc0 : sc1;
-    md[((long long)iz * P + yx0 + j) * BC + bc0 + b] = make_float2(re * sc, im * sc);
+  }
+  float o_r[F::BL][F::RL], o_i[F::BL][F::RL];
+  F::run(in_r, in_i, o_r, o_i, re, im, twr, twi, tid);
+#pragma unroll
+  for (int q = 0; q < F::BL; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::RL>(b, m, j);
+    const int yx = yx0 + m % kZyx, bc = bc0 + m / kZyx;
+    if ((F::TOTL % NTB == 0 || b < F::TOTL) && yx < P && bc < BC) {
+      const float sc = (yx % M == 0) ? sc0 : sc1;
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r) {
+        const int iz = kslot<N>(j + r * (N / F::RL), M);
+        if (iz >= 0) md[((long long)iz * P + yx) * BC + bc] = make_float2(o_r[q][r] * sc, o_i[q][r] * sc);
+      }
+    }
   }
 }
 
-// z inverse: md -> t2[bc][z][yx] (e^{+i}), same tiles
+// z inverse: md -> t2[bc][z][yx]
 template <int N>
 __global__ __launch_bounds__(NTB) void k_dft_z_inv(const float2* __restrict__ md, float2* __restrict__ t2, int BC, int M,
                                                    const float2* __restrict__ twg) {
-  __shared__ float2 tw[N];
-  __shared__ float2 tile[N * kZyx * (kZbc + 1)];
-  load_tw<N>(tw, twg);
+  using F = typename ST<N>::template F<+1>;
+  __shared__ float re[N * ST<N>::SN], im[N * ST<N>::SN], twr[N], twi[N];
+  load_tw_split<N>(twr, twi, twg);
+  __syncthreads();
+  const int tid = threadIdx.x;
   const int P = 2 * M * M;
   const int nyx = (P + kZyx - 1) / kZyx;
   const int bc0 = (blockIdx.x / nyx) * kZbc, yx0 = (blockIdx.x % nyx) * kZyx;
-  for (int e = threadIdx.x; e < 2 * M * kZyx * kZbc; e += NTB) {
-    const int b = e % kZbc, j = (e / kZbc) % kZyx, iz = e / (kZbc * kZyx);
-    float2 v = make_float2(0.f, 0.f);
-    if (bc0 + b < BC && yx0 + j < P) v = md[((long long)iz * P + yx0 + j) * BC + bc0 + b];
-    tile[(iz * kZyx + j) * (kZbc + 1) + b] = v;
-  }
-  __syncthreads();
-  for (int o = threadIdx.x; o < kZbc * N * kZyx; o += NTB) {
-    const int j = o % kZyx, z = (o / kZyx) % N, b = o / (kZyx * N);
-    if (bc0 + b >= BC || yx0 + j >= P) continue;
-    float re = 0.f, im = 0.f;
-    for (int iz = 0; iz < 2 * M; ++iz) {
-      const float2 a = tile[(iz * kZyx + j) * (kZbc + 1) + b];
-      const float2 w = tw[(kidx<N>(iz, M) * z) & (N - 1)];
-      re += a.x * w.x - a.y * w.y;
-      im += a.y * w.x + a.x * w.y;
+  float in_r[F::B0][F::R0], in_i[F::B0][F::R0];
+#pragma unroll
+  for (int q = 0; q < F::B0; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::R0>(b, m, j);
+    const int yx = yx0 + m % kZyx, bc = bc0 + m / kZyx;
+    const bool ok = (F::TOT0 % NTB == 0 || b < F::TOT0) && yx < P && bc < BC;
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      const int iz = kslot<N>(j + r * (N / F::R0), M);
+      float2 v = make_float2(0.0f, 0.0f);
+      if (ok && iz >= 0) v = md[((long long)iz * P + yx) * BC + bc];
+      in_r[q][r] = v.x;
+      in_i[q][r] = v.y;
     }
-    t2[((long long)(bc0 + b) * N + z) * P + yx0 + j] = make_float2(re, im);
+  }
+  float o_r[F::BL][F::RL], o_i[F::BL][F::RL];
+  F::run(in_r, in_i, o_r, o_i, re, im, twr, twi, tid);
+#pragma unroll
+  for (int q = 0; q < F::BL; ++q) {
+    const int b = tid + q * NTB;
+    int m, j;
+    F::template bj<F::RL>(b, m, j);
+    const int yx = yx0 + m % kZyx, bc = bc0 + m / kZyx;
+    if ((F::TOTL % NTB == 0 || b < F::TOTL) && yx < P && bc < BC) {
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r)
+        t2[((long long)bc * N + j + r * (N / F::RL)) * P + yx] = make_float2(o_r[q][r], o_i[q][r]);
+    }
   }
 }
 
@@ -636,9 +760,9 @@ template <int N>
 static hipError_t dft_fwd_n(int M, int BC, const float* h, float2* t1, float2* t2, float2* md, float sc0, float sc1,
                             const float2* tw, hipStream_t s) {
   const long long rows = (long long)BC * N * N;
-  hipLaunchKernelGGL(k_dft_x_fwd<N>, dim3(nblocks(rows, kRows)), NTB, 0, s, h, t1, rows, M, tw);
+  hipLaunchKernelGGL(k_dft_x_fwd<N>, dim3(nblocks(rows, XT<N>::MP)), NTB, 0, s, h, t1, rows, M, tw);
   const long long nbz = (long long)BC * N;
-  hipLaunchKernelGGL(k_dft_y_fwd<N>, dim3(nblocks(nbz, kSlabs)), NTB, 0, s, t1, t2, nbz, M, tw);
+  hipLaunchKernelGGL(k_dft_y_fwd<N>, dim3(nblocks(nbz * M, kPen)), NTB, 0, s, t1, t2, nbz, M, tw);
   const int P = 2 * M * M;
   const unsigned nz = nblocks(BC, kZbc) * nblocks(P, kZyx);
   hipLaunchKernelGGL(k_dft_z_fwd<N>, dim3(nz), NTB, 0, s, t2, md, BC, M, sc0, sc1, tw);
@@ -652,9 +776,9 @@ static hipError_t dft_inv_n(int M, int BC, const float2* md, float2* t2, float2*
   const unsigned nz = nblocks(BC, kZbc) * nblocks(P, kZyx);
   hipLaunchKernelGGL(k_dft_z_inv<N>, dim3(nz), NTB, 0, s, md, t2, BC, M, tw);
   const long long nbz = (long long)BC * N;
-  hipLaunchKernelGGL(k_dft_y_inv<N>, dim3(nblocks(nbz * M, NTB)), NTB, 0, s, t2, t1, nbz, M, tw);
+  hipLaunchKernelGGL(k_dft_y_inv<N>, dim3(nblocks(nbz * M, kPen)), NTB, 0, s, t2, t1, nbz, M, tw);
   const long long rows = (long long)BC * N * N;
-  hipLaunchKernelGGL(k_dft_x_inv<N>, dim3(nblocks(rows, kRows)), NTB, 0, s, t1, out, rows, M, c0, c1, tw);
+  hipLaunchKernelGGL(k_dft_x_inv<N>, dim3(nblocks(rows, XT<N>::MP)), NTB, 0, s, t1, out, rows, M, c0, c1, tw);
   return hipGetLastError();
 }
 
