@@ -461,33 +461,19 @@ __global__ __launch_bounds__(NTB) void k_dft_x_fwd(const float* __restrict__ h, 
   __syncthreads();
   const int tid = threadIdx.x;
   const long long row0 = (long long)blockIdx.x * MP;
-  const int nr = (int)((rows - row0) < MP ? (rows - row0) : MP);
-  // the tile's rows arrive as coalesced 16-byte loads into LDS
-  for (int e = tid; e < MP * N / 4; e += NTB) {
-    const int m = (4 * e) / N, x = (4 * e) - m * N;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (m < nr) v = reinterpret_cast<const float4*>(h + row0 * N)[e];
-    float* d = re + m * XT<N>::SM + x;
-    d[0] = v.x;
-    d[1] = v.y;
-    d[2] = v.z;
-    d[3] = v.w;
-  }
-  __syncthreads();
   float in_r[F::B0][F::R0], in_i[F::B0][F::R0];
 #pragma unroll
   for (int q = 0; q < F::B0; ++q) {
     const int b = tid + q * NTB;
     int m, j;
     F::template bj<F::R0>(b, m, j);
-    const bool ok = F::TOT0 % NTB == 0 || b < F::TOT0;
+    const bool ok = (F::TOT0 % NTB == 0 || b < F::TOT0) && row0 + m < rows;
 #pragma unroll
     for (int r = 0; r < F::R0; ++r) {
-      in_r[q][r] = ok ? re[m * XT<N>::SM + j + r * (N / F::R0)] : 0.0f;
+      in_r[q][r] = ok ? h[(row0 + m) * N + j + r * (N / F::R0)] : 0.0f;
       in_i[q][r] = 0.0f;
     }
   }
-  __syncthreads();   // the transform's first pass rewrites the tile
   float o_r[F::BL][F::RL], o_i[F::BL][F::RL];
   F::run(in_r, in_i, o_r, o_i, re, im, twr, twi, tid);
 #pragma unroll
