@@ -191,12 +191,12 @@ def test_fp32_refined_mixed_48_64_96_batch(torch_dev):
         assert err < 1e-5, err
 
 
-def test_config1_full_shift_average(torch_dev):
+def test_2d_64_full_shift_average(torch_dev):
     """The 2D 64x64 workload's translated average over all 256 intra-cell
     shifts (FP64), against the oracle's literal average (microstructure
     shifted, Eqs. 3.3-3.6): same iteration counts, every accumulator
     component element by element."""
-    say("config-1 2D 64x64: 256-shift translated average vs oracle")
+    say("2D 64x64 (4x4 cells of 16x16): 256-shift translated average vs oracle")
     torch, dev = torch_dev
     from paper_2601_00822_amd import Plan
     shape = (64, 64)

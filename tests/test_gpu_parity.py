@@ -57,7 +57,7 @@ def gpu_solve(torch_dev, shape, phase, lame, f, prec="f64", scheme="basic", tol=
     return res, rep
 
 
-def config1_inputs(seed=0):
+def inputs_2d_64(seed=0):
     shape = (64, 64)
     phase, _ = gen.inclusion_per_cell(shape, 16, 0.2)
     f = gen.bump_force(shape, gen.random_center(shape, seed), 8.0, [1.0, 0.0])
@@ -125,12 +125,12 @@ def check_iterates(torch_dev, shape, phase, lame, f, js, tol=1e-8, scheme="basic
     return rep, ref
 
 
-def test_config1_2d_fp64_iterates(torch_dev):
+def test_2d_64_fp64_iterates(torch_dev):
     """64x64 plane strain, one disk per 16x16 cell (vf 0.2, contrast 10),
     bump R = 8 along x, reference medium = mean of extreme Lame constants,
     basic scheme to 1e-8."""
-    say("config-1 2D 64x64 FP64 iterate parity")
-    shape, phase, f = config1_inputs(0)
+    say("2D 64x64 FP64 iterate parity")
+    shape, phase, f = inputs_2d_64(0)
     rep, ref = check_iterates(torch_dev, shape, phase, LAME10, f, js=[0, 1, 2, 7, 30])
     print(f"iters={rep.iters} residual={rep.residual:.3e}")
 
@@ -234,9 +234,9 @@ def test_fp32_3d_vs_fp64_oracle(torch_dev):
     assert err < 1e-5
 
 
-def test_fp32_2d_config1(torch_dev):
-    say("FP32 2D config-1")
-    shape, phase, f = config1_inputs(1)
+def test_fp32_2d_64(torch_dev):
+    say("FP32 2D 64x64")
+    shape, phase, f = inputs_2d_64(1)
     ref = O.solve_basic(phase, LAME10, f, tol=1e-8)
     res, rep = gpu_solve(torch_dev, shape, phase, LAME10, f, prec="f32", tol=1e-8)
     err = O.relative_strain_error_voigt(res["eps"], O.to_voigt(ref.eps))

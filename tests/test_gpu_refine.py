@@ -109,7 +109,7 @@ def test_fp32_cg_alone_reaches_tol(torch_dev, kappa):
     assert err < 5e-6
 
 
-def test_refined_config1_2d(torch_dev):
+def test_refined_2d_64(torch_dev):
     say("FP32+FP64 refinement, 64x64 plane strain, one disk per cell")
     shape = (64, 64)
     phase, _ = gen.inclusion_per_cell(shape, 16, 0.2)

@@ -28,7 +28,7 @@ def rand_force(shape, seed):
 
 def test_lame_pin_bulk_modulus_identity():
     """lambda + 2 mu / 3 equals the bulk modulus E / (3 (1 - 2 nu)), and
-    mu = E / (2 (1 + nu)): the config values E = 1, nu = 0.3 give
+    mu = E / (2 (1 + nu)): the matrix phase E = 1, nu = 0.3 gives
     (0.576923..., 0.384615...)."""
     tab = np.array([[1.0, 0.3], [10.0, 0.3], [3.0, 0.1], [2.0, 0.45]])
     lame = O.lame_from_young(tab)
