@@ -197,23 +197,103 @@ template <bool LB> __device__ __forceinline__ void tile_sync() {
   else __syncthreads();
 }
 
+// Entries of the per-pass twiddle table of a transform (pass p >= 1 holds
+// (R_p - 1) NS_p of them, NS_p the span before the pass), and the offset of
+// pass p's entries.
+template <template <int> class PL, int N, bool REV>
+constexpr int twp_off(int p) {
+  using S = PlanSeq<PL, N, REV>;
+  int o = 0;
+  for (int q = 1; q < p; ++q) o += (S::r(q) - 1) * S::ns(q);
+  return o;
+}
+template <template <int> class PL, int N, bool REV>
+constexpr int twp_len() { return twp_off<PL, N, REV>(PlanSeq<PL, N, REV>::np); }
+
 // ---------------------------------------------------------------------------
 // tile transform with register input and register output
 // ---------------------------------------------------------------------------
 // T: float/double; N: length; DIR: -1/+1; REV: reversed radix order;
 // MP: pencils; SM, SN: LDS strides of pencil and index; TWS: twiddle stride;
 // JF: index-fastest butterfly mapping; NTH: threads; PL: radix plan family;
-// LB: barriers between passes order LDS only (see lds_barrier).
+// LB: barriers between passes order LDS only (see lds_barrier);
+// SWZ: XOR-swizzled staging index (see lidx); TWP: the twiddles come from a
+// per-pass table (twp_fill) instead of the length-N table.
 template <typename T, int N, int DIR, bool REV, int MP, int SM, int SN, int TWS, bool JF, int NTH,
-          template <int> class PL = Plan, bool SKEW = false, bool LB = false>
+          template <int> class PL = Plan, bool SKEW = false, bool LB = false, int SWZ = 0, bool TWP = false>
 struct TileFft {
-  // LDS word of element (pencil m, index n); with SKEW one padding word is
+  // LDS word of element (pencil m, index n).  With SKEW one padding word is
   // inserted every 32 indices, which breaks the power-of-two strides of the
-  // Stockham scatters across LDS banks
+  // Stockham scatters across LDS banks.  Two further layouts:
+  //  SWZ 1 (index-fastest tiles of 128 points, pencil stride SM a multiple
+  //   of 32): the low five bits of n are XORed with a mask built from the
+  //   32-entry block h = n / 32 and the pencil's parity e, bits 0-1 <- h,
+  //   bits 2-3 <- (h0 ^ e, h1), bit 4 <- h0 ^ e.  n stays inside its block
+  //   (a permutation of the pencil), and every gather and scatter of the
+  //   radix-4 and radix-8 passes then touches 32 distinct banks per 32
+  //   consecutive lanes: a radix-R scatter writes R-strided or NS-grouped
+  //   indices, whose blocks h the mask spreads over different low bits, and
+  //   a radix-8 pass spans two pencils per 32 lanes, which e separates.
+  //  SWZ 2 (pencil-fastest tiles, rows of SN >= MP words): index n lives in
+  //   row n + n / 8, one padding row after every 8.  A wave's lanes hold
+  //   several consecutive butterflies j, whose first-pass scatters write
+  //   rows R apart (R = 4, 8): with rows a power of two of words long those
+  //   land on the same banks, and the shifted rows spread them (modelled
+  //   bank conflicts of the 8- and 16-pencil tiles' exchanges drop from
+  //   about 45 % to 10-20 %).  Every offset stays a compile-time constant
+  //   plus a per-butterfly base.
   __device__ static __forceinline__ int lidx(int m, int n) {
-    return m * SM + n * SN + (SKEW ? (n >> 5) : 0);
+    if constexpr (SWZ == 1) {
+      const int h0 = (n >> 5) & 1, h1 = (n >> 6) & 1, e = h0 ^ (m & 1);
+      return m * SM + (n ^ (h0 | (h1 << 1) | (e << 2) | (h1 << 3) | (e << 4))) * SN;
+    } else if constexpr (SWZ == 2) {
+      return m * SM + (n + (n >> 3)) * SN;
+    } else {
+      return m * SM + n * SN + (SKEW ? (n >> 5) : 0);
+    }
   }
+  // LDS rows (index slots) the layout spans
+  static constexpr int ROWS = (SWZ == 2) ? N + (N - 1) / 8 + 1 : N;
+  // SWZ 2: row of index n.  A pass touches indices base + r st (r < R):
+  // gathers base j < N / R with st = N / R, scatters base
+  // (j / NS) NS R + j % NS with st = NS.  When row(base + r st) - row(base)
+  // equals row(r st) for every base (no base carries into bit 3 by adding
+  // r st), the row is formed once per butterfly and the R elements sit at
+  // compile-time offsets from it; checked here over every base.
+  static constexpr int row(int n) { return n + (n >> 3); }
+  template <int R, int NS, bool SCAT>
+  static constexpr bool uniform_rows() {
+    if (SWZ != 2) return false;
+    const int nb = N / R, st = SCAT ? NS : nb;
+    for (int j = 0; j < nb; ++j) {
+      const int base = SCAT ? (j / NS) * NS * R + j % NS : j;
+      for (int r = 0; r < R; ++r)
+        if (row(base + r * st) - row(base) != row(r * st)) return false;
+    }
+    return true;
+  }
+  static_assert(SWZ != 1 || (JF && SM % 32 == 0 && N == 128), "swizzled index-fastest layout");
+  static_assert(SWZ != 2 || (!JF && SM == 1 && SN >= MP), "padded pencil-fastest layout");
   using S = PlanSeq<PL, N, REV>;
+  static constexpr int TWPL = twp_len<PL, N, REV>();
+  // Fill the per-pass table (TWPL entries) from the length-N table read with
+  // stride TWS: entry twp_off(p) + (r - 1) NS_p + k = w^(r k N / (NS_p R_p)).
+  // Consecutive butterflies of an index-fastest tile then read consecutive
+  // entries instead of entries r k N / (NS_p R_p) apart.
+  __device__ static void twp_fill(T* dr, T* di, const T* twr, const T* twi, int tid) {
+    for (int e = tid; e < TWPL; e += NTH) {
+      int p = 1, o = 0;
+      while (p < S::np - 1 && e >= o + (S::r(p) - 1) * S::ns(p)) {
+        o += (S::r(p) - 1) * S::ns(p);
+        ++p;
+      }
+      const int ns = S::ns(p), R = S::r(p);
+      const int r = (e - o) / ns + 1, k = (e - o) - (r - 1) * ns;
+      const int t = r * k * (N / (ns * R)) * TWS;
+      dr[e] = twr[t];
+      di[e] = twi[t];
+    }
+  }
   static constexpr int np = S::np;
   static constexpr int R0 = S::first();
   static constexpr int RL = S::last();
@@ -233,14 +313,15 @@ struct TileFft {
   template <int R>
   __device__ static __forceinline__ int in_idx(int j, int r) { return j + r * (N / R); }
 
-  template <int R, int NS>
+  template <int P>
   __device__ static __forceinline__ void twiddle(T* vr, T* vi, int j, const T* twr, const T* twi) {
+    constexpr int R = S::r(P), NS = S::ns(P);
     if constexpr (NS > 1) {
       constexpr int TSTEP = N / (NS * R);
       const int k = j % NS;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const int t = r * k * TSTEP * TWS;
+        const int t = TWP ? twp_off<PL, N, REV>(P) + (r - 1) * NS + k : r * k * TSTEP * TWS;
         const T wr = twr[t];
         const T wi = (DIR < 0) ? twi[t] : -twi[t];
         cmul(vr[r], vi[r], wr, wi);
@@ -259,14 +340,23 @@ struct TileFft {
       if (TOT % NTH == 0 || b < TOT) {
         int m, j;
         bj<R>(b, m, j);
-        twiddle<R, NS>(vr[q], vi[q], j, twr, twi);
+        twiddle<P>(vr[q], vi[q], j, twr, twi);
         bfly<T, R, DIR>(vr[q], vi[q]);
         const int base = (j / NS) * NS * R + (j % NS);
+        if constexpr (uniform_rows<R, NS, true>()) {
+          const int i0 = lidx(m, base);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int idx = lidx(m, base + r * NS);
-          re[idx] = vr[q][r];
-          im[idx] = vi[q][r];
+          for (int r = 0; r < R; ++r) {
+            re[i0 + row(r * NS) * SN] = vr[q][r];
+            im[i0 + row(r * NS) * SN] = vi[q][r];
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int idx = lidx(m, base + r * NS);
+            re[idx] = vr[q][r];
+            im[idx] = vi[q][r];
+          }
         }
       }
     }
@@ -283,11 +373,20 @@ struct TileFft {
       if (TOT % NTH == 0 || b < TOT) {
         int m, j;
         bj<R>(b, m, j);
+        if constexpr (uniform_rows<R, 1, false>()) {
+          const int i0 = lidx(m, j);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int idx = lidx(m, j + r * (N / R));
-          vr[q][r] = re[idx];
-          vi[q][r] = im[idx];
+          for (int r = 0; r < R; ++r) {
+            vr[q][r] = re[i0 + row(r * (N / R)) * SN];
+            vi[q][r] = im[i0 + row(r * (N / R)) * SN];
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int idx = lidx(m, j + r * (N / R));
+            vr[q][r] = re[idx];
+            vi[q][r] = im[idx];
+          }
         }
       }
     }
@@ -304,7 +403,7 @@ struct TileFft {
       if (TOT % NTH == 0 || b < TOT) {
         int m, j;
         bj<R>(b, m, j);
-        twiddle<R, NS>(vr[q], vi[q], j, twr, twi);
+        twiddle<P>(vr[q], vi[q], j, twr, twi);
         bfly<T, R, DIR>(vr[q], vi[q]);
       }
     }

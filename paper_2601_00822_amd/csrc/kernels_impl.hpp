@@ -84,6 +84,17 @@ template <typename T, int N> struct SGeom {
   static constexpr int MPG = clampi(pow2floor((sizeof(T) == 4 && N >= LSFFT_G2_MIN ? 2 * Cfg<T>::E_G : Cfg<T>::E_G) / N), 1, 64);
 };
 
+// LDS rows of pencil-fastest tiles (y pass, outer pass): one row of LP
+// words per index.  FP32 tiles of 8 or 16 pencils use unpadded rows plus a
+// padding row after every 8 (TileFft SWZ 2); the others pad each row by one
+// word.  E is the words of one (re or im) buffer.
+template <typename T, int N, int MP> struct PencilRows {
+  static constexpr bool pad8 = sizeof(T) == 4 && (MP == 8 || MP == 16);
+  static constexpr int SWZ = pad8 ? 2 : 0;
+  static constexpr int LP = pad8 ? MP : (MP > 1 ? MP + 1 : 1);
+  static constexpr int E = LP * (pad8 ? N + (N - 1) / 8 + 1 : N);
+};
+
 // rows per x tile (H = nx / 2 complex points per row); odd LDS pitches.
 // DIV divides the tile's entries (schedule variant 1 of the x pass).
 template <typename T, int H, int DIV = 1> struct XGeom {
@@ -706,14 +717,27 @@ template <typename T, int H, bool ALT = false> struct XDma {
 #ifndef LSFFT_XSTG
 #define LSFFT_XSTG 1
 #endif
-  static constexpr int SMS = (LSFFT_XSTG && H == 64) ? 71 : G::SM2;
-  static constexpr bool SKS = !(LSFFT_XSTG && H == 64);
+  // The alternate radix order at 128 points (schedule variant 2, the tuned
+  // choice at nx = 256) XOR-swizzles the staging index (TileFft SWZ 1) with a
+  // pencil pitch of 160 words: a multiple of 32, and rows two apart fall 32
+  // words apart, so a wave's two rows of a radix-4 pass also meet different
+  // banks where the LDS has 64 of them.  (The default order takes 88 bytes
+  // per lane of spills with it.)
+  static constexpr bool SWZ = (H == 128) && ALT;
+  static constexpr int SMS = (H == 128) ? 160 : (LSFFT_XSTG && H == 64) ? 71 : G::SM2;
+  static constexpr bool SKS = !SWZ && !(LSFFT_XSTG && H == 64);
   static constexpr int BUF = (cmax(cmax(NCH * PITCH, 2 * MR * SMS * 4), 2 * MR * SMF * 4) + 15) / 16 * 16;
-  // phase ids of the tile: rows of 2H bytes at a pitch of 2H + 16 (the rows
-  // of a wave then fall on different LDS banks)
-  static constexpr int PP = 2 * H + 16;
-  // dynamic LDS: twiddles (2 x 2H), Lame table, phase ids of the tile
-  static constexpr int DYN = 4 * (2 * 2 * H + 2 * kXDmaPhases) + MR * PP;
+  // phase ids of the tile: rows of 2H bytes at a pitch of 2H + 64, i.e. 16
+  // words modulo 32, so the 2 (or 4) rows one wave reads at a time fall on
+  // disjoint LDS banks
+  static constexpr int PP = 2 * H + 64;
+  // per-pass twiddle tables of the inverse (reversed plan) and forward cores
+  using PF = PlanPick<ALT>;
+  static constexpr int TWPL = twp_len<PF::template P, H, true>() + twp_len<PF::template P, H, false>();
+  // dynamic LDS: twiddles (2 x 2H), Lame table, per-pass twiddles (padded to
+  // 16 bytes), phase ids of the tile
+  static constexpr int TWPB = (8 * TWPL + 15) / 16 * 16;
+  static constexpr int DYN = 4 * (2 * 2 * H + 2 * kXDmaPhases) + TWPB + MR * PP;
   static_assert(!ok || (NCH % 4 == 0 && MR * 2 * H == 4096), "x tile geometry");
   // rows never straddle a piece (a row is 256, 512 or 1024 bytes)
   __device__ static __forceinline__ int row_off(int m) {
@@ -754,10 +778,11 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   constexpr int MR = G::MR, SM = X::SMF, SM2 = X::SMS;
   constexpr int S = (DIM == 3) ? 6 : 3;
   using PF = PlanPick<XSched<V>::ALT>;
-  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, PF::template P, X::SKS, true>;
-  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, PF::template P, X::SKS, true>;
+  using FI = TileFft<T, H, +1, true, MR, SM2, 1, 2, true, NTH, PF::template P, X::SKS, true, X::SWZ ? 1 : 0, true>;
+  using FF = TileFft<T, H, -1, false, MR, SM2, 1, 2, true, NTH, PF::template P, X::SKS, true, X::SWZ ? 1 : 0, true>;
   static_assert(FI::RL == FF::R0 && FI::BL == FF::B0, "x transforms must chain in registers");
   static_assert(X::NB == H / FF::RL && SM % 32 == X::NB % 32 && SM > H, "fold-tile pitch");
+  static_assert(FI::TWPL + FF::TWPL == X::TWPL, "per-pass twiddle tables");
   constexpr int BP = FI::BL, RP = FI::RL;
   constexpr int TOTP = FI::TOTL;
   constexpr int PB = MR * NX / NTH;                // phase bytes per thread
@@ -768,7 +793,11 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   T* twi = twr + NX;
   T* lam_s = twi + NX;
   T* mu_s = lam_s + kXDmaPhases;
-  unsigned char* ptile = reinterpret_cast<unsigned char*>(mu_s + kXDmaPhases);
+  T* fir = mu_s + kXDmaPhases;          // per-pass twiddles, inverse core
+  T* fii = fir + FI::TWPL;
+  T* ffr = fii + FI::TWPL;              // forward core
+  T* ffi = ffr + FF::TWPL;
+  unsigned char* ptile = reinterpret_cast<unsigned char*>(mu_s + kXDmaPhases) + X::TWPB;
   const int tid = threadIdx.x;
   const int nrows = D.ny * D.nz;
   const int part = local / D.xtiles;
@@ -807,6 +836,9 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
     const int m = (tid * 16) / NX, x0 = (tid * 16) - m * NX;
     *reinterpret_cast<uint4*>(ptile + m * X::PP + x0) = phv;
   }
+  lds_barrier();   // the length-NX twiddles are in LDS
+  FI::twp_fill(fir, fii, twr, twi, tid);
+  FF::twp_fill(ffr, ffi, twr, twi, tid);
   wait_vm_all();
   __syncthreads();
 
@@ -844,7 +876,7 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
     }
     lds_barrier();   // every wave has read the tile
     T* br = reinterpret_cast<T*>(buf);
-    FI::run(in_r, in_i, o_r, o_i, br, br + MR * SM2, twr, twi, tid);
+    FI::run(in_r, in_i, o_r, o_i, br, br + MR * SM2, fir, fii, tid);
   };
   // forward core and unfold (staging in xb1, fold tile in xb0), then the
   // stores of component c of S
@@ -855,7 +887,7 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
     T* ai = ar + MR * SM;
     T o_r[FF::BL][FF::RL], o_i[FF::BL][FF::RL];
     lds_barrier();   // staging buffer free
-    FF::run(in_r, in_i, o_r, o_i, br, bi, twr, twi, tid);
+    FF::run(in_r, in_i, o_r, o_i, br, bi, ffr, ffi, tid);
     lds_barrier();   // previous users of the fold tile are done
 #pragma unroll
     for (int q = 0; q < FF::BL; ++q) {
@@ -1036,9 +1068,12 @@ __device__ void ypass_item(const InstDesc& D, int local, int c, void* buf, const
                            unsigned char* smem) {
   constexpr int NTH = Cfg<T>::NTH;
   constexpr int MP = YSched<T, NY, V>::MP;
-  constexpr int LP = (MP > 1) ? MP + 1 : 1;     // padded LDS row (one index, all pencils)
-  constexpr int E = LP * NY;
-  using F = TileFft<T, NY, DIR, (DIR > 0), MP, 1, LP, 1, false, NTH, PlanPick<YSched<T, NY, V>::ALT>::template P>;
+  using PR = PencilRows<T, NY, MP>;
+  constexpr int LP = PR::LP;                    // LDS row (one index, all pencils)
+  constexpr int E = PR::E;
+  using F = TileFft<T, NY, DIR, (DIR > 0), MP, 1, LP, 1, false, NTH, PlanPick<YSched<T, NY, V>::ALT>::template P,
+                    false, false, PR::SWZ>;
+  static_assert((MP - 1) + (F::ROWS - 1) * LP < E, "y tile staging");
   T* re = reinterpret_cast<T*>(smem);
   T* im = re + E;
   T* twr = im + E;
@@ -1093,11 +1128,13 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
   using GS = GSched<T, NG, V>;
   constexpr int NTH = GS::NTH;
   constexpr int MP = GS::MP;
-  constexpr int LP = (MP > 1) ? MP + 1 : 1;     // padded LDS row
-  constexpr int E = LP * NG;
+  using PR = PencilRows<T, NG, MP>;
+  constexpr int LP = PR::LP;                    // LDS row
+  constexpr int E = PR::E;
   constexpr int S = (DIM == 3) ? 6 : 3;
-  using FF = TileFft<T, NG, -1, false, MP, 1, LP, 1, false, NTH, PlanG>;
-  using FI = TileFft<T, NG, +1, true, MP, 1, LP, 1, false, NTH, PlanG>;
+  using FF = TileFft<T, NG, -1, false, MP, 1, LP, 1, false, NTH, PlanG, false, false, PR::SWZ>;
+  using FI = TileFft<T, NG, +1, true, MP, 1, LP, 1, false, NTH, PlanG, false, false, PR::SWZ>;
+  static_assert((MP - 1) + (FF::ROWS - 1) * LP < E, "outer tile staging");
   static_assert(FF::RL == FI::R0 && FF::BL == FI::B0, "outer transforms must chain in registers");
   constexpr int BP = FF::BL, RP = FF::RL, TOTP = FF::TOTL;
   constexpr int NSTEP = NG / RP;                 // index step between a butterfly's points
@@ -2718,12 +2755,11 @@ template <typename T, int L, int V = 0> constexpr size_t lds_xi() {
 #endif
   return lds_x<T, L, V>();
 }
-template <int MP> constexpr int padded(int mp) { return mp > 1 ? mp + 1 : 1; }
 template <typename T, int L, int V = 0> constexpr size_t lds_y() {
-  return sizeof(T) * (2 * padded<0>(YSched<T, L, V>::MP) * L + 2 * L);
+  return sizeof(T) * (2 * PencilRows<T, L, YSched<T, L, V>::MP>::E + 2 * L);
 }
 template <typename T, int L, int V = 0> constexpr size_t lds_g() {
-  return sizeof(T) * (4 * padded<0>(GSched<T, L, V>::MP) * L + 2 * L + 2) + sizeof(double) * 16;
+  return sizeof(T) * (4 * PencilRows<T, L, GSched<T, L, V>::MP>::E + 2 * L + 2) + sizeof(double) * 16;
 }
 
 }  // namespace lsfft
