@@ -454,10 +454,12 @@ lsfft_status lsfft_schedule_set(lsfft_plan_t p, int dim, int kind, int len, int 
 /*
  * lsfft_autotune -- time every schedule variant of the plan's 3D grids and
  * keep the fastest per pass kind and length.  For each distinct 3D grid a
- * synthetic solve (two phases of Young's contrast 10 in 8-voxel blocks, a
- * deterministic pseudo-random force) runs `iters` iterations (1..10000) once
- * per variant round with every launch timed by a HIP event pair; each pass
- * kind is judged by its own mean kernel time per launch.  The plan's own
+ * batch of identical synthetic solves (two phases of Young's contrast 10 in
+ * 8-voxel blocks, a deterministic pseudo-random force; as many solves as
+ * fill about 8 M voxels, at most the plan's max_batch, so a plan of one
+ * solve is tuned on one solve) runs `iters` iterations (1..10000) once per
+ * variant round with every launch timed by a HIP event pair; each pass kind
+ * is judged by its own mean kernel time per launch.  The plan's own
  * precision and scheme are used (FP32 inner solves for LSFFT_REFINE64).
  *  cache_path  NULL, or a file to merge the choices into: a flat JSON object
  *              {"f32/3d/outer/256": 2, ...}; lsfft_plan reads the file named

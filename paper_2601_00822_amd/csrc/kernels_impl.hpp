@@ -692,11 +692,13 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
 // ---------------------------------------------------------------------------
 // x pass of the iteration with row tiles staged by direct global->LDS loads
 // ---------------------------------------------------------------------------
-// FP32 tiles of 2048 complex entries (nx = 64, 128, 256).  The main block of
-// a row tile (MR rows x H entries) is contiguous in HBM; it lands in LDS in
-// 1 KB pieces, one per wave-wide 16-byte-per-lane load, each piece followed
-// by 64 bytes of padding so that row pairs of consecutive pieces fall on
-// different LDS banks.  Loads bypass the registers, so the
+// FP32 tiles of 2048 complex entries (nx = 64, 128, 256) or 1536 (nx = 48,
+// 96: 64 or 32 rows).  The main block of a row tile (MR rows x H entries) is
+// contiguous in HBM; it lands in LDS in 1 KB pieces, one per wave-wide
+// 16-byte-per-lane load.  Where rows divide a piece (2048-entry tiles) each
+// piece is followed by 64 bytes of padding so that row pairs of consecutive
+// pieces fall on different LDS banks; 384-byte rows straddle pieces, so
+// those tiles are dense.  Loads bypass the registers, so the
 // normal group fetches the next component into the second buffer while the
 // current one is transformed.  The buffers double as transform staging and
 // fold tiles once their data has been read.
@@ -705,8 +707,8 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <typename T, int H, bool ALT = false> struct XDma {
   using G = XGeom<T, H>;
   static constexpr int MR = G::MR;
-  static constexpr bool ok = sizeof(T) == 4 && MR * H == 2048 && Cfg<T>::NTH_X == 256;
-  static constexpr int KB = 1024, PAD = 64, PITCH = KB + PAD;
+  static constexpr bool ok = sizeof(T) == 4 && (MR * H == 2048 || MR * H == 1536) && Cfg<T>::NTH_X == 256;
+  static constexpr int KB = 1024, PAD = (KB % (H * 8) == 0) ? 64 : 0, PITCH = KB + PAD;
   static constexpr int NCH = MR * H * 8 / KB;                 // 1 KB pieces per tile
   // fold-tile pitch for the unfold: the forward core leaves NB = H / RL
   // consecutive entries of a row in consecutive lanes, so a pitch of NB
@@ -727,10 +729,10 @@ template <typename T, int H, bool ALT = false> struct XDma {
   static constexpr int SMS = (H == 128) ? 160 : (LSFFT_XSTG && H == 64) ? 71 : G::SM2;
   static constexpr bool SKS = !SWZ && !(LSFFT_XSTG && H == 64);
   static constexpr int BUF = (cmax(cmax(NCH * PITCH, 2 * MR * SMS * 4), 2 * MR * SMF * 4) + 15) / 16 * 16;
-  // phase ids of the tile: rows of 2H bytes at a pitch of 2H + 64, i.e. 16
-  // words modulo 32, so the 2 (or 4) rows one wave reads at a time fall on
-  // disjoint LDS banks
-  static constexpr int PP = 2 * H + 64;
+  // phase ids of the tile: rows of 2H bytes at a pitch of 16 words modulo
+  // 32, so two consecutive rows fall on disjoint halves of the LDS banks
+  static constexpr int PP = 2 * H + 4 * (((16 - H / 2) % 32 + 32) % 32);
+  static_assert(!ok || (PP % 16 == 0 && (PP / 4) % 32 == 16), "phase-id row pitch");
   // per-pass twiddle tables of the inverse (reversed plan) and forward cores
   using PF = PlanPick<ALT>;
   static constexpr int TWPL = twp_len<PF::template P, H, true>() + twp_len<PF::template P, H, false>();
@@ -738,8 +740,9 @@ template <typename T, int H, bool ALT = false> struct XDma {
   // 16 bytes), phase ids of the tile
   static constexpr int TWPB = (8 * TWPL + 15) / 16 * 16;
   static constexpr int DYN = 4 * (2 * 2 * H + 2 * kXDmaPhases) + TWPB + MR * PP;
-  static_assert(!ok || (NCH % 4 == 0 && MR * 2 * H == 4096), "x tile geometry");
-  // rows never straddle a piece (a row is 256, 512 or 1024 bytes)
+  static_assert(!ok || (NCH % 4 == 0 && (MR * 2 * H == 4096 || MR * 2 * H == 3072)), "x tile geometry");
+  // padded tiles: rows never straddle a piece (a row is 256, 512 or 1024
+  // bytes); dense tiles: PAD = 0
   __device__ static __forceinline__ int row_off(int m) {
     const int p = m * H * 8;
     return p + (p >> 10) * PAD;
@@ -806,24 +809,31 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   const int cfirst = (part == 0) ? 0 : DIM + part - 1;
 
   xdma_issue<T, H>(cptr<T>(D.S, Pc, cfirst), row0, nrows, xb0, tid);
-  // phase ids of the tile, 16 consecutive x of one row per thread, read at
-  // the shifted positions
-  static_assert(PB == 16, "x tile phase map");
-  uint4 phv = make_uint4(0u, 0u, 0u, 0u);
+  // phase ids of the tile, PB = 16 (2048-entry tiles) or 12 (1536-entry
+  // tiles) consecutive x of one row per thread, read at the shifted
+  // positions: as one 16-byte load or three 4-byte loads where the shift
+  // keeps the group whole and aligned, byte by byte otherwise
+  static_assert(PB == 16 || PB == 12, "x tile phase map");
+  constexpr int PW = PB / 4;
+  unsigned phw[4] = {0u, 0u, 0u, 0u};
   {
-    const int m = (tid * 16) / NX, x0 = (tid * 16) - m * NX;
+    const int m = (tid * PB) / NX, x0 = (tid * PB) - m * NX;
     const int row = row0 + m;
     if (row < nrows) {
       const int z = row / D.ny, y = row - (row / D.ny) * D.ny;
       const long long rbase = (long long)(wrap(z - D.sz, D.nz) * D.ny + wrap(y - D.sy, D.ny)) * NX;
-      if (((reinterpret_cast<unsigned long long>(D.phase) | (unsigned)D.sx) & 15ull) == 0) {
-        phv = gld<uint4>(D.phase + rbase + wrap(x0 - D.sx, NX), 0);
-      } else {
-        unsigned w[4] = {0u, 0u, 0u, 0u};
+      const unsigned long long pa = reinterpret_cast<unsigned long long>(D.phase);
+      if (PB == 16 && ((pa | (unsigned)D.sx) & 15ull) == 0) {
+        const uint4 v = gld<uint4>(D.phase + rbase + wrap(x0 - D.sx, NX), 0);
+        phw[0] = v.x; phw[1] = v.y; phw[2] = v.z; phw[3] = v.w;
+      } else if (PB == 12 && (pa & 3ull) == 0 && D.sx % 12 == 0) {
+        const uint8_t* g = D.phase + rbase + wrap(x0 - D.sx, NX);
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-          w[i >> 2] |= (unsigned)gld<uint8_t>(D.phase, rbase + wrap(x0 + i - D.sx, NX)) << (8 * (i & 3));
-        phv = make_uint4(w[0], w[1], w[2], w[3]);
+        for (int i = 0; i < PW; ++i) phw[i] = gld<unsigned>(g, i);
+      } else {
+#pragma unroll
+        for (int i = 0; i < PB; ++i)
+          phw[i >> 2] |= (unsigned)gld<uint8_t>(D.phase, rbase + wrap(x0 + i - D.sx, NX)) << (8 * (i & 3));
       }
     }
   }
@@ -833,8 +843,13 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
     mu_s[p] = T(gld<double>(lame, 2 * (D.lame_off + p) + 1));
   }
   {
-    const int m = (tid * 16) / NX, x0 = (tid * 16) - m * NX;
-    *reinterpret_cast<uint4*>(ptile + m * X::PP + x0) = phv;
+    const int m = (tid * PB) / NX, x0 = (tid * PB) - m * NX;
+    if constexpr (PB == 16) {
+      *reinterpret_cast<uint4*>(ptile + m * X::PP + x0) = make_uint4(phw[0], phw[1], phw[2], phw[3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < PW; ++i) reinterpret_cast<unsigned*>(ptile + m * X::PP + x0)[i] = phw[i];
+    }
   }
   lds_barrier();   // the length-NX twiddles are in LDS
   FI::twp_fill(fir, fii, twr, twi, tid);

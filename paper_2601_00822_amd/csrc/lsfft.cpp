@@ -1879,6 +1879,12 @@ lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, l
     }
     if (rounds == 1) continue;
     const long long nvox = (long long)lens[0] * lens[1] * lens[2];
+    // Solves of this grid per tuning launch: as many as fill about 8 M
+    // voxels, within the plan's batch size, as a batch of the plan's size
+    // would.  A single solve of a small grid leaves most of the 256 CUs idle
+    // and times the launch latency instead of the pass (at 96^3 it ranked
+    // the tiles the other way round).  They share one force spectrum.
+    const int nrep = (int)std::max(1LL, std::min((long long)p->max_batch, (8LL << 20) / nvox));
     std::vector<uint8_t> hph((size_t)nvox);
     std::vector<double> hf(3 * (size_t)nvox);
     unsigned long long st = 0x9e3779b97f4a7c15ull;
@@ -1921,11 +1927,14 @@ lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, l
       (void)resolve_ref(&tab, nullptr, &sp.lam0, &sp.mu0);
       sp.f = df;
       sp.leader = 0;
-      b.specs.push_back(sp);
-      lsfft_report rep;
+      for (int k = 0; k < nrep; ++k) {
+        sp.out_index = k;
+        b.specs.push_back(sp);
+      }
+      std::vector<lsfft_report> reps((size_t)nrep);
       lsfft_kernel_times_reset(p);
       p->force_timing = true;
-      const lsfft_status rs_ = run_batch(b, &rep, now_s());
+      const lsfft_status rs_ = run_batch(b, reps.data(), now_s());
       p->force_timing = false;
       if (rs_ == LSFFT_E_ARG || rs_ == LSFFT_E_ALLOC || rs_ == LSFFT_E_DEVICE) {
         ls = rs_;

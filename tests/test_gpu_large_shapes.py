@@ -112,9 +112,9 @@ def test_fp64_iterates_long_x(torch_dev, shape):
                                    (96, 48, 8)])
 @pytest.mark.parametrize("refine", [False, True])
 def test_fp32_large_axes_vs_oracle(torch_dev, shape, refine):
-    """FP32 transforms on the long axes (x at 48 and 96 through the register-
-    staged x pass; y and outer at 48, 96 and 256), with and without the FP64
-    defect correction, against the oracle's FP64 solution at 1e-8."""
+    """FP32 transforms on the long axes (x at 48 and 96 through the x pass's
+    dense 1536-entry tiles; y and outer at 48, 96 and 256), with and without
+    the FP64 defect correction, against the oracle's FP64 solution at 1e-8."""
     say(f"FP32 {'+ FP64 correction ' if refine else ''}vs oracle {shape}")
     phase = rand_phase(shape, 91)
     f = gen.bump_force(shape, gen.random_center(shape, 92), 3.0, gen.random_direction(3, 93))

@@ -245,11 +245,13 @@ def test_fp32_2d_64(torch_dev):
     assert err < 1e-5
 
 
-@pytest.mark.parametrize("shape", [(4, 6, 128), (6, 12, 128), (6, 16, 64), (4, 6, 256), (24, 128), (48, 64)])
+@pytest.mark.parametrize("shape", [(4, 6, 128), (6, 12, 128), (6, 16, 64), (4, 6, 256), (24, 128), (48, 64),
+                                   (4, 6, 96), (8, 12, 96), (6, 16, 48), (4, 12, 48), (24, 96), (96, 48)])
 def test_fp32_staged_x_tiles(torch_dev, shape):
     """FP32 x pass with row tiles staged by direct global->LDS loads (nx = 64,
-    128, 256; 32, 64 or 16 rows per tile): single and ragged row tiles, 2D and
-    3D."""
+    128, 256: 2048-entry tiles of 64, 32 or 16 rows; nx = 48,
+    96: dense 1536-entry tiles of 64 and 32 rows): single, several and ragged
+    row tiles, 2D and 3D."""
     say(f"FP32 staged x tiles {shape}")
     phase = rand_phase(shape, 51)
     f = rand_force(shape, 52)
@@ -289,6 +291,30 @@ def test_fp32_staged_x_tiles_shifted(torch_dev):
     shifts = np.array([[0, 0, 0], [1, 2, 16], [3, 1, 5], [2, 5, 37]], dtype=np.int32)
     ref, _ = O.translate_average(phase, LAME10, f, shifts, tol=1e-10)
     plan = Plan([shape], prec="f32", max_batch=4)
+    avg, reps = plan.translate_average(torch.from_numpy(phase).to(dev), LAME10,
+                                       torch.from_numpy(f).to(dev).float(), shifts, tol=1e-8)
+    a = avg.cpu().numpy()
+    print("iters", [r.iters for r in reps])
+    s = 6
+    assert O.relative_strain_error_voigt(a[6:6 + s], ref[6:6 + s]) < 1e-5
+    np.testing.assert_array_equal(a[-1], ref[-1])
+    plan.close()
+
+
+@pytest.mark.parametrize("nx", [48, 96])
+def test_fp32_staged_x_tiles_1536_shifted(torch_dev, nx):
+    """Shifted microstructures in the dense 1536-entry x tiles: x shifts that
+    are multiples of 12 (word reads of the phase map) and others (byte
+    reads), against the oracle's translated average."""
+    say(f"FP32 staged 1536-entry x tiles, translated average 4x6x{nx}")
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import Plan
+    shape = (4, 6, nx)
+    phase = rand_phase(shape, 57)
+    f = gen.bump_force(shape, (1.7, 2.2, nx / 2 + 0.5), 3.0, gen.random_direction(3, 58))
+    shifts = np.array([[0, 0, 0], [1, 2, 12], [3, 1, 5], [2, 5, nx - 12]], dtype=np.int32)   # 4: exact averages
+    ref, _ = O.translate_average(phase, LAME10, f, shifts, tol=1e-10)
+    plan = Plan([shape], prec="f32", max_batch=len(shifts))
     avg, reps = plan.translate_average(torch.from_numpy(phase).to(dev), LAME10,
                                        torch.from_numpy(f).to(dev).float(), shifts, tol=1e-8)
     a = avg.cpu().numpy()
