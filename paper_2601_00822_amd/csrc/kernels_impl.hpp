@@ -693,7 +693,8 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
 // x pass of the iteration with row tiles staged by direct global->LDS loads
 // ---------------------------------------------------------------------------
 // FP32 tiles of 2048 complex entries (nx = 64, 128, 256) or 1536 (nx = 48,
-// 96: 64 or 32 rows).  The main block of a row tile (MR rows x H entries) is
+// 96: 64 or 32 rows), and with the halved tiles of schedule variant 1 the
+// 768-entry tiles of nx = 48 and 96 (32 or 16 rows).  The main block of a row tile (MR rows x H entries) is
 // contiguous in HBM; it lands in LDS in 1 KB pieces, one per wave-wide
 // 16-byte-per-lane load.  Where rows divide a piece (2048-entry tiles) each
 // piece is followed by 64 bytes of padding so that row pairs of consecutive
@@ -704,10 +705,13 @@ __device__ void xpass_item_std(const InstDesc& D, int local, const double* __res
 // fold tiles once their data has been read.
 constexpr int kXDmaPhases = kMaxPhases;
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-template <typename T, int H, bool ALT = false> struct XDma {
-  using G = XGeom<T, H>;
+template <typename T, int H, bool ALT = false, int DIV = 1> struct XDma {
+  using G = XGeom<T, H, DIV>;
   static constexpr int MR = G::MR;
-  static constexpr bool ok = sizeof(T) == 4 && (MR * H == 2048 || MR * H == 1536) && Cfg<T>::NTH_X == 256;
+  // 2048- and 1536-entry tiles; with the halved tiles of schedule variant 1,
+  // the 768-entry ones of nx = 48 and 96
+  static constexpr bool ok = sizeof(T) == 4 && Cfg<T>::NTH_X == 256 &&
+                             (DIV == 1 ? (MR * H == 2048 || MR * H == 1536) : (DIV == 2 && MR * H == 768));
   static constexpr int KB = 1024, PAD = (KB % (H * 8) == 0) ? 64 : 0, PITCH = KB + PAD;
   static constexpr int NCH = MR * H * 8 / KB;                 // 1 KB pieces per tile
   // fold-tile pitch for the unfold: the forward core leaves NB = H / RL
@@ -740,7 +744,7 @@ template <typename T, int H, bool ALT = false> struct XDma {
   // 16 bytes), phase ids of the tile
   static constexpr int TWPB = (8 * TWPL + 15) / 16 * 16;
   static constexpr int DYN = 4 * (2 * 2 * H + 2 * kXDmaPhases) + TWPB + MR * PP;
-  static_assert(!ok || (NCH % 4 == 0 && (MR * 2 * H == 4096 || MR * 2 * H == 3072)), "x tile geometry");
+  static_assert(!ok || (MR * 2 * H == 4096 || MR * 2 * H == 3072 || MR * 2 * H == 1536), "x tile geometry");
   // padded tiles: rows never straddle a piece (a row is 256, 512 or 1024
   // bytes); dense tiles: PAD = 0
   __device__ static __forceinline__ int row_off(int m) {
@@ -755,14 +759,15 @@ typedef __attribute__((address_space(3))) void* lds_vptr;
 // tile row0 into LDS buffer `buf`.  Lanes past the last row load nothing.
 // Every supported axis length is even, so the component stride (ny nz H
 // entries of 8 bytes) keeps every component base 16-byte aligned.
-template <typename T, int H>
+template <typename X, int H>
 __device__ __forceinline__ void xdma_issue(const char* comp, int row0, int nrows, unsigned char* buf, int tid) {
-  using X = XDma<T, H>;
   const int wave = tid >> 6, lane = tid & 63;
   const char* mainp = comp + (long long)row0 * H * 8;
+  // piece g by wave g mod 4 (768-entry tiles: 6 pieces, two waves take two)
 #pragma unroll
-  for (int i = 0; i < X::NCH / 4; ++i) {
+  for (int i = 0; i < (X::NCH + 3) / 4; ++i) {
     const int g = i * 4 + wave;
+    if (X::NCH % 4 != 0 && g >= X::NCH) break;
     const int b = g * X::KB + lane * 16;
     if (row0 + b / (H * 8) < nrows)
       __builtin_amdgcn_global_load_lds((const void*)(mainp + b), (lds_vptr)(buf + g * X::PITCH), 16, 0, 0);
@@ -776,8 +781,8 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
                                const T* __restrict__ twtab, unsigned char* smem) {
   constexpr int NTH = 256;
   constexpr int H = NX / 2;
-  using G = XGeom<T, H>;
-  using X = XDma<T, H, XSched<V>::ALT>;
+  using G = XGeom<T, H, XSched<V>::EX_DIV>;
+  using X = XDma<T, H, XSched<V>::ALT, XSched<V>::EX_DIV>;
   constexpr int MR = G::MR, SM = X::SMF, SM2 = X::SMS;
   constexpr int S = (DIM == 3) ? 6 : 3;
   using PF = PlanPick<XSched<V>::ALT>;
@@ -808,12 +813,12 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   const long long Pc = D.Pc;
   const int cfirst = (part == 0) ? 0 : DIM + part - 1;
 
-  xdma_issue<T, H>(cptr<T>(D.S, Pc, cfirst), row0, nrows, xb0, tid);
-  // phase ids of the tile, PB = 16 (2048-entry tiles) or 12 (1536-entry
-  // tiles) consecutive x of one row per thread, read at the shifted
-  // positions: as one 16-byte load or three 4-byte loads where the shift
-  // keeps the group whole and aligned, byte by byte otherwise
-  static_assert(PB == 16 || PB == 12, "x tile phase map");
+  xdma_issue<X, H>(cptr<T>(D.S, Pc, cfirst), row0, nrows, xb0, tid);
+  // phase ids of the tile, PB = 16 (2048-entry tiles), 12 (1536) or 6
+  // (768) consecutive x of one row per thread, read at the shifted
+  // positions: as one 16-byte load, three 4-byte or three 2-byte loads where
+  // the shift keeps the group whole and aligned, byte by byte otherwise
+  static_assert(PB == 16 || PB == 12 || PB == 6, "x tile phase map");
   constexpr int PW = PB / 4;
   unsigned phw[4] = {0u, 0u, 0u, 0u};
   {
@@ -830,6 +835,10 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
         const uint8_t* g = D.phase + rbase + wrap(x0 - D.sx, NX);
 #pragma unroll
         for (int i = 0; i < PW; ++i) phw[i] = gld<unsigned>(g, i);
+      } else if (PB == 6 && (pa & 1ull) == 0 && D.sx % 6 == 0) {
+        const uint8_t* g = D.phase + rbase + wrap(x0 - D.sx, NX);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) phw[i >> 1] |= (unsigned)gld<unsigned short>(g, i) << (16 * (i & 1));
       } else {
 #pragma unroll
         for (int i = 0; i < PB; ++i)
@@ -846,9 +855,13 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
     const int m = (tid * PB) / NX, x0 = (tid * PB) - m * NX;
     if constexpr (PB == 16) {
       *reinterpret_cast<uint4*>(ptile + m * X::PP + x0) = make_uint4(phw[0], phw[1], phw[2], phw[3]);
-    } else {
+    } else if constexpr (PB == 12) {
 #pragma unroll
       for (int i = 0; i < PW; ++i) reinterpret_cast<unsigned*>(ptile + m * X::PP + x0)[i] = phw[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        reinterpret_cast<unsigned short*>(ptile + m * X::PP + x0)[i] = (unsigned short)(phw[i >> 1] >> (16 * (i & 1)));
     }
   }
   lds_barrier();   // the length-NX twiddles are in LDS
@@ -977,11 +990,11 @@ __device__ void xpass_iter_dma(const InstDesc& D, int local, const double* __res
   // normal components, coupled through the trace; component c + 1 is in
   // flight while component c is transformed
   T n_r[DIM][BP][RP], n_i[DIM][BP][RP];
-  xdma_issue<T, H>(cptr<T>(D.S, Pc, 1), row0, nrows, xb1, tid);
+  xdma_issue<X, H>(cptr<T>(D.S, Pc, 1), row0, nrows, xb1, tid);
   c2r(xb0, n_r[0], n_i[0]);
   wait_vm_all();
   __syncthreads();   // component 1 landed; the staging of component 0 is free
-  if constexpr (DIM == 3) xdma_issue<T, H>(cptr<T>(D.S, Pc, 2), row0, nrows, xb0, tid);
+  if constexpr (DIM == 3) xdma_issue<X, H>(cptr<T>(D.S, Pc, 2), row0, nrows, xb0, tid);
   c2r(xb1, n_r[1], n_i[1]);
   if constexpr (DIM == 3) {
     wait_vm_all();
@@ -1010,7 +1023,7 @@ template <typename T, int NX, int DIM, int MODE, int V>
 __device__ __forceinline__ void xpass_item(const InstDesc& D, int local, const double* __restrict__ lame,
                                            const T* __restrict__ twtab, unsigned char* smem) {
 #ifndef LSFFT_NO_XDMA
-  if constexpr (MODE == M_ITER && XSched<V>::EX_DIV == 1 && XDma<T, NX / 2, XSched<V>::ALT>::ok) {
+  if constexpr (MODE == M_ITER && XDma<T, NX / 2, XSched<V>::ALT, XSched<V>::EX_DIV>::ok) {
     xpass_iter_dma<T, NX, DIM, V>(D, local, lame, twtab, smem);
     return;
   }
@@ -2766,7 +2779,7 @@ template <typename T, int L, int V = 0> constexpr size_t lds_x() {
 // in static LDS buffers)
 template <typename T, int L, int V = 0> constexpr size_t lds_xi() {
 #ifndef LSFFT_NO_XDMA
-  if (XSched<V>::EX_DIV == 1 && XDma<T, L / 2, XSched<V>::ALT>::ok) return XDma<T, L / 2, XSched<V>::ALT>::DYN;
+  if (XDma<T, L / 2, XSched<V>::ALT, XSched<V>::EX_DIV>::ok) return XDma<T, L / 2, XSched<V>::ALT, XSched<V>::EX_DIV>::DYN;
 #endif
   return lds_x<T, L, V>();
 }

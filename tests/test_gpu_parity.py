@@ -301,12 +301,14 @@ def test_fp32_staged_x_tiles_shifted(torch_dev):
     plan.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("nx", [48, 96])
-def test_fp32_staged_x_tiles_1536_shifted(torch_dev, nx):
-    """Shifted microstructures in the dense 1536-entry x tiles: x shifts that
-    are multiples of 12 (word reads of the phase map) and others (byte
-    reads), against the oracle's translated average."""
-    say(f"FP32 staged 1536-entry x tiles, translated average 4x6x{nx}")
+def test_fp32_staged_x_tiles_1536_shifted(torch_dev, nx, variant):
+    """Shifted microstructures in the dense x tiles of nx = 48 and 96 (1536
+    entries in schedule variant 0, 768 in variant 1): x shifts that are
+    multiples of 12 (word or half-word reads of the phase map) and others
+    (byte reads), against the oracle's translated average."""
+    say(f"FP32 staged dense x tiles (variant {variant}), translated average 4x6x{nx}")
     torch, dev = torch_dev
     from paper_2601_00822_amd import Plan
     shape = (4, 6, nx)
@@ -315,6 +317,7 @@ def test_fp32_staged_x_tiles_1536_shifted(torch_dev, nx):
     shifts = np.array([[0, 0, 0], [1, 2, 12], [3, 1, 5], [2, 5, nx - 12]], dtype=np.int32)   # 4: exact averages
     ref, _ = O.translate_average(phase, LAME10, f, shifts, tol=1e-10)
     plan = Plan([shape], prec="f32", max_batch=len(shifts))
+    plan.set_schedule("x", nx, variant)
     avg, reps = plan.translate_average(torch.from_numpy(phase).to(dev), LAME10,
                                        torch.from_numpy(f).to(dev).float(), shifts, tol=1e-8)
     a = avg.cpu().numpy()
