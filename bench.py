@@ -432,9 +432,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, prec: str):
+def measured_traffic(kernel: str, workload: str, prec: str, variant: int = 0):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the current kernel sources and on the schedule variant the
+    timed run uses for that pass (every counter pass of the summary names
+    its kernel, whose last template argument is the variant); else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}_counters.md")
     if not os.path.exists(path):
         return None
@@ -442,6 +444,10 @@ def measured_traffic(kernel: str, workload: str, prec: str):
     m_hash = re.search(r"kernel_source_hash:\s*(\w+)", text)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    line = next((ln for ln in text.splitlines() if ln.startswith("Kernel:")), "")
+    measured = {int(v) for v in re.findall(r"k_%s<[^>]*?(\d+)>" % kernel, line)}
+    if measured != {int(variant)}:
         return None
     return float(m_bytes.group(1))
 
@@ -694,9 +700,12 @@ def main() -> int:
     elapsed_t = time.perf_counter() - t1
 
     per, dom = class_rooflines(plan_t, [(0, iters_t)], args.scheme != "basic")
-    # the counter summaries were taken on the default schedule of every pass
-    tuned = any(e["chosen"] and e["variant"] != 0 for e in tune)
-    traffic = None if tuned else measured_traffic(dom, args.workload, args.prec)
+    # the counter summary counts only if it measured the variant this run
+    # uses for the dominant pass (the default where nothing was tuned)
+    kind = {"green": "outer", "xpass": "x", "ypass": "y"}.get(dom)
+    axis = {"outer": wl["shape"][0], "y": wl["shape"][-2], "x": wl["shape"][-1]}.get(kind)
+    used = next((e["variant"] for e in tune if e["chosen"] and e["kind"] == kind and e["len"] == axis), 0)
+    traffic = measured_traffic(dom, args.workload, args.prec, used) if kind else None
     # whole solve: algorithmic bytes of every solver kernel per iteration
     # times the iterations, over the wall time of the graph region (host
     # polls, setup, FP64 correction and materialization included)
