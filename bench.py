@@ -703,9 +703,10 @@ def main() -> int:
     # the counter summary counts only if it measured the variant this run
     # uses for the dominant pass (the default where nothing was tuned)
     kind = {"green": "outer", "xpass": "x", "ypass": "y"}.get(dom)
-    axis = {"outer": wl["shape"][0], "y": wl["shape"][-2], "x": wl["shape"][-1]}.get(kind)
-    used = next((e["variant"] for e in tune if e["chosen"] and e["kind"] == kind and e["len"] == axis), 0)
-    traffic = measured_traffic(dom, args.workload, args.prec, used) if kind else None
+    traffic = None
+    if kind is not None and len(wl["shape"]) == 3:
+        axis = {"outer": wl["shape"][0], "y": wl["shape"][1], "x": wl["shape"][2]}[kind]
+        traffic = measured_traffic(dom, args.workload, args.prec, plan_t.schedule(kind, axis)[0])
     # whole solve: algorithmic bytes of every solver kernel per iteration
     # times the iterations, over the wall time of the graph region (host
     # polls, setup, FP64 correction and materialization included)
