@@ -111,3 +111,28 @@ def test_fp32_refined_256_against_the_verified_fp64_solution(setup, gpu_results)
     np.testing.assert_allclose(O.to_voigt(O.stress(O.from_voigt(r32["eps"], 3), lam, mu)), r32["sig"], rtol=0,
                                atol=2e-6 * np.abs(r32["sig"]).max())
     assert compatibility_error(r32["eps"], r32["u"]) < 1e-5
+
+
+@pytest.mark.parametrize("scheme", ["cg", "cg_plain", "anderson"])
+def test_other_schemes_256_against_the_verified_fp64_solution(setup, gpu_results, scheme):
+    """The Krylov and accelerated schemes at the full 256^3 contrast-100 size
+    (FP32 inner solves with the FP64 correction, default schedules): FP64
+    residual <= 1e-8 as reported and as recomputed on the host from the
+    returned stress (to the FP32 rounding of the field), strain within 1e-6
+    of the basic scheme's verified FP64 solution."""
+    torch, dev, phase, f, lame = setup
+    from paper_2601_00822_amd import Plan
+    r64, _ = gpu_results["f64"]
+    say(f"256^3 contrast-100 solve, scheme {scheme}, fp32 + fp64 correction")
+    plan = Plan([SHAPE], prec="f32", refine=True, scheme=scheme)
+    res, rep = plan.solve(torch.from_numpy(phase).to(dev), lame, torch.from_numpy(f).to(dev).float(), tol=1e-8)
+    torch.cuda.synchronize()
+    out = {k: v.double().cpu().numpy() for k, v in res.items()}
+    plan.close()
+    err = O.relative_strain_error_voigt(out["eps"], r64["eps"])
+    r = independent_residual(phase, lame, f, out["sig"])
+    print(f"{scheme}: status={rep.status} iters={rep.iters} residual={rep.residual:.3e}; host residual of the "
+          f"fp32 fields {r:.3e}; strain err {err:.3e} against the fp64 basic solution", flush=True)
+    assert rep.status == 0 and rep.residual <= 1e-8
+    assert err < 1e-6
+    assert r < 2e-4
