@@ -432,11 +432,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, prec: str, variant: int = 0):
+def measured_traffic(kernel: str, workload: str, prec: str, variant: int = 0, layout: str = "blocked"):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources and on the schedule variant the
+    was taken on the current kernel sources, on the schedule variant the
     timed run uses for that pass (every counter pass of the summary names
-    its kernel, whose last template argument is the variant); else None."""
+    its kernel, whose last template argument is the variant) and on the same
+    spectral layout ("rows" or "blocked"); else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}_counters.md")
     if not os.path.exists(path):
         return None
@@ -448,6 +449,9 @@ def measured_traffic(kernel: str, workload: str, prec: str, variant: int = 0):
     line = next((ln for ln in text.splitlines() if ln.startswith("Kernel:")), "")
     measured = {int(v) for v in re.findall(r"k_%s<[^>]*?(\d+)>" % kernel, line)}
     if measured != {int(variant)}:
+        return None
+    m_lay = re.search(r"spectral_layout:\s*(\w+)", text)
+    if not m_lay or m_lay.group(1) != layout:
         return None
     return float(m_bytes.group(1))
 
@@ -706,7 +710,8 @@ def main() -> int:
     traffic = None
     if kind is not None and len(wl["shape"]) == 3:
         axis = {"outer": wl["shape"][0], "y": wl["shape"][1], "x": wl["shape"][2]}[kind]
-        traffic = measured_traffic(dom, args.workload, args.prec, plan_t.schedule(kind, axis)[0])
+        layout = "blocked" if plan_t.schedule("layout", 0)[0] == 1 else "rows"
+        traffic = measured_traffic(dom, args.workload, args.prec, plan_t.schedule(kind, axis)[0], layout)
     # whole solve: algorithmic bytes of every solver kernel per iteration
     # times the iterations, over the wall time of the graph region (host
     # polls, setup, FP64 correction and materialization included)

@@ -433,22 +433,37 @@ lsfft_status lsfft_iteration_bytes(lsfft_plan_t p, int grid_idx, int kernel_clas
  * pass: default, row tiles of half the entries, the other radix order).
  * Every variant computes the same transforms; results differ only by
  * rounding order.
+ *
+ * Kind 3 is the spectral layout of one grid, `len` being the grid's index
+ * in the plan: variant 0 keeps the spectra in rows of nx/2 entries
+ * throughout; variant 1 (the default, for 3D grids with nx a multiple of
+ * 16) keeps them between the y and outer passes in 8-wide kx blocks, entry
+ * (kx, y, z) at ((kx/8) ny + y) 8 nz + 8 z + kx mod 8, so that each outer
+ * transform tile reads and writes contiguous blocks; the y passes then
+ * convert between the two layouts out of place, and each such solve holds
+ * s + d more spectral components of workspace.  Other grids have variant 0
+ * only.  The layout changes addressing only: a basic-scheme solve's fields
+ * are bit for bit the same under both (the residual sums, taken in another
+ * tile order, may differ in the last bits).
  */
 typedef struct {
-  int kind;       /* 0 x pass, 1 y pass, 2 outer pass */
-  int len;        /* transform length */
+  int kind;       /* 0 x pass, 1 y pass, 2 outer pass, 3 spectral layout */
+  int len;        /* transform length; for kind 3 the grid's index in the plan */
   int variant;
   int chosen;     /* 1 for the variant the plan now uses */
-  double us;      /* mean kernel time per launch in microseconds, summed over the plan's grids sharing that length */
+  double us;      /* mean kernel time per launch in microseconds, summed over the plan's grids sharing that length;
+                     kind 3: kernel time of the x, y and outer passes per iteration of the tuning batch */
 } lsfft_tune_entry;
 
 /* Current variant and number of variants of one pass of the plan's 3D (or
- * 2D) grids on an axis of `len` points.  LSFFT_E_ARG for a bad kind,
- * dimension or unsupported length. */
+ * 2D) grids on an axis of `len` points (kind 3: of the layout of grid
+ * `len`, whose dimension must be `dim`).  LSFFT_E_ARG for a bad kind,
+ * dimension, unsupported length or grid index. */
 lsfft_status lsfft_schedule_get(lsfft_plan_t p, int dim, int kind, int len, int* variant, int* nvariants);
 
 /* Select a variant explicitly (0 <= variant < nvariants, else LSFFT_E_ARG);
- * applies to the plan's later solves.  2D grids keep variant 0. */
+ * applies to the plan's later solves (kind 3: to its FP64 companion's too).
+ * 2D grids keep variant 0. */
 lsfft_status lsfft_schedule_set(lsfft_plan_t p, int dim, int kind, int len, int variant);
 
 /*
@@ -456,26 +471,33 @@ lsfft_status lsfft_schedule_set(lsfft_plan_t p, int dim, int kind, int len, int 
  * keep the fastest per pass kind and length.  For each distinct 3D grid a
  * batch of identical synthetic solves (two phases of Young's contrast 10 in
  * 8-voxel blocks, a deterministic pseudo-random force; as many solves as
- * fill about 8 M voxels, at most the plan's max_batch, so a plan of one
+ * fill about 64 M voxels, at most the plan's max_batch, so a plan of one
  * solve is tuned on one solve) runs `iters` iterations (1..10000) once per
  * variant round with every launch timed by a HIP event pair; each pass kind
- * is judged by its own mean kernel time per launch.  The plan's own
- * precision and scheme are used (FP32 inner solves for LSFFT_REFINE64).
+ * is judged by its own mean kernel time per launch.  A grid that has two
+ * spectral layouts runs its rounds under each; it keeps the layout whose
+ * fastest variants give the smaller kernel time of the x, y and outer
+ * passes per iteration, and the variants are chosen on the times under the
+ * chosen layouts.  The plan's own precision and scheme are used (FP32 inner
+ * solves for LSFFT_REFINE64).
  *  cache_path  NULL, or a file to merge the choices into: a flat JSON object
- *              {"f32/3d/outer/256": 2, ...}; lsfft_plan reads the file named
- *              by the environment variable LSFFT_TUNE_CACHE and applies the
- *              entries matching its grids
+ *              {"f32/3d/outer/256": 2, "f32/3d/layout/256x256x256": 1, ...}
+ *              (layouts keyed by nx x ny x nz); lsfft_plan reads the file
+ *              named by the environment variable LSFFT_TUNE_CACHE and applies
+ *              the entries matching its grids
  *  out         host [max_out] or NULL: every variant timed (kind, length,
  *              variant, chosen flag, microseconds), *nout entries in all
  * Allocates device memory for the synthetic inputs; synchronises the plan's
  * stream.  LSFFT_E_ARG for bad arguments or a cache file that cannot be
- * written.  FP64 plans and 2D grids have nothing to tune (*nout = 0).
+ * written.  FP64 plans and 2D grids have nothing to tune (*nout = 0; FP64
+ * plans keep the default layout).
  */
 lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, lsfft_tune_entry* out, int max_out,
                             int* nout);
 
-/* The cached variant for (precision, dimension, kind, length) in the text of
- * a schedule cache, or -1 if there is no valid entry (host only, no GPU). */
+/* The cached variant for (precision, dimension, kind 0..2, length) in the
+ * text of a schedule cache, or -1 if there is no valid entry (host only, no
+ * GPU). */
 int lsfft_tune_cache_lookup(const char* json_text, int prec, int dim, int kind, int len);
 
 #ifdef __cplusplus

@@ -214,6 +214,15 @@ __device__ __forceinline__ void stc(void* base, unsigned i, T re, T im) {
   const unsigned off = i * (unsigned)sizeof(V);
   *reinterpret_cast<LSFFT_GLOBAL V*>((LSFFT_GLOBAL char*)base + off) = v;
 }
+// the same store, marked non-temporal (streamed past the caches)
+template <typename T>
+__device__ __forceinline__ void stc_nt(void* base, unsigned i, T re, T im) {
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  V2 v;
+  v.x = re;
+  v.y = im;
+  __builtin_nontemporal_store(v, reinterpret_cast<LSFFT_GLOBAL V2*>((LSFFT_GLOBAL char*)base + (size_t)i * sizeof(V2)));
+}
 template <typename T>
 __device__ __forceinline__ const char* cptr(const void* base, long long comp_stride, int c) {
   return static_cast<const char*>(base) + (size_t)c * comp_stride * sizeof(T) * 2;
@@ -1037,13 +1046,39 @@ __device__ __forceinline__ void xpass_item(const InstDesc& D, int local, const d
 // A tile is MP pencils of length N: mpk consecutive kx columns times MP / mpk
 // consecutive lines of the other axis.  Element (m, n) of component c lives
 // at c Pc + off(m) + n sn.
+// Index of spectrum entry (kx, ky, kz) in the layout of D (rows of H
+// entries, or 8-wide kx blocks), and the inverse.
+__device__ __forceinline__ long long spec_at(const InstDesc& D, int kx, int ky, int kz) {
+  if (D.blk) return ((long long)(kx >> 3) * D.ny + ky) * D.bls + kz * 8 + (kx & 7);
+  return ((long long)kz * D.ny + ky) * D.H + kx;
+}
+__device__ __forceinline__ void spec_coords(const InstDesc& D, long long g, int& kx, int& ky, int& kz) {
+  if (D.blk) {
+    const long long line = g / D.bls, w = g - line * D.bls;
+    const long long b = line / D.ny;
+    kx = int(b * 8 + (w & 7));
+    ky = int(line - b * D.ny);
+    kz = int(w >> 3);
+  } else {
+    kx = int(g % D.H);
+    const long long rest = g / D.H;
+    ky = int(rest % D.ny);
+    kz = int(rest / D.ny);
+  }
+}
+
 struct TileAddr {
   int sn;              // stride along the pencil (elements)
   int base;            // offset of pencil 0 within a component
   int so;              // stride between lines of the other axis
   int mpk, lg;         // kx pencils per line (power of 2), log2
   int kx0, o0, nother; // first kx, first line, lines in the grid
-  __device__ __forceinline__ int off(int m) const { return base + (m >> lg) * so + (m & (mpk - 1)); }
+  int bs = 0;          // kx-blocked layout: stride of 8-wide kx blocks (0: rows)
+  __device__ __forceinline__ int off(int m) const {
+    if (bs == 0) return base + (m >> lg) * so + (m & (mpk - 1));
+    const int k = kx0 + (m & (mpk - 1));
+    return base + (k >> 3) * bs + (o0 + (m >> lg)) * so + (k & 7);
+  }
   __device__ __forceinline__ bool valid(int m) const { return o0 + (m >> lg) < nother; }
   __device__ __forceinline__ int kx(int m) const { return kx0 + (m & (mpk - 1)); }
   __device__ __forceinline__ int other(int m) const { return o0 + (m >> lg); }
@@ -1064,6 +1099,15 @@ __device__ __forceinline__ TileAddr ytile(const InstDesc& D, int local, int MP) 
   t.base = t.o0 * t.so + t.kx0;
   return t;
 }
+// the same y tile in the kx-blocked layout: pencil stride bls, z lines 8 apart
+__device__ __forceinline__ TileAddr ytile_blk(const InstDesc& D, int local, int MP) {
+  TileAddr t = ytile(D, local, MP);
+  t.sn = D.bls;
+  t.so = 8;
+  t.bs = D.ny * D.bls;
+  t.base = 0;
+  return t;
+}
 
 // outer pass: pencils along z (3D, other axis y) or y (2D, no other axis)
 template <int DIM>
@@ -1073,13 +1117,31 @@ __device__ __forceinline__ TileAddr gtile(const InstDesc& D, int local, int MP) 
   t.lg = D.lg_g;
   if constexpr (DIM == 3) {
     const int per = MP >> D.lg_g;
-    const int ty = local / D.ntk_g, tk = local - (local / D.ntk_g) * D.ntk_g;
-    t.kx0 = tk * D.mpk_g;
-    t.o0 = ty * per;
-    t.nother = D.ny;
-    t.sn = D.ny * D.H;
-    t.so = D.H;
-    t.base = t.o0 * D.H + t.kx0;
+    if (D.blk) {
+      // kx-blocked: consecutive tiles cover consecutive y lines of one kx
+      // block (each line an 8 x nz block of the layout; tiles narrower than
+      // 8 kx take the parts of a line in turn)
+      const int nty = (D.ny + per - 1) / per;
+      const int sb = D.mpk_g < 8 ? 8 / D.mpk_g : 1;
+      const int wk = D.mpk_g < 8 ? 8 : D.mpk_g;
+      const int kg = local / (nty * sb), rem = local - kg * (nty * sb);
+      const int ty = rem / sb, sub = rem - ty * sb;
+      t.kx0 = kg * wk + sub * D.mpk_g;
+      t.o0 = ty * per;
+      t.nother = D.ny;
+      t.sn = 8;
+      t.so = D.bls;
+      t.bs = D.ny * D.bls;
+      t.base = 0;
+    } else {
+      const int ty = local / D.ntk_g, tk = local - (local / D.ntk_g) * D.ntk_g;
+      t.kx0 = tk * D.mpk_g;
+      t.o0 = ty * per;
+      t.nother = D.ny;
+      t.sn = D.ny * D.H;
+      t.so = D.H;
+      t.base = t.o0 * D.H + t.kx0;
+    }
   } else {
     t.kx0 = local * D.mpk_g;
     t.o0 = 0;
@@ -1092,8 +1154,8 @@ __device__ __forceinline__ TileAddr gtile(const InstDesc& D, int local, int MP) 
 }
 
 template <typename T, int NY, int DIR, int V>
-__device__ void ypass_item(const InstDesc& D, int local, int c, void* buf, const T* __restrict__ twtab,
-                           unsigned char* smem) {
+__device__ void ypass_item(const InstDesc& D, int local, int c, const void* src, void* dst,
+                           const T* __restrict__ twtab, unsigned char* smem) {
   constexpr int NTH = Cfg<T>::NTH;
   constexpr int MP = YSched<T, NY, V>::MP;
   using PR = PencilRows<T, NY, MP>;
@@ -1109,8 +1171,12 @@ __device__ void ypass_item(const InstDesc& D, int local, int c, void* buf, const
   const int tid = threadIdx.x;
   load_tw<T, NY, NTH>(twr, twi, twtab, tid);
   __syncthreads();
-  const TileAddr t = ytile(D, local, MP);
-  char* cb = mptr<T>(buf, D.Pc, c);
+  // kx-blocked spectra: the forward transforms leave the row layout for the
+  // blocked one, the inverse transforms come back (out of place)
+  const TileAddr t = (D.blk && DIR > 0) ? ytile_blk(D, local, MP) : ytile(D, local, MP);
+  const TileAddr td = (D.blk && DIR < 0) ? ytile_blk(D, local, MP) : ytile(D, local, MP);
+  const char* cb = cptr<T>(src, D.Pc, c);
+  char* db = mptr<T>(dst, D.Pc, c);
   T in_r[F::B0][F::R0], in_i[F::B0][F::R0];
 #pragma unroll
   for (int q = 0; q < F::B0; ++q) {
@@ -1138,11 +1204,17 @@ __device__ void ypass_item(const InstDesc& D, int local, int c, void* buf, const
     const int b = tid + q * NTH;
     int m, j;
     F::template bj<F::RL>(b, m, j);
-    if ((F::TOTL % NTH == 0 || b < F::TOTL) && t.valid(m)) {
-      const int o = t.off(m);
+    if ((F::TOTL % NTH == 0 || b < F::TOTL) && td.valid(m)) {
+      const int o = td.off(m);
+      if (D.blk) {
 #pragma unroll
-      for (int r = 0; r < F::RL; ++r)
-        stc<T>(cb, o + (j + r * (NY / F::RL)) * t.sn, o_r[q][r], o_i[q][r]);
+        for (int r = 0; r < F::RL; ++r)
+          stc_nt<T>(db, o + (j + r * (NY / F::RL)) * td.sn, o_r[q][r], o_i[q][r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < F::RL; ++r)
+          stc<T>(db, o + (j + r * (NY / F::RL)) * td.sn, o_r[q][r], o_i[q][r]);
+      }
     }
   }
 }
@@ -1182,6 +1254,8 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
 
   const TileAddr t = gtile<DIM>(D, local, MP);
   const long long Pc = D.Pc;
+  // spectra between the y passes and this one: kx-blocked copies, or in place
+  void* const SS = D.blk ? D.S2 : D.S;
   const T inv_n = T(D.inv_nvox);
   const T mu0 = T(D.mu0);
   const T c0 = T((D.lam0 + D.mu0) / (D.lam0 + 2.0 * D.mu0));
@@ -1295,9 +1369,15 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
         FI::template bj<FI::RL>(b, m, j);
         if ((FI::TOTL % NTH == 0 || b < FI::TOTL) && t.valid(m)) {
           const int o = t.off(m);
+          if (D.blk) {
 #pragma unroll
-          for (int r = 0; r < FI::RL; ++r)
-            stc<T>(cb, o + (j + r * (NG / FI::RL)) * t.sn, o_r[q][r], o_i[q][r]);
+            for (int r = 0; r < FI::RL; ++r)
+              stc_nt<T>(cb, o + (j + r * (NG / FI::RL)) * t.sn, o_r[q][r], o_i[q][r]);
+          } else {
+#pragma unroll
+            for (int r = 0; r < FI::RL; ++r)
+              stc<T>(cb, o + (j + r * (NG / FI::RL)) * t.sn, o_r[q][r], o_i[q][r]);
+          }
         }
       }
     }
@@ -1344,7 +1424,7 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
 
   if constexpr (MODE == M_FT) {
     // finish the force transform, record the removed mean, project off Z
-    forward_all(D.F, std::integral_constant<int, DIM>{}, [&](int c, int q, int r, T re, T im) {
+    forward_all(D.blk ? D.S2 : D.F, std::integral_constant<int, DIM>{}, [&](int c, int q, int r, T re, T im) {
       vr[c][q][r] = re;
       vi[c][q][r] = im;
     });
@@ -1369,7 +1449,7 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
   } else if constexpr (MODE == M_INIT || MODE == M_ITER || MODE == M_CG_INIT) {
     zero_v();
     if constexpr (MODE != M_INIT) {
-      forward_all(D.S, std::integral_constant<int, S>{},
+      forward_all(SS, std::integral_constant<int, S>{},
                   [&](int c, int q, int r, T re, T im) { div_acc(c, q, r, re, im, T(1)); });
     }
 #pragma unroll
@@ -1440,7 +1520,7 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
         }
       }
     }
-    inverse_all(D.S, 0, std::integral_constant<int, S>{}, strain_gen);
+    inverse_all(SS, 0, std::integral_constant<int, S>{}, strain_gen);
   } else if constexpr (MODE == M_MAT) {
 #pragma unroll
     for (int q = 0; q < BP; ++q)
@@ -1457,8 +1537,8 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
           vr[a][q][r] = re;
           vi[a][q][r] = im;
         }
-    inverse_all(D.S, 0, std::integral_constant<int, S>{}, strain_gen);
-    inverse_all(D.S, S, std::integral_constant<int, DIM>{}, [&](int c, int q, int r, T& re, T& im) {
+    inverse_all(SS, 0, std::integral_constant<int, S>{}, strain_gen);
+    inverse_all(SS, S, std::integral_constant<int, DIM>{}, [&](int c, int q, int r, T& re, T& im) {
       re = vr[c][q][r] * inv_n;
       im = vi[c][q][r] * inv_n;
     });
@@ -1466,7 +1546,7 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
   } else if constexpr (MODE == M_CG_AP) {
     // q = A p = -i xi . sigma^(p): stored, and the partial p.q
     zero_v();
-    forward_all(D.S, std::integral_constant<int, S>{},
+    forward_all(SS, std::integral_constant<int, S>{},
                 [&](int c, int q, int r, T re, T im) { div_acc(c, q, r, re, im, T(-1)); });
 #pragma unroll
     for (int q = 0; q < BP; ++q) {
@@ -1515,7 +1595,7 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
         }
       }
     }
-    inverse_all(D.S, 0, std::integral_constant<int, S>{}, strain_gen);
+    inverse_all(SS, 0, std::integral_constant<int, S>{}, strain_gen);
   } else if constexpr (MODE == M_KCONV) {
     // periodic convolution with a kernel given by its half spectrum:
     // eps^_c = sum_j Kh_cj f^_j / |N| from the (projected) force spectrum,
@@ -1548,14 +1628,14 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
       pk0[q] = t.kx(m) == 0;
       pth[q] = t.other(m);
     }
-    inverse_all(D.S, 0, std::integral_constant<int, S>{}, [&](int c, int q, int r, T& re, T& im) {
+    inverse_all(SS, 0, std::integral_constant<int, S>{}, [&](int c, int q, int r, T& re, T& im) {
       re = T(0);
       im = T(0);
       if (!pv[q]) return;
       const int g = gidx(q, r);
       if (pk0[q]) {
         const int n = pj[q] + r * NSTEP;
-        const int gp = (DIM == 3) ? (((D.nz - n) % D.nz) * D.ny + (D.ny - pth[q]) % D.ny) * D.H
+        const int gp = (DIM == 3) ? (int)spec_at(D, 0, (D.ny - pth[q]) % D.ny, (D.nz - n) % D.nz)
                                   : ((D.ny - n) % D.ny) * D.H;
 #pragma unroll
         for (int j = 0; j < DIM; ++j) {
@@ -1592,7 +1672,7 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
     // (k - 1) mod m, F into Fp, and the inner products of the window's dF_j
     // (newest first) with dF and with F.  No inverse transforms.
     zero_v();
-    forward_all(D.S, std::integral_constant<int, S>{},
+    forward_all(SS, std::integral_constant<int, S>{},
                 [&](int c, int q, int r, T re, T im) { div_acc(c, q, r, re, im, T(1)); });
     const int k = St->iter;
     const int m = D.aa_m;
@@ -1711,7 +1791,7 @@ __device__ void green_item(const InstDesc& D, InstState* __restrict__ St, int lo
         }
       }
     }
-    inverse_all(D.S, 0, std::integral_constant<int, S>{}, strain_gen);
+    inverse_all(SS, 0, std::integral_constant<int, S>{}, strain_gen);
     return;
   }
 
@@ -1766,10 +1846,8 @@ __device__ void cg_update_item(const InstDesc& D, InstState* St, int local, unsi
     for (int qq = 0; qq < QB; ++qq) {
       const long long g = (long long)local * NTH * 4 + (q0 + qq) * NTH + tid;
       if (g >= Pc) continue;
-      const int kx = int(g % D.H);
-      const long long rest = g / D.H;
-      const int ky = int(rest % D.ny);
-      const int kz = int(rest / D.ny);
+      int kx, ky, kz;
+      spec_coords(D, g, kx, ky, kz);
       T xi[DIM];
       xi[0] = T(wavenum(kx, D.nx, D.kx));
       xi[1] = T(wavenum(ky, D.ny, D.ky));
@@ -2008,8 +2086,13 @@ __global__ __launch_bounds__(Cfg<T>::NTH) __attribute__((amdgpu_waves_per_eu((YS
         continue;
       }
     }
-    void* buf = (which == 0) ? D.S : D.F;
-    ypass_item<T, NY, DIR, V>(D, it.local, c, buf, tw, smem);
+    void* src = (which == 0) ? D.S : D.F;
+    void* dst = src;
+    if (D.blk) {
+      if (DIR < 0) dst = D.S2;
+      else src = D.S2;
+    }
+    ypass_item<T, NY, DIR, V>(D, it.local, c, src, dst, tw, smem);
     __syncthreads();
   }
 }
@@ -2693,11 +2776,11 @@ __global__ __launch_bounds__(NTR) void k_nl_apply1(NlGeom G, const T* __restrict
 // Wavevector of entry g of the packed half spectrum (xi_x = 0 on the kx = 0
 // column, which also carries the kx = H plane).
 __device__ inline void spectrum_xi(const InstDesc& D, long long g, double xi[3]) {
-  const int kx = int(g % D.H);
-  const long long rest = g / D.H;
+  int kx, ky, kz;
+  spec_coords(D, g, kx, ky, kz);
   xi[0] = wavenum(kx, D.nx, D.kx);
-  xi[1] = wavenum(int(rest % D.ny), D.ny, D.ky);
-  xi[2] = (D.dim == 3) ? wavenum(int(rest / D.ny), D.nz, D.kz) : 0.0;
+  xi[1] = wavenum(ky, D.ny, D.ky);
+  xi[2] = (D.dim == 3) ? wavenum(kz, D.nz, D.kz) : 0.0;
 }
 
 __global__ __launch_bounds__(NTR) void k_widen(const float* __restrict__ src, double* __restrict__ dst, long long n) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -152,6 +153,9 @@ struct lsfft_plan_s {
   // schedule variant per pass kind (0 x, 1 y, 2 outer) and length index,
   // used by FP32 3D solves (lsfft_autotune, lsfft_schedule_set, the cache)
   int sched[3][kNumLens] = {};
+  // spectral layout per grid (index into grids): 1 kx-blocked between the y
+  // and outer passes where the grid allows it, 0 rows throughout
+  std::vector<int> layout;
 };
 
 namespace {
@@ -206,8 +210,13 @@ struct Geometry {
   int var_x, var_y, var_g;   // schedule variants of the three passes
   long long Pm, Pc, nvox;
   int xtiles, items_x, items_xall, items_xft, items_y, mpk_y, ntk_y, items_g, mpk_g, ntk_g, items_cg;
+  int blk;                              // kx-blocked spectra between the y and outer passes
+  int bls;                              // blocked: entries from one y line of a block to the next (8 nz)
   size_t lds_x, lds_xi, lds_y, lds_g;   // lds_xi: x pass of the iteration
 };
+
+// the kx-blocked layout needs a 3D grid with nx a multiple of 16
+bool blocked_layout_ok(const lsfft_grid& g) { return g.dim == 3 && gnx(g) % 16 == 0; }
 
 int ilog2(int v) {
   int l = 0;
@@ -236,7 +245,7 @@ int plan_variant(const int sched[3][kNumLens], bool f64, int dim, int kind, int 
   return (v > 0 && v < schedule_variants(f64, dim, kind, len)) ? v : 0;
 }
 
-bool geometry(bool f64, const lsfft_grid& g, const int sched[3][kNumLens], Geometry* o) {
+bool geometry(bool f64, const lsfft_grid& g, const int sched[3][kNumLens], Geometry* o, int layout) {
   o->dim = g.dim;
   o->nx = (int)gnx(g);
   o->ny = (int)gny(g);
@@ -245,6 +254,8 @@ bool geometry(bool f64, const lsfft_grid& g, const int sched[3][kNumLens], Geome
   o->s = g.dim == 3 ? 6 : 3;
   // kx = 0 and kx = H share one column (packed half spectrum): no Nyquist plane
   o->Pm = (long long)o->nz * o->ny * o->H;
+  o->blk = (layout == 1 && blocked_layout_ok(g)) ? 1 : 0;
+  o->bls = o->blk ? 8 * o->nz : 0;
   o->Pc = o->Pm;
   o->nvox = (long long)o->nz * o->ny * o->nx;
   int mr = 0, mpy = 0, mpg = 0;
@@ -263,7 +274,9 @@ bool geometry(bool f64, const lsfft_grid& g, const int sched[3][kNumLens], Geome
   o->items_xall = o->xtiles * (1 + o->s);                 // + displacement components
   o->items_xft = o->xtiles * o->dim;                      // force components
   if (g.dim == 3) {
-    o->mpk_y = kx_pencils(mpy, o->H);
+    // blocked: at most 16 kx per z line, so that both layouts see runs of
+    // 128 bytes (FP32) or more
+    o->mpk_y = kx_pencils(o->blk ? std::min(mpy, 16) : mpy, o->H);
     const int per = mpy / o->mpk_y;
     o->ntk_y = o->H / o->mpk_y;
     o->items_y = o->ntk_y * ((o->nz + per - 1) / per);
@@ -572,7 +585,7 @@ lsfft_status prepare(Batch& b, bool validate = true) {
   b.state.assign(n, InstState{});
   b.lame.clear();
   for (int i = 0; i < n; ++i) {
-    if (!geometry(f64, p->grids[b.specs[i].grid], p->sched, &b.geo[i])) return LSFFT_E_ARG;
+    if (!geometry(f64, p->grids[b.specs[i].grid], p->sched, &b.geo[i], p->layout[b.specs[i].grid])) return LSFFT_E_ARG;
   }
 
   // workspace layout
@@ -580,11 +593,12 @@ lsfft_status prepare(Batch& b, bool validate = true) {
   const bool aa = p->scheme == LSFFT_ANDERSON;
   const int aam = aa ? p->aa_m : 0;
   std::vector<size_t> o_S(n), o_U0(n), o_U1(n), o_F(n), o_R(n), o_P(n), o_Q(n), o_oe(n), o_ou(n), o_part(n), o_hist(n);
-  std::vector<size_t> o_Fp(n), o_DF(n), o_DU(n), o_aa(n);
+  std::vector<size_t> o_Fp(n), o_DF(n), o_DU(n), o_aa(n), o_S2(n);
   for (int i = 0; i < n; ++i) {
     const Geometry& g = b.geo[i];
     const size_t comp = (size_t)g.Pc * cs;
     o_S[i] = off; off = align_up(off + comp * (g.s + g.dim));
+    if (g.blk) { o_S2[i] = off; off = align_up(off + comp * (g.s + g.dim)); }
     o_U0[i] = off; off = align_up(off + comp * g.dim);
     if (!cg) { o_U1[i] = off; off = align_up(off + comp * g.dim); }
     if (b.specs[i].leader == i) { o_F[i] = off; off = align_up(off + comp * g.dim); }
@@ -695,6 +709,9 @@ lsfft_status prepare(Batch& b, bool validate = true) {
     D.phase = sp.phase;
     D.f_in = sp.f;
     D.S = A + o_S[i];
+    D.blk = g.blk;
+    D.bls = g.bls;
+    D.S2 = g.blk ? (void*)(A + o_S2[i]) : nullptr;
     D.U[0] = A + o_U0[i];
     D.U[1] = cg ? D.U[0] : (void*)(A + o_U1[i]);
     D.F = A + o_F[sp.leader];
@@ -1314,8 +1331,31 @@ bool write_tune_cache(const char* path, const std::map<std::string, int>& m) {
   return ok && std::rename(tmp.c_str(), path) == 0;
 }
 
+// cache key of a grid's spectral layout
+std::string layout_key(bool f64, const lsfft_grid& g) {
+  char buf[96];
+  std::snprintf(buf, sizeof buf, "%s/3d/layout/%lldx%lldx%lld", f64 ? "f64" : "f32", (long long)gnx(g),
+                (long long)gny(g), (long long)gnz(g));
+  return buf;
+}
+
+bool same_shape(const lsfft_grid& a, const lsfft_grid& b) {
+  return a.dim == b.dim && gnx(a) == gnx(b) && gny(a) == gny(b) && gnz(a) == gnz(b);
+}
+
+// layout of grid gi, in the plan and in its FP64 companion
+void set_layout(lsfft_plan_s* p, int gi, int v) {
+  p->layout[gi] = v;
+  if (p->sub) p->sub->layout[gi] = v;
+}
+
 // apply every cache entry that matches one of the plan's grids
 void apply_tune_cache(lsfft_plan_s* p, const std::map<std::string, int>& m) {
+  for (size_t gi = 0; gi < p->grids.size(); ++gi) {
+    if (!blocked_layout_ok(p->grids[gi])) continue;
+    const auto it = m.find(layout_key(p->f64, p->grids[gi]));
+    if (it != m.end() && it->second <= 1) set_layout(p, (int)gi, it->second);
+  }
   for (const lsfft_grid& g : p->grids) {
     const int lens[3] = {(int)gnx(g), (int)gny(g), (int)(g.dim == 3 ? gnz(g) : gny(g))};
     for (int kind = 0; kind < 3; ++kind) {
@@ -1474,6 +1514,7 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
   p->grids.assign(grids, grids + ngrid);
   for (auto& G : p->grids)
     if (G.dim == 2) { G.n[2] = 1; G.h[2] = 1.0; }
+  p->layout.assign(p->grids.size(), 1);
   p->max_batch = max_batch;
   // schedule variants chosen by an earlier lsfft_autotune, if a cache is named
   if (const char* path = std::getenv("LSFFT_TUNE_CACHE")) {
@@ -1504,6 +1545,7 @@ lsfft_status lsfft_plan(lsfft_plan_t* out, const lsfft_grid* grids, int ngrid, i
     q->scheme = LSFFT_BASIC;
     q->flags = flags & LSFFT_STRICT_EQUIL;   // the force check runs on the FP64 force transform
     q->grids = p->grids;
+    q->layout = p->layout;   // the FP64 and FP32 spectra of a solve share one layout
     q->max_batch = p->max_batch;
     p->sub = q;
     if (!upload_twiddles(q)) {
@@ -1796,8 +1838,8 @@ lsfft_status lsfft_iteration_bytes(lsfft_plan_t p, int grid_idx, int kernel_clas
   if (!p || !bytes || grid_idx < 0 || grid_idx >= (int)p->grids.size()) return LSFFT_E_ARG;
   if (kernel_class < 0 || kernel_class >= LSFFT_K_COUNT) return LSFFT_E_ARG;
   Geometry g;
-  if (!geometry(p->f64, p->grids[grid_idx], p->sched, &g)) return LSFFT_E_ARG;
-  const double comp = (double)g.Pc * (p->f64 ? 16.0 : 8.0);  // one complex half-spectrum stream
+  if (!geometry(p->f64, p->grids[grid_idx], p->sched, &g, p->layout[grid_idx])) return LSFFT_E_ARG;
+  const double comp = (double)g.Pm * (p->f64 ? 16.0 : 8.0);  // one complex half-spectrum stream
   const double s = g.s, d = g.dim;
   const bool cg = p->scheme == LSFFT_CG || p->scheme == LSFFT_CG_PLAIN;
   double b = 0.0;
@@ -1826,6 +1868,14 @@ lsfft_status lsfft_iteration_bytes(lsfft_plan_t p, int grid_idx, int kernel_clas
 }
 
 lsfft_status lsfft_schedule_get(lsfft_plan_t p, int dim, int kind, int len, int* variant, int* nvariants) {
+  if (p && kind == 3) {
+    // spectral layout of grid `len`
+    if (len < 0 || len >= (int)p->grids.size() || p->grids[len].dim != dim) return LSFFT_E_ARG;
+    const bool ok = blocked_layout_ok(p->grids[len]);
+    if (variant) *variant = ok ? p->layout[len] : 0;
+    if (nvariants) *nvariants = ok ? 2 : 1;
+    return LSFFT_OK;
+  }
   if (!p || (dim != 2 && dim != 3) || kind < 0 || kind > 2 || len_index(len) < 0) return LSFFT_E_ARG;
   if (variant) *variant = plan_variant(p->sched, p->f64, dim, kind, len);
   if (nvariants) *nvariants = schedule_variants(p->f64, dim, kind, len);
@@ -1833,6 +1883,12 @@ lsfft_status lsfft_schedule_get(lsfft_plan_t p, int dim, int kind, int len, int*
 }
 
 lsfft_status lsfft_schedule_set(lsfft_plan_t p, int dim, int kind, int len, int variant) {
+  if (p && kind == 3) {
+    int cur = 0, nv = 0;
+    if (lsfft_schedule_get(p, dim, kind, len, &cur, &nv) != LSFFT_OK || variant < 0 || variant >= nv) return LSFFT_E_ARG;
+    if (nv == 2) set_layout(p, len, variant);
+    return LSFFT_OK;
+  }
   if (!p || (dim != 2 && dim != 3) || kind < 0 || kind > 2 || len_index(len) < 0) return LSFFT_E_ARG;
   if (variant < 0 || variant >= schedule_variants(p->f64, dim, kind, len)) return LSFFT_E_ARG;
   if (dim == 3) p->sched[kind][len_index(len)] = variant;   // 2D grids have the default only
@@ -1853,9 +1909,6 @@ lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, l
   if (check_plan(p) != LSFFT_OK || iters < 1 || iters > 10000 || max_out < 0 || (max_out > 0 && !out)) return LSFFT_E_ARG;
   if (nout) *nout = 0;
   if (enter(p) != LSFFT_OK) return LSFFT_E_DEVICE;
-  // kernel time per launch of every variant, keyed by (kind, length) and
-  // summed over the plan's grids that share that pass length
-  std::map<std::pair<int, int>, std::vector<double>> times;
   const size_t rs = p->f64 ? 8 : 4;
   // the tuning problem: two phases (E = 1 and 10, nu = 0.3) in a pattern of
   // 8-voxel blocks, a deterministic pseudo-random force, `iters` iterations
@@ -1863,28 +1916,36 @@ lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, l
   const double e_nu[4] = {1.0, 0.3, 10.0, 0.3};
   if (lsfft_lame_from_young(2, e_nu, lame) != LSFFT_OK) return LSFFT_E_ARG;
   lsfft_phases tab{2, lame};
+  // the distinct 3D grids, each with its synthetic inputs on the device
+  struct TuneGrid {
+    int gi;
+    void* ph = nullptr;
+    void* f = nullptr;
+  };
+  std::vector<TuneGrid> tg;
+  struct Release {
+    std::vector<TuneGrid>* v;
+    ~Release() {
+      for (auto& t : *v) {
+        if (t.ph) (void)hipFree(t.ph);
+        if (t.f) (void)hipFree(t.f);
+      }
+    }
+  } release{&tg};
   for (size_t gi = 0; gi < p->grids.size(); ++gi) {
     const lsfft_grid& g = p->grids[gi];
     if (g.dim != 3) continue;
     bool seen = false;
-    for (size_t gj = 0; gj < gi; ++gj)
-      seen = seen || (p->grids[gj].dim == 3 && p->grids[gj].n[0] == g.n[0] && p->grids[gj].n[1] == g.n[1] &&
-                      p->grids[gj].n[2] == g.n[2]);
+    for (const auto& t : tg) {
+      const lsfft_grid& h = p->grids[t.gi];
+      seen = seen || (h.n[0] == g.n[0] && h.n[1] == g.n[1] && h.n[2] == g.n[2]);
+    }
     if (seen) continue;
     const int lens[3] = {(int)gnx(g), (int)gny(g), (int)gnz(g)};
-    int nv[3], rounds = 1;
-    for (int k = 0; k < 3; ++k) {
-      nv[k] = schedule_variants(p->f64, 3, k, lens[k]);
-      rounds = std::max(rounds, nv[k]);
-    }
-    if (rounds == 1) continue;
+    bool tuned = !p->f64 && blocked_layout_ok(g);   // FP64 plans keep the default layout
+    for (int k = 0; k < 3; ++k) tuned = tuned || schedule_variants(p->f64, 3, k, lens[k]) > 1;
+    if (!tuned) continue;
     const long long nvox = (long long)lens[0] * lens[1] * lens[2];
-    // Solves of this grid per tuning launch: as many as fill about 8 M
-    // voxels, within the plan's batch size, as a batch of the plan's size
-    // would.  A single solve of a small grid leaves most of the 256 CUs idle
-    // and times the launch latency instead of the pass (at 96^3 it ranked
-    // the tiles the other way round).  They share one force spectrum.
-    const int nrep = (int)std::max(1LL, std::min((long long)p->max_batch, (8LL << 20) / nvox));
     std::vector<uint8_t> hph((size_t)nvox);
     std::vector<double> hf(3 * (size_t)nvox);
     unsigned long long st = 0x9e3779b97f4a7c15ull;
@@ -1896,68 +1957,138 @@ lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, l
       st = st * 6364136223846793005ull + 1442695040888963407ull;
       q = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
     }
-    void *dph = nullptr, *df = nullptr;
-    if (hipMalloc(&dph, (size_t)nvox) != hipSuccess) return LSFFT_E_ALLOC;
-    if (hipMalloc(&df, 3 * (size_t)nvox * rs) != hipSuccess) {
-      (void)hipFree(dph);
+    tg.push_back(TuneGrid{(int)gi});
+    TuneGrid& t = tg.back();
+    if (hipMalloc(&t.ph, (size_t)nvox) != hipSuccess || hipMalloc(&t.f, 3 * (size_t)nvox * rs) != hipSuccess)
       return LSFFT_E_ALLOC;
-    }
-    hipError_t he = hipMemcpy(dph, hph.data(), (size_t)nvox, hipMemcpyHostToDevice);
+    hipError_t he = hipMemcpy(t.ph, hph.data(), (size_t)nvox, hipMemcpyHostToDevice);
     if (he == hipSuccess) {
       if (p->f64) {
-        he = hipMemcpy(df, hf.data(), 3 * (size_t)nvox * rs, hipMemcpyHostToDevice);
+        he = hipMemcpy(t.f, hf.data(), 3 * (size_t)nvox * rs, hipMemcpyHostToDevice);
       } else {
         std::vector<float> ff(hf.begin(), hf.end());
-        he = hipMemcpy(df, ff.data(), 3 * (size_t)nvox * rs, hipMemcpyHostToDevice);
+        he = hipMemcpy(t.f, ff.data(), 3 * (size_t)nvox * rs, hipMemcpyHostToDevice);
       }
     }
-    lsfft_status ls = he == hipSuccess ? LSFFT_OK : LSFFT_E_DEVICE;
+    if (he != hipSuccess) return LSFFT_E_DEVICE;
+  }
+  // `iters` timed iterations of a batch of identical solves of one grid with
+  // the plan's current schedules and layouts: as many solves as fill about
+  // 64 M voxels, within the plan's batch size, as a batch of the plan's size
+  // would.  A single solve of a small grid leaves most of the 256 CUs idle
+  // and times the launch latency instead of the pass (at 96^3 it ranked the
+  // tiles the other way round), and a batch whose spectra fit the 256 MB
+  // Infinity Cache ranks the layouts differently from one that streams from
+  // HBM (at 96^3, 9 solves favoured rows, the 64 of a 512-solve batch the
+  // blocked layout).  They share one force spectrum.  The kernel times are
+  // left in kt_ms.
+  auto time_grid = [&](const TuneGrid& t) -> lsfft_status {
+    const lsfft_grid& g = p->grids[t.gi];
+    const long long nvox = gnx(g) * gny(g) * gnz(g);
+    const int nrep = (int)std::max(1LL, std::min((long long)p->max_batch, (64LL << 20) / nvox));
+    Batch b;
+    b.p = p;
+    b.tol = 1e-300;
+    b.max_iter = iters;
+    Spec sp;
+    sp.grid = t.gi;
+    sp.phase = static_cast<const uint8_t*>(t.ph);
+    sp.tab = &tab;
+    (void)resolve_ref(&tab, nullptr, &sp.lam0, &sp.mu0);
+    sp.f = t.f;
+    sp.leader = 0;
+    for (int k = 0; k < nrep; ++k) {
+      sp.out_index = k;
+      b.specs.push_back(sp);
+    }
+    std::vector<lsfft_report> reps((size_t)nrep);
+    lsfft_kernel_times_reset(p);
+    p->force_timing = true;
+    const lsfft_status rs_ = run_batch(b, reps.data(), now_s());
+    p->force_timing = false;
+    if (rs_ == LSFFT_E_ARG || rs_ == LSFFT_E_ALLOC || rs_ == LSFFT_E_DEVICE) return rs_;
+    return LSFFT_OK;
+  };
+  // Per grid and layout (the kx-blocked one first, then rows, where the
+  // grid has both; FP64 plans keep theirs), one round per variant index with
+  // every pass of the grid on that variant (or its default where it has
+  // fewer): kernel ms per iteration of each pass kind.
+  const int cls[3] = {LSFFT_K_XPASS, LSFFT_K_YPASS, LSFFT_K_GREEN};
+  const double per_iter[3] = {1.0, 2.0, p->scheme == LSFFT_BASIC ? 1.0 : 2.0};   // CG, Anderson: two outer launches
+  struct GridTimes {
+    int nl = 1, lay[2] = {0, 0}, nv[3] = {1, 1, 1}, lens[3] = {0, 0, 0}, rounds = 1;
+    std::vector<std::array<double, 3>> ms[2];
+  };
+  std::vector<GridTimes> gt(tg.size());
+  for (size_t ti = 0; ti < tg.size(); ++ti) {
+    const TuneGrid& t = tg[ti];
+    GridTimes& G = gt[ti];
+    const lsfft_grid& g = p->grids[t.gi];
+    G.lens[0] = (int)gnx(g);
+    G.lens[1] = (int)gny(g);
+    G.lens[2] = (int)gnz(g);
+    for (int k = 0; k < 3; ++k) {
+      G.nv[k] = schedule_variants(p->f64, 3, k, G.lens[k]);
+      G.rounds = std::max(G.rounds, G.nv[k]);
+    }
+    const bool two = !p->f64 && blocked_layout_ok(g);
+    G.nl = two ? 2 : 1;
+    G.lay[0] = two ? 1 : p->layout[t.gi];
     int keep[3];
-    for (int k = 0; k < 3; ++k) keep[k] = p->sched[k][len_index(lens[k])];
-    for (int r = 0; r < rounds && ls == LSFFT_OK; ++r) {
-      for (int k = 0; k < 3; ++k) p->sched[k][len_index(lens[k])] = r < nv[k] ? r : 0;
-      Batch b;
-      b.p = p;
-      b.tol = 1e-300;
-      b.max_iter = iters;
-      Spec sp;
-      sp.grid = (int)gi;
-      sp.phase = static_cast<const uint8_t*>(dph);
-      sp.tab = &tab;
-      (void)resolve_ref(&tab, nullptr, &sp.lam0, &sp.mu0);
-      sp.f = df;
-      sp.leader = 0;
-      for (int k = 0; k < nrep; ++k) {
-        sp.out_index = k;
-        b.specs.push_back(sp);
-      }
-      std::vector<lsfft_report> reps((size_t)nrep);
-      lsfft_kernel_times_reset(p);
-      p->force_timing = true;
-      const lsfft_status rs_ = run_batch(b, reps.data(), now_s());
-      p->force_timing = false;
-      if (rs_ == LSFFT_E_ARG || rs_ == LSFFT_E_ALLOC || rs_ == LSFFT_E_DEVICE) {
-        ls = rs_;
-        break;
-      }
-      const int cls[3] = {LSFFT_K_XPASS, LSFFT_K_YPASS, LSFFT_K_GREEN};
-      const double per_iter[3] = {1.0, 2.0, p->scheme == LSFFT_BASIC ? 1.0 : 2.0};   // CG, Anderson: two outer launches
-      for (int k = 0; k < 3; ++k) {
-        if (r >= nv[k] || nv[k] == 1) continue;   // passes with the default only are not tuned
-        auto& v = times[{k, lens[k]}];
-        if ((int)v.size() < nv[k]) v.resize(nv[k], 0.0);
-        v[r] += 1e3 * p->kt_ms[cls[k]] / (per_iter[k] * iters);
+    for (int k = 0; k < 3; ++k) keep[k] = p->sched[k][len_index(G.lens[k])];
+    lsfft_status ls = LSFFT_OK;
+    for (int l = 0; l < G.nl && ls == LSFFT_OK; ++l) {
+      for (size_t gj = 0; gj < p->grids.size(); ++gj)
+        if (same_shape(p->grids[gj], g)) set_layout(p, (int)gj, G.lay[l]);
+      G.ms[l].assign(G.rounds, std::array<double, 3>{0.0, 0.0, 0.0});
+      for (int r = 0; r < G.rounds; ++r) {
+        for (int k = 0; k < 3; ++k) p->sched[k][len_index(G.lens[k])] = r < G.nv[k] ? r : 0;
+        if ((ls = time_grid(t)) != LSFFT_OK) break;
+        for (int k = 0; k < 3; ++k) G.ms[l][r][k] = p->kt_ms[cls[k]] / iters;
       }
     }
-    for (int k = 0; k < 3; ++k) p->sched[k][len_index(lens[k])] = keep[k];
-    (void)hipFree(dph);
-    (void)hipFree(df);
+    for (int k = 0; k < 3; ++k) p->sched[k][len_index(G.lens[k])] = keep[k];
     lsfft_kernel_times_reset(p);
     if (ls != LSFFT_OK) return ls;
   }
-  // keep the fastest variant per (kind, length)
+  // Layout per grid: the smaller kernel time of the three passes per
+  // iteration, each pass on its fastest variant under that layout (ties go
+  // to the blocked layout).
   std::map<std::string, int> chosen;
+  std::vector<int> li(tg.size(), 0);
   int n = 0;
+  std::vector<lsfft_tune_entry> lay_rows;
+  for (size_t ti = 0; ti < tg.size(); ++ti) {
+    const GridTimes& G = gt[ti];
+    const lsfft_grid& g = p->grids[tg[ti].gi];
+    double cost[2] = {0.0, 0.0};
+    for (int l = 0; l < G.nl; ++l)
+      for (int k = 0; k < 3; ++k) {
+        double best = G.ms[l][0][k];
+        for (int r = 1; r < G.nv[k]; ++r) best = std::min(best, G.ms[l][r][k]);
+        cost[l] += best;
+      }
+    li[ti] = (G.nl == 2 && cost[1] < cost[0]) ? 1 : 0;
+    for (size_t gj = 0; gj < p->grids.size(); ++gj)
+      if (same_shape(p->grids[gj], g)) set_layout(p, (int)gj, G.lay[li[ti]]);
+    if (G.nl == 2) {
+      chosen[layout_key(p->f64, g)] = G.lay[li[ti]];
+      for (int l = 0; l < 2; ++l)
+        lay_rows.push_back(lsfft_tune_entry{3, tg[ti].gi, G.lay[l], l == li[ti] ? 1 : 0, 1e3 * cost[l]});
+    }
+  }
+  // Variant per (kind, length): mean kernel time per launch, summed over the
+  // grids sharing that length, each under its chosen layout.
+  std::map<std::pair<int, int>, std::vector<double>> times;
+  for (size_t ti = 0; ti < tg.size(); ++ti) {
+    const GridTimes& G = gt[ti];
+    for (int k = 0; k < 3; ++k) {
+      if (G.nv[k] == 1) continue;   // passes with the default only are not tuned
+      auto& v = times[{k, G.lens[k]}];
+      if ((int)v.size() < G.nv[k]) v.resize(G.nv[k], 0.0);
+      for (int r = 0; r < G.nv[k]; ++r) v[r] += 1e3 * G.ms[li[ti]][r][k] / per_iter[k];
+    }
+  }
   for (const auto& kv : times) {
     const int kind = kv.first.first, len = kv.first.second;
     const auto& v = kv.second;
@@ -1968,6 +2099,10 @@ lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, l
     chosen[tune_key(p->f64, 3, kind, len)] = best;
     for (int r = 0; r < (int)v.size(); ++r, ++n)
       if (n < max_out) out[n] = lsfft_tune_entry{kind, len, r, r == best ? 1 : 0, v[r]};
+  }
+  for (const auto& e : lay_rows) {
+    if (n < max_out) out[n] = e;
+    ++n;
   }
   if (nout) *nout = n;
   if (cache_path && !chosen.empty()) {
@@ -1995,7 +2130,7 @@ lsfft_status lsfft_kernel_convolve(lsfft_plan_t p, int grid_idx, const void* ker
     if (!f[i] || !out[i]) return LSFFT_E_ARG;
   const lsfft_grid& gr = p->grids[grid_idx];
   Geometry geo;
-  if (!geometry(p->f64, gr, p->sched, &geo)) return LSFFT_E_ARG;
+  if (!geometry(p->f64, gr, p->sched, &geo, p->layout[grid_idx])) return LSFFT_E_ARG;
   const int d = geo.dim, s = geo.s;
   const size_t rs = p->f64 ? 8 : 4, cs = 2 * rs;
   if (!p->kspec.ensure(cs * (size_t)(s * d) * (size_t)geo.Pc)) return LSFFT_E_ALLOC;

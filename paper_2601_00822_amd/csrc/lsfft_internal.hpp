@@ -90,6 +90,8 @@ struct InstDesc {
   int precond;         // CG: 1 = preconditioned by N0, 0 = plain (Algorithm 3)
   int cg_start;        // CG: 1 = Algorithm 3's printed start u1 = b^A
   int aa_m;            // Anderson memory (1..kAAMax), 0 = not Anderson
+  int blk;             // 3D, nx a multiple of 16: kx-blocked layout of S2 (see S2)
+  int bls;             // blocked: entries between consecutive y lines of a block (8 nz)
   long long Pm, Pc;    // complex entries: main block, component stride
   long long nvox;      // nx * ny * nz
   double kx, ky, kz;   // 2 pi / (n h) per axis
@@ -98,7 +100,17 @@ struct InstDesc {
   double tol;
   const uint8_t* phase;
   const void* f_in;    // real force [d][nvox]
-  void* S;             // spectral work [ncomp_s + d][Pc]
+  void* S;             // spectral work [ncomp_s + d][Pc], rows (z, y) of H entries
+  // With blk, the spectra between the y passes and the outer pass (stress
+  // after the forward y transforms, strain and displacement before the
+  // inverse ones, the force before its outer transform) live here instead,
+  // kx-blocked: entry (kx, y, z) at ((kx / 8) ny + y) bls + 8 z + kx % 8,
+  // so that an outer-pass tile reads and writes whole 8 x nz blocks; the y
+  // passes convert between the two layouts (out of place).  The other
+  // spectral buffers that only the outer pass and the element-wise kernels
+  // touch (state, force, search directions, Anderson history) take the
+  // same layout.
+  void* S2;            // [ncomp_s + d][Pc] or null
   void* U[2];          // displacement spectrum, double-buffered [d][Pc]
   void* F;             // force spectrum [d][Pc] (may be shared)
   void* R;             // CG residual [d][Pc]

@@ -35,7 +35,9 @@ EXPORTS = [
     "lsfft_block_mean", "lsfft_sample_norms", "lsfft_bump_forces", "lsfft_nonlocal_normal_equations",
     "lsfft_nonlocal_apply", "lsfft_nonlocal_fit",
 ]
-PASS_KINDS = {"x": 0, "y": 1, "outer": 2}
+# schedule kinds: the three passes (keyed by transform length) and the
+# spectral layout (keyed by the grid's index in the plan)
+PASS_KINDS = {"x": 0, "y": 1, "outer": 2, "layout": 3}
 
 
 class Rve(C.Structure):
@@ -601,7 +603,9 @@ class Plan:
     # ------------------------------------------------------------------ schedules
     def schedule(self, kind: str, length: int, dim: int = 3):
         """(variant in use, number of variants) of pass ``kind`` ("x", "y" or
-        "outer") on an axis of ``length`` points."""
+        "outer") on an axis of ``length`` points; for ``kind`` "layout", of
+        the spectral layout of grid ``length`` (its index in the plan): 0
+        rows, 1 kx-blocked (3D grids with nx a multiple of 16)."""
         v, n = C.c_int(), C.c_int()
         st = self.lib.lsfft_schedule_get(self.handle, int(dim), PASS_KINDS[kind], int(length), C.byref(v), C.byref(n))
         if st != OK:
@@ -614,8 +618,11 @@ class Plan:
             raise LsfftError(st, "lsfft_schedule_set")
 
     def autotune(self, iters: int = 20, cache_path=None):
-        """Time every schedule variant of the plan's 3D grids and keep the
-        fastest; returns the timings as a list of dicts."""
+        """Time every schedule variant of the plan's 3D grids under each of
+        their spectral layouts, keep the faster layout per grid and the
+        fastest variants under it; returns the timings as a list of dicts
+        (layout entries: kind "layout", len = the grid's index, us = kernel
+        time of the three passes per iteration on their fastest variants)."""
         cap = 64
         out = (TuneEntry * cap)()
         n = C.c_int()

@@ -100,8 +100,9 @@ def test_schedule_argument_checks(torch_dev):
 
 def test_autotune_choice_solves_like_the_oracle_and_is_cached(torch_dev, tmp_path):
     """The tuner times every variant of the 48^3 and 4x64x96 grids' passes,
-    keeps the fastest per (kind, length), writes them to the cache, and a
-    plan built with LSFFT_TUNE_CACHE naming that file starts from the same
+    keeps the fastest per (kind, length), then times both spectral layouts
+    of each grid and keeps the faster, writes them to the cache, and a plan
+    built with LSFFT_TUNE_CACHE naming that file starts from the same
     choices; the tuned plan's solves match the oracle (FP32 bar) in a mixed
     batch."""
     torch, dev = torch_dev
@@ -113,8 +114,17 @@ def test_autotune_choice_solves_like_the_oracle_and_is_cached(torch_dev, tmp_pat
     table = plan.autotune(iters=8, cache_path=str(cache))
     for e in table:
         print(e)
-    keys = {(e["kind"], e["len"]) for e in table}
+    keys = {(e["kind"], e["len"]) for e in table if e["kind"] != "layout"}
     assert keys == {("x", 48), ("y", 48), ("outer", 48), ("x", 96), ("y", 64)}
+    # one layout pair per grid (both have nx a multiple of 16)
+    lay = {}
+    for g in range(len(shapes)):
+        rows = [e for e in table if e["kind"] == "layout" and e["len"] == g]
+        assert sorted(e["variant"] for e in rows) == [0, 1] and all(e["us"] > 0 for e in rows)
+        best = min(rows, key=lambda e: (e["us"], -e["variant"]))
+        assert [e["variant"] for e in rows if e["chosen"]] == [best["variant"]]
+        assert plan.schedule("layout", g)[0] == best["variant"]
+        lay[g] = best["variant"]
     for k in keys:
         rows = [e for e in table if (e["kind"], e["len"]) == k]
         assert sorted(e["variant"] for e in rows) == list(range(plan.schedule(*k)[1]))
@@ -125,6 +135,9 @@ def test_autotune_choice_solves_like_the_oracle_and_is_cached(torch_dev, tmp_pat
     cached = json.loads(cache.read_text())
     for kind, n in keys:
         assert cached[f"f32/3d/{kind}/{n}"] == plan.schedule(kind, n)[0]
+    lkey = {g: "f32/3d/layout/%dx%dx%d" % shp[::-1] for g, shp in enumerate(shapes)}
+    for g in lay:
+        assert cached[lkey[g]] == lay[g]
     # the tuned plan solves like the oracle
     probs, refs = [], []
     for g, shp in enumerate(shapes):
@@ -144,6 +157,8 @@ def test_autotune_choice_solves_like_the_oracle_and_is_cached(torch_dev, tmp_pat
         p2 = Plan(shapes, prec="f32")
         for kind, n in keys:
             assert p2.schedule(kind, n)[0] == cached[f"f32/3d/{kind}/{n}"]
+        for g in lay:
+            assert p2.schedule("layout", g)[0] == lay[g]
         p2.close()
     finally:
         del os.environ["LSFFT_TUNE_CACHE"]
