@@ -436,8 +436,9 @@ lsfft_status lsfft_iteration_bytes(lsfft_plan_t p, int grid_idx, int kernel_clas
  *
  * Kind 3 is the spectral layout of one grid, `len` being the grid's index
  * in the plan: variant 0 keeps the spectra in rows of nx/2 entries
- * throughout; variant 1 (the default, for 3D grids with nx a multiple of
- * 16) keeps them between the y and outer passes in 8-wide kx blocks, entry
+ * throughout (the default of FP64 plans); variant 1 (the default of FP32
+ * plans, for 3D grids with nx a multiple of 16) keeps them between the y
+ * and outer passes in 8-wide kx blocks, entry
  * (kx, y, z) at ((kx/8) ny + y) 8 nz + 8 z + kx mod 8, so that each outer
  * transform tile reads and writes contiguous blocks; the y passes then
  * convert between the two layouts out of place, and each such solve holds
@@ -489,8 +490,8 @@ lsfft_status lsfft_schedule_set(lsfft_plan_t p, int dim, int kind, int len, int 
  *              variant, chosen flag, microseconds), *nout entries in all
  * Allocates device memory for the synthetic inputs; synchronises the plan's
  * stream.  LSFFT_E_ARG for bad arguments or a cache file that cannot be
- * written.  FP64 plans and 2D grids have nothing to tune (*nout = 0; FP64
- * plans keep the default layout).
+ * written.  FP64 plans tune the layout only (their passes have one variant
+ * each); 2D grids have nothing to tune (*nout = 0).
  */
 lsfft_status lsfft_autotune(lsfft_plan_t p, int iters, const char* cache_path, lsfft_tune_entry* out, int max_out,
                             int* nout);

@@ -94,8 +94,14 @@ def test_schedule_argument_checks(torch_dev):
     plan.close()
     p64 = Plan([(16, 16, 256)], prec="f64")
     assert p64.schedule("x", 256) == (0, 1)            # FP64: the default only
-    assert p64.autotune(iters=2) == []
+    assert p64.schedule("layout", 0) == (0, 2)         # FP64 plans start in rows
+    table = p64.autotune(iters=2)                      # and tune the layout only
+    assert sorted((e["kind"], e["len"], e["variant"]) for e in table) == [("layout", 0, 0), ("layout", 0, 1)]
+    assert p64.schedule("layout", 0)[0] == [e["variant"] for e in table if e["chosen"]][0]
     p64.close()
+    p2d = Plan([(16, 64)], prec="f32")
+    assert p2d.autotune(iters=2) == []                 # 2D: nothing to tune
+    p2d.close()
 
 
 def test_autotune_choice_solves_like_the_oracle_and_is_cached(torch_dev, tmp_path):
