@@ -195,3 +195,36 @@ def test_layout_schedule_arguments(torch_dev):
     with pytest.raises(LsfftError):
         plan.schedule("layout", 2)                         # grid 2 is 2D
     plan.close()
+
+
+def test_mixed_layouts_in_one_batch(torch_dev):
+    """One batch whose grids use different layouts in the same launches (the
+    kernels read the layout per solve): every solve equals its oracle solve
+    and, bit for bit, the same batch with the layouts swapped."""
+    torch, dev = torch_dev
+    from paper_2601_00822_amd import Plan
+    shapes = [(8, 8, 32), (6, 12, 48), (4, 6, 24)]
+    say(f"FP64 batch over {shapes} with mixed layouts")
+    probs, refs = [], []
+    for g, shp in enumerate(shapes):
+        phase, f = problem(shp, 81 + g)
+        probs.append(dict(grid=g, phase=torch.from_numpy(phase).to(dev), lame=LAME, f=torch.from_numpy(f).to(dev)))
+        refs.append(O.solve_basic(phase, LAME, f, tol=1e-8))
+    plan = Plan(shapes, prec="f64", max_batch=len(shapes))
+    assert plan.schedule("layout", 2) == (0, 1)            # nx = 24: rows only
+    results = []
+    for lays in ((1, 0), (0, 1)):
+        plan.set_schedule("layout", 0, lays[0])
+        plan.set_schedule("layout", 1, lays[1])
+        outs, reps, st = plan.solve_batch(probs, tol=1e-8)
+        torch.cuda.synchronize()
+        assert st == 0
+        results.append(([{k: v.cpu().numpy() for k, v in o.items()} for o in outs], [r.iters for r in reps]))
+        for o, r, ref in zip(outs, reps, refs):
+            assert r.iters == ref.iters
+            assert O.relative_strain_error_voigt(o["eps"].cpu().numpy(), O.to_voigt(ref.eps)) < 1e-10
+    plan.close()
+    assert results[0][1] == results[1][1]
+    for a, b in zip(results[0][0], results[1][0]):
+        for k in a:
+            np.testing.assert_array_equal(a[k], b[k], err_msg=k)
