@@ -623,7 +623,7 @@ class Plan:
         fastest variants under it; returns the timings as a list of dicts
         (layout entries: kind "layout", len = the grid's index, us = kernel
         time of the three passes per iteration on their fastest variants)."""
-        cap = 64
+        cap = 512
         out = (TuneEntry * cap)()
         n = C.c_int()
         st = self.lib.lsfft_autotune(self.handle, int(iters), None if cache_path is None else str(cache_path).encode(),
